@@ -1,0 +1,297 @@
+"""Plain CPU oracle for the FX correlator hot path (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The GPU library never does, and the two
+share no code.  The arithmetic lives in ``oracle.c`` (FP64 / int64, built with
+gcc); this module only marshals numpy arrays into it and adds the few
+definitions that are clearer in numpy (pair indexing, error metrics).
+
+Each wrapper names the passage of Roy et al. (arXiv:0910.1517) it follows; the
+C source restates the definition.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (no fast-math) into liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build()
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.orc_dft.argtypes = [P, P, i64]
+    lib.orc_fft.argtypes = [P, i64]
+    lib.orc_fft.restype = i32
+    lib.orc_fengine.argtypes = [P, i64, i32, i64, i64, i64, P, P, P, P, dbl, dbl, i32, i32, P]
+    lib.orc_fengine.restype = i32
+    lib.orc_fengine_channels.argtypes = [P, i64, i32, i64, i64, i64, P, P, P, P, dbl, dbl, i32,
+                                         P, i32, P]
+    lib.orc_fengine_channels.restype = i32
+    lib.orc_xengine_f64.argtypes = [P, i32, i64, i64, P]
+    lib.orc_xengine_int.argtypes = [P, i32, i64, i64, P]
+    lib.orc_sigma.argtypes = [P, i32, i64, i64, P]
+    lib.orc_quantize_int8.argtypes = [P, P, i32, i64, i64, P]
+    lib.orc_quantize_fp8.argtypes = [P, P, i32, i64, i64, P]
+    lib.orc_e4m3_decode.argtypes = [ctypes.c_uint8]
+    lib.orc_e4m3_decode.restype = dbl
+    lib.orc_e4m3_encode.argtypes = [dbl]
+    lib.orc_e4m3_encode.restype = ctypes.c_uint8
+    lib.orc_scale_visibilities.argtypes = [P, P, i32, i64, P]
+    lib.orc_median.argtypes = [P, i64]
+    lib.orc_median.restype = dbl
+    lib.orc_mad_flags.argtypes = [P, i64, dbl, P, P, P]
+    lib.orc_mad_flags.restype = i64
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# Transforms (section 2.1: FX correlator -- channelise by FFT first)
+# ---------------------------------------------------------------------------
+def dft(z: np.ndarray) -> np.ndarray:
+    """Direct DFT X[k] = sum_n z[n] exp(-2 pi i k n / N), FP64."""
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    out = np.empty_like(z)
+    _load().orc_dft(_p(z), _p(out), z.size)
+    return out
+
+
+def fft(z: np.ndarray) -> np.ndarray:
+    """Radix-2 FFT with the same definition as :func:`dft`, FP64."""
+    z = np.array(z, dtype=np.complex128, order="C", copy=True)
+    if _load().orc_fft(_p(z), z.size) != 0:
+        raise ValueError("length must be a power of two")
+    return z
+
+
+class Geometry:
+    """Per-signal delay/fringe parameters of one call (section 2.1, Eq. 2).
+
+    D: integer delay in samples (read-pointer advance), f: fractional delay in
+    samples in [0, 1), psi0: fringe phase in cycles at the call's reference
+    epoch, rate: fringe rate in Hz.
+    """
+
+    def __init__(self, D, f, psi0, rate):
+        self.D = np.ascontiguousarray(D, dtype=np.int32)
+        self.f = np.ascontiguousarray(f, dtype=np.float64)
+        self.psi0 = np.ascontiguousarray(psi0, dtype=np.float64)
+        self.rate = np.ascontiguousarray(rate, dtype=np.float64)
+
+
+def fengine(x: np.ndarray, N: int, T: int, geom: Geometry, fs: float, nu_bb: float = 0.0,
+            sideband: int = 1, spectrum0: int = 0, method: str = "fft") -> np.ndarray:
+    """F-engine of section 2.1 / 2.3.2 with Eq. 2 phase; returns Y[S][T][C] complex128.
+
+    x: int8 [S][row_stride]; row s must hold at least T*N + D_s samples.
+    """
+    x = np.ascontiguousarray(x, dtype=np.int8)
+    S, stride = x.shape
+    if np.any(geom.D < 0) or np.any(T * N + geom.D > stride):
+        raise ValueError("delay window runs past the row")
+    C = N // 2
+    Y = np.empty((S, T, C), dtype=np.complex128)
+    rc = _load().orc_fengine(_p(x), stride, S, N, T, spectrum0, _p(geom.D), _p(geom.f),
+                             _p(geom.psi0), _p(geom.rate), fs, nu_bb, sideband,
+                             1 if method == "dft" else 0, _p(Y))
+    if rc != 0:
+        raise ValueError("orc_fengine failed (%d)" % rc)
+    return Y
+
+
+def fengine_channels(x: np.ndarray, N: int, T: int, geom: Geometry, fs: float, channels,
+                     nu_bb: float = 0.0, sideband: int = 1, spectrum0: int = 0) -> np.ndarray:
+    """Direct-DFT F-engine for selected channels; returns Y[S][T][len(channels)]."""
+    x = np.ascontiguousarray(x, dtype=np.int8)
+    S, stride = x.shape
+    if np.any(geom.D < 0) or np.any(T * N + geom.D > stride):
+        raise ValueError("delay window runs past the row")
+    kk = np.ascontiguousarray(channels, dtype=np.int64)
+    Y = np.empty((S, T, kk.size), dtype=np.complex128)
+    rc = _load().orc_fengine_channels(_p(x), stride, S, N, T, spectrum0, _p(geom.D), _p(geom.f),
+                                      _p(geom.psi0), _p(geom.rate), fs, nu_bb, sideband,
+                                      _p(kk), kk.size, _p(Y))
+    if rc != 0:
+        raise ValueError("orc_fengine_channels failed (%d)" % rc)
+    return Y
+
+
+# ---------------------------------------------------------------------------
+# X-engine (section 2.1: cross-multiply every pair, integrate over time)
+# ---------------------------------------------------------------------------
+def n_pairs(S: int) -> int:
+    return S * (S + 1) // 2
+
+
+def pair_index(i: int, j: int) -> int:
+    """Pair (i <= j) -> p = j(j+1)/2 + i."""
+    if i > j:
+        raise ValueError("pair index needs i <= j")
+    return j * (j + 1) // 2 + i
+
+
+def pair_table(S: int):
+    """Arrays (i, j) indexed by p."""
+    ii = np.empty(n_pairs(S), dtype=np.int64)
+    jj = np.empty(n_pairs(S), dtype=np.int64)
+    for j in range(S):
+        for i in range(j + 1):
+            ii[pair_index(i, j)] = i
+            jj[pair_index(i, j)] = j
+    return ii, jj
+
+
+def xengine(Y: np.ndarray, V: np.ndarray | None = None) -> np.ndarray:
+    """V[C][P] += sum_m Y_i conj(Y_j) (FP64 triple loop).  Y: complex [S][T][C]."""
+    Y = np.ascontiguousarray(Y, dtype=np.complex128)
+    S, T, C = Y.shape
+    if V is None:
+        V = np.zeros((C, n_pairs(S)), dtype=np.complex128)
+    _load().orc_xengine_f64(_p(Y), S, T, C, _p(V))
+    return V
+
+
+def xengine_int(q: np.ndarray, A: np.ndarray | None = None) -> np.ndarray:
+    """A[C][P][2] += sum_m q_i conj(q_j) in int64.  q: int8 [S][T][C][2]."""
+    q = np.ascontiguousarray(q, dtype=np.int8)
+    S, T, C, two = q.shape
+    assert two == 2
+    if A is None:
+        A = np.zeros((C, n_pairs(S), 2), dtype=np.int64)
+    _load().orc_xengine_int(_p(q), S, T, C, _p(A))
+    return A
+
+
+# ---------------------------------------------------------------------------
+# Requantisation (section 4.1) and FP8 encoding
+# ---------------------------------------------------------------------------
+def sigma(Y: np.ndarray) -> np.ndarray:
+    """sigma[s][k] = sqrt(sum_m |Y|^2 / (2T)): RMS of one component."""
+    Y = np.ascontiguousarray(Y, dtype=np.complex128)
+    S, T, C = Y.shape
+    out = np.empty((S, C), dtype=np.float64)
+    _load().orc_sigma(_p(Y), S, T, C, _p(out))
+    return out
+
+
+def int8_scale(sig: np.ndarray) -> np.ndarray:
+    """Recorded int8 scale 4 sigma / 127 (1 where sigma is 0), as float32."""
+    s = (4.0 * np.asarray(sig, dtype=np.float64) / 127.0).astype(np.float32)
+    s[s == 0] = 1.0
+    return s
+
+
+def fp8_scale(sig: np.ndarray) -> np.ndarray:
+    """Recorded e4m3 scale 4 sigma / 448 (1 where sigma is 0), as float32."""
+    s = (4.0 * np.asarray(sig, dtype=np.float64) / 448.0).astype(np.float32)
+    s[s == 0] = 1.0
+    return s
+
+
+def quantize_int8(Y: np.ndarray, scale: np.ndarray) -> np.ndarray:
+    """q = clamp(rne(Y/scale), +-127) per component -> int8 [S][T][C][2]."""
+    Y = np.ascontiguousarray(Y, dtype=np.complex128)
+    S, T, C = Y.shape
+    sc = np.ascontiguousarray(scale, dtype=np.float64)
+    q = np.empty((S, T, C, 2), dtype=np.int8)
+    _load().orc_quantize_int8(_p(Y), _p(sc), S, T, C, _p(q))
+    return q
+
+
+def quantize_fp8(Y: np.ndarray, scale: np.ndarray) -> np.ndarray:
+    """b = e4m3(Y/scale) per component -> uint8 codes [S][T][C][2]."""
+    Y = np.ascontiguousarray(Y, dtype=np.complex128)
+    S, T, C = Y.shape
+    sc = np.ascontiguousarray(scale, dtype=np.float64)
+    q = np.empty((S, T, C, 2), dtype=np.uint8)
+    _load().orc_quantize_fp8(_p(Y), _p(sc), S, T, C, _p(q))
+    return q
+
+
+def e4m3_decode(codes) -> np.ndarray:
+    lib = _load()
+    c = np.asarray(codes, dtype=np.uint8)
+    return np.array([lib.orc_e4m3_decode(int(b)) for b in c.ravel()]).reshape(c.shape)
+
+
+def e4m3_decode_table() -> np.ndarray:
+    """All 256 code values (NaN for 0x7F / 0xFF)."""
+    return e4m3_decode(np.arange(256, dtype=np.uint8))
+
+
+def e4m3_encode(v: float) -> int:
+    return int(_load().orc_e4m3_encode(float(v)))
+
+
+def scale_visibilities(A: np.ndarray, scale: np.ndarray, V: np.ndarray | None = None):
+    """V += scale_i scale_j A (FP64).  A: [C][P][2] int64/float; scale [S][C]."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    C, P, _ = A.shape
+    S = int(round((np.sqrt(8 * P + 1) - 1) / 2))
+    sc = np.ascontiguousarray(scale, dtype=np.float64)
+    out = np.zeros((C, P, 2), dtype=np.float64) if V is None else V
+    _load().orc_scale_visibilities(_p(A), _p(sc), S, C, _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# MAD (section 5, Eq. 3 and Eq. 4)
+# ---------------------------------------------------------------------------
+def median(v) -> float:
+    v = np.ascontiguousarray(v, dtype=np.float64).ravel()
+    return float(_load().orc_median(_p(v), v.size))
+
+
+def mad_flags(x, M: float = 3.0):
+    """Flags of Eq. 4 on the block x; returns (flags uint8, median, MAD)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    fl = np.empty(x.size, dtype=np.uint8)
+    med = ctypes.c_double()
+    mad = ctypes.c_double()
+    _load().orc_mad_flags(_p(x), x.size, M, _p(fl), ctypes.byref(med), ctypes.byref(mad))
+    return fl, med.value, mad.value
+
+
+# ---------------------------------------------------------------------------
+# Error metrics (the paper's tolerance is not stated; these are the build's)
+# ---------------------------------------------------------------------------
+def normalized_error(V: np.ndarray, V64: np.ndarray, S: int):
+    """(e_max, e_fro): e_max = max |V - V64| / sqrt(V64_ii V64_jj) over all
+    channels and pairs; e_fro = ||V - V64||_F / ||V64||_F."""
+    V = np.asarray(V, dtype=np.complex128)
+    V64 = np.asarray(V64, dtype=np.complex128)
+    ii, jj = pair_table(S)
+    auto = np.real(V64[:, [pair_index(s, s) for s in range(S)]])  # [C][S]
+    denom = np.sqrt(np.abs(auto[:, ii] * auto[:, jj]))
+    denom = np.where(denom > 0, denom, 1.0)
+    err = np.abs(V - V64)
+    e_max = float(np.max(err / denom))
+    e_fro = float(np.linalg.norm(V - V64) / max(np.linalg.norm(V64), 1e-300))
+    return e_max, e_fro

@@ -1,0 +1,418 @@
+/*
+ * oracle.c -- plain, slow, obviously correct CPU reference for the FX
+ * correlator hot path of Roy et al., "A real-time software backend for the
+ * GMRT" (arXiv:0910.1517).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant
+ * generator with the GPU library.
+ *
+ * Arithmetic is IEEE double precision (FP64) for floating point and int64 for
+ * the integer X-engine.  Each function follows one definition of the paper,
+ * written out without blocking, fusion or reordering:
+ *
+ *   integer delay        section 2.1 (block shift) and section 2.3.2
+ *                        (read-pointer offset into the overlapped slice)
+ *   channelisation       section 2.1 (FX architecture: FFT, then multiply)
+ *   FSTC + fringe        Eq. 2 of section 2.1
+ *   cross-multiply       section 2.1 (all four polar products per baseline,
+ *                        integrated over time)
+ *   requantisation       section 4.1 (fixed-point pipeline up to the MAC,
+ *                        32-bit products, float long-term accumulation)
+ *   MAD statistic        Eq. 3 and Eq. 4 of section 5
+ *
+ * Readings where the paper is silent (FFT sign, bins kept, time stamp of a
+ * spectrum, sign convention of Eq. 2, requantisation scale, e4m3 format) are
+ * the ones listed in the design notes of the repository and are restated at
+ * each function below.
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC oracle.c -o liboracle.so -lm
+ * (no -ffast-math: every operation is the plain IEEE one).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef double complex cplx;
+
+static int is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+/* ------------------------------------------------------------------------ */
+/* Discrete Fourier transform, X[k] = sum_n z[n] exp(-2 pi i k n / N).        */
+/* Sign negative, no normalisation, rectangular window (section 2.1 leaves    */
+/* these open; this is the textbook forward DFT).                             */
+/* ------------------------------------------------------------------------ */
+
+/* Direct evaluation of the definition.  The exponent k*n is reduced modulo N
+ * in exact integer arithmetic before the libm cos/sin call. */
+void orc_dft(const double *zin, double *zout, int64_t n)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        cplx acc = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t r = (k * j) % n;
+            double a = -2.0 * M_PI * (double)r / (double)n;
+            cplx w = cos(a) + I * sin(a);
+            acc += (zin[2 * j] + I * zin[2 * j + 1]) * w;
+        }
+        zout[2 * k] = creal(acc);
+        zout[2 * k + 1] = cimag(acc);
+    }
+}
+
+/* Radix-2 decimation-in-time Cooley-Tukey FFT, in place, same definition as
+ * orc_dft.  Textbook form: bit-reversal permutation, then log2(N) stages of
+ * butterflies whose twiddles come straight from libm cos/sin. */
+static void fft_inplace(cplx *z, int64_t n)
+{
+    for (int64_t i = 1, j = 0; i < n; ++i) {
+        int64_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) { cplx t = z[i]; z[i] = z[j]; z[j] = t; }
+    }
+    for (int64_t len = 2; len <= n; len <<= 1) {
+        int64_t half = len >> 1;
+        for (int64_t j = 0; j < half; ++j) {
+            double a = -2.0 * M_PI * (double)j / (double)len;
+            cplx w = cos(a) + I * sin(a);
+            for (int64_t i = 0; i < n; i += len) {
+                cplx u = z[i + j];
+                cplx v = z[i + j + half] * w;
+                z[i + j] = u + v;
+                z[i + j + half] = u - v;
+            }
+        }
+    }
+}
+
+int orc_fft(double *z, int64_t n)
+{
+    if (!is_pow2(n)) return -1;
+    fft_inplace((cplx *)z, n);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* F-engine.                                                                  */
+/*                                                                            */
+/* Signal s, spectrum m (0-based inside this call, absolute index             */
+/* spectrum0 + m):                                                            */
+/*   window   w[n] = x[s][m*N + D_s + n],  n = 0..N-1   (integer delay as a   */
+/*            read-pointer advance into a row that carries D_pad extra        */
+/*            samples, the paper's overlap region)                            */
+/*   spectrum X[k] = sum_n w[n] exp(-2 pi i k n / N),  k = 0..N/2-1           */
+/*            (DC kept, Nyquist bin dropped)                                  */
+/*   phase    theta = 2 pi [ (nu_BB + k fs/N) * f_s/fs                        */
+/*                          + sigma * (psi_s + r_s * t_m) ],                  */
+/*            t_m = (spectrum0 + m + 1/2) N / fs, the window centre measured  */
+/*            from the call's reference epoch (Eq. 2; f_s is the fractional   */
+/*            delay in samples, so tau_frac = f_s/fs; psi_s and r_s are the   */
+/*            fringe phase in cycles and the fringe rate in Hz, sigma = +-1   */
+/*            the sideband sign of Eq. 2)                                     */
+/*   output   Y[k] = X[k] * exp(+i theta)                                     */
+/*                                                                            */
+/* Y layout: [S][T][C][2] doubles, C = N/2.                                   */
+/* method 0: radix-2 FFT; method 1: direct DFT.                               */
+/* ------------------------------------------------------------------------ */
+static double fstc_fringe_phase(int64_t k, int64_t N, double fs, double nu_bb,
+                                double f, double psi0, double rate,
+                                int sideband, int64_t spectrum)
+{
+    double nu_k = (double)k * fs / (double)N;
+    double t_m = ((double)spectrum + 0.5) * (double)N / fs;
+    return 2.0 * M_PI * ((nu_bb + nu_k) * f / fs +
+                         (double)sideband * (psi0 + rate * t_m));
+}
+
+int orc_fengine(const int8_t *x, int64_t row_stride, int S, int64_t N,
+                int64_t T, int64_t spectrum0, const int32_t *D,
+                const double *f, const double *psi0, const double *rate,
+                double fs, double nu_bb, int sideband, int method, double *Y)
+{
+    if (!is_pow2(N) || S <= 0 || T < 0) return -1;
+    int64_t C = N / 2;
+    int bad = 0;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int s = 0; s < S; ++s) {
+        for (int64_t m = 0; m < T; ++m) {
+            cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+            cplx *X = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+            if (!w || !X) { bad = 1; free(w); free(X); continue; }
+            const int8_t *row = x + (int64_t)s * row_stride;
+            for (int64_t n = 0; n < N; ++n)
+                w[n] = (double)row[m * N + D[s] + n];
+            if (method == 1) {
+                orc_dft((const double *)w, (double *)X, N);
+            } else {
+                memcpy(X, w, sizeof(cplx) * (size_t)N);
+                fft_inplace(X, N);
+            }
+            double *out = Y + (((int64_t)s * T + m) * C) * 2;
+            for (int64_t k = 0; k < C; ++k) {
+                double th = fstc_fringe_phase(k, N, fs, nu_bb, f[s], psi0[s],
+                                              rate[s], sideband, spectrum0 + m);
+                cplx y = X[k] * (cos(th) + I * sin(th));
+                out[2 * k] = creal(y);
+                out[2 * k + 1] = cimag(y);
+            }
+            free(w);
+            free(X);
+        }
+    }
+    return bad ? -2 : 0;
+}
+
+/* Same F-engine for a list of channels only, by the direct DFT sum of the
+ * definition (used to check sampled outputs of full-size runs).
+ * Y layout: [S][T][nk][2]. */
+int orc_fengine_channels(const int8_t *x, int64_t row_stride, int S,
+                         int64_t N, int64_t T, int64_t spectrum0,
+                         const int32_t *D, const double *f, const double *psi0,
+                         const double *rate, double fs, double nu_bb,
+                         int sideband, const int64_t *kk, int nk, double *Y)
+{
+    if (!is_pow2(N) || S <= 0 || T < 0 || nk <= 0) return -1;
+    for (int i = 0; i < nk; ++i)
+        if (kk[i] < 0 || kk[i] >= N / 2) return -1;
+    /* exp(-2 pi i r / N) for r = 0..N-1, from libm */
+    cplx *tw = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    if (!tw) return -2;
+    for (int64_t r = 0; r < N; ++r) {
+        double a = -2.0 * M_PI * (double)r / (double)N;
+        tw[r] = cos(a) + I * sin(a);
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int s = 0; s < S; ++s) {
+        for (int64_t m = 0; m < T; ++m) {
+            const int8_t *w = x + (int64_t)s * row_stride + m * N + D[s];
+            for (int i = 0; i < nk; ++i) {
+                int64_t k = kk[i];
+                cplx acc = 0;
+                for (int64_t n = 0; n < N; ++n)
+                    acc += (double)w[n] * tw[(k * n) % N];
+                double th = fstc_fringe_phase(k, N, fs, nu_bb, f[s], psi0[s],
+                                              rate[s], sideband, spectrum0 + m);
+                cplx y = acc * (cos(th) + I * sin(th));
+                double *out = Y + (((int64_t)s * T + m) * nk + i) * 2;
+                out[0] = creal(y);
+                out[1] = cimag(y);
+            }
+        }
+    }
+    free(tw);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* X-engine (section 2.1): for every channel k and every signal pair i <= j   */
+/*   V_k[i][j] = sum_m Y_i[m,k] * conj(Y_j[m,k])                              */
+/* stored at pair index p = j(j+1)/2 + i.  Autocorrelations (i == j) and the  */
+/* cross-polar products are included: with s = 2a + pol this yields RR*, RL*, */
+/* LR* and LL* of every baseline.  V is accumulated (+=) so that a caller can */
+/* integrate over several calls.                                              */
+/* Y layout [S][T][C][2]; V layout [C][P][2].                                 */
+/* ------------------------------------------------------------------------ */
+void orc_xengine_f64(const double *Y, int S, int64_t T, int64_t C, double *V)
+{
+    int64_t P = (int64_t)S * (S + 1) / 2;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < C; ++k) {
+        for (int j = 0; j < S; ++j) {
+            for (int i = 0; i <= j; ++i) {
+                cplx acc = 0;
+                for (int64_t m = 0; m < T; ++m) {
+                    const double *yi = Y + (((int64_t)i * T + m) * C + k) * 2;
+                    const double *yj = Y + (((int64_t)j * T + m) * C + k) * 2;
+                    acc += (yi[0] + I * yi[1]) * (yj[0] - I * yj[1]);
+                }
+                int64_t p = (int64_t)j * (j + 1) / 2 + i;
+                V[(k * P + p) * 2] += creal(acc);
+                V[(k * P + p) * 2 + 1] += cimag(acc);
+            }
+        }
+    }
+}
+
+/* Integer X-engine: the same triple loop on requantised int8 spectra,
+ * accumulated in int64 (exact).  q layout [S][T][C][2]; A layout [C][P][2]. */
+void orc_xengine_int(const int8_t *q, int S, int64_t T, int64_t C, int64_t *A)
+{
+    int64_t P = (int64_t)S * (S + 1) / 2;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < C; ++k) {
+        for (int j = 0; j < S; ++j) {
+            for (int i = 0; i <= j; ++i) {
+                int64_t re = 0, im = 0;
+                for (int64_t m = 0; m < T; ++m) {
+                    const int8_t *a = q + (((int64_t)i * T + m) * C + k) * 2;
+                    const int8_t *b = q + (((int64_t)j * T + m) * C + k) * 2;
+                    /* (ar + i ai)(br - i bi) */
+                    re += (int64_t)a[0] * b[0] + (int64_t)a[1] * b[1];
+                    im += (int64_t)a[1] * b[0] - (int64_t)a[0] * b[1];
+                }
+                int64_t p = (int64_t)j * (j + 1) / 2 + i;
+                A[(k * P + p) * 2] += re;
+                A[(k * P + p) * 2 + 1] += im;
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Requantisation (section 4.1: fixed point up to the MAC with tuned levels). */
+/* sigma[s][k] = sqrt( sum_m |Y_s[m,k]|^2 / (2T) )  -- RMS of one component. */
+/* ------------------------------------------------------------------------ */
+void orc_sigma(const double *Y, int S, int64_t T, int64_t C, double *sigma)
+{
+    for (int s = 0; s < S; ++s)
+        for (int64_t k = 0; k < C; ++k) {
+            double acc = 0;
+            for (int64_t m = 0; m < T; ++m) {
+                const double *y = Y + (((int64_t)s * T + m) * C + k) * 2;
+                acc += y[0] * y[0] + y[1] * y[1];
+            }
+            sigma[(int64_t)s * C + k] = sqrt(acc / (2.0 * (double)T));
+        }
+}
+
+/* Round half to even, written out from its definition. */
+static double round_half_even(double u)
+{
+    double fl = floor(u);
+    double d = u - fl;
+    if (d > 0.5) return fl + 1.0;
+    if (d < 0.5) return fl;
+    return (fmod(fl, 2.0) == 0.0) ? fl : fl + 1.0;
+}
+
+/* q = clamp(rne(Y / scale), -127, +127) for both components; -128 is never
+ * produced, so conjugation and negation stay exact.  scale layout [S][C]. */
+void orc_quantize_int8(const double *Y, const double *scale, int S, int64_t T,
+                       int64_t C, int8_t *q)
+{
+    for (int s = 0; s < S; ++s)
+        for (int64_t m = 0; m < T; ++m)
+            for (int64_t k = 0; k < C; ++k)
+                for (int c = 0; c < 2; ++c) {
+                    int64_t idx = (((int64_t)s * T + m) * C + k) * 2 + c;
+                    double u = Y[idx] / scale[(int64_t)s * C + k];
+                    double r = round_half_even(u);
+                    if (r > 127.0) r = 127.0;
+                    if (r < -127.0) r = -127.0;
+                    q[idx] = (int8_t)r;
+                }
+}
+
+/* OCP 8-bit float E4M3 ("e4m3fn"): 1 sign bit, 4 exponent bits (bias 7),
+ * 3 mantissa bits, subnormals, no infinities, 0x7F/0xFF are NaN, largest
+ * finite magnitude 448. */
+double orc_e4m3_decode(uint8_t b)
+{
+    int sign = b >> 7, e = (b >> 3) & 0xF, mnt = b & 7;
+    double v;
+    if (e == 0xF && mnt == 7) return NAN;
+    if (e == 0) v = ldexp((double)mnt / 8.0, -6);
+    else v = ldexp(1.0 + (double)mnt / 8.0, e - 7);
+    return sign ? -v : v;
+}
+
+/* Round to the nearest finite e4m3 value, ties to the even code, saturating
+ * to +-448: a brute-force search over the 127 non-negative finite codes. */
+uint8_t orc_e4m3_encode(double v)
+{
+    double a = fabs(v);
+    int best = 0;
+    double bestd = INFINITY;
+    for (int c = 0; c <= 0x7E; ++c) {
+        double d = fabs(orc_e4m3_decode((uint8_t)c) - a);
+        if (d < bestd || (d == bestd && (c & 1) == 0 && (best & 1) == 1)) {
+            bestd = d;
+            best = c;
+        }
+    }
+    if (a > 448.0) best = 0x7E;
+    if (best == 0) return 0; /* +0 for both signs */
+    return (uint8_t)(best | (v < 0 ? 0x80 : 0));
+}
+
+/* FP8 requantisation: b = e4m3(Y / scale8), scale8 = 4 sigma / 448. */
+void orc_quantize_fp8(const double *Y, const double *scale, int S, int64_t T,
+                      int64_t C, uint8_t *q)
+{
+#pragma omp parallel for schedule(static)
+    for (int s = 0; s < S; ++s)
+        for (int64_t m = 0; m < T; ++m)
+            for (int64_t k = 0; k < C; ++k)
+                for (int c = 0; c < 2; ++c) {
+                    int64_t idx = (((int64_t)s * T + m) * C + k) * 2 + c;
+                    q[idx] = orc_e4m3_encode(Y[idx] / scale[(int64_t)s * C + k]);
+                }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integration (section 2.3.2 / 4.1): visibilities of the integer path are    */
+/* V = scale_i * scale_j * A, formed and accumulated in floating point.       */
+/* scale layout [S][C]; A layout [C][P][2]; V layout [C][P][2] (+=).          */
+/* ------------------------------------------------------------------------ */
+void orc_scale_visibilities(const double *A, const double *scale, int S,
+                            int64_t C, double *V)
+{
+    int64_t P = (int64_t)S * (S + 1) / 2;
+    for (int64_t k = 0; k < C; ++k)
+        for (int j = 0; j < S; ++j)
+            for (int i = 0; i <= j; ++i) {
+                int64_t p = (int64_t)j * (j + 1) / 2 + i;
+                double g = scale[(int64_t)i * C + k] * scale[(int64_t)j * C + k];
+                V[(k * P + p) * 2] += g * A[(k * P + p) * 2];
+                V[(k * P + p) * 2 + 1] += g * A[(k * P + p) * 2 + 1];
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* MAD statistic, Eq. 3 and Eq. 4 of section 5.                               */
+/* ------------------------------------------------------------------------ */
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Median of n values; for even n the mean of the two middle values. */
+double orc_median(const double *v, int64_t n)
+{
+    double *t = (double *)malloc(sizeof(double) * (size_t)n);
+    memcpy(t, v, sizeof(double) * (size_t)n);
+    qsort(t, (size_t)n, sizeof(double), cmp_double);
+    double med = (n & 1) ? t[n / 2] : 0.5 * (t[n / 2 - 1] + t[n / 2]);
+    free(t);
+    return med;
+}
+
+/* Eq. 3: MAD = median |x_i - median(x)|.  Eq. 4: flag x_i when
+ * |x_i - median(x)| > M * MAD / 0.6745 (strict).  Returns the number flagged
+ * and writes flags[i] in {0, 1}; med and mad are returned through pointers. */
+int64_t orc_mad_flags(const double *x, int64_t n, double M, uint8_t *flags,
+                      double *med_out, double *mad_out)
+{
+    double med = orc_median(x, n);
+    double *dev = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) dev[i] = fabs(x[i] - med);
+    double mad = orc_median(dev, n);
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        flags[i] = dev[i] > M * mad / 0.6745;
+        cnt += flags[i];
+    }
+    free(dev);
+    if (med_out) *med_out = med;
+    if (mad_out) *mad_out = mad;
+    return cnt;
+}

@@ -1,0 +1,208 @@
+"""Seeded synthetic GMRT-shaped inputs for the FX correlator.
+
+This module is the only code that both the GPU tests/benchmark and the CPU
+oracle consume.  It generates input samples and geometry; it holds none of the
+correlator's arithmetic (no channelisation, phase correction, cross-multiply or
+requantisation).
+
+Recipe (stand-in for recorded GMRT baseband, which is not available):
+
+* signal s = 2a + pol for antenna a and polarisation pol;
+* per antenna: integer delay D ~ U{0..16} samples, fractional delay
+  f ~ U[0, 1) samples, fringe phase psi0 ~ U[0, 1) cycles, fringe rate
+  r ~ U[-5, 5] Hz; both polarisations share them;
+* a common sky component per polarisation (independent for the two
+  polarisations): white Gaussian noise, band-limited to (0, fs/2), delayed
+  by D + f samples and fringe-rotated by exp(-2 pi i sigma (psi0 + r t)) --
+  the forward model whose inverse the correlator applies;
+* independent receiver noise per signal;
+* optional CW tone at the centre of one channel, delayed and rotated like
+  the sky component;
+* x = clip(rint(sigma_t (sqrt(rho) c + sqrt(1 - rho) n) + tone), -127, 127).
+
+``mode="physical"`` synthesises the delayed, fringe-rotated analytic signal in
+the frequency domain with numpy's FFT, in circular blocks of ``block`` samples.
+``mode="bulk"`` (large inputs where only the shape, rate and distribution
+matter) uses the integer part of the delay only and no fringe rotation; it is
+cheap and multi-threaded.
+
+Random numbers come from numpy's Philox counter-based generator keyed by
+(seed, purpose, signal, block), so any slice can be regenerated.
+"""
+from __future__ import annotations
+
+import concurrent.futures as _cf
+import os
+
+import numpy as np
+
+BASE_SEED = 0x09101517
+
+
+def rng(seed: int, *key: int) -> np.random.Generator:
+    """Philox-4x32-10 stream keyed by (seed, *key)."""
+    ss = np.random.SeedSequence([int(seed) & 0xFFFFFFFF, *[int(k) & 0xFFFFFFFF for k in key]])
+    return np.random.Generator(np.random.Philox(ss))
+
+
+class Geom:
+    """Per-signal geometry: D (int32), f, psi0, rate (float64) arrays."""
+
+    def __init__(self, D, f, psi0, rate):
+        self.D = np.asarray(D, dtype=np.int32)
+        self.f = np.asarray(f, dtype=np.float64)
+        self.psi0 = np.asarray(psi0, dtype=np.float64)
+        self.rate = np.asarray(rate, dtype=np.float64)
+
+    @property
+    def S(self):
+        return self.D.size
+
+    def subset(self, idx):
+        return Geom(self.D[idx], self.f[idx], self.psi0[idx], self.rate[idx])
+
+
+def make_geometry(n_ant: int, n_pol: int = 2, seed: int = BASE_SEED, max_delay: int = 16,
+                  rate_max: float = 5.0, frac: bool = True, fringe: bool = True) -> Geom:
+    """Antenna-based delays/fringes, repeated for each polarisation (s = n_pol*a + pol)."""
+    g = rng(seed, 1)
+    D = g.integers(0, max_delay + 1, size=n_ant)
+    f = g.random(n_ant) if frac else np.zeros(n_ant)
+    psi0 = g.random(n_ant) if fringe else np.zeros(n_ant)
+    rate = g.uniform(-rate_max, rate_max, size=n_ant) if fringe else np.zeros(n_ant)
+    rep = lambda a: np.repeat(a, n_pol)
+    return Geom(rep(D), rep(f), rep(psi0), rep(rate))
+
+
+def _analytic_block(g: np.random.Generator, B: int) -> np.ndarray:
+    """One-sided white spectrum Z[nu], nu = 0..B-1 (only 1..B/2-1 non-zero),
+    scaled so that Re of the analytic signal has unit variance."""
+    nb = B // 2 - 1
+    Z = np.zeros(B, dtype=np.complex128)
+    amp = np.sqrt(2.0 / nb) / np.sqrt(2.0)
+    Z[1:B // 2] = amp * (g.standard_normal(nb) + 1j * g.standard_normal(nb))
+    return Z
+
+
+def voltages(S: int, n_samples: int, geom: Geom, fs: float, *, seed: int = BASE_SEED,
+             rho: float = 0.3, sigma_t: float = 12.0, sideband: int = 1, n_pol: int = 2,
+             tone_bin: int | None = None, tone_N: int | None = None, tone_amp: float = 4.0,
+             sources: list | None = None, noise: bool = True, block: int = 1 << 20,
+             mode: str = "physical", threads: int | None = None) -> np.ndarray:
+    """int8 [S][n_samples] streams (see module docstring).
+
+    sources: list of dicts {"power": p, "dD": per-signal extra delay (samples),
+    "drate": per-signal extra fringe rate (Hz)}; default one source of power
+    rho at the phase centre.
+    """
+    if sources is None:
+        sources = [{"power": rho}]
+    if mode == "bulk":
+        return _voltages_bulk(S, n_samples, geom, seed=seed, rho=rho, sigma_t=sigma_t,
+                              n_pol=n_pol, tone_bin=tone_bin, tone_N=tone_N, tone_amp=tone_amp,
+                              noise=noise, threads=threads)
+    tot_src = float(sum(s["power"] for s in sources))
+    out = np.empty((S, n_samples), dtype=np.int8)
+    n_blocks = -(-n_samples // block)
+    nu = np.fft.fftfreq(block) * block  # integer frequencies (cycles per block)
+    for b in range(n_blocks):
+        n0 = b * block
+        nb = min(block, n_samples - n0)
+        t = (n0 + np.arange(nb)) / fs
+        acc = np.zeros((S, nb), dtype=np.float64)
+        for si, src in enumerate(sources):
+            amp_src = np.sqrt(src["power"])
+            dD = np.asarray(src.get("dD", np.zeros(S)), dtype=np.float64)
+            drate = np.asarray(src.get("drate", np.zeros(S)), dtype=np.float64)
+            for pol in range(n_pol):
+                Z = _analytic_block(rng(seed, 2, si, pol, b), block)
+                for s in range(pol, S, n_pol):
+                    tau = geom.D[s] + geom.f[s] + dD[s]
+                    u = np.fft.ifft(Z * np.exp(-2j * np.pi * nu * tau / block)) * block
+                    ph = np.exp(-2j * np.pi * sideband * (geom.psi0[s] + (geom.rate[s] + drate[s]) * t))
+                    acc[s] += amp_src * np.real(u[:nb] * ph)
+        if noise:
+            for s in range(S):
+                acc[s] += np.sqrt(max(0.0, 1.0 - tot_src)) * rng(seed, 3, s, b).standard_normal(nb)
+        acc *= sigma_t
+        if tone_bin is not None:
+            n = n0 + np.arange(nb)
+            for s in range(S):
+                tau = geom.D[s] + geom.f[s]
+                ph = 2 * np.pi * (tone_bin / tone_N) * (n - tau) \
+                    - 2 * np.pi * sideband * (geom.psi0[s] + geom.rate[s] * t)
+                acc[s] += tone_amp * np.cos(ph)
+        out[:, n0:n0 + nb] = np.clip(np.rint(acc), -127, 127).astype(np.int8)
+    return out
+
+
+def _voltages_bulk(S, n_samples, geom, *, seed, rho, sigma_t, n_pol, tone_bin, tone_N, tone_amp,
+                   noise, threads):
+    """Integer-delayed common component + noise (+ undelayed tone), multi-threaded."""
+    out = np.empty((S, n_samples), dtype=np.int8)
+    chunk = 1 << 22
+    maxD = int(geom.D.max()) if geom.S else 0
+    threads = threads or min(16, os.cpu_count() or 1)
+    a, bn = np.float32(sigma_t * np.sqrt(rho)), np.float32(sigma_t * np.sqrt(max(0.0, 1.0 - rho)))
+
+    def work(job):
+        pol, c0 = job
+        nb = min(chunk, n_samples - c0)
+        # common component for samples [c0 - maxD, c0 + nb)
+        g = rng(seed, 4, pol, c0 // chunk)
+        common = g.standard_normal(nb + maxD, dtype=np.float32)
+        for s in range(pol, S, n_pol):
+            d = int(geom.D[s])
+            v = a * common[maxD - d:maxD - d + nb]
+            if noise:
+                v = v + bn * rng(seed, 5, s, c0 // chunk).standard_normal(nb, dtype=np.float32)
+            if tone_bin is not None:
+                n = np.arange(c0, c0 + nb, dtype=np.float64)
+                v = v + (tone_amp * np.cos(2 * np.pi * (tone_bin / tone_N) * (n - d))).astype(np.float32)
+            np.clip(np.rint(v), -127, 127, out=v)
+            out[s, c0:c0 + nb] = v.astype(np.int8)
+
+    jobs = [(pol, c0) for pol in range(n_pol) for c0 in range(0, n_samples, chunk)]
+    with _cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(work, jobs))
+    return out
+
+
+def random_spectra_int8(S: int, T: int, C: int, seed: int = BASE_SEED, sigma: float = 32.0,
+                        extremes: bool = True) -> np.ndarray:
+    """Requantised-spectrum-like int8 [S][T][C][2] in [-127, 127] for X-engine tests.
+
+    Gaussian of the given sigma, clipped; with ``extremes`` a few entries are
+    forced to +-127 so that the largest products are exercised."""
+    g = rng(seed, 6, S, T, C)
+    q = np.clip(np.rint(g.standard_normal((S, T, C, 2), dtype=np.float32) * sigma), -127, 127)
+    q = q.astype(np.int8)
+    if extremes and q.size:
+        idx = g.integers(0, q.size, size=max(1, q.size // 1000))
+        q.reshape(-1)[idx] = np.where(g.random(idx.size) < 0.5, -127, 127).astype(np.int8)
+    return q
+
+
+def random_spectra_f32(S: int, T: int, C: int, seed: int = BASE_SEED, sigma: float = 100.0):
+    """complex64 [S][T][C] Gaussian spectra for FP32 X-engine tests."""
+    g = rng(seed, 7, S, T, C)
+    re = g.standard_normal((S, T, C), dtype=np.float32) * sigma
+    im = g.standard_normal((S, T, C), dtype=np.float32) * sigma
+    return (re + 1j * im).astype(np.complex64)
+
+
+def point_sources(S: int, n_src: int, power: float, seed: int = BASE_SEED, n_pol: int = 2):
+    """n_src sources sharing total power; source 0 at the phase centre, the others
+    with per-antenna extra delay U[-2, 2] samples and rate U[-0.5, 0.5] Hz."""
+    g = rng(seed, 8)
+    n_ant = S // n_pol
+    out = []
+    for k in range(n_src):
+        if k == 0:
+            dD = np.zeros(S)
+            dr = np.zeros(S)
+        else:
+            dD = np.repeat(g.uniform(-2, 2, n_ant), n_pol)
+            dr = np.repeat(g.uniform(-0.5, 0.5, n_ant), n_pol)
+        out.append({"power": power / n_src, "dD": dD, "drate": dr})
+    return out
