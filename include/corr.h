@@ -1,0 +1,209 @@
+/*
+ * corr.h -- C ABI of libcorr, an FX correlator for AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the real-time correlator data path of Roy et al.,
+ * "A real-time software backend for the GMRT" (arXiv:0910.1517):
+ *
+ *   F-engine   integer-sample delay by read-pointer offset (section 2.1 and
+ *              the overlap scheme of section 2.3.2), real-to-complex FFT
+ *              channelisation (section 2.1, FX design; section 3.1), post-FFT
+ *              fractional-sample-time correction and fringe stopping with the
+ *              phase of Eq. 2 (section 2.1), requantisation (the fixed-point
+ *              pipeline of section 4.1) and the corner turn into the X layout.
+ *   X-engine   all signal-pair products per channel, self and cross
+ *              polarisation (RR*, RL*, LR*, LL* of section 2.1), accumulated
+ *              over time (the MAC of sections 2.3.2 and 3.4).
+ *   integrate  long-term accumulation in floating point (section 4.1) and
+ *              dump of the visibilities.
+ *
+ * Conventions used everywhere below
+ *   S   number of signals (antenna a, polarisation pol -> s = 2a + pol)
+ *   N   FFT length (power of two), C = N/2 channels (DC kept, Nyquist bin
+ *       dropped), channel k centred at nu_BB + k fs / N
+ *   T   spectra per call (T_call of the plan)
+ *   P   S(S+1)/2 signal pairs; pair (i <= j) has index p = j(j+1)/2 + i and
+ *       holds V_ij = sum_m Y_i[m] * conj(Y_j[m])
+ *
+ * Every function is extern "C", never throws, and returns a corr_status
+ * (0 = success, < 0 = error; see corr_status_string).  All device pointers are
+ * caller-owned device memory (for example torch tensors); the library never
+ * allocates device memory itself: a plan's device tables and scratch live in a
+ * workspace the caller binds.  "stream" is a hipStream_t (NULL = the null
+ * stream); every call only enqueues work on it.  A plan must be used by one
+ * stream at a time.  Device-side argument errors (a delay outside
+ * [0, max_delay]) are recorded in the workspace and reported by
+ * corr_check_device_errors.
+ */
+#ifndef CORR_H
+#define CORR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t corr_status;
+
+#define CORR_OK 0
+#define CORR_ERR_INVALID (-1)     /* an argument value is out of range          */
+#define CORR_ERR_NULL (-2)        /* a required pointer is NULL                 */
+#define CORR_ERR_ALIGN (-3)       /* a pointer or stride is misaligned          */
+#define CORR_ERR_UNSUPPORTED (-4) /* shape / precision not built for this GPU   */
+#define CORR_ERR_WORKSPACE (-5)   /* no workspace bound, or too small           */
+#define CORR_ERR_OVERFLOW (-6)    /* int32 accumulator bound would be exceeded  */
+#define CORR_ERR_DEVICE (-7)      /* HIP runtime error (message in last_error)  */
+#define CORR_ERR_NOMEM (-8)       /* host allocation failed                     */
+#define CORR_ERR_STATE (-9)       /* call sequence not allowed in this state    */
+#define CORR_ERR_DEVICE_ARG (-10) /* a device-resident argument was invalid     */
+
+/* Arithmetic of the spectra handed from the F- to the X-engine. */
+#define CORR_FP32 0     /* complex64 spectra, FP32 MFMA X-engine                */
+#define CORR_INT8 1     /* int8 (re, im) in [-127, 127], int8 MFMA, int32 sums  */
+#define CORR_FP8_E4M3 2 /* OCP e4m3 (re, im), FP8 MFMA, FP32 sums               */
+
+/* Requantisation scale handling (INT8 / FP8 only). */
+#define CORR_SCALE_HOLD 0    /* use the scales passed in d_scale (set once,      */
+                             /* like the paper's gain table, section 2.3.2)     */
+#define CORR_SCALE_COMPUTE 1 /* measure sigma on this call's spectra first and   */
+                             /* write the scales to d_scale (two passes)        */
+
+/* corr_integrate flags */
+#define CORR_DUMP 1u  /* write the accumulated visibilities to d_vis_out         */
+#define CORR_RESET 2u /* zero the FP64 state after the (optional) dump          */
+
+/* Plan description. */
+typedef struct {
+    int32_t n_signals;    /* S, 1..64                                            */
+    int32_t fft_len;      /* N, power of two, 512..16384                         */
+    int64_t n_spectra;    /* T, spectra per call, multiple of 32, >= 32          */
+    int32_t max_delay;    /* largest integer delay D in samples (>= 0); the      */
+                          /* rows of the input carry T*N + max_delay samples    */
+    int32_t precision;    /* CORR_FP32 / CORR_INT8 / CORR_FP8_E4M3               */
+    int32_t sideband;     /* sigma of Eq. 2: +1 (nu_RF >= nu_LO) or -1           */
+    int32_t scale_mode;   /* CORR_SCALE_HOLD / CORR_SCALE_COMPUTE                */
+    double sample_rate;   /* fs in Hz (> 0)                                      */
+    double nu_bb;         /* baseband frequency of the band's lower edge (Hz)    */
+    int32_t x_split;      /* X-engine K-splits (0 = library choice)              */
+    int32_t reserved[7];  /* must be zero                                        */
+} corr_desc_t;
+
+/*
+ * Per-signal geometry of one call (section 2.1, Eq. 2), device-resident so
+ * that captured graphs read fresh values:
+ *   D     integer delay in samples; window m of signal s starts at sample
+ *         m*N + D of its row (read-pointer advance, section 2.3.2)
+ *   frac  fractional delay f in samples, [0, 1): tau_frac = f / fs
+ *   psi0  fringe phase (cycles) at the call's reference epoch
+ *   rate  fringe rate (Hz)
+ * Spectrum m (absolute index spectrum0 + m) is phase-corrected by
+ *   exp(+2 pi i [ (nu_BB + k fs/N) f/fs + sideband (psi0 + rate t_m) ]),
+ *   t_m = (spectrum0 + m + 1/2) N / fs  (window centre).
+ * 24 bytes, 8-byte aligned.
+ */
+typedef struct {
+    int32_t D;
+    float frac;
+    double psi0;
+    double rate;
+} corr_geom_t;
+
+typedef struct corr_plan corr_plan_t;
+
+/* ----------------------------------------------------------------- plans */
+
+/* Validate desc and build host tables.  Errors: NULL, INVALID (shape, rate,
+ * sideband, reserved fields), UNSUPPORTED (no gfx950 device current), NOMEM. */
+corr_status corr_plan_create(const corr_desc_t *desc, corr_plan_t **out);
+void corr_plan_destroy(corr_plan_t *plan);
+
+/* Bytes of device workspace the plan needs (twiddle and pair tables,
+ * calibration partial sums, device error word).  0 on a NULL plan. */
+size_t corr_plan_workspace_bytes(const corr_plan_t *plan);
+/* Sizes of the caller-owned buffers of the data path (bytes):
+ *   spectra  F-engine output / X-engine input, layout below
+ *   acc      X-engine accumulator, [splits][C][P][2] int32 (INT8) or float
+ *   state    integrator state, [C][P][2] double
+ *   vis      dumped visibilities, [C][P][2] float (complex64) */
+size_t corr_plan_spectra_bytes(const corr_plan_t *plan);
+size_t corr_plan_acc_bytes(const corr_plan_t *plan);
+size_t corr_plan_state_bytes(const corr_plan_t *plan);
+size_t corr_plan_vis_bytes(const corr_plan_t *plan);
+int32_t corr_plan_x_splits(const corr_plan_t *plan);
+
+/* Attach caller-owned device workspace (>= workspace_bytes, 256-byte
+ * aligned) and upload the tables on `stream`.  The workspace must stay
+ * allocated while the plan is used.  Errors: NULL, ALIGN, WORKSPACE, DEVICE. */
+corr_status corr_plan_bind_workspace(corr_plan_t *plan, void *d_ws, size_t bytes,
+                                     void *stream);
+
+/* --------------------------------------------------------------- F-engine */
+
+/*
+ * Channelise T spectra of all S signals.
+ *   d_x        int8 samples, row s at d_x + s*row_stride; 16-byte aligned;
+ *              row_stride a multiple of 16 and >= T*N + max_delay
+ *   d_geom     corr_geom_t[S] (device)
+ *   spectrum0  absolute index of this call's first spectrum (fringe time)
+ *   d_spec     output spectra, corr_plan_spectra_bytes, 256-byte aligned:
+ *                FP32:  [C][T/4][S][4] complex64  (chunks of 4 spectra)
+ *                INT8 / FP8: [C][T/16][S][32 B]: bytes 0..15 the real parts
+ *                of spectra 16g..16g+15, bytes 16..31 their imaginary parts
+ *   d_scale    [S][C] float; INT8: q = clamp(rne(Y / scale), -127, 127),
+ *              FP8: q = e4m3_rne_satfinite(Y / scale).  Read in HOLD mode,
+ *              written (scale = 4 sigma / 127 or 4 sigma / 448, sigma the RMS
+ *              of one component of Y over this call) in COMPUTE mode.
+ *              Unused (may be NULL) for FP32.
+ * Errors: NULL, ALIGN, INVALID (row_stride), WORKSPACE, DEVICE.
+ */
+corr_status corr_fengine(corr_plan_t *plan, const int8_t *d_x, int64_t row_stride,
+                         const corr_geom_t *d_geom, int64_t spectrum0, void *d_spec,
+                         float *d_scale, void *stream);
+
+/* Corner turn of externally produced spectra into the X layout above.
+ *   d_in: [S][T][C][2] elements (float for FP32, int8 for INT8, e4m3 bytes
+ *   for FP8), 16-byte aligned.  Errors: NULL, ALIGN, DEVICE. */
+corr_status corr_xpack(corr_plan_t *plan, const void *d_in, void *d_spec, void *stream);
+
+/* --------------------------------------------------------------- X-engine */
+
+/*
+ * d_acc[split][k][p] += sum over this split's spectra of Y_i conj(Y_j), for
+ * every channel k and pair p (int32 exact for INT8; float for FP32/FP8).
+ * d_acc holds corr_plan_acc_bytes, 256-byte aligned, and must be zeroed once
+ * before the first call (corr_integrate zeroes it afterwards).  INT8: rejects
+ * with OVERFLOW a call that would take the spectra accumulated since the
+ * last corr_integrate above 66572 (2 * 127^2 * T < 2^31).  COMPUTE scale mode:
+ * rejects with STATE a second call before corr_integrate, since the scales
+ * change per call.  Errors: NULL, ALIGN, OVERFLOW, STATE, DEVICE.
+ */
+corr_status corr_xengine(corr_plan_t *plan, const void *d_spec, void *d_acc, void *stream);
+
+/* -------------------------------------------------------------- integrate */
+
+/*
+ * d_state[k][p] += (INT8/FP8: scale_i[k] * scale_j[k] *) sum_split d_acc,
+ * in FP64 (the paper's float long-term accumulation, section 4.1), then
+ * zero d_acc.  CORR_DUMP: d_vis_out[k][p] = (complex64) d_state[k][p].
+ * CORR_RESET: d_state = 0 afterwards.  d_scale is ignored for FP32.
+ * Errors: NULL, ALIGN, DEVICE.
+ */
+corr_status corr_integrate(corr_plan_t *plan, void *d_acc, const float *d_scale,
+                           double *d_state, float *d_vis_out, uint32_t flags, void *stream);
+
+/* ------------------------------------------------------------------ misc */
+
+/* Synchronise `stream` and report (and clear) device-side argument errors:
+ * CORR_ERR_DEVICE_ARG if a delay was outside [0, max_delay] (such signals
+ * are read with the delay clamped into range).  Errors: WORKSPACE, DEVICE. */
+corr_status corr_check_device_errors(corr_plan_t *plan, void *stream);
+
+const char *corr_status_string(corr_status st);
+/* Last error message of the plan (or of plan creation when plan is NULL). */
+const char *corr_last_error(const corr_plan_t *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CORR_H */

@@ -1,0 +1,250 @@
+"""Python binding of libcorr, the MI355X (gfx950) FX correlator of
+Roy et al., "A real-time software backend for the GMRT" (arXiv:0910.1517).
+
+This module only marshals arguments into the C ABI declared in
+``include/corr.h``: every step of the correlator runs in the library's HIP
+kernels.  PyTorch supplies device memory and streams.  There is no fallback:
+if ``libcorr.so`` is missing the import of the handle raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcorr.so")
+
+FP32, INT8, FP8_E4M3 = 0, 1, 2
+SCALE_HOLD, SCALE_COMPUTE = 0, 1
+DUMP, RESET = 1, 2
+MAX_INT8_SPECTRA = 66572
+
+STATUS = {
+    0: "OK", -1: "INVALID", -2: "NULL", -3: "ALIGN", -4: "UNSUPPORTED", -5: "WORKSPACE",
+    -6: "OVERFLOW", -7: "DEVICE", -8: "NOMEM", -9: "STATE", -10: "DEVICE_ARG",
+}
+
+# corr_geom_t: {int32 D; float frac; double psi0; double rate} (24 bytes)
+GEOM_DTYPE = np.dtype([("D", "<i4"), ("frac", "<f4"), ("psi0", "<f8"), ("rate", "<f8")])
+assert GEOM_DTYPE.itemsize == 24
+
+
+class CorrDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_signals", ctypes.c_int32),
+        ("fft_len", ctypes.c_int32),
+        ("n_spectra", ctypes.c_int64),
+        ("max_delay", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("sideband", ctypes.c_int32),
+        ("scale_mode", ctypes.c_int32),
+        ("sample_rate", ctypes.c_double),
+        ("nu_bb", ctypes.c_double),
+        ("x_split", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class CorrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+_lib = None
+
+# Exported symbols of include/corr.h (checked by the tests).
+SYMBOLS = [
+    "corr_plan_create", "corr_plan_destroy", "corr_plan_workspace_bytes", "corr_plan_spectra_bytes",
+    "corr_plan_acc_bytes", "corr_plan_state_bytes", "corr_plan_vis_bytes", "corr_plan_x_splits",
+    "corr_plan_bind_workspace", "corr_fengine", "corr_xpack", "corr_xengine", "corr_integrate",
+    "corr_check_device_errors", "corr_status_string", "corr_last_error",
+]
+
+
+def lib():
+    """Load libcorr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcorr.so not built: run `python -m paper_0910_1517_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, st, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    L.corr_plan_create.argtypes = [ctypes.POINTER(CorrDesc), ctypes.POINTER(P)]
+    L.corr_plan_create.restype = st
+    L.corr_plan_destroy.argtypes = [P]
+    L.corr_plan_destroy.restype = None
+    for n in ("workspace", "spectra", "acc", "state", "vis"):
+        f = getattr(L, "corr_plan_%s_bytes" % n)
+        f.argtypes = [P]
+        f.restype = sz
+    L.corr_plan_x_splits.argtypes = [P]
+    L.corr_plan_x_splits.restype = ctypes.c_int32
+    L.corr_plan_bind_workspace.argtypes = [P, P, sz, P]
+    L.corr_plan_bind_workspace.restype = st
+    L.corr_fengine.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, P, P]
+    L.corr_fengine.restype = st
+    L.corr_xpack.argtypes = [P, P, P, P]
+    L.corr_xpack.restype = st
+    L.corr_xengine.argtypes = [P, P, P, P]
+    L.corr_xengine.restype = st
+    L.corr_integrate.argtypes = [P, P, P, P, P, ctypes.c_uint32, P]
+    L.corr_integrate.restype = st
+    L.corr_check_device_errors.argtypes = [P, P]
+    L.corr_check_device_errors.restype = st
+    L.corr_status_string.argtypes = [st]
+    L.corr_status_string.restype = ctypes.c_char_p
+    L.corr_last_error.argtypes = [P]
+    L.corr_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_desc(n_signals, fft_len, n_spectra, *, max_delay=16, precision=FP32, sideband=1,
+              scale_mode=SCALE_HOLD, sample_rate=66.666666e6, nu_bb=0.0, x_split=0) -> CorrDesc:
+    d = CorrDesc()
+    d.n_signals, d.fft_len, d.n_spectra = n_signals, fft_len, n_spectra
+    d.max_delay, d.precision, d.sideband, d.scale_mode = max_delay, precision, sideband, scale_mode
+    d.sample_rate, d.nu_bb, d.x_split = sample_rate, nu_bb, x_split
+    return d
+
+
+class Plan:
+    """A correlator plan (corr_plan_t) with its workspace bound to device memory."""
+
+    def __init__(self, n_signals: int, fft_len: int, n_spectra: int, *, max_delay: int = 16,
+                 precision: int = FP32, sideband: int = 1, scale_mode: int = SCALE_HOLD,
+                 sample_rate: float = 66.666666e6, nu_bb: float = 0.0, x_split: int = 0,
+                 device=None, bind: bool = True):
+        L = lib()
+        self.desc = make_desc(n_signals, fft_len, n_spectra, max_delay=max_delay, precision=precision,
+                              sideband=sideband, scale_mode=scale_mode, sample_rate=sample_rate,
+                              nu_bb=nu_bb, x_split=x_split)
+        h = ctypes.c_void_p()
+        rc = L.corr_plan_create(ctypes.byref(self.desc), ctypes.byref(h))
+        if rc != 0:
+            raise CorrError(rc, L.corr_last_error(None).decode())
+        self._h = h
+        self.S, self.N, self.T = n_signals, fft_len, n_spectra
+        self.C = fft_len // 2
+        self.P = n_signals * (n_signals + 1) // 2
+        self.precision = precision
+        self.max_delay = max_delay
+        self.workspace = None
+        if bind:
+            self.bind(device)
+
+    # ---------------------------------------------------------------- sizes
+    @property
+    def handle(self):
+        return self._h
+
+    def _size(self, n):
+        return int(getattr(lib(), "corr_plan_%s_bytes" % n)(self._h))
+
+    workspace_bytes = property(lambda self: self._size("workspace"))
+    spectra_bytes = property(lambda self: self._size("spectra"))
+    acc_bytes = property(lambda self: self._size("acc"))
+    state_bytes = property(lambda self: self._size("state"))
+    vis_bytes = property(lambda self: self._size("vis"))
+    splits = property(lambda self: int(lib().corr_plan_x_splits(self._h)))
+
+    def _check(self, rc):
+        if rc != 0:
+            raise CorrError(rc, lib().corr_last_error(self._h).decode())
+
+    # ------------------------------------------------------------- buffers
+    def bind(self, device=None):
+        import torch
+        dev = torch.device(device or "cuda")
+        self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=dev)
+        self._check(lib().corr_plan_bind_workspace(self._h, _ptr(self.workspace), self.workspace.numel(),
+                                                   _stream(None)))
+
+    def alloc(self, what: str, device=None, zero: bool = True):
+        """Caller-owned device buffer of the right size: spectra | acc | state | vis."""
+        import torch
+        n = self._size(what)
+        dt = {"spectra": torch.uint8, "acc": torch.int32 if self.precision == INT8 else torch.float32,
+              "state": torch.float64, "vis": torch.float32}[what]
+        el = torch.tensor([], dtype=dt).element_size()
+        f = torch.zeros if zero else torch.empty
+        return f(n // el, dtype=dt, device=device or "cuda")
+
+    # ---------------------------------------------------------------- calls
+    def fengine(self, x, geom, spec, scale=None, *, row_stride=None, spectrum0=0, stream=None):
+        """x: int8 device tensor [S][row_stride]; geom: uint8 device tensor holding corr_geom_t[S]."""
+        rs = x.stride(0) if row_stride is None else row_stride
+        self._check(lib().corr_fengine(self._h, _ptr(x), rs, _ptr(geom), spectrum0, _ptr(spec),
+                                       _ptr(scale), _stream(stream)))
+
+    def xpack(self, inp, spec, stream=None):
+        self._check(lib().corr_xpack(self._h, _ptr(inp), _ptr(spec), _stream(stream)))
+
+    def xengine(self, spec, acc, stream=None):
+        self._check(lib().corr_xengine(self._h, _ptr(spec), _ptr(acc), _stream(stream)))
+
+    def integrate(self, acc, state, vis=None, scale=None, flags=DUMP, stream=None):
+        self._check(lib().corr_integrate(self._h, _ptr(acc), _ptr(scale), _ptr(state), _ptr(vis), flags,
+                                         _stream(stream)))
+
+    def check_device_errors(self, stream=None):
+        self._check(lib().corr_check_device_errors(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().corr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def geom_array(D, frac, psi0, rate) -> np.ndarray:
+    """corr_geom_t[S] as a numpy structured array (host)."""
+    g = np.zeros(len(D), dtype=GEOM_DTYPE)
+    g["D"], g["frac"], g["psi0"], g["rate"] = D, frac, psi0, rate
+    return g
+
+
+def geom_to_device(g: np.ndarray, device="cuda"):
+    import torch
+    return torch.from_numpy(g.view(np.uint8).copy()).to(device)
+
+
+def vis_complex(vis, C: int, P: int) -> np.ndarray:
+    """Dumped complex64 visibilities (device float tensor) -> numpy complex [C][P]."""
+    v = vis.detach().cpu().numpy().reshape(C, P, 2)
+    return v[..., 0].astype(np.float64) + 1j * v[..., 1].astype(np.float64)
+
+
+def unpack_spectra(spec, precision: int, S: int, C: int, T: int) -> np.ndarray:
+    """X-layout spectra (device uint8 tensor) -> numpy [S][T][C][2] (float32 / int8 / uint8 codes).
+
+    Host-side reader for tests and diagnostics; the X-engine reads the layout directly."""
+    raw = spec.detach().cpu().numpy()
+    if precision == FP32:
+        a = raw.view(np.float32).reshape(C, T // 2, S, 2, 2)   # [k][chunk][s][q][re/im]
+        return np.ascontiguousarray(a.transpose(2, 1, 3, 0, 4).reshape(S, T, C, 2))
+    a = raw.reshape(C, T // 8, S, 2, 8)                        # [k][chunk][s][re/im][q]
+    out = a.transpose(2, 1, 4, 0, 3).reshape(S, T, C, 2)
+    return np.ascontiguousarray(out.view(np.int8) if precision == INT8 else out)

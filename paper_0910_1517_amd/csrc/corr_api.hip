@@ -1,0 +1,305 @@
+// corr_api.hip -- host side of libcorr: plan validation, tables, workspace
+// layout, argument checks and kernel launches behind the C ABI of corr.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "corr_internal.h"
+
+using namespace corr;
+
+struct corr_plan {
+    corr_desc_t d;
+    int log2m = 0;
+    int M = 0;  // complex points of the half-length transform = channels C
+    int64_t P = 0;
+    int splits = 1;
+    WsLayout ws{};
+    char *d_ws = nullptr;
+    size_t ws_bytes = 0;
+    bool bound = false;
+    int64_t acc_spectra = 0;  // spectra accumulated in acc since the last integrate
+    int x_calls = 0;
+    char err[512] = {0};
+};
+
+namespace {
+
+thread_local char g_create_err[512];
+
+corr_status fail(corr_plan *p, corr_status st, const char *fmt, ...) {
+    char *buf = p ? p->err : g_create_err;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+corr_status hip_fail(corr_plan *p, hipError_t e, const char *what) {
+    return fail(p, CORR_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void *ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
+
+int chunk_of(int precision) { return precision == CORR_FP32 ? kChunk32 : kChunk8; }
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Default K-split of the X-engine: enough waves to fill the GPU (>= 4096
+// (split, channel) waves), FP32 also keeps every wave's running FP32 sum at
+// <= 1024 spectra; each split must be a whole number of 32-spectrum steps.
+int choose_splits(const corr_desc_t &d, int C) {
+    const int64_t steps = d.n_spectra / 32;
+    int64_t target = (4096 + C - 1) / C;
+    if (d.precision == CORR_FP32) target = std::max<int64_t>(target, (d.n_spectra + 1023) / 1024);
+    if (d.x_split > 0) target = d.x_split;
+    int best = 1;
+    for (int64_t s = 1; s <= std::min<int64_t>(target, steps); ++s)
+        if (steps % s == 0) best = (int)s;
+    return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *corr_status_string(corr_status st) {
+    switch (st) {
+    case CORR_OK: return "ok";
+    case CORR_ERR_INVALID: return "invalid argument";
+    case CORR_ERR_NULL: return "null pointer";
+    case CORR_ERR_ALIGN: return "misaligned pointer or stride";
+    case CORR_ERR_UNSUPPORTED: return "unsupported on this device";
+    case CORR_ERR_WORKSPACE: return "workspace missing or too small";
+    case CORR_ERR_OVERFLOW: return "int32 accumulator bound exceeded";
+    case CORR_ERR_DEVICE: return "HIP runtime error";
+    case CORR_ERR_NOMEM: return "out of host memory";
+    case CORR_ERR_STATE: return "call not allowed in this state";
+    case CORR_ERR_DEVICE_ARG: return "invalid device-resident argument";
+    default: return "unknown status";
+    }
+}
+
+const char *corr_last_error(const corr_plan_t *plan) { return plan ? plan->err : g_create_err; }
+
+corr_status corr_plan_create(const corr_desc_t *desc, corr_plan_t **out) {
+    if (!desc || !out) return fail(nullptr, CORR_ERR_NULL, "desc and out must be non-null");
+    *out = nullptr;
+    const corr_desc_t &d = *desc;
+    if (d.n_signals < 1 || d.n_signals > kMaxSignals)
+        return fail(nullptr, CORR_ERR_INVALID, "n_signals %d outside 1..%d", d.n_signals, kMaxSignals);
+    if (d.fft_len < 512 || d.fft_len > 16384 || (d.fft_len & (d.fft_len - 1)))
+        return fail(nullptr, CORR_ERR_INVALID, "fft_len %d is not a power of two in 512..16384", d.fft_len);
+    if (d.n_spectra < 32 || d.n_spectra % 32 || d.n_spectra > (int64_t)1 << 30)
+        return fail(nullptr, CORR_ERR_INVALID, "n_spectra %lld must be a multiple of 32 in 32..2^30",
+                    (long long)d.n_spectra);
+    if ((int64_t)d.fft_len * d.n_spectra > ((int64_t)1 << 40))
+        return fail(nullptr, CORR_ERR_INVALID, "fft_len * n_spectra too large");
+    if (d.max_delay < 0 || d.max_delay > (1 << 26))
+        return fail(nullptr, CORR_ERR_INVALID, "max_delay %d outside 0..2^26", d.max_delay);
+    if (d.precision != CORR_FP32 && d.precision != CORR_INT8 && d.precision != CORR_FP8_E4M3)
+        return fail(nullptr, CORR_ERR_INVALID, "unknown precision %d", d.precision);
+    if (d.sideband != 1 && d.sideband != -1)
+        return fail(nullptr, CORR_ERR_INVALID, "sideband must be +1 or -1 (got %d)", d.sideband);
+    if (d.scale_mode != CORR_SCALE_HOLD && d.scale_mode != CORR_SCALE_COMPUTE)
+        return fail(nullptr, CORR_ERR_INVALID, "unknown scale_mode %d", d.scale_mode);
+    if (!(d.sample_rate > 0) || !std::isfinite(d.sample_rate) || !std::isfinite(d.nu_bb))
+        return fail(nullptr, CORR_ERR_INVALID, "sample_rate must be finite and > 0, nu_bb finite");
+    if (d.x_split < 0 || d.x_split > 4096)
+        return fail(nullptr, CORR_ERR_INVALID, "x_split %d outside 0..4096", d.x_split);
+    for (int i = 0; i < 7; ++i)
+        if (d.reserved[i]) return fail(nullptr, CORR_ERR_INVALID, "reserved[%d] must be zero", i);
+
+    corr_plan *p = new (std::nothrow) corr_plan;
+    if (!p) return fail(nullptr, CORR_ERR_NOMEM, "plan allocation failed");
+    p->d = d;
+    p->M = d.fft_len / 2;
+    p->log2m = 0;
+    while ((1 << p->log2m) < p->M) ++p->log2m;
+    p->P = (int64_t)d.n_signals * (d.n_signals + 1) / 2;
+    p->splits = choose_splits(d, p->M);
+
+    WsLayout &w = p->ws;
+    size_t o = 0;
+    w.tw = o; o = round_up(o + sizeof(float2) * p->M, 256);
+    w.wn = o; o = round_up(o + sizeof(float2) * p->M, 256);
+    w.pairs = o; o = round_up(o + sizeof(uint16_t) * 2 * p->P, 256);
+    w.err = o; o = round_up(o + 16, 256);
+    w.part = o;
+    if (d.precision != CORR_FP32 && d.scale_mode == CORR_SCALE_COMPUTE)
+        o = round_up(o + sizeof(float) * d.n_signals * (d.n_spectra / 16) * p->M, 256);
+    w.total = o;
+    *out = p;
+    return CORR_OK;
+}
+
+void corr_plan_destroy(corr_plan_t *plan) { delete plan; }
+
+size_t corr_plan_workspace_bytes(const corr_plan_t *p) { return p ? p->ws.total : 0; }
+size_t corr_plan_spectra_bytes(const corr_plan_t *p) {
+    if (!p) return 0;
+    const size_t per = p->d.precision == CORR_FP32 ? 8 : 2;
+    return per * (size_t)p->M * p->d.n_spectra * p->d.n_signals;
+}
+size_t corr_plan_acc_bytes(const corr_plan_t *p) {
+    return p ? (size_t)p->splits * p->M * p->P * 2 * 4 : 0;
+}
+size_t corr_plan_state_bytes(const corr_plan_t *p) { return p ? (size_t)p->M * p->P * 2 * 8 : 0; }
+size_t corr_plan_vis_bytes(const corr_plan_t *p) { return p ? (size_t)p->M * p->P * 2 * 4 : 0; }
+int32_t corr_plan_x_splits(const corr_plan_t *p) { return p ? p->splits : 0; }
+
+corr_status corr_plan_bind_workspace(corr_plan_t *p, void *d_ws, size_t bytes, void *stream) {
+    if (!p || !d_ws) return fail(p, CORR_ERR_NULL, "plan and workspace must be non-null");
+    if (!aligned(d_ws, 256)) return fail(p, CORR_ERR_ALIGN, "workspace must be 256-byte aligned");
+    if (bytes < p->ws.total)
+        return fail(p, CORR_ERR_WORKSPACE, "workspace of %zu bytes < %zu needed", bytes, p->ws.total);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(p, e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(p, e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(p, CORR_ERR_UNSUPPORTED, "device %s is not gfx950", prop.gcnArchName);
+
+    // Twiddle tables in FP64, rounded once to FP32.
+    const int M = p->M, N = p->d.fft_len;
+    std::vector<float2> tw(M), wn(M);
+    for (int n = 0; n < M; ++n) {
+        const double a = -2.0 * M_PI * (double)n / (double)M;
+        tw[n] = make_float2((float)std::cos(a), (float)std::sin(a));
+        const double b = -2.0 * M_PI * (double)n / (double)N;
+        wn[n] = make_float2((float)std::cos(b), (float)std::sin(b));
+    }
+    std::vector<uint16_t> pairs(2 * p->P);
+    for (int j = 0; j < p->d.n_signals; ++j)
+        for (int i = 0; i <= j; ++i) {
+            const int64_t q = (int64_t)j * (j + 1) / 2 + i;
+            pairs[2 * q] = (uint16_t)i;
+            pairs[2 * q + 1] = (uint16_t)j;
+        }
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)d_ws;
+    if ((e = hipMemcpyAsync(ws + p->ws.tw, tw.data(), sizeof(float2) * M, hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(ws + p->ws.wn, wn.data(), sizeof(float2) * M, hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(ws + p->ws.pairs, pairs.data(), sizeof(uint16_t) * pairs.size(),
+                            hipMemcpyHostToDevice, st)) ||
+        (e = hipMemsetAsync(ws + p->ws.err, 0, 16, st)) || (e = hipStreamSynchronize(st)))
+        return hip_fail(p, e, "uploading plan tables");
+    p->d_ws = ws;
+    p->ws_bytes = bytes;
+    p->bound = true;
+    return CORR_OK;
+}
+
+corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, const corr_geom_t *d_geom,
+                         int64_t spectrum0, void *d_spec, float *d_scale, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_x || !d_geom || !d_spec) return fail(p, CORR_ERR_NULL, "d_x, d_geom and d_spec are required");
+    const bool q8 = p->d.precision != CORR_FP32;
+    if (q8 && !d_scale) return fail(p, CORR_ERR_NULL, "d_scale is required for INT8/FP8");
+    if (!p->bound) return fail(p, CORR_ERR_WORKSPACE, "no workspace bound");
+    if (!aligned(d_x, 16) || row_stride % 16) return fail(p, CORR_ERR_ALIGN, "d_x and row_stride must be 16-byte aligned");
+    if (!aligned(d_geom, 8)) return fail(p, CORR_ERR_ALIGN, "d_geom must be 8-byte aligned");
+    if (!aligned(d_spec, 256)) return fail(p, CORR_ERR_ALIGN, "d_spec must be 256-byte aligned");
+    if (d_scale && !aligned(d_scale, 4)) return fail(p, CORR_ERR_ALIGN, "d_scale must be 4-byte aligned");
+    const int64_t need = (int64_t)p->d.fft_len * p->d.n_spectra + p->d.max_delay;
+    if (row_stride < need)
+        return fail(p, CORR_ERR_INVALID, "row_stride %lld < T*N + max_delay = %lld", (long long)row_stride,
+                    (long long)need);
+    if (spectrum0 < 0) return fail(p, CORR_ERR_INVALID, "spectrum0 must be >= 0");
+
+    FLaunch a{};
+    a.x = d_x;
+    a.row_stride = row_stride;
+    a.geom = d_geom;
+    a.spectrum0 = spectrum0;
+    a.spec = d_spec;
+    a.scale = d_scale;
+    a.part = reinterpret_cast<float *>(p->d_ws + p->ws.part);
+    a.tw = reinterpret_cast<const float2 *>(p->d_ws + p->ws.tw);
+    a.wn = reinterpret_cast<const float2 *>(p->d_ws + p->ws.wn);
+    a.err = reinterpret_cast<uint32_t *>(p->d_ws + p->ws.err);
+    a.S = p->d.n_signals;
+    a.T = (int)p->d.n_spectra;
+    a.max_delay = p->d.max_delay;
+    a.sideband = p->d.sideband;
+    a.fs = p->d.sample_rate;
+    a.nu_bb = p->d.nu_bb;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (q8 && p->d.scale_mode == CORR_SCALE_COMPUTE) {
+        if ((e = launch_fengine(p->log2m, 3, a, st)) != hipSuccess) return hip_fail(p, e, "calibration pass");
+        if ((e = launch_calib_reduce(a.part, a.S, p->M, a.T / 16, a.T, p->d.precision, d_scale, st)) != hipSuccess)
+            return hip_fail(p, e, "calibration reduce");
+    }
+    const int mode = p->d.precision == CORR_FP32 ? 0 : (p->d.precision == CORR_INT8 ? 1 : 2);
+    if ((e = launch_fengine(p->log2m, mode, a, st)) != hipSuccess) return hip_fail(p, e, "F-engine launch");
+    return CORR_OK;
+}
+
+corr_status corr_xpack(corr_plan_t *p, const void *d_in, void *d_spec, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_in || !d_spec) return fail(p, CORR_ERR_NULL, "d_in and d_spec are required");
+    if (!aligned(d_in, 16) || !aligned(d_spec, 256)) return fail(p, CORR_ERR_ALIGN, "d_in 16 B / d_spec 256 B alignment");
+    hipError_t e = launch_xpack(p->d.precision, d_in, d_spec, p->d.n_signals, p->M, (int)p->d.n_spectra,
+                                (hipStream_t)stream);
+    return e == hipSuccess ? CORR_OK : hip_fail(p, e, "xpack launch");
+}
+
+corr_status corr_xengine(corr_plan_t *p, const void *d_spec, void *d_acc, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_spec || !d_acc) return fail(p, CORR_ERR_NULL, "d_spec and d_acc are required");
+    if (!aligned(d_spec, 256) || !aligned(d_acc, 256)) return fail(p, CORR_ERR_ALIGN, "d_spec/d_acc must be 256-byte aligned");
+    if (p->d.precision == CORR_INT8 && p->acc_spectra + p->d.n_spectra > kMaxInt8Spectra)
+        return fail(p, CORR_ERR_OVERFLOW, "%lld spectra since the last integrate would exceed the int32 bound (%lld)",
+                    (long long)(p->acc_spectra + p->d.n_spectra), (long long)kMaxInt8Spectra);
+    if (p->d.precision != CORR_FP32 && p->d.scale_mode == CORR_SCALE_COMPUTE && p->x_calls > 0)
+        return fail(p, CORR_ERR_STATE, "COMPUTE scales change per call: integrate before the next X-engine call");
+    hipError_t e = launch_xengine(p->d.precision, d_spec, d_acc, p->d.n_signals, p->M, (int)p->d.n_spectra,
+                                  p->splits, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(p, e, "X-engine launch");
+    p->acc_spectra += p->d.n_spectra;
+    p->x_calls += 1;
+    return CORR_OK;
+}
+
+corr_status corr_integrate(corr_plan_t *p, void *d_acc, const float *d_scale, double *d_state, float *d_vis_out,
+                           uint32_t flags, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_acc || !d_state) return fail(p, CORR_ERR_NULL, "d_acc and d_state are required");
+    if (p->d.precision != CORR_FP32 && !d_scale) return fail(p, CORR_ERR_NULL, "d_scale is required for INT8/FP8");
+    if ((flags & CORR_DUMP) && !d_vis_out) return fail(p, CORR_ERR_NULL, "CORR_DUMP needs d_vis_out");
+    if (flags & ~(CORR_DUMP | CORR_RESET)) return fail(p, CORR_ERR_INVALID, "unknown flags 0x%x", flags);
+    if (!p->bound) return fail(p, CORR_ERR_WORKSPACE, "no workspace bound");
+    if (!aligned(d_acc, 256) || !aligned(d_state, 16) || (d_vis_out && !aligned(d_vis_out, 8)))
+        return fail(p, CORR_ERR_ALIGN, "d_acc 256 B, d_state 16 B, d_vis_out 8 B alignment");
+    hipError_t e = launch_integrate(p->d.precision, d_acc, d_scale, d_state, d_vis_out,
+                                    reinterpret_cast<const uint16_t *>(p->d_ws + p->ws.pairs), p->d.n_signals, p->M,
+                                    p->splits, flags, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(p, e, "integrate launch");
+    p->acc_spectra = 0;
+    p->x_calls = 0;
+    return CORR_OK;
+}
+
+corr_status corr_check_device_errors(corr_plan_t *p, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!p->bound) return fail(p, CORR_ERR_WORKSPACE, "no workspace bound");
+    uint32_t w[4] = {0, 0, 0, 0};
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(w, p->d_ws + p->ws.err, sizeof(w), hipMemcpyDeviceToHost, st)) ||
+        (e = hipStreamSynchronize(st)) || (e = hipMemsetAsync(p->d_ws + p->ws.err, 0, sizeof(w), st)) ||
+        (e = hipStreamSynchronize(st)))
+        return hip_fail(p, e, "reading device error words");
+    if (w[0] & 1u) return fail(p, CORR_ERR_DEVICE_ARG, "a signal delay was outside [0, max_delay] (clamped)");
+    return CORR_OK;
+}
+
+}  // extern "C"

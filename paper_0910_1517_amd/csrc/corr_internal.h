@@ -1,0 +1,70 @@
+// corr_internal.h -- declarations shared by the translation units of libcorr
+// (host API, F-engine, X-engine, integrator).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/corr.h"
+
+namespace corr {
+
+// Geometry as the kernels read it (same bytes as corr_geom_t).
+static_assert(sizeof(corr_geom_t) == 24, "corr_geom_t must stay 24 bytes");
+
+// Largest signal count the X-engine tiles handle (two 32-signal MFMA tiles).
+constexpr int kMaxSignals = 64;
+// Spectra per 16-byte X-layout chunk: 8 for the 8-bit precisions, 2 for FP32.
+constexpr int kChunk8 = 8;
+constexpr int kChunk32 = 2;
+// int32 accumulator bound: 2 * 127^2 * T <= 2^31 - 1.
+constexpr int64_t kMaxInt8Spectra = 66572;
+
+// Device workspace layout (byte offsets from the bound base pointer).
+struct WsLayout {
+    size_t tw;        // float2[M]   exp(-2 pi i n / M), Stockham twiddles
+    size_t wn;        // float2[M]   exp(-2 pi i k / N), real-FFT post-process
+    size_t pairs;     // uint16[2P]  (i, j) of each pair index
+    size_t err;       // uint32[4]   device error words
+    size_t part;      // float[S][nblk*fpar][C] calibration partial sums
+    size_t total;
+};
+
+struct FLaunch {
+    const int8_t *x;
+    int64_t row_stride;
+    const corr_geom_t *geom;
+    int64_t spectrum0;
+    void *spec;
+    const float *scale;  // HOLD-mode scales [S][C]
+    float *part;         // calibration partials
+    const float2 *tw;
+    const float2 *wn;
+    uint32_t *err;
+    int S;
+    int T;
+    int max_delay;
+    int sideband;
+    double fs;
+    double nu_bb;
+};
+
+// mode: 0 FP32 spectra, 1 INT8, 2 FP8, 3 calibration partial sums
+hipError_t launch_fengine(int log2m, int mode, const FLaunch &a, hipStream_t st);
+// geometry of the F-engine launch: spectra handled per workgroup, workgroups per signal
+int fengine_spectra_per_block(int log2m);
+int fengine_fpar(int log2m);
+
+hipError_t launch_calib_reduce(const float *part, int S, int C, int nparts, int T, int precision,
+                               float *scale, hipStream_t st);
+
+hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int C, int T,
+                          int splits, hipStream_t st);
+hipError_t launch_xpack(int precision, const void *in, void *spec, int S, int C, int T,
+                        hipStream_t st);
+
+hipError_t launch_integrate(int precision, void *acc, const float *scale, double *state,
+                            float *vis, const uint16_t *pairs, int S, int C, int splits,
+                            uint32_t flags, hipStream_t st);
+
+}  // namespace corr

@@ -67,7 +67,8 @@ def make_geometry(n_ant: int, n_pol: int = 2, seed: int = BASE_SEED, max_delay: 
     """Antenna-based delays/fringes, repeated for each polarisation (s = n_pol*a + pol)."""
     g = rng(seed, 1)
     D = g.integers(0, max_delay + 1, size=n_ant)
-    f = g.random(n_ant) if frac else np.zeros(n_ant)
+    # fractions are float32-representable: the device geometry holds them as float
+    f = (g.random(n_ant).astype(np.float32).astype(np.float64)) if frac else np.zeros(n_ant)
     psi0 = g.random(n_ant) if fringe else np.zeros(n_ant)
     rate = g.uniform(-rate_max, rate_max, size=n_ant) if fringe else np.zeros(n_ant)
     rep = lambda a: np.repeat(a, n_pol)

@@ -1,0 +1,64 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C ABI on
+seeded synthetic inputs and return host arrays for comparison with the oracle.
+Every buffer is sized from the plan's own size queries before any launch."""
+from __future__ import annotations
+
+import numpy as np
+
+import paper_0910_1517_amd as corr
+
+FS = 66.666666e6
+
+
+def row_stride_for(N: int, T: int, max_delay: int) -> int:
+    need = N * T + max_delay
+    return (need + 255) // 256 * 256
+
+
+def upload_streams(x_host: np.ndarray, N: int, T: int, max_delay: int):
+    """int8 [S][n] host streams -> device tensor with a 256-aligned row stride."""
+    import torch
+    S, n = x_host.shape
+    rs = row_stride_for(N, T, max_delay)
+    assert n >= N * T + max_delay
+    buf = np.zeros((S, rs), dtype=np.int8)
+    buf[:, :min(n, rs)] = x_host[:, :min(n, rs)]
+    return torch.from_numpy(buf).cuda(), rs
+
+
+def geom_dev(geom):
+    return corr.geom_to_device(corr.geom_array(geom.D, geom.f, geom.psi0, geom.rate))
+
+
+def run_fengine(plan: corr.Plan, x_dev, rs: int, g_dev, scale_dev=None, spectrum0: int = 0):
+    spec = plan.alloc("spectra", zero=False)
+    plan.fengine(x_dev, g_dev, spec, scale_dev, row_stride=rs, spectrum0=spectrum0)
+    return spec
+
+
+def run_x_integrate(plan: corr.Plan, spec, scale_dev=None):
+    import torch
+    acc = plan.alloc("acc")
+    state = plan.alloc("state")
+    vis = plan.alloc("vis")
+    plan.xengine(spec, acc)
+    acc_host = acc.cpu().numpy().copy()
+    plan.integrate(acc, state, vis, scale_dev, flags=corr.DUMP)
+    torch.cuda.synchronize()
+    st = state.cpu().numpy().reshape(plan.C, plan.P, 2)
+    return acc_host, st[..., 0] + 1j * st[..., 1], corr.vis_complex(vis, plan.C, plan.P)
+
+
+def acc_sum(acc_host: np.ndarray, plan: corr.Plan) -> np.ndarray:
+    """[splits][C][P][2] -> summed over splits (int64 or float64) [C][P][2]."""
+    a = acc_host.reshape(plan.splits, plan.C, plan.P, 2)
+    return a.astype(np.int64).sum(0) if a.dtype == np.int32 else a.astype(np.float64).sum(0)
+
+
+def pack_input(plan: corr.Plan, arr: np.ndarray):
+    """[S][T][C][2] host array -> device X layout via the library's corner turn."""
+    import torch
+    inp = torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+    spec = plan.alloc("spectra", zero=False)
+    plan.xpack(inp, spec)
+    return spec

@@ -1,0 +1,112 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and validates plan descriptions on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_0910_1517_amd as corr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "corr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(corr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert header_functions() == sorted(corr.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = corr.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+
+
+def test_status_strings():
+    L = corr.lib()
+    for code in corr.STATUS:
+        assert L.corr_status_string(code)
+    assert L.corr_status_string(0) == b"ok"
+
+
+def create(**kw):
+    args = dict(n_signals=64, fft_len=4096, n_spectra=32768, precision=corr.INT8)
+    args.update(kw)
+    n, N, T = args.pop("n_signals"), args.pop("fft_len"), args.pop("n_spectra")
+    d = corr.make_desc(n, N, T, **args)
+    h = ctypes.c_void_p()
+    rc = corr.lib().corr_plan_create(ctypes.byref(d), ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_signals=0), -1), (dict(n_signals=65), -1), (dict(fft_len=1000), -1),
+    (dict(fft_len=256), -1), (dict(fft_len=32768), -1), (dict(n_spectra=48), -1),
+    (dict(n_spectra=0), -1), (dict(max_delay=-1), -1), (dict(precision=7), -1),
+    (dict(sideband=0), -1), (dict(scale_mode=3), -1), (dict(sample_rate=0.0), -1),
+    (dict(sample_rate=float("nan")), -1), (dict(x_split=-2), -1),
+])
+def test_plan_create_rejects_bad_descriptions(kw, code):
+    rc, h = create(**kw)
+    assert rc == code and not h.value
+    assert corr.lib().corr_last_error(None)
+
+
+def test_plan_create_rejects_reserved_and_null():
+    d = corr.make_desc(8, 512, 1024)
+    d.reserved[3] = 1
+    h = ctypes.c_void_p()
+    assert corr.lib().corr_plan_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert corr.lib().corr_plan_create(None, ctypes.byref(h)) == -2
+
+
+def test_plan_sizes_and_calls_without_workspace():
+    L = corr.lib()
+    rc, h = create(n_signals=64, fft_len=4096, n_spectra=32768, precision=corr.INT8)
+    assert rc == 0
+    try:
+        C, P = 2048, 64 * 65 // 2
+        assert L.corr_plan_spectra_bytes(h) == 2 * C * 32768 * 64
+        assert L.corr_plan_state_bytes(h) == C * P * 16
+        assert L.corr_plan_vis_bytes(h) == C * P * 8
+        sp = L.corr_plan_x_splits(h)
+        assert sp >= 1 and (32768 // 32) % sp == 0
+        assert L.corr_plan_acc_bytes(h) == sp * C * P * 8
+        assert L.corr_plan_workspace_bytes(h) >= 2 * 8 * C
+        # data-path calls before a workspace is bound are rejected on the host, before
+        # any launch (the placeholder pointer is never dereferenced)
+        fake = ctypes.c_void_p(1 << 20)
+        assert L.corr_fengine(h, fake, 32768 * 4096 + 64, fake, 0, fake, fake, None) == -5
+        assert L.corr_integrate(h, fake, fake, fake, None, 0, None) == -5
+        assert L.corr_fengine(h, None, 0, fake, 0, fake, fake, None) == -2
+    finally:
+        L.corr_plan_destroy(h)
+
+
+def test_workspace_grows_with_compute_scale_mode():
+    L = corr.lib()
+    rc1, h1 = create(scale_mode=corr.SCALE_HOLD)
+    rc2, h2 = create(scale_mode=corr.SCALE_COMPUTE)
+    assert rc1 == 0 and rc2 == 0
+    try:
+        assert L.corr_plan_workspace_bytes(h2) > L.corr_plan_workspace_bytes(h1)
+    finally:
+        L.corr_plan_destroy(h1)
+        L.corr_plan_destroy(h2)
+
+
+def test_fp32_split_choice_bounds_running_sums():
+    L = corr.lib()
+    rc, h = create(n_signals=64, fft_len=1024, n_spectra=16384, precision=corr.FP32)
+    assert rc == 0
+    try:
+        sp = L.corr_plan_x_splits(h)
+        assert 16384 // sp <= 1024
+    finally:
+        L.corr_plan_destroy(h)
