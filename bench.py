@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the FX correlator hot path on one MI355X.
+
+Workload (default): the precision form of the GMRT-scale correlator --
+64 signals (32 antennas x 2 polarisations), 4096-point FFT (2048 channels),
+32768 spectra per step (one 2.01 s block at 66.67 MS/s), F-engine ->
+X-engine -> integrate, all inputs resident in HBM.  The headline value is the
+int8-MFMA path's correlated bandwidth; the FP32 path at the same shape is
+timed beside it.  One step = F-engine (held requantisation scales, set once
+on a calibration pass like the paper's gain table) + X-engine + integrate
+with dump, over one block of all 64 signals.
+
+Prints one JSON line.  Options: --steps K --warmup W --gpus 1 [--config c2|c3]
+[--no-fp32] [--no-cpu-baseline].
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FS = 66.666666e6
+CONFIGS = {
+    # name: (S, N, T, description)
+    "c3": (64, 4096, 32768, "precision form: 64 signals, 4096-pt FFT (2048 ch), 32768 spectra"),
+    "c2": (64, 1024, 16384, "GMRT scale: 64 signals, 1024-pt FFT (512 ch), 16384 spectra"),
+}
+HBM_PEAK = 8.0e12           # B/s
+INT8_PEAK = 5.0e15          # dense int8 MFMA OP/s
+FP32_MFMA_PEAK = 157.3e12   # dense FP32 matrix FLOP/s
+FP32_VALU_PEAK = 157.3e12   # FP32 vector FLOP/s (datasheet, packed); 78.6e12 unpacked
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def f_algorithmic(S, N, T, out_bytes_per_ch):
+    """F-engine algorithmic flops and bytes per launch.
+    flops/spectrum: real FFT 2.5 N log2 N + phase rotation 6 per channel;
+    bytes/spectrum: N int8 samples in + N/2 channels x out_bytes_per_ch out."""
+    C = N // 2
+    flops = S * T * (2.5 * N * np.log2(N) + 6.0 * C)
+    nbytes = S * T * (N + C * out_bytes_per_ch)
+    return flops, nbytes
+
+
+def x_algorithmic(S, N, T, in_bytes_per_ch):
+    """X-engine algorithmic ops (8 per complex MAC over all S(S+1)/2 pairs) and input bytes."""
+    C, P = N // 2, S * (S + 1) // 2
+    return 8.0 * P * C * T, float(S * C * T * in_bytes_per_ch)
+
+
+def run_path(corr, torch, prec, S, N, T, x_dev, rs, g_dev, steps, warmup, scale=None):
+    """Time `steps` F+X+integrate passes; per-kernel times from HIP events on the launch stream."""
+    plan = corr.Plan(S, N, T, precision=prec, max_delay=16, scale_mode=corr.SCALE_HOLD)
+    spec = plan.alloc("spectra", zero=False)
+    acc, state, vis = plan.alloc("acc"), plan.alloc("state"), plan.alloc("vis")
+    st = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+
+    def step(e=None):
+        if e: e[0].record(st)
+        plan.fengine(x_dev, g_dev, spec, scale, row_stride=rs, stream=st)
+        if e: e[1].record(st)
+        plan.xengine(spec, acc, stream=st)
+        if e: e[2].record(st)
+        plan.integrate(acc, state, vis, scale, flags=corr.DUMP | corr.RESET, stream=st)
+        if e: e[3].record(st)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(ev[i])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    tf = np.mean([e[0].elapsed_time(e[1]) for e in ev]) * 1e-3
+    tx = np.mean([e[1].elapsed_time(e[2]) for e in ev]) * 1e-3
+    ti = np.mean([e[2].elapsed_time(e[3]) for e in ev]) * 1e-3
+    tstep = np.mean([e[0].elapsed_time(e[3]) for e in ev]) * 1e-3
+    plan.check_device_errors()
+    del spec, acc, state, vis
+    return dict(t_step=tstep, t_f=tf, t_x=tx, t_int=ti, wall=wall, splits=plan.splits)
+
+
+def calibrate_scales(corr, torch, S, N, T, x_dev, rs, g_dev):
+    plan = corr.Plan(S, N, T, precision=corr.INT8, max_delay=16, scale_mode=corr.SCALE_COMPUTE)
+    spec = plan.alloc("spectra", zero=False)
+    scale = torch.zeros(S * plan.C, dtype=torch.float32, device="cuda")
+    plan.fengine(x_dev, g_dev, spec, scale, row_stride=rs)
+    torch.cuda.synchronize()
+    del spec, plan
+    torch.cuda.empty_cache()
+    return scale
+
+
+def cpu_baseline(S, N, T_sample, chunk=256):
+    """The CPU oracle (FP64 F-engine, int8 requantisation, int64 X-engine, FP64 scaling),
+    as it stands, on T_sample spectra of the same shape; returns MHz and cores used."""
+    import oracle
+    import synth
+    geo = synth.make_geometry(S // 2, seed=synth.BASE_SEED + 2)
+    og = oracle.Geometry(geo.D, geo.f, geo.psi0, geo.rate)
+    x = synth.voltages(S, N * T_sample + 64, geo, FS, mode="bulk", seed=synth.BASE_SEED + 2,
+                       tone_bin=37, tone_N=N)
+    oracle.build()
+    t0 = time.perf_counter()
+    A = None
+    scale = None
+    for m0 in range(0, T_sample, chunk):
+        xs = np.ascontiguousarray(x[:, m0 * N:])
+        Y = oracle.fengine(xs, N, chunk, og, FS, spectrum0=m0)
+        if scale is None:
+            scale = oracle.int8_scale(oracle.sigma(Y)).astype(np.float64)
+        q = oracle.quantize_int8(Y, scale)
+        A = oracle.xengine_int(q, A)
+    V = oracle.scale_visibilities(A, scale)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(V).all()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return N * T_sample / (2 * dt) / 1e6, dt, cores
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="spectra in the CPU-oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_0910_1517_amd as corr
+    import synth
+
+    S, N, T, desc = CONFIGS[args.config]
+    C = N // 2
+    torch.cuda.set_device(0)
+    geo = synth.make_geometry(S // 2, seed=synth.BASE_SEED + 2)
+    rs = (N * T + 16 + 255) // 256 * 256
+    log("generating %d x %d int8 samples on the GPU" % (S, rs))
+    x_dev = synth.voltages_device(S, N * T + 16, geo, seed=synth.BASE_SEED + 2, tone_bin=37, tone_N=N,
+                                  row_stride=rs)
+    g_dev = corr.geom_to_device(corr.geom_array(geo.D, geo.f, geo.psi0, geo.rate))
+    torch.cuda.synchronize()
+
+    log("calibrating int8 scales")
+    scale = calibrate_scales(corr, torch, S, N, T, x_dev, rs, g_dev)
+    log("timing int8 path: %d warmup + %d steps" % (args.warmup, args.steps))
+    r8 = run_path(corr, torch, corr.INT8, S, N, T, x_dev, rs, g_dev, args.steps, args.warmup, scale)
+    log("int8: step %.3f ms (F %.3f, X %.3f, int %.3f)" % (r8["t_step"] * 1e3, r8["t_f"] * 1e3,
+                                                          r8["t_x"] * 1e3, r8["t_int"] * 1e3))
+    r32 = None
+    if not args.no_fp32:
+        torch.cuda.empty_cache()
+        log("timing fp32 path")
+        r32 = run_path(corr, torch, corr.FP32, S, N, T, x_dev, rs, g_dev, max(3, args.steps // 4),
+                       min(2, args.warmup))
+        log("fp32: step %.3f ms (F %.3f, X %.3f, int %.3f)" % (r32["t_step"] * 1e3, r32["t_f"] * 1e3,
+                                                              r32["t_x"] * 1e3, r32["t_int"] * 1e3))
+
+    bw = lambda t: N * T / (2.0 * t) / 1e6  # correlated bandwidth, MHz
+    xops8, xin8 = x_algorithmic(S, N, T, 2)
+    ff8, fb8 = f_algorithmic(S, N, T, 2)
+    out = {
+        "metric": "correlated bandwidth (MHz) & X-engine TOP/s, 64 signals: int8-MFMA vs FP32",
+        "value": round(bw(r8["t_step"]), 3),
+        "unit": "MHz",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r8["t_step"] * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic (seeded Gaussian + common source + tone, generated on the GPU)",
+        "config": {"workload": desc, "signals": S, "fft_len": N, "channels": C, "spectra": T,
+                   "pairs": S * (S + 1) // 2, "sample_rate_hz": FS, "parallelism": "single GPU"},
+        "int8": {"x_engine_tops": round(xops8 / r8["t_x"] / 1e12, 3),
+                 "ms": {k: round(v * 1e3, 4) for k, v in r8.items() if k.startswith("t_")},
+                 "x_splits": r8["splits"]},
+    }
+    # dominant kernel of the int8 step and its roofline
+    tf, tx = r8["t_f"], r8["t_x"]
+    f_alu_frac = ff8 / tf / FP32_VALU_PEAK
+    f_hbm_frac = fb8 / tf / HBM_PEAK
+    if tf >= tx:
+        bound = "alu" if ff8 / FP32_VALU_PEAK > fb8 / HBM_PEAK else "hbm"
+        if bound == "alu":
+            ach, peak, unit = ff8 / tf / 1e12, FP32_VALU_PEAK / 1e12, "TFLOP/s"
+        else:
+            ach, peak, unit = fb8 / tf / 1e9, HBM_PEAK / 1e9, "GB/s"
+        kern = "fengine_kernel (int8 requantising F-engine)"
+    else:
+        bound, ach, peak, unit = "hbm", xin8 / tx / 1e9, HBM_PEAK / 1e9, "GB/s"
+        kern = "xengine_i8_kernel"
+    out["roofline"] = {"kernel": kern, "bound": bound, "achieved": round(ach, 3), "peak": peak,
+                       "unit": unit, "frac": round(ach / peak, 4), "traffic": None,
+                       "f_engine": {"alu_frac_vs_157TF": round(f_alu_frac, 4),
+                                    "hbm_frac": round(f_hbm_frac, 4)},
+                       "x_engine": {"hbm_frac": round(xin8 / tx / HBM_PEAK, 4),
+                                    "mfma_frac_algorithmic": round(xops8 / tx / INT8_PEAK, 4)}}
+    if r32:
+        xops32, xin32 = x_algorithmic(S, N, T, 8)
+        out["fp32"] = {"correlated_bandwidth_mhz": round(bw(r32["t_step"]), 3),
+                       "x_engine_tops": round(xops32 / r32["t_x"] / 1e12, 3),
+                       "ms": {k: round(v * 1e3, 4) for k, v in r32.items() if k.startswith("t_")},
+                       "x_mfma_frac_algorithmic": round(xops32 / r32["t_x"] / FP32_MFMA_PEAK, 4),
+                       "x_splits": r32["splits"]}
+        out["int8_vs_fp32_speedup"] = round(r32["t_step"] / r8["t_step"], 3)
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on %d spectra" % args.cpu_sample)
+        mhz, dt, cores = cpu_baseline(S, N, args.cpu_sample)
+        out["cpu_baseline"] = {"value": round(mhz, 4), "unit": "MHz", "cores": cores, "kind": "oracle",
+                               "sample": "%d spectra x %d signals, N=%d, int8 path (FP64 F-engine, "
+                                         "int64 X-engine), %.1f s" % (args.cpu_sample, S, N, dt)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -146,10 +146,13 @@ corr_status corr_plan_bind_workspace(corr_plan_t *plan, void *d_ws, size_t bytes
  *              row_stride a multiple of 16 and >= T*N + max_delay
  *   d_geom     corr_geom_t[S] (device)
  *   spectrum0  absolute index of this call's first spectrum (fringe time)
- *   d_spec     output spectra, corr_plan_spectra_bytes, 256-byte aligned:
- *                FP32:  [C][T/4][S][4] complex64  (chunks of 4 spectra)
- *                INT8 / FP8: [C][T/16][S][32 B]: bytes 0..15 the real parts
- *                of spectra 16g..16g+15, bytes 16..31 their imaginary parts
+ *   d_spec     output spectra, corr_plan_spectra_bytes, 256-byte aligned,
+ *              in 16-byte chunks indexed [g][k/8][s][k mod 8] (the chunks of
+ *              8 consecutive channels of one signal form one 128-byte line):
+ *                FP32: chunk g of channel k, signal s = spectra 2g, 2g+1 as
+ *                      two complex64
+ *                INT8 / FP8: chunk g = bytes 0..7 the real parts of spectra
+ *                      8g..8g+7, bytes 8..15 their imaginary parts
  *   d_scale    [S][C] float; INT8: q = clamp(rne(Y / scale), -127, 127),
  *              FP8: q = e4m3_rne_satfinite(Y / scale).  Read in HOLD mode,
  *              written (scale = 4 sigma / 127 or 4 sigma / 448, sigma the RMS

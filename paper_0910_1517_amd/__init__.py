@@ -243,8 +243,8 @@ def unpack_spectra(spec, precision: int, S: int, C: int, T: int) -> np.ndarray:
     Host-side reader for tests and diagnostics; the X-engine reads the layout directly."""
     raw = spec.detach().cpu().numpy()
     if precision == FP32:
-        a = raw.view(np.float32).reshape(C, T // 2, S, 2, 2)   # [k][chunk][s][q][re/im]
-        return np.ascontiguousarray(a.transpose(2, 1, 3, 0, 4).reshape(S, T, C, 2))
-    a = raw.reshape(C, T // 8, S, 2, 8)                        # [k][chunk][s][re/im][q]
-    out = a.transpose(2, 1, 4, 0, 3).reshape(S, T, C, 2)
+        a = raw.view(np.float32).reshape(T // 2, C // 8, S, 8, 2, 2)  # [g][kb][s][kk][q][re/im]
+        return np.ascontiguousarray(a.transpose(2, 0, 4, 1, 3, 5).reshape(S, T, C, 2))
+    a = raw.reshape(T // 8, C // 8, S, 8, 2, 8)                       # [g][kb][s][kk][re/im][q]
+    out = a.transpose(2, 0, 5, 1, 3, 4).reshape(S, T, C, 2)
     return np.ascontiguousarray(out.view(np.int8) if precision == INT8 else out)

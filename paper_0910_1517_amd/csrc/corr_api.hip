@@ -126,7 +126,9 @@ corr_status corr_plan_create(const corr_desc_t *desc, corr_plan_t **out) {
 
     WsLayout &w = p->ws;
     size_t o = 0;
-    w.tw = o; o = round_up(o + sizeof(float2) * p->M, 256);
+    size_t ntw = 0;
+    fengine_twiddle_table(p->log2m, nullptr, &ntw);
+    w.twp = o; o = round_up(o + sizeof(float2) * std::max<size_t>(ntw, 1), 256);
     w.wn = o; o = round_up(o + sizeof(float2) * p->M, 256);
     w.pairs = o; o = round_up(o + sizeof(uint16_t) * 2 * p->P, 256);
     w.err = o; o = round_up(o + 16, 256);
@@ -169,10 +171,11 @@ corr_status corr_plan_bind_workspace(corr_plan_t *p, void *d_ws, size_t bytes, v
 
     // Twiddle tables in FP64, rounded once to FP32.
     const int M = p->M, N = p->d.fft_len;
-    std::vector<float2> tw(M), wn(M);
+    size_t ntw = 0;
+    fengine_twiddle_table(p->log2m, nullptr, &ntw);
+    std::vector<float2> tw(std::max<size_t>(ntw, 1)), wn(M);
+    fengine_twiddle_table(p->log2m, tw.data(), &ntw);
     for (int n = 0; n < M; ++n) {
-        const double a = -2.0 * M_PI * (double)n / (double)M;
-        tw[n] = make_float2((float)std::cos(a), (float)std::sin(a));
         const double b = -2.0 * M_PI * (double)n / (double)N;
         wn[n] = make_float2((float)std::cos(b), (float)std::sin(b));
     }
@@ -185,7 +188,7 @@ corr_status corr_plan_bind_workspace(corr_plan_t *p, void *d_ws, size_t bytes, v
         }
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)d_ws;
-    if ((e = hipMemcpyAsync(ws + p->ws.tw, tw.data(), sizeof(float2) * M, hipMemcpyHostToDevice, st)) ||
+    if ((e = hipMemcpyAsync(ws + p->ws.twp, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice, st)) ||
         (e = hipMemcpyAsync(ws + p->ws.wn, wn.data(), sizeof(float2) * M, hipMemcpyHostToDevice, st)) ||
         (e = hipMemcpyAsync(ws + p->ws.pairs, pairs.data(), sizeof(uint16_t) * pairs.size(),
                             hipMemcpyHostToDevice, st)) ||
@@ -222,7 +225,7 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
     a.spec = d_spec;
     a.scale = d_scale;
     a.part = reinterpret_cast<float *>(p->d_ws + p->ws.part);
-    a.tw = reinterpret_cast<const float2 *>(p->d_ws + p->ws.tw);
+    a.twp = reinterpret_cast<const float2 *>(p->d_ws + p->ws.twp);
     a.wn = reinterpret_cast<const float2 *>(p->d_ws + p->ws.wn);
     a.err = reinterpret_cast<uint32_t *>(p->d_ws + p->ws.err);
     a.S = p->d.n_signals;

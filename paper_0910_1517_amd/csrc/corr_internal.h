@@ -22,7 +22,7 @@ constexpr int64_t kMaxInt8Spectra = 66572;
 
 // Device workspace layout (byte offsets from the bound base pointer).
 struct WsLayout {
-    size_t tw;        // float2[M]   exp(-2 pi i n / M), Stockham twiddles
+    size_t twp;       // float2[sum P R] per-pass Stockham twiddles W_{PR}^{rk}, [pass][k][r]
     size_t wn;        // float2[M]   exp(-2 pi i k / N), real-FFT post-process
     size_t pairs;     // uint16[2P]  (i, j) of each pair index
     size_t err;       // uint32[4]   device error words
@@ -38,7 +38,7 @@ struct FLaunch {
     void *spec;
     const float *scale;  // HOLD-mode scales [S][C]
     float *part;         // calibration partials
-    const float2 *tw;
+    const float2 *twp;
     const float2 *wn;
     uint32_t *err;
     int S;
@@ -54,6 +54,8 @@ hipError_t launch_fengine(int log2m, int mode, const FLaunch &a, hipStream_t st)
 // geometry of the F-engine launch: spectra handled per workgroup, workgroups per signal
 int fengine_spectra_per_block(int log2m);
 int fengine_fpar(int log2m);
+// per-pass twiddle table of the Stockham passes: W_{P R}^{r k} at [pass][k][r]
+void fengine_twiddle_table(int log2m, float2 *out, size_t *count);
 
 hipError_t launch_calib_reduce(const float *part, int S, int C, int nparts, int T, int precision,
                                float *scale, hipStream_t st);

@@ -13,10 +13,11 @@
 //     real samples are packed as M complex points z[n] = x[2n] + i x[2n+1] and
 //     transformed by a Stockham autosort FFT, radix-8 passes plus one radix-4
 //     or radix-2 pass, every thread holding 8 points in registers and the
-//     passes exchanging through LDS (ping-pong buffers, one barrier per pass).
+//     passes exchanging through LDS (ping-pong buffers, one barrier per pass;
+//     one pad element per 16 keeps the passes free of bank conflicts).
 //     The half-length trick X[k] = E[k] + W_N^k O[k] recovers channels
 //     k = 0..M-1 (DC kept, Nyquist dropped).  Twiddles are FP32 values rounded
-//     from FP64, read from small L1-resident tables.
+//     from FP64, read per pass from a contiguous table [k][r] (L1-resident).
 //  3. FSTC and fringe stop (Eq. 2): Y[k] = X[k] exp(2 pi i (k f/N + c_m)),
 //     c_m = nu_BB f/fs + sideband (psi0 + rate t_m) reduced mod 1 in FP64 once
 //     per spectrum; the per-channel ramp exp(2 pi i k f / N) is computed once
@@ -25,11 +26,14 @@
 //     clamp(rne(Y/scale), +-127) or OCP e4m3 RNE satfinite; FP32 keeps Y.
 //  5. corner turn: a thread owns channels k = t + L*j (j = 0..7) of every
 //     spectrum it transforms, so it gathers a whole X-layout chunk per channel
-//     in registers (8 spectra of int8/e4m3 re+im, or 2 complex64: 16 bytes)
-//     and writes it with one 16-byte store.
+//     in registers (8 spectra of int8/e4m3 re+im, or 2 complex64: 16 bytes).
+//     The X layout keeps the chunks of 8 consecutive channels of one signal
+//     together, so the 8 lanes holding them write one full 128-byte line.
 //
 // Calibration mode (scale COMPUTE) runs steps 1-2 and sums |X|^2 per channel
 // (the phase rotation does not change it) into per-workgroup partials.
+#include <cmath>
+
 #include "corr_internal.h"
 
 namespace corr {
@@ -46,12 +50,16 @@ struct FCfg {
     static constexpr int RLAST = 1 << (LOGM % 3);          // 1 = no extra pass
     static constexpr int NPASS = NPASS8 + (RLAST > 1 ? 1 : 0);
     static constexpr int NBUF = (LOGM >= 13) ? 1 : 2;      // ping-pong if it fits
-    static constexpr int PADM = M + (M >> 3);
+    static constexpr int PADM = M + (M >> 4);
 };
 
-// One pad element every 8 keeps the strided radix-8 writes of the first passes
-// spread over the LDS banks.
-__device__ __forceinline__ int padi(int j) { return j + (j >> 3); }
+// One pad element every 16 float2: with it the contiguous reads and the strided
+// radix-8 writes of every pass hit distinct banks (except a 2-way conflict on
+// the writes of the pass with P = 8).  For any c that is a multiple of 16,
+// padi(j + c) = padi(j) + c + c/16, so every LDS access below is a per-thread
+// base plus a compile-time offset.
+__device__ __forceinline__ constexpr int padi(int j) { return j + (j >> 4); }
+__device__ __forceinline__ constexpr int padc(int c) { return c + c / 16; }  // c % 16 == 0
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -101,35 +109,54 @@ __device__ __forceinline__ void dftR(float2 *v) {
     }
 }
 
+// Radix of pass ps and offset of its twiddle block: passes 1..ps-1 precede it.
+constexpr int pass_radix(int logm, int ps) { return ps < logm / 3 ? 8 : (1 << (logm % 3)); }
+constexpr int twiddle_offset(int logm, int ps) {
+    int o = 0;
+    for (int q = 1; q < ps; ++q) o += (1 << (3 * q)) * pass_radix(logm, q);
+    return o;
+}
+
 template <int LOGM, int PS>
 struct Pass {
     using C = FCfg<LOGM>;
     static constexpr int R = (PS < C::NPASS8) ? 8 : C::RLAST;
     static constexpr int P = 1 << (3 * PS);  // size of the sub-transforms already done
     static constexpr int NB = 8 / R;         // butterflies per thread
+    // offset (float2) of this pass's twiddle block [P][R] in the table
+    static constexpr int TOFF = twiddle_offset(LOGM, PS);
 };
 
 // Radix-R Stockham pass PS >= 1: butterfly i reads src[i + r M/R], applies
-// W_{P R}^{r k} = tw[r k M / (P R)] with k = i mod P, transforms, and writes
-// dst[(i - k) R + k + q P].  Twiddles come from the FP32 table in global
-// memory (a few KB, L1-resident) rather than registers.
+// W_{P R}^{r k} (k = i mod P), transforms, and writes dst[(i - k) R + k + q P].
+// The twiddles of butterfly k are the contiguous entries [k][0..R) of this
+// pass's block of the FP32 table (entry 0 is 1 and unused).
 template <int LOGM, int PS>
-__device__ __forceinline__ void fft_pass(const float2 *src, float2 *dst, const float2 *__restrict__ tw, int t) {
+__device__ __forceinline__ void fft_pass(const float2 *src, float2 *dst, const float2 *__restrict__ twp, int t) {
     using Ps = Pass<LOGM, PS>;
     using C = FCfg<LOGM>;
     constexpr int R = Ps::R, P = Ps::P, NB = Ps::NB, M = C::M, L = C::L;
     float2 v[8];
+    const float2 *s0 = src + padi(t);
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[u * R + r] = src[padi(t + L * u + r * (M / R))];
+        for (int r = 0; r < R; ++r) v[u * R + r] = s0[padc(L * u + r * (M / R))];
     }
     if constexpr (C::NBUF == 1) __syncthreads();  // single buffer: all reads before any write
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const int k = (t + L * u) & (P - 1);
+        const float4 *tw4 = reinterpret_cast<const float4 *>(twp + Ps::TOFF + k * R);
+        float2 w[8];
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[u * R + r] = cmul(v[u * R + r], tw[(r * k) * (M / (P * R))]);
+        for (int h = 0; h < R / 2; ++h) {
+            const float4 q = tw4[h];
+            w[2 * h] = make_float2(q.x, q.y);
+            w[2 * h + 1] = make_float2(q.z, q.w);
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[u * R + r] = cmul(v[u * R + r], w[r]);
         dftR<R>(&v[u * R]);
     }
 #pragma unroll
@@ -137,8 +164,19 @@ __device__ __forceinline__ void fft_pass(const float2 *src, float2 *dst, const f
         const int i = t + L * u;
         const int k = i & (P - 1);
         const int j = (i - k) * R + k;
+        if constexpr (P >= 16) {
+            float2 *d0 = dst + padi(j);
 #pragma unroll
-        for (int q = 0; q < R; ++q) dst[padi(j + q * P)] = v[u * R + q];
+            for (int q = 0; q < R; ++q) d0[padc(q * P)] = v[u * R + q];
+        } else if constexpr (P == 8) {
+            // j = 64 a + b (b < 8): padi(j + 8 q) = 68 a + b + 8 q + (q >> 1)
+            float2 *d0 = dst + (j + ((j >> 6) << 2));
+#pragma unroll
+            for (int q = 0; q < R; ++q) d0[8 * q + (q >> 1)] = v[u * R + q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < R; ++q) dst[padi(j + q * P)] = v[u * R + q];
+        }
     }
 }
 
@@ -274,7 +312,6 @@ fengine_kernel(FLaunch a) {
         pacc[j] = 0.f;
     }
 
-    const int ngrp = a.T / G;
 #pragma unroll 1
     for (int r = 0; r < 16; ++r) {
         const int m = m0 + r;
@@ -303,11 +340,13 @@ fengine_kernel(FLaunch a) {
                 v[q] = make_float2((float)(int8_t)(p & 0xFF), (float)(int8_t)(p >> 8));
             }
             dft8(v);
+            // padi(8 t + q) = 8 t + (t >> 1) + q
+            float2 *d0 = b0 + (8 * tt + (tt >> 1));
 #pragma unroll
-            for (int q = 0; q < 8; ++q) b0[padi(8 * tt + q)] = v[q];
+            for (int q = 0; q < 8; ++q) d0[q] = v[q];
         }
         // 2b. remaining passes
-        fft_passes<LOGM, 1>(b0, b1, a.tw, tt);
+        fft_passes<LOGM, 1>(b0, b1, a.twp, tt);
         __syncthreads();
         const float2 *Z = result_buffer<LOGM>(b0, b1);
         const float2 *wn = a.wn;
@@ -325,14 +364,20 @@ fengine_kernel(FLaunch a) {
         // byte lane of this spectrum inside its dword of the chunk
         // (v_perm selector: byte 4 = the new value's low byte, bytes 0..3 = the old dword)
         const uint32_t bsel = (0x03020100u & ~(0xFFu << (8 * (r & 3)))) | (0x04u << (8 * (r & 3)));
+        // Z[k] and Z[M - k] for k = t + L j: bases plus compile-time offsets
+        const float2 *za0 = Z + padi(tt);
+        const int nb = -tt + ((-tt) >> 4);  // padi((8 - j) L - t) = padc((8 - j) L) + nb
+        const float2 *zb0p = Z + nb;
+        const float2 *zbz = (tt == 0) ? Z : (Z + padc(M) + nb);  // j = 0: index (M - t) mod M
+        // chunk of spectrum m: 16-byte index g*C*S + ((t/8) S + s) 8 + t%8 + j L S
+        const int64_t obase = (int64_t)(m / G) * M * a.S + (((tt >> 3) * a.S + s) << 3) + (tt & 7);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int k = tt + L * j;
-            const float2 za = Z[padi(k)];
-            const float2 zb0 = Z[padi((M - k) & (M - 1))];
+            const float2 za = za0[padc(L * j)];
+            const float2 zb0 = (j == 0) ? zbz[0] : zb0p[padc((8 - j) * L)];
             const float2 zb = make_float2(zb0.x, -zb0.y);
             const float2 sm = cadd(za, zb), df = csub(za, zb);
-            const float2 w = wn[k];
+            const float2 w = wn[tt + L * j];
             // X = (a + b)/2 - (i/2) w (a - b)
             float2 X;
             X.x = 0.5f * (sm.x + (w.x * df.y + w.y * df.x));
@@ -344,8 +389,7 @@ fengine_kernel(FLaunch a) {
                 if constexpr (MODE == 0) {
                     if (r & 1) {
                         if (active) {
-                            float4 *dst = reinterpret_cast<float4 *>(a.spec) +
-                                          ((int64_t)k * ngrp + (m >> 1)) * a.S + s;
+                            float4 *dst = reinterpret_cast<float4 *>(a.spec) + obase + (int64_t)j * L * a.S;
                             *dst = make_float4(f0[j].x, f0[j].y, Y.x, Y.y);
                         }
                     } else {
@@ -360,20 +404,16 @@ fengine_kernel(FLaunch a) {
                         qr = e4m3_rne_sat(Y.x * inv[j]);
                         qi = e4m3_rne_sat(Y.y * inv[j]);
                     }
-                    // insert the byte of spectrum r into its dword, keeping the other bytes
-                    if (r & 4) {
-                        q1[j] = __builtin_amdgcn_perm(qr, q1[j], bsel);
-                        h1[j] = __builtin_amdgcn_perm(qi, h1[j], bsel);
-                    } else {
-                        q0[j] = __builtin_amdgcn_perm(qr, q0[j], bsel);
-                        h0[j] = __builtin_amdgcn_perm(qi, h0[j], bsel);
-                    }
-                    if ((r & 7) == 7) {
-                        if (active) {
-                            uint4 *dst = reinterpret_cast<uint4 *>(a.spec) + ((int64_t)k * ngrp + (m >> 3)) * a.S + s;
-                            *dst = make_uint4(q0[j], q1[j], h0[j], h1[j]);
-                        }
-                        q0[j] = q1[j] = h0[j] = h1[j] = 0u;
+                    // insert the byte of spectrum r into the current dword (the other
+                    // bytes are overwritten by the next spectra before they are used)
+                    q1[j] = __builtin_amdgcn_perm(qr, q1[j], bsel);
+                    h1[j] = __builtin_amdgcn_perm(qi, h1[j], bsel);
+                    if ((r & 7) == 3) {  // spectra 0..3 of the chunk complete
+                        q0[j] = q1[j];
+                        h0[j] = h1[j];
+                    } else if ((r & 7) == 7 && active) {
+                        uint4 *dst = reinterpret_cast<uint4 *>(a.spec) + obase + (int64_t)j * L * a.S;
+                        *dst = make_uint4(q0[j], q1[j], h0[j], h1[j]);
                     }
                 }
             }
@@ -435,6 +475,26 @@ int fengine_fpar(int log2m) {
 }
 
 int fengine_spectra_per_block(int log2m) { return 16 * fengine_fpar(log2m); }
+
+// Twiddles of passes 1..NPASS-1 in the order of Pass<>::TOFF: for each pass the
+// block [k < P][r < R] of W_{P R}^{r k} = exp(-2 pi i r k / (P R)), computed in
+// FP64 and rounded once to FP32.  With out == nullptr only the count is returned.
+void fengine_twiddle_table(int log2m, float2 *out, size_t *count) {
+    const int npass8 = log2m / 3, rlast = 1 << (log2m % 3);
+    const int npass = npass8 + (rlast > 1 ? 1 : 0);
+    size_t n = 0;
+    for (int ps = 1; ps < npass; ++ps) {
+        const int R = ps < npass8 ? 8 : rlast;
+        const int P = 1 << (3 * ps);
+        for (int k = 0; k < P; ++k)
+            for (int r = 0; r < R; ++r, ++n)
+                if (out) {
+                    const double a = -2.0 * M_PI * (double)r * (double)k / ((double)P * (double)R);
+                    out[n] = make_float2((float)std::cos(a), (float)std::sin(a));
+                }
+    }
+    *count = n;
+}
 
 hipError_t launch_fengine(int log2m, int mode, const FLaunch &a, hipStream_t st) {
     switch (log2m) {

@@ -16,10 +16,13 @@
 // l holds signal 32a + (l mod 32) and the chunks of spectra picked by l / 32;
 // since A and B lanes hold the same spectra in the same byte order, the
 // product is exact regardless of how the hardware orders K inside a lane.
-// Each wave owns one (split, channel) pair: it streams that channel's
-// contiguous chunk rows (S * 16 bytes per chunk), keeps the accumulator tiles
-// in registers, and at the end forms Im = M - M^T through LDS and adds its
-// result into acc[split][k][p] (sole owner, so no atomics and a fixed order).
+// X layout: 16-byte chunks indexed [g][k/8][s][k mod 8] (g = chunk of spectra),
+// so the chunks of 8 consecutive channels of one signal form one 128-byte
+// line.  A workgroup of 8 waves owns 8 consecutive channels and one split of
+// the spectra; wave w handles channel 8 kb + w, so the 8 waves together read
+// whole lines.  Each wave keeps its accumulator tiles in registers and at the
+// end forms Im = M - M^T through LDS and adds its result into
+// acc[split][k][p] (sole owner, so no atomics and a fixed order).
 #include "corr_internal.h"
 
 namespace corr {
@@ -40,7 +43,7 @@ __device__ __forceinline__ int acc_row(int r, int lg) { return 8 * (r >> 2) + 4 
 template <int NT, typename ACC, typename V16>
 __device__ __forceinline__ void x_epilogue(const V16 (&accR)[ntri(NT)], const V16 (&accM)[NT * NT],
                                            ACC *acc_out, int S, int64_t P, ACC (*mlds)[32][33]) {
-    const int lane = threadIdx.x, col = lane & 31, lg = lane >> 5;
+    const int lane = threadIdx.x & 63, col = lane & 31, lg = lane >> 5;
 #pragma unroll
     for (int t = 0; t < NT * NT; ++t)
 #pragma unroll
@@ -70,18 +73,21 @@ __device__ __forceinline__ void x_epilogue(const V16 (&accR)[ntri(NT)], const V1
 // Chunk indices of K-step st: lanes 0-31 take chunks 4st and 4st+2, lanes
 // 32-63 chunks 4st+1 and 4st+3 (the two lane groups form the K halves).
 // INT8/FP8 chunk: 8 real bytes then 8 imaginary bytes; FP32 chunk: 2 complex64.
+constexpr int kXWaves = 8;  // channels (waves) per workgroup
 
 // ---------------------------------------------------------------- INT8 ----
 template <int NT>
-__global__ void __launch_bounds__(64) xengine_i8_kernel(const uint8_t *__restrict__ spec, int32_t *acc,
+__global__ void __launch_bounds__(64 * kXWaves) xengine_i8_kernel(const uint8_t *__restrict__ spec, int32_t *acc,
                                                           int S, int C, int T, int splits) {
-    __shared__ int32_t mlds[NT * NT][32][33];
-    const int c = blockIdx.x, sp = blockIdx.y;
-    const int lane = threadIdx.x, row = lane & 31, lg = lane >> 5;
+    __shared__ int32_t mlds[kXWaves][NT * NT][32][33];
+    const int kb = blockIdx.x, sp = blockIdx.y, wv = threadIdx.x >> 6, c = kXWaves * kb + wv;
+    const int lane = threadIdx.x & 63, row = lane & 31, lg = lane >> 5;
     const int ngrp = T / kChunk8;
     const int steps = ngrp / 4 / splits;  // K-steps of 32 spectra for this split
     const int64_t P = (int64_t)S * (S + 1) / 2;
-    const v4i *base = reinterpret_cast<const v4i *>(spec) + (int64_t)c * ngrp * S;
+    // chunk (g, s) of channel c at 16-byte index g C S + (kb S + s) 8 + wv
+    const v4i *base = reinterpret_cast<const v4i *>(spec) + (int64_t)kb * S * 8 + wv;
+    const int64_t gstride = (int64_t)C * S;
 
     v16i accR[ntri(NT)], accM[NT * NT];
 #pragma unroll
@@ -98,8 +104,8 @@ __global__ void __launch_bounds__(64) xengine_i8_kernel(const uint8_t *__restric
 #pragma unroll
         for (int a = 0; a < NT; ++a) {
             if (valid[a]) {
-                c0[a] = base[(int64_t)g0 * S + 32 * a + row];
-                c1[a] = base[(int64_t)(g0 + 2) * S + 32 * a + row];
+                c0[a] = base[g0 * gstride + (32 * a + row) * 8];
+                c1[a] = base[(g0 + 2) * gstride + (32 * a + row) * 8];
             } else {
                 c0[a] = v4i{0};
                 c1[a] = v4i{0};
@@ -135,20 +141,22 @@ __global__ void __launch_bounds__(64) xengine_i8_kernel(const uint8_t *__restric
             c1[a] = n1[a];
         }
     }
-    x_epilogue<NT, int32_t>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, mlds);
+    x_epilogue<NT, int32_t>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, &mlds[wv][0]);
 }
 
 // ----------------------------------------------------------------- FP8 ----
 template <int NT>
-__global__ void __launch_bounds__(64) xengine_f8_kernel(const uint8_t *__restrict__ spec, float *acc,
+__global__ void __launch_bounds__(64 * kXWaves) xengine_f8_kernel(const uint8_t *__restrict__ spec, float *acc,
                                                           int S, int C, int T, int splits) {
-    __shared__ float mlds[NT * NT][32][33];
-    const int c = blockIdx.x, sp = blockIdx.y;
-    const int lane = threadIdx.x, row = lane & 31, lg = lane >> 5;
+    __shared__ float mlds[kXWaves][NT * NT][32][33];
+    const int kb = blockIdx.x, sp = blockIdx.y, wv = threadIdx.x >> 6, c = kXWaves * kb + wv;
+    const int lane = threadIdx.x & 63, row = lane & 31, lg = lane >> 5;
     const int ngrp = T / kChunk8;
     const int steps = ngrp / 4 / splits;
     const int64_t P = (int64_t)S * (S + 1) / 2;
-    const v4i *base = reinterpret_cast<const v4i *>(spec) + (int64_t)c * ngrp * S;
+    // chunk (g, s) of channel c at 16-byte index g C S + (kb S + s) 8 + wv
+    const v4i *base = reinterpret_cast<const v4i *>(spec) + (int64_t)kb * S * 8 + wv;
+    const int64_t gstride = (int64_t)C * S;
 
     v16f accR[ntri(NT)], accM[NT * NT];
 #pragma unroll
@@ -165,8 +173,8 @@ __global__ void __launch_bounds__(64) xengine_f8_kernel(const uint8_t *__restric
 #pragma unroll
         for (int a = 0; a < NT; ++a) {
             if (valid[a]) {
-                c0[a] = base[(int64_t)g0 * S + 32 * a + row];
-                c1[a] = base[(int64_t)(g0 + 2) * S + 32 * a + row];
+                c0[a] = base[g0 * gstride + (32 * a + row) * 8];
+                c1[a] = base[(g0 + 2) * gstride + (32 * a + row) * 8];
             } else {
                 c0[a] = v4i{0};
                 c1[a] = v4i{0};
@@ -207,20 +215,21 @@ __global__ void __launch_bounds__(64) xengine_f8_kernel(const uint8_t *__restric
             c1[a] = n1[a];
         }
     }
-    x_epilogue<NT, float>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, mlds);
+    x_epilogue<NT, float>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, &mlds[wv][0]);
 }
 
 // ----------------------------------------------------------------- FP32 ---
 template <int NT>
-__global__ void __launch_bounds__(64) xengine_f32_kernel(const float *__restrict__ spec, float *acc,
+__global__ void __launch_bounds__(64 * kXWaves) xengine_f32_kernel(const float *__restrict__ spec, float *acc,
                                                            int S, int C, int T, int splits) {
-    __shared__ float mlds[NT * NT][32][33];
-    const int c = blockIdx.x, sp = blockIdx.y;
-    const int lane = threadIdx.x, row = lane & 31, lg = lane >> 5;
+    __shared__ float mlds[kXWaves][NT * NT][32][33];
+    const int kb = blockIdx.x, sp = blockIdx.y, wv = threadIdx.x >> 6, c = kXWaves * kb + wv;
+    const int lane = threadIdx.x & 63, row = lane & 31, lg = lane >> 5;
     const int ngrp = T / kChunk32;
     const int steps = ngrp / 4 / splits;  // K-steps of 8 spectra
     const int64_t P = (int64_t)S * (S + 1) / 2;
-    const float4 *base = reinterpret_cast<const float4 *>(spec) + (int64_t)c * ngrp * S;
+    const float4 *base = reinterpret_cast<const float4 *>(spec) + (int64_t)kb * S * 8 + wv;
+    const int64_t gstride = (int64_t)C * S;
 
     v16f accR[ntri(NT)], accM[NT * NT];
 #pragma unroll
@@ -237,8 +246,8 @@ __global__ void __launch_bounds__(64) xengine_f32_kernel(const float *__restrict
 #pragma unroll
         for (int a = 0; a < NT; ++a) {
             if (valid[a]) {
-                c0[a] = base[(int64_t)g0 * S + 32 * a + row];
-                c1[a] = base[(int64_t)(g0 + 2) * S + 32 * a + row];
+                c0[a] = base[g0 * gstride + (32 * a + row) * 8];
+                c1[a] = base[(g0 + 2) * gstride + (32 * a + row) * 8];
             } else {
                 c0[a] = make_float4(0.f, 0.f, 0.f, 0.f);
                 c1[a] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -279,7 +288,7 @@ __global__ void __launch_bounds__(64) xengine_f32_kernel(const float *__restrict
             c1[a] = n1[a];
         }
     }
-    x_epilogue<NT, float>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, mlds);
+    x_epilogue<NT, float>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, &mlds[wv][0]);
 }
 
 // --------------------------------------------------------------- xpack ----
@@ -294,7 +303,8 @@ __global__ void xpack_kernel(const E *__restrict__ in, E *out, int S, int C, int
     const int64_t rest = idx / S;
     const int tg = (int)(rest % ngrp);
     const int k = (int)(rest / ngrp);
-    E *dst = out + idx * (2 * G);
+    // X layout: 16-byte chunk index g C S + ((k / 8) S + s) 8 + k mod 8
+    E *dst = out + ((int64_t)tg * C * S + ((int64_t)(k >> 3) * S + s) * 8 + (k & 7)) * (2 * G);
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         const E *src = in + (((int64_t)s * T + (int64_t)tg * G + q) * C + k) * 2;
@@ -312,7 +322,7 @@ __global__ void xpack_kernel(const E *__restrict__ in, E *out, int S, int C, int
 
 hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int C, int T, int splits,
                           hipStream_t st) {
-    const dim3 grid(C, splits), block(64);
+    const dim3 grid(C / kXWaves, splits), block(64 * kXWaves);
     const bool two = S > 32;
     switch (precision) {
     case CORR_INT8:

@@ -169,6 +169,37 @@ def _voltages_bulk(S, n_samples, geom, *, seed, rho, sigma_t, n_pol, tone_bin, t
     return out
 
 
+def voltages_device(S: int, n_samples: int, geom: Geom, *, seed: int = BASE_SEED, rho: float = 0.3,
+                    sigma_t: float = 12.0, n_pol: int = 2, tone_bin: int | None = None,
+                    tone_N: int | None = None, tone_amp: float = 4.0, row_stride: int | None = None,
+                    device="cuda"):
+    """The ``bulk`` recipe generated on the GPU with torch's seeded Philox generator
+    (for inputs of many GB).  Returns an int8 device tensor [S][row_stride] whose
+    first n_samples columns hold the streams (the rest is zero)."""
+    import torch
+    rs = row_stride or n_samples
+    out = torch.zeros((S, rs), dtype=torch.int8, device=device)
+    maxD = int(geom.D.max()) if geom.S else 0
+    a, bn = float(sigma_t * np.sqrt(rho)), float(sigma_t * np.sqrt(max(0.0, 1.0 - rho)))
+    gen = torch.Generator(device=device)
+    if tone_bin is not None:
+        n = torch.arange(n_samples, device=device, dtype=torch.float64)
+    for pol in range(n_pol):
+        gen.manual_seed((int(seed) * 1000003 + 17 * pol + 1) & 0x7FFFFFFFFFFFFFFF)
+        common = torch.randn(n_samples + maxD, generator=gen, device=device, dtype=torch.float32)
+        for s in range(pol, S, n_pol):
+            d = int(geom.D[s])
+            gen.manual_seed((int(seed) * 1000003 + 7919 * (s + 1) + 2) & 0x7FFFFFFFFFFFFFFF)
+            v = torch.randn(n_samples, generator=gen, device=device, dtype=torch.float32).mul_(bn)
+            v.add_(common[maxD - d:maxD - d + n_samples], alpha=a)
+            if tone_bin is not None:
+                v.add_((tone_amp * torch.cos(2 * np.pi * (tone_bin / tone_N) * (n - d))).float())
+            out[s, :n_samples] = v.round_().clamp_(-127, 127).to(torch.int8)
+            del v
+        del common
+    return out
+
+
 def random_spectra_int8(S: int, T: int, C: int, seed: int = BASE_SEED, sigma: float = 32.0,
                         extremes: bool = True) -> np.ndarray:
     """Requantised-spectrum-like int8 [S][T][C][2] in [-127, 127] for X-engine tests.
