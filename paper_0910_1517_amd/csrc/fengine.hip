@@ -279,12 +279,14 @@ fengine_kernel(FLaunch a) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int k = t + L * j;
+        // the post-process below forms 2 X[k]; the factor 1/2 is folded (exactly)
+        // into the ramp (FP32 output) or the inverse scale (requantised output)
         if constexpr (MODE != 3) {
             float sn, cs;
             sincospif(2.0f * ((float)k * (g.frac / (float)N)), &sn, &cs);
-            ramp[j] = make_float2(cs, sn);
+            ramp[j] = (MODE == 0) ? make_float2(0.5f * cs, 0.5f * sn) : make_float2(cs, sn);
         }
-        if constexpr (MODE == 1 || MODE == 2) inv[j] = 1.0f / a.scale[(int64_t)s * M + k];
+        if constexpr (MODE == 1 || MODE == 2) inv[j] = 0.5f / a.scale[(int64_t)s * M + k];
     }
 
     const uint32_t *row = reinterpret_cast<const uint32_t *>(a.x + (int64_t)s * a.row_stride);
@@ -378,10 +380,10 @@ fengine_kernel(FLaunch a) {
             const float2 zb = make_float2(zb0.x, -zb0.y);
             const float2 sm = cadd(za, zb), df = csub(za, zb);
             const float2 w = wn[tt + L * j];
-            // X = (a + b)/2 - (i/2) w (a - b)
+            // 2 X = (a + b) - i w (a - b)
             float2 X;
-            X.x = 0.5f * (sm.x + (w.x * df.y + w.y * df.x));
-            X.y = 0.5f * (sm.y - (w.x * df.x - w.y * df.y));
+            X.x = sm.x + (w.x * df.y + w.y * df.x);
+            X.y = sm.y - (w.x * df.x - w.y * df.y);
             if constexpr (MODE == 3) {
                 pacc[j] += X.x * X.x + X.y * X.y;
             } else {
@@ -425,7 +427,7 @@ fengine_kernel(FLaunch a) {
             // slot m0/16 of T/16 per signal: the active slots are exactly the first T/16
             float *dst = a.part + ((int64_t)s * (a.T / 16) + (m0 >> 4)) * M;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) dst[t + L * j] = pacc[j];
+            for (int j = 0; j < 8; ++j) dst[t + L * j] = 0.25f * pacc[j];  // |2X|^2 / 4
         }
     }
 }

@@ -19,10 +19,13 @@
 // X layout: 16-byte chunks indexed [g][k/8][s][k mod 8] (g = chunk of spectra),
 // so the chunks of 8 consecutive channels of one signal form one 128-byte
 // line.  A workgroup of 8 waves owns 8 consecutive channels and one split of
-// the spectra; wave w handles channel 8 kb + w, so the 8 waves together read
-// whole lines.  Each wave keeps its accumulator tiles in registers and at the
+// the spectra; wave w handles channel 8 kb + w.  The workgroup stages each
+// K-step's lines through LDS (below).  Each wave keeps its accumulator tiles in
+// registers and at the
 // end forms Im = M - M^T through LDS and adds its result into
 // acc[split][k][p] (sole owner, so no atomics and a fixed order).
+#include <type_traits>
+
 #include "corr_internal.h"
 
 namespace corr {
@@ -70,225 +73,163 @@ __device__ __forceinline__ void x_epilogue(const V16 (&accR)[ntri(NT)], const V1
         }
 }
 
-// Chunk indices of K-step st: lanes 0-31 take chunks 4st and 4st+2, lanes
-// 32-63 chunks 4st+1 and 4st+3 (the two lane groups form the K halves).
-// INT8/FP8 chunk: 8 real bytes then 8 imaginary bytes; FP32 chunk: 2 complex64.
-constexpr int kXWaves = 8;  // channels (waves) per workgroup
+// K-step st covers chunks g0..g0+3, g0 = 4 (split offset + st): lanes 0-31
+// take chunks g0 and g0+2, lanes 32-63 chunks g0+1 and g0+3 (the two lane
+// groups form the K halves).  INT8/FP8 chunk: 8 real bytes then 8 imaginary
+// bytes (8 spectra); FP32 chunk: 2 complex64.
+//
+// Staging: the workgroup's 8 channels x S signals of one chunk form one
+// contiguous block of S x 128 bytes; the 512 threads copy the 4 blocks of the
+// next K-step with one 16-byte load each per block (fully coalesced) while the
+// MFMAs of the current step run, then store them into LDS with a 144-byte row
+// pitch per signal so that the per-channel 16-byte operand reads of a wave
+// (stride 144 B across lanes) are free of bank conflicts.  Double-buffered;
+// the accumulator exchange of the epilogue reuses the same LDS.
+constexpr int kXWaves = 8;                  // channels (waves) per workgroup
+constexpr int kRowPitch = 144;              // LDS bytes per signal row (8 x 16 + 16)
+constexpr int kBlk = kMaxSignals * kRowPitch;  // LDS bytes per staged chunk block
 
-// ---------------------------------------------------------------- INT8 ----
 template <int NT>
-__global__ void __launch_bounds__(64 * kXWaves) xengine_i8_kernel(const uint8_t *__restrict__ spec, int32_t *acc,
-                                                          int S, int C, int T, int splits) {
-    __shared__ int32_t mlds[kXWaves][NT * NT][32][33];
-    const int kb = blockIdx.x, sp = blockIdx.y, wv = threadIdx.x >> 6, c = kXWaves * kb + wv;
-    const int lane = threadIdx.x & 63, row = lane & 31, lg = lane >> 5;
-    const int ngrp = T / kChunk8;
-    const int steps = ngrp / 4 / splits;  // K-steps of 32 spectra for this split
-    const int64_t P = (int64_t)S * (S + 1) / 2;
-    // chunk (g, s) of channel c at 16-byte index g C S + (kb S + s) 8 + wv
-    const v4i *base = reinterpret_cast<const v4i *>(spec) + (int64_t)kb * S * 8 + wv;
-    const int64_t gstride = (int64_t)C * S;
-
-    v16i accR[ntri(NT)], accM[NT * NT];
-#pragma unroll
-    for (int t = 0; t < ntri(NT); ++t) accR[t] = v16i{0};
-#pragma unroll
-    for (int t = 0; t < NT * NT; ++t) accM[t] = v16i{0};
-
-    bool valid[NT];
-#pragma unroll
-    for (int a = 0; a < NT; ++a) valid[a] = (32 * a + row) < S;
-
-    auto load = [&](int st, v4i (&c0)[NT], v4i (&c1)[NT]) {
-        const int g0 = 4 * (sp * steps + st) + lg;
-#pragma unroll
-        for (int a = 0; a < NT; ++a) {
-            if (valid[a]) {
-                c0[a] = base[g0 * gstride + (32 * a + row) * 8];
-                c1[a] = base[(g0 + 2) * gstride + (32 * a + row) * 8];
-            } else {
-                c0[a] = v4i{0};
-                c1[a] = v4i{0};
-            }
-        }
-    };
-
-    v4i c0[NT], c1[NT], n0[NT], n1[NT];
-    load(0, c0, c1);
-    for (int st = 0; st < steps; ++st) {
-        if (st + 1 < steps) load(st + 1, n0, n1);
-        v4i im[NT], re[NT];  // imaginary / real bytes of both chunks
-#pragma unroll
-        for (int a = 0; a < NT; ++a) {
-            im[a] = v4i{c0[a].z, c0[a].w, c1[a].z, c1[a].w};
-            re[a] = v4i{c0[a].x, c0[a].y, c1[a].x, c1[a].y};
-        }
-#pragma unroll
-        for (int b = 0; b < NT; ++b) {
-#pragma unroll
-            for (int a = 0; a <= b; ++a) {
-                v16i &d = accR[tri_idx(a, b)];
-                d = __builtin_amdgcn_mfma_i32_32x32x32_i8(c0[a], c0[b], d, 0, 0, 0);
-                d = __builtin_amdgcn_mfma_i32_32x32x32_i8(c1[a], c1[b], d, 0, 0, 0);
-            }
-#pragma unroll
-            for (int a = 0; a < NT; ++a)
-                accM[a * NT + b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im[a], re[b], accM[a * NT + b], 0, 0, 0);
-        }
-#pragma unroll
-        for (int a = 0; a < NT; ++a) {
-            c0[a] = n0[a];
-            c1[a] = n1[a];
-        }
-    }
-    x_epilogue<NT, int32_t>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, &mlds[wv][0]);
+constexpr int x_lds_bytes() {
+    return (2 * 4 * kBlk > kXWaves * NT * NT * 32 * 33 * 4) ? 2 * 4 * kBlk : kXWaves * NT * NT * 32 * 33 * 4;
 }
 
-// ----------------------------------------------------------------- FP8 ----
-template <int NT>
-__global__ void __launch_bounds__(64 * kXWaves) xengine_f8_kernel(const uint8_t *__restrict__ spec, float *acc,
-                                                          int S, int C, int T, int splits) {
-    __shared__ float mlds[kXWaves][NT * NT][32][33];
+// PREC: CORR_FP32, CORR_INT8 or CORR_FP8_E4M3; ACC: float or int32_t
+template <int NT, int PREC, typename ACC>
+__global__ void __launch_bounds__(64 * kXWaves)
+xengine_kernel(const uint8_t *__restrict__ spec, ACC *acc, int S, int C, int T, int splits) {
+    using V16 = typename std::conditional<PREC == CORR_INT8, v16i, v16f>::type;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[x_lds_bytes<NT>()];
     const int kb = blockIdx.x, sp = blockIdx.y, wv = threadIdx.x >> 6, c = kXWaves * kb + wv;
     const int lane = threadIdx.x & 63, row = lane & 31, lg = lane >> 5;
-    const int ngrp = T / kChunk8;
-    const int steps = ngrp / 4 / splits;
+    const int G = (PREC == CORR_FP32) ? kChunk32 : kChunk8;
+    const int steps = T / G / 4 / splits;
     const int64_t P = (int64_t)S * (S + 1) / 2;
-    // chunk (g, s) of channel c at 16-byte index g C S + (kb S + s) 8 + wv
-    const v4i *base = reinterpret_cast<const v4i *>(spec) + (int64_t)kb * S * 8 + wv;
-    const int64_t gstride = (int64_t)C * S;
 
-    v16f accR[ntri(NT)], accM[NT * NT];
-#pragma unroll
-    for (int t = 0; t < ntri(NT); ++t) accR[t] = v16f{0.f};
-#pragma unroll
-    for (int t = 0; t < NT * NT; ++t) accM[t] = v16f{0.f};
+    // staging copy: thread i moves bytes [16 i, 16 i + 16) of each block
+    const int i = threadIdx.x;
+    const bool cp = i < S * 8;
+    const int lds_dst = (i >> 3) * kRowPitch + (i & 7) * 16;
+    const uint4 *gsrc = reinterpret_cast<const uint4 *>(spec) + (int64_t)kb * S * 8 + i;
+    const int64_t gstride = (int64_t)C * S;  // 16-byte units between chunks g and g+1
+    uint4 p0 = make_uint4(0, 0, 0, 0), p1 = p0, p2 = p0, p3 = p0;
+#define X_GLOAD(st)                                                   \
+    if (cp) {                                                         \
+        const uint4 *g_ = gsrc + 4 * ((int64_t)sp * steps + (st)) * gstride; \
+        p0 = g_[0];                                                   \
+        p1 = g_[gstride];                                             \
+        p2 = g_[2 * gstride];                                         \
+        p3 = g_[3 * gstride];                                         \
+    }
+#define X_LSTORE(buf)                                                 \
+    if (cp) {                                                         \
+        uint8_t *l_ = lds + (buf) * 4 * kBlk + lds_dst;               \
+        *reinterpret_cast<uint4 *>(l_) = p0;                          \
+        *reinterpret_cast<uint4 *>(l_ + kBlk) = p1;                   \
+        *reinterpret_cast<uint4 *>(l_ + 2 * kBlk) = p2;               \
+        *reinterpret_cast<uint4 *>(l_ + 3 * kBlk) = p3;               \
+    }
 
+    V16 accR[ntri(NT)], accM[NT * NT];
+#pragma unroll
+    for (int t = 0; t < ntri(NT); ++t) accR[t] = V16{0};
+#pragma unroll
+    for (int t = 0; t < NT * NT; ++t) accM[t] = V16{0};
     bool valid[NT];
 #pragma unroll
     for (int a = 0; a < NT; ++a) valid[a] = (32 * a + row) < S;
 
-    auto load = [&](int st, v4i (&c0)[NT], v4i (&c1)[NT]) {
-        const int g0 = 4 * (sp * steps + st) + lg;
+    X_GLOAD(0)
+    X_LSTORE(0)
+    __syncthreads();
+    for (int st = 0; st < steps; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < steps) {
+            X_GLOAD(st + 1)
+        }
+        v4i c0[NT], c1[NT];
 #pragma unroll
         for (int a = 0; a < NT; ++a) {
-            if (valid[a]) {
-                c0[a] = base[g0 * gstride + (32 * a + row) * 8];
-                c1[a] = base[(g0 + 2) * gstride + (32 * a + row) * 8];
-            } else {
-                c0[a] = v4i{0};
-                c1[a] = v4i{0};
-            }
+            const uint8_t *b = lds + (buf * 4 + lg) * kBlk + (32 * a + row) * kRowPitch + wv * 16;
+            c0[a] = valid[a] ? *reinterpret_cast<const v4i *>(b) : v4i{0};
+            c1[a] = valid[a] ? *reinterpret_cast<const v4i *>(b + 2 * kBlk) : v4i{0};
         }
-    };
-    auto lo = [](v4i v) { return (long)(((unsigned long)(unsigned)v.y << 32) | (unsigned)v.x); };
-    auto hi = [](v4i v) { return (long)(((unsigned long)(unsigned)v.w << 32) | (unsigned)v.z); };
-
-    v4i c0[NT], c1[NT], n0[NT], n1[NT];
-    load(0, c0, c1);
-    for (int st = 0; st < steps; ++st) {
-        if (st + 1 < steps) load(st + 1, n0, n1);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            long re[NT], im[NT];
+        if constexpr (PREC == CORR_INT8) {
+            v4i im[NT], re[NT];  // imaginary / real bytes of both chunks
 #pragma unroll
             for (int a = 0; a < NT; ++a) {
-                re[a] = lo(h ? c1[a] : c0[a]);
-                im[a] = hi(h ? c1[a] : c0[a]);
+                im[a] = v4i{c0[a].z, c0[a].w, c1[a].z, c1[a].w};
+                re[a] = v4i{c0[a].x, c0[a].y, c1[a].x, c1[a].y};
             }
 #pragma unroll
             for (int b = 0; b < NT; ++b) {
 #pragma unroll
                 for (int a = 0; a <= b; ++a) {
-                    v16f &d = accR[tri_idx(a, b)];
-                    d = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(re[a], re[b], d, 0, 0, 0);
-                    d = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(im[a], im[b], d, 0, 0, 0);
+                    V16 &d = accR[tri_idx(a, b)];
+                    d = __builtin_amdgcn_mfma_i32_32x32x32_i8(c0[a], c0[b], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_i32_32x32x32_i8(c1[a], c1[b], d, 0, 0, 0);
                 }
 #pragma unroll
                 for (int a = 0; a < NT; ++a)
-                    accM[a * NT + b] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(im[a], re[b], accM[a * NT + b], 0, 0, 0);
+                    accM[a * NT + b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(im[a], re[b], accM[a * NT + b], 0, 0, 0);
             }
-        }
+        } else if constexpr (PREC == CORR_FP8_E4M3) {
 #pragma unroll
-        for (int a = 0; a < NT; ++a) {
-            c0[a] = n0[a];
-            c1[a] = n1[a];
-        }
-    }
-    x_epilogue<NT, float>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, &mlds[wv][0]);
-}
-
-// ----------------------------------------------------------------- FP32 ---
-template <int NT>
-__global__ void __launch_bounds__(64 * kXWaves) xengine_f32_kernel(const float *__restrict__ spec, float *acc,
-                                                           int S, int C, int T, int splits) {
-    __shared__ float mlds[kXWaves][NT * NT][32][33];
-    const int kb = blockIdx.x, sp = blockIdx.y, wv = threadIdx.x >> 6, c = kXWaves * kb + wv;
-    const int lane = threadIdx.x & 63, row = lane & 31, lg = lane >> 5;
-    const int ngrp = T / kChunk32;
-    const int steps = ngrp / 4 / splits;  // K-steps of 8 spectra
-    const int64_t P = (int64_t)S * (S + 1) / 2;
-    const float4 *base = reinterpret_cast<const float4 *>(spec) + (int64_t)kb * S * 8 + wv;
-    const int64_t gstride = (int64_t)C * S;
-
-    v16f accR[ntri(NT)], accM[NT * NT];
+            for (int h = 0; h < 2; ++h) {
+                long re[NT], im[NT];
 #pragma unroll
-    for (int t = 0; t < ntri(NT); ++t) accR[t] = v16f{0.f};
-#pragma unroll
-    for (int t = 0; t < NT * NT; ++t) accM[t] = v16f{0.f};
-
-    bool valid[NT];
-#pragma unroll
-    for (int a = 0; a < NT; ++a) valid[a] = (32 * a + row) < S;
-
-    auto load = [&](int st, float4 (&c0)[NT], float4 (&c1)[NT]) {
-        const int g0 = 4 * (sp * steps + st) + lg;
-#pragma unroll
-        for (int a = 0; a < NT; ++a) {
-            if (valid[a]) {
-                c0[a] = base[g0 * gstride + (32 * a + row) * 8];
-                c1[a] = base[(g0 + 2) * gstride + (32 * a + row) * 8];
-            } else {
-                c0[a] = make_float4(0.f, 0.f, 0.f, 0.f);
-                c1[a] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-        }
-    };
-
-    float4 c0[NT], c1[NT], n0[NT], n1[NT];
-    load(0, c0, c1);
-    for (int st = 0; st < steps; ++st) {
-        if (st + 1 < steps) load(st + 1, n0, n1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {  // spectra (chunk 0: 0, 1; chunk 1: 2, 3)
-            float rr[NT], qq[NT];
-#pragma unroll
-            for (int a = 0; a < NT; ++a) {
-                if (q == 0) { rr[a] = c0[a].x; qq[a] = c0[a].y; }
-                if (q == 1) { rr[a] = c0[a].z; qq[a] = c0[a].w; }
-                if (q == 2) { rr[a] = c1[a].x; qq[a] = c1[a].y; }
-                if (q == 3) { rr[a] = c1[a].z; qq[a] = c1[a].w; }
-            }
-#pragma unroll
-            for (int b = 0; b < NT; ++b) {
-#pragma unroll
-                for (int a = 0; a <= b; ++a) {
-                    v16f &d = accR[tri_idx(a, b)];
-                    d = __builtin_amdgcn_mfma_f32_32x32x2f32(rr[a], rr[b], d, 0, 0, 0);
-                    d = __builtin_amdgcn_mfma_f32_32x32x2f32(qq[a], qq[b], d, 0, 0, 0);
+                for (int a = 0; a < NT; ++a) {
+                    const v4i v = h ? c1[a] : c0[a];
+                    re[a] = (long)(((unsigned long)(unsigned)v.y << 32) | (unsigned)v.x);
+                    im[a] = (long)(((unsigned long)(unsigned)v.w << 32) | (unsigned)v.z);
                 }
 #pragma unroll
-                for (int a = 0; a < NT; ++a)
-                    accM[a * NT + b] = __builtin_amdgcn_mfma_f32_32x32x2f32(qq[a], rr[b], accM[a * NT + b], 0, 0, 0);
+                for (int b = 0; b < NT; ++b) {
+#pragma unroll
+                    for (int a = 0; a <= b; ++a) {
+                        V16 &d = accR[tri_idx(a, b)];
+                        d = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(re[a], re[b], d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(im[a], im[b], d, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int a = 0; a < NT; ++a)
+                        accM[a * NT + b] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(im[a], re[b], accM[a * NT + b], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {  // spectra (chunk 0: 0, 1; chunk 1: 2, 3)
+                float rr[NT], qq[NT];
+#pragma unroll
+                for (int a = 0; a < NT; ++a) {
+                    const v4i v = (q < 2) ? c0[a] : c1[a];
+                    rr[a] = __int_as_float((q & 1) ? v.z : v.x);
+                    qq[a] = __int_as_float((q & 1) ? v.w : v.y);
+                }
+#pragma unroll
+                for (int b = 0; b < NT; ++b) {
+#pragma unroll
+                    for (int a = 0; a <= b; ++a) {
+                        V16 &d = accR[tri_idx(a, b)];
+                        d = __builtin_amdgcn_mfma_f32_32x32x2f32(rr[a], rr[b], d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_32x32x2f32(qq[a], qq[b], d, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int a = 0; a < NT; ++a)
+                        accM[a * NT + b] = __builtin_amdgcn_mfma_f32_32x32x2f32(qq[a], rr[b], accM[a * NT + b], 0, 0, 0);
+                }
             }
         }
-#pragma unroll
-        for (int a = 0; a < NT; ++a) {
-            c0[a] = n0[a];
-            c1[a] = n1[a];
+        if (st + 1 < steps) {
+            X_LSTORE(buf ^ 1)
         }
+        __syncthreads();
     }
-    x_epilogue<NT, float>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, &mlds[wv][0]);
+#undef X_GLOAD
+#undef X_LSTORE
+    // the staging buffers are free now: the epilogue's M-tile exchange reuses them
+    auto *mlds = reinterpret_cast<ACC(*)[32][33]>(lds + wv * NT * NT * 32 * 33 * 4);
+    x_epilogue<NT, ACC>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, mlds);
 }
 
 // --------------------------------------------------------------- xpack ----
@@ -323,19 +264,20 @@ __global__ void xpack_kernel(const E *__restrict__ in, E *out, int S, int C, int
 hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int C, int T, int splits,
                           hipStream_t st) {
     const dim3 grid(C / kXWaves, splits), block(64 * kXWaves);
+    const uint8_t *sp8 = (const uint8_t *)spec;
     const bool two = S > 32;
     switch (precision) {
     case CORR_INT8:
-        if (two) hipLaunchKernelGGL(xengine_i8_kernel<2>, grid, block, 0, st, (const uint8_t *)spec, (int32_t *)acc, S, C, T, splits);
-        else hipLaunchKernelGGL(xengine_i8_kernel<1>, grid, block, 0, st, (const uint8_t *)spec, (int32_t *)acc, S, C, T, splits);
+        if (two) hipLaunchKernelGGL((xengine_kernel<2, CORR_INT8, int32_t>), grid, block, 0, st, sp8, (int32_t *)acc, S, C, T, splits);
+        else hipLaunchKernelGGL((xengine_kernel<1, CORR_INT8, int32_t>), grid, block, 0, st, sp8, (int32_t *)acc, S, C, T, splits);
         break;
     case CORR_FP8_E4M3:
-        if (two) hipLaunchKernelGGL(xengine_f8_kernel<2>, grid, block, 0, st, (const uint8_t *)spec, (float *)acc, S, C, T, splits);
-        else hipLaunchKernelGGL(xengine_f8_kernel<1>, grid, block, 0, st, (const uint8_t *)spec, (float *)acc, S, C, T, splits);
+        if (two) hipLaunchKernelGGL((xengine_kernel<2, CORR_FP8_E4M3, float>), grid, block, 0, st, sp8, (float *)acc, S, C, T, splits);
+        else hipLaunchKernelGGL((xengine_kernel<1, CORR_FP8_E4M3, float>), grid, block, 0, st, sp8, (float *)acc, S, C, T, splits);
         break;
     case CORR_FP32:
-        if (two) hipLaunchKernelGGL(xengine_f32_kernel<2>, grid, block, 0, st, (const float *)spec, (float *)acc, S, C, T, splits);
-        else hipLaunchKernelGGL(xengine_f32_kernel<1>, grid, block, 0, st, (const float *)spec, (float *)acc, S, C, T, splits);
+        if (two) hipLaunchKernelGGL((xengine_kernel<2, CORR_FP32, float>), grid, block, 0, st, sp8, (float *)acc, S, C, T, splits);
+        else hipLaunchKernelGGL((xengine_kernel<1, CORR_FP32, float>), grid, block, 0, st, sp8, (float *)acc, S, C, T, splits);
         break;
     default:
         return hipErrorInvalidValue;
