@@ -216,10 +216,13 @@ __device__ __forceinline__ uint32_t e4m3_rne_sat(float v) {
     return sign | code;
 }
 
-__device__ __forceinline__ uint32_t quant_i8(float v, float inv) {
-    float q = rintf(v * inv);
-    q = fminf(fmaxf(q, -127.0f), 127.0f);
-    return (uint32_t)((int32_t)q) & 0xFFu;
+// int8 code of an already-scaled value: clamp to [-127, 127] (integers, so the
+// clamp commutes with rounding), then add 1.5 * 2^23 -- the FP32 add rounds to
+// the nearest integer, ties to even, and leaves it in the low mantissa bits,
+// whose low byte is the two's-complement code.
+__device__ __forceinline__ uint32_t quant_i8(float v) {
+    const float c = fminf(fmaxf(v, -127.0f), 127.0f);
+    return __float_as_uint(c + 12582912.0f);  // only the low byte is used
 }
 
 // Logical workgroup id with consecutive ids on the same XCD (hardware hands
@@ -275,18 +278,21 @@ fengine_kernel(FLaunch a) {
     // per-thread channel constants, k_j = t + L j: FSTC ramp exp(2 pi i k f / N)
     // and the inverse requantisation scale
     float2 ramp[8];
-    float inv[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int k = t + L * j;
         // the post-process below forms 2 X[k]; the factor 1/2 is folded (exactly)
-        // into the ramp (FP32 output) or the inverse scale (requantised output)
+        // into the ramp
         if constexpr (MODE != 3) {
             float sn, cs;
             sincospif(2.0f * ((float)k * (g.frac / (float)N)), &sn, &cs);
-            ramp[j] = (MODE == 0) ? make_float2(0.5f * cs, 0.5f * sn) : make_float2(cs, sn);
+            ramp[j] = make_float2(0.5f * cs, 0.5f * sn);
         }
-        if constexpr (MODE == 1 || MODE == 2) inv[j] = 0.5f / a.scale[(int64_t)s * M + k];
+        // requantised output: the ramp also carries 1 / scale, so Y arrives scaled
+        if constexpr (MODE == 1 || MODE == 2) {
+            const float inv = 1.0f / a.scale[(int64_t)s * M + k];
+            ramp[j] = make_float2(ramp[j].x * inv, ramp[j].y * inv);
+        }
     }
 
     const uint32_t *row = reinterpret_cast<const uint32_t *>(a.x + (int64_t)s * a.row_stride);
@@ -400,11 +406,11 @@ fengine_kernel(FLaunch a) {
                 } else {
                     uint32_t qr, qi;
                     if constexpr (MODE == 1) {
-                        qr = quant_i8(Y.x, inv[j]);
-                        qi = quant_i8(Y.y, inv[j]);
+                        qr = quant_i8(Y.x);
+                        qi = quant_i8(Y.y);
                     } else {
-                        qr = e4m3_rne_sat(Y.x * inv[j]);
-                        qi = e4m3_rne_sat(Y.y * inv[j]);
+                        qr = e4m3_rne_sat(Y.x);
+                        qi = e4m3_rne_sat(Y.y);
                     }
                     // insert the byte of spectrum r into the current dword (the other
                     // bytes are overwritten by the next spectra before they are used)
