@@ -35,7 +35,30 @@ CONFIGS = {
 HBM_PEAK = 8.0e12           # B/s
 INT8_PEAK = 5.0e15          # dense int8 MFMA OP/s
 FP32_MFMA_PEAK = 157.3e12   # dense FP32 matrix FLOP/s
-FP32_VALU_PEAK = 157.3e12   # FP32 vector FLOP/s (datasheet, packed); 78.6e12 unpacked
+# FP32 vector peak without packed-FP32 instructions (which this library never
+# emits): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.  The 157.3
+# TFLOP/s datasheet figure assumes two FP32 FMAs per lane per cycle (packed).
+FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the
+# calibration copy, see profiles/), valid only for the kernel source they were
+# taken from: reported as `traffic` when the source hash still matches.
+MEASURED_TRAFFIC = {
+    "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine.hip", "sha256": None,
+                        "read": None, "write": None},
+}
+
+
+def measured_traffic(key):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(key)
+    if not rec or not rec["sha256"]:
+        return None
+    try:
+        h = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return rec["read"] + rec["write"] if h == rec["sha256"] else None
 
 
 def log(*a):
@@ -205,24 +228,25 @@ def main():
     }
     # dominant kernel of the int8 step and its roofline
     tf, tx = r8["t_f"], r8["t_x"]
-    f_alu_frac = ff8 / tf / FP32_VALU_PEAK
-    f_hbm_frac = fb8 / tf / HBM_PEAK
+    x_part = {"kernel": "xengine_kernel<2, 1> (int8 MFMA X-engine)", "bound": "hbm",
+              "achieved_gbs": round(xin8 / tx / 1e9, 1), "hbm_frac": round(xin8 / tx / HBM_PEAK, 4),
+              "mfma_frac_algorithmic": round(xops8 / tx / INT8_PEAK, 4)}
+    f_part = {"kernel": "fengine_kernel<log2M, 1> (int8 F-engine)",
+              "alu_tflops": round(ff8 / tf / 1e12, 3), "alu_frac": round(ff8 / tf / FP32_VALU_PEAK, 4),
+              "hbm_gbs": round(fb8 / tf / 1e9, 1), "hbm_frac": round(fb8 / tf / HBM_PEAK, 4)}
     if tf >= tx:
         bound = "alu" if ff8 / FP32_VALU_PEAK > fb8 / HBM_PEAK else "hbm"
         if bound == "alu":
             ach, peak, unit = ff8 / tf / 1e12, FP32_VALU_PEAK / 1e12, "TFLOP/s"
         else:
             ach, peak, unit = fb8 / tf / 1e9, HBM_PEAK / 1e9, "GB/s"
-        kern = "fengine_kernel (int8 requantising F-engine)"
+        kern, traffic = f_part["kernel"], measured_traffic("fengine_int8_%s" % args.config)
     else:
         bound, ach, peak, unit = "hbm", xin8 / tx / 1e9, HBM_PEAK / 1e9, "GB/s"
-        kern = "xengine_i8_kernel"
-    out["roofline"] = {"kernel": kern, "bound": bound, "achieved": round(ach, 3), "peak": peak,
-                       "unit": unit, "frac": round(ach / peak, 4), "traffic": None,
-                       "f_engine": {"alu_frac_vs_157TF": round(f_alu_frac, 4),
-                                    "hbm_frac": round(f_hbm_frac, 4)},
-                       "x_engine": {"hbm_frac": round(xin8 / tx / HBM_PEAK, 4),
-                                    "mfma_frac_algorithmic": round(xops8 / tx / INT8_PEAK, 4)}}
+        kern, traffic = x_part["kernel"], None
+    out["roofline"] = {"kernel": kern, "bound": bound, "achieved": round(ach, 3), "peak": round(peak, 2),
+                       "unit": unit, "frac": round(ach / peak, 4), "traffic": traffic,
+                       "f_engine": f_part, "x_engine": x_part}
     if r32:
         xops32, xin32 = x_algorithmic(S, N, T, 8)
         out["fp32"] = {"correlated_bandwidth_mhz": round(bw(r32["t_step"]), 3),

@@ -158,11 +158,14 @@ corr_status corr_plan_bind_workspace(corr_plan_t *plan, void *d_ws, size_t bytes
  *              written (scale = 4 sigma / 127 or 4 sigma / 448, sigma the RMS
  *              of one component of Y over this call) in COMPUTE mode.
  *              Unused (may be NULL) for FP32.
+ *   d_power    optional (NULL: not written) FP32 power |X|^2 of every cell,
+ *              [S][T][C] -- the dynamic spectra the flaggers below read
+ *              (corr_plan_power_bytes).
  * Errors: NULL, ALIGN, INVALID (row_stride), WORKSPACE, DEVICE.
  */
 corr_status corr_fengine(corr_plan_t *plan, const int8_t *d_x, int64_t row_stride,
                          const corr_geom_t *d_geom, int64_t spectrum0, void *d_spec,
-                         float *d_scale, void *stream);
+                         float *d_scale, float *d_power, void *stream);
 
 /* Corner turn of externally produced spectra into the X layout above.
  *   d_in: [S][T][C][2] elements (float for FP32, int8 for INT8, e4m3 bytes
@@ -194,6 +197,40 @@ corr_status corr_xengine(corr_plan_t *plan, const void *d_spec, void *d_acc, voi
  */
 corr_status corr_integrate(corr_plan_t *plan, void *d_acc, const float *d_scale,
                            double *d_state, float *d_vis_out, uint32_t flags, void *stream);
+
+/* --------------------------------------------------------------- flagging */
+
+/* RFI flags from the MAD statistic of section 5 (Eq. 3: MAD = median
+ * |x - median(x)|; Eq. 4: flag when |x - median(x)| > M MAD / 0.6745), taken
+ * per signal on tiles of 64 spectra x 256 channels of d_power: the row
+ * statistic (mean power of a spectrum over the tile's channels) exposes
+ * broadband bursts, the column statistic (mean power of a channel over the
+ * tile's spectra) persistent tones; a cell is flagged (1) when its row or its
+ * column is.  Median of an even count = mean of the two middle values.
+ *   d_flags  [S][T][C] uint8 (corr_plan_flags_bytes).
+ * Needs T % 64 == 0 (C = N/2 >= 256 is always a multiple of 256).
+ * Errors: NULL, ALIGN, INVALID (shape, M <= 0), DEVICE. */
+corr_status corr_mad_flag(corr_plan_t *plan, const float *d_power, float M, uint8_t *d_flags,
+                          void *stream);
+
+/* Zero the flagged cells of X-layout spectra in place (both components), and
+ * optionally (d_keep != NULL) write bit-packed keep masks [C][S][T/32] uint32
+ * (bit i of word w = spectrum 32 w + i not flagged; corr_plan_keep_bytes).
+ * d_flags may come from corr_mad_flag or from any other flagger.
+ * Errors: NULL, ALIGN, DEVICE. */
+corr_status corr_apply_flags(corr_plan_t *plan, const uint8_t *d_flags, void *d_spec,
+                             uint32_t *d_keep, void *stream);
+
+/* d_counts[k][p] += n_ij[k] = sum_m (1 - F_i[m,k]) (1 - F_j[m,k]): the number
+ * of spectra in which neither signal of pair p was flagged (int32 [C][P],
+ * exact; zero it before the first call).  Divide an integrated visibility by
+ * it for a flag-corrected mean.  Errors: NULL, ALIGN, WORKSPACE, DEVICE. */
+corr_status corr_pair_counts(corr_plan_t *plan, const uint32_t *d_keep, int32_t *d_counts,
+                             void *stream);
+
+size_t corr_plan_power_bytes(const corr_plan_t *plan);
+size_t corr_plan_flags_bytes(const corr_plan_t *plan);
+size_t corr_plan_keep_bytes(const corr_plan_t *plan);
 
 /* ------------------------------------------------------------------ misc */
 

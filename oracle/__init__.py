@@ -63,6 +63,9 @@ def _load():
     lib.orc_median.restype = dbl
     lib.orc_mad_flags.argtypes = [P, i64, dbl, P, P, P]
     lib.orc_mad_flags.restype = i64
+    lib.orc_mad_tile_flags.argtypes = [P, i32, i64, i64, i32, i32, dbl, P]
+    lib.orc_mad_tile_flags.restype = i32
+    lib.orc_pair_counts.argtypes = [P, i32, i64, i64, P]
     _lib = lib
     return lib
 
@@ -277,6 +280,35 @@ def mad_flags(x, M: float = 3.0):
     mad = ctypes.c_double()
     _load().orc_mad_flags(_p(x), x.size, M, _p(fl), ctypes.byref(med), ctypes.byref(mad))
     return fl, med.value, mad.value
+
+
+def power(Y: np.ndarray) -> np.ndarray:
+    """|Y|^2 of F-engine spectra [S][T][C] (FP64)."""
+    return np.abs(np.asarray(Y)) ** 2
+
+
+def mad_tile_flags(pw: np.ndarray, M: float = 3.0, TT: int = 64, KT: int = 256) -> np.ndarray:
+    """Eq. 3 / Eq. 4 on TT x KT power tiles (row and column statistics); flags [S][T][C] uint8."""
+    pw = np.ascontiguousarray(pw, dtype=np.float64)
+    S, T, C = pw.shape
+    fl = np.empty((S, T, C), dtype=np.uint8)
+    if _load().orc_mad_tile_flags(_p(pw), S, T, C, TT, KT, M, _p(fl)) != 0:
+        raise ValueError("T must be a multiple of %d and C of %d" % (TT, KT))
+    return fl
+
+
+def pair_counts(flags: np.ndarray) -> np.ndarray:
+    """n_ij[k] = number of spectra where neither signal is flagged; int64 [C][P]."""
+    fl = np.ascontiguousarray(flags, dtype=np.uint8)
+    S, T, C = fl.shape
+    n = np.zeros((C, n_pairs(S)), dtype=np.int64)
+    _load().orc_pair_counts(_p(fl), S, T, C, _p(n))
+    return n
+
+
+def apply_flags(Y: np.ndarray, flags: np.ndarray) -> np.ndarray:
+    """Zero flagged cells (the north-star's "flagged samples are zeroed")."""
+    return np.where(np.asarray(flags) != 0, 0, Y)
 
 
 # ---------------------------------------------------------------------------

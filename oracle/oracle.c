@@ -416,3 +416,67 @@ int64_t orc_mad_flags(const double *x, int64_t n, double M, uint8_t *flags,
     if (mad_out) *mad_out = mad;
     return cnt;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Flagging on dynamic spectra (section 5: MAD statistic of Eq. 3 / Eq. 4).   */
+/*                                                                            */
+/* The paper blanks time-domain voltages; on the channelised path the same    */
+/* statistic is taken on power tiles of TT spectra x KT channels of one       */
+/* signal: per tile, the row statistic (mean power of a spectrum over the     */
+/* tile's channels, which exposes broadband bursts) and the column statistic  */
+/* (mean power of a channel over the tile's spectra, which exposes persistent */
+/* tones) are each thresholded with Eq. 4, and a cell is flagged when its row */
+/* or its column is.  power layout [S][T][C]; flags layout [S][T][C] (0/1).   */
+/* T must be a multiple of TT and C of KT.                                    */
+/* ------------------------------------------------------------------------ */
+int orc_mad_tile_flags(const double *power, int S, int64_t T, int64_t C, int TT,
+                       int KT, double M, uint8_t *flags)
+{
+    if (T % TT || C % KT) return -1;
+    double *row = (double *)malloc(sizeof(double) * (size_t)TT);
+    double *col = (double *)malloc(sizeof(double) * (size_t)KT);
+    uint8_t *rf = (uint8_t *)malloc((size_t)TT);
+    uint8_t *cf = (uint8_t *)malloc((size_t)KT);
+    for (int s = 0; s < S; ++s)
+        for (int64_t m0 = 0; m0 < T; m0 += TT)
+            for (int64_t k0 = 0; k0 < C; k0 += KT) {
+                for (int r = 0; r < TT; ++r) {
+                    double acc = 0;
+                    for (int k = 0; k < KT; ++k)
+                        acc += power[((int64_t)s * T + m0 + r) * C + k0 + k];
+                    row[r] = acc / KT;
+                }
+                for (int k = 0; k < KT; ++k) {
+                    double acc = 0;
+                    for (int r = 0; r < TT; ++r)
+                        acc += power[((int64_t)s * T + m0 + r) * C + k0 + k];
+                    col[k] = acc / TT;
+                }
+                orc_mad_flags(row, TT, M, rf, NULL, NULL);
+                orc_mad_flags(col, KT, M, cf, NULL, NULL);
+                for (int r = 0; r < TT; ++r)
+                    for (int k = 0; k < KT; ++k)
+                        flags[((int64_t)s * T + m0 + r) * C + k0 + k] = rf[r] | cf[k];
+            }
+    free(row);
+    free(col);
+    free(rf);
+    free(cf);
+    return 0;
+}
+
+/* Unflagged-product counts: n_ij[k] = sum_m (1 - F_i[m,k]) (1 - F_j[m,k]) for
+ * every pair i <= j (p = j(j+1)/2 + i).  flags [S][T][C]; n [C][P] (+=). */
+void orc_pair_counts(const uint8_t *flags, int S, int64_t T, int64_t C, int64_t *n)
+{
+    int64_t P = (int64_t)S * (S + 1) / 2;
+    for (int64_t k = 0; k < C; ++k)
+        for (int j = 0; j < S; ++j)
+            for (int i = 0; i <= j; ++i) {
+                int64_t cnt = 0;
+                for (int64_t m = 0; m < T; ++m)
+                    cnt += (flags[((int64_t)i * T + m) * C + k] == 0) &&
+                           (flags[((int64_t)j * T + m) * C + k] == 0);
+                n[k * P + (int64_t)j * (j + 1) / 2 + i] += cnt;
+            }
+}

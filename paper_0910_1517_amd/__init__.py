@@ -61,6 +61,8 @@ SYMBOLS = [
     "corr_plan_acc_bytes", "corr_plan_state_bytes", "corr_plan_vis_bytes", "corr_plan_x_splits",
     "corr_plan_bind_workspace", "corr_fengine", "corr_xpack", "corr_xengine", "corr_integrate",
     "corr_check_device_errors", "corr_status_string", "corr_last_error",
+    "corr_mad_flag", "corr_apply_flags", "corr_pair_counts", "corr_plan_power_bytes",
+    "corr_plan_flags_bytes", "corr_plan_keep_bytes",
 ]
 
 
@@ -77,7 +79,7 @@ def lib():
     L.corr_plan_create.restype = st
     L.corr_plan_destroy.argtypes = [P]
     L.corr_plan_destroy.restype = None
-    for n in ("workspace", "spectra", "acc", "state", "vis"):
+    for n in ("workspace", "spectra", "acc", "state", "vis", "power", "flags", "keep"):
         f = getattr(L, "corr_plan_%s_bytes" % n)
         f.argtypes = [P]
         f.restype = sz
@@ -85,7 +87,13 @@ def lib():
     L.corr_plan_x_splits.restype = ctypes.c_int32
     L.corr_plan_bind_workspace.argtypes = [P, P, sz, P]
     L.corr_plan_bind_workspace.restype = st
-    L.corr_fengine.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, P, P]
+    L.corr_fengine.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P]
+    L.corr_mad_flag.argtypes = [P, P, ctypes.c_float, P, P]
+    L.corr_mad_flag.restype = st
+    L.corr_apply_flags.argtypes = [P, P, P, P, P]
+    L.corr_apply_flags.restype = st
+    L.corr_pair_counts.argtypes = [P, P, P, P]
+    L.corr_pair_counts.restype = st
     L.corr_fengine.restype = st
     L.corr_xpack.argtypes = [P, P, P, P]
     L.corr_xpack.restype = st
@@ -182,17 +190,27 @@ class Plan:
         import torch
         n = self._size(what)
         dt = {"spectra": torch.uint8, "acc": torch.int32 if self.precision == INT8 else torch.float32,
-              "state": torch.float64, "vis": torch.float32}[what]
+              "state": torch.float64, "vis": torch.float32, "power": torch.float32,
+              "flags": torch.uint8, "keep": torch.int32}[what]
         el = torch.tensor([], dtype=dt).element_size()
         f = torch.zeros if zero else torch.empty
         return f(n // el, dtype=dt, device=device or "cuda")
 
     # ---------------------------------------------------------------- calls
-    def fengine(self, x, geom, spec, scale=None, *, row_stride=None, spectrum0=0, stream=None):
+    def fengine(self, x, geom, spec, scale=None, *, power=None, row_stride=None, spectrum0=0, stream=None):
         """x: int8 device tensor [S][row_stride]; geom: uint8 device tensor holding corr_geom_t[S]."""
         rs = x.stride(0) if row_stride is None else row_stride
         self._check(lib().corr_fengine(self._h, _ptr(x), rs, _ptr(geom), spectrum0, _ptr(spec),
-                                       _ptr(scale), _stream(stream)))
+                                       _ptr(scale), _ptr(power), _stream(stream)))
+
+    def mad_flag(self, power, flags, M=3.0, stream=None):
+        self._check(lib().corr_mad_flag(self._h, _ptr(power), M, _ptr(flags), _stream(stream)))
+
+    def apply_flags(self, flags, spec, keep=None, stream=None):
+        self._check(lib().corr_apply_flags(self._h, _ptr(flags), _ptr(spec), _ptr(keep), _stream(stream)))
+
+    def pair_counts(self, keep, counts, stream=None):
+        self._check(lib().corr_pair_counts(self._h, _ptr(keep), _ptr(counts), _stream(stream)))
 
     def xpack(self, inp, spec, stream=None):
         self._check(lib().corr_xpack(self._h, _ptr(inp), _ptr(spec), _stream(stream)))

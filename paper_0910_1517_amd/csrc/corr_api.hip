@@ -201,7 +201,7 @@ corr_status corr_plan_bind_workspace(corr_plan_t *p, void *d_ws, size_t bytes, v
 }
 
 corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, const corr_geom_t *d_geom,
-                         int64_t spectrum0, void *d_spec, float *d_scale, void *stream) {
+                         int64_t spectrum0, void *d_spec, float *d_scale, float *d_power, void *stream) {
     if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
     if (!d_x || !d_geom || !d_spec) return fail(p, CORR_ERR_NULL, "d_x, d_geom and d_spec are required");
     const bool q8 = p->d.precision != CORR_FP32;
@@ -211,6 +211,7 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
     if (!aligned(d_geom, 8)) return fail(p, CORR_ERR_ALIGN, "d_geom must be 8-byte aligned");
     if (!aligned(d_spec, 256)) return fail(p, CORR_ERR_ALIGN, "d_spec must be 256-byte aligned");
     if (d_scale && !aligned(d_scale, 4)) return fail(p, CORR_ERR_ALIGN, "d_scale must be 4-byte aligned");
+    if (d_power && !aligned(d_power, 4)) return fail(p, CORR_ERR_ALIGN, "d_power must be 4-byte aligned");
     const int64_t need = (int64_t)p->d.fft_len * p->d.n_spectra + p->d.max_delay;
     if (row_stride < need)
         return fail(p, CORR_ERR_INVALID, "row_stride %lld < T*N + max_delay = %lld", (long long)row_stride,
@@ -225,6 +226,7 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
     a.spec = d_spec;
     a.scale = d_scale;
     a.part = reinterpret_cast<float *>(p->d_ws + p->ws.part);
+    a.power = d_power;
     a.twp = reinterpret_cast<const float2 *>(p->d_ws + p->ws.twp);
     a.wn = reinterpret_cast<const float2 *>(p->d_ws + p->ws.wn);
     a.err = reinterpret_cast<uint32_t *>(p->d_ws + p->ws.err);
@@ -237,10 +239,12 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (q8 && p->d.scale_mode == CORR_SCALE_COMPUTE) {
+        a.power = nullptr;
         if ((e = launch_fengine(p->log2m, 3, a, st)) != hipSuccess) return hip_fail(p, e, "calibration pass");
         if ((e = launch_calib_reduce(a.part, a.S, p->M, a.T / 16, a.T, p->d.precision, d_scale, st)) != hipSuccess)
             return hip_fail(p, e, "calibration reduce");
     }
+    a.power = d_power;
     const int mode = p->d.precision == CORR_FP32 ? 0 : (p->d.precision == CORR_INT8 ? 1 : 2);
     if ((e = launch_fengine(p->log2m, mode, a, st)) != hipSuccess) return hip_fail(p, e, "F-engine launch");
     return CORR_OK;
@@ -289,6 +293,49 @@ corr_status corr_integrate(corr_plan_t *p, void *d_acc, const float *d_scale, do
     p->acc_spectra = 0;
     p->x_calls = 0;
     return CORR_OK;
+}
+
+corr_status corr_mad_flag(corr_plan_t *p, const float *d_power, float M, uint8_t *d_flags, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_power || !d_flags) return fail(p, CORR_ERR_NULL, "d_power and d_flags are required");
+    if (!aligned(d_power, 4)) return fail(p, CORR_ERR_ALIGN, "d_power must be 4-byte aligned");
+    if (p->d.n_spectra % kFlagTileSpectra || p->M % kFlagTileChannels)
+        return fail(p, CORR_ERR_INVALID, "flagging needs T %% %d == 0 and C %% %d == 0", kFlagTileSpectra,
+                    kFlagTileChannels);
+    if (!(M > 0) || !std::isfinite(M)) return fail(p, CORR_ERR_INVALID, "threshold M must be finite and > 0");
+    hipError_t e = launch_mad_flag(d_power, p->d.n_signals, (int)p->d.n_spectra, p->M, M, d_flags,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? CORR_OK : hip_fail(p, e, "MAD flag launch");
+}
+
+corr_status corr_apply_flags(corr_plan_t *p, const uint8_t *d_flags, void *d_spec, uint32_t *d_keep, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_flags || !d_spec) return fail(p, CORR_ERR_NULL, "d_flags and d_spec are required");
+    if (!aligned(d_spec, 256) || (d_keep && !aligned(d_keep, 4)))
+        return fail(p, CORR_ERR_ALIGN, "d_spec 256 B / d_keep 4 B alignment");
+    hipError_t e = launch_apply_flags(p->d.precision, d_flags, d_spec, d_keep, p->d.n_signals,
+                                      (int)p->d.n_spectra, p->M, (hipStream_t)stream);
+    return e == hipSuccess ? CORR_OK : hip_fail(p, e, "apply-flags launch");
+}
+
+corr_status corr_pair_counts(corr_plan_t *p, const uint32_t *d_keep, int32_t *d_counts, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_keep || !d_counts) return fail(p, CORR_ERR_NULL, "d_keep and d_counts are required");
+    if (!p->bound) return fail(p, CORR_ERR_WORKSPACE, "no workspace bound");
+    if (!aligned(d_keep, 4) || !aligned(d_counts, 4)) return fail(p, CORR_ERR_ALIGN, "4-byte alignment");
+    hipError_t e = launch_pair_counts(d_keep, reinterpret_cast<const uint16_t *>(p->d_ws + p->ws.pairs),
+                                      p->d.n_signals, (int)p->d.n_spectra, p->M, d_counts, (hipStream_t)stream);
+    return e == hipSuccess ? CORR_OK : hip_fail(p, e, "pair-count launch");
+}
+
+size_t corr_plan_flags_bytes(const corr_plan_t *p) {
+    return p ? (size_t)p->d.n_signals * p->d.n_spectra * p->M : 0;
+}
+size_t corr_plan_keep_bytes(const corr_plan_t *p) {
+    return p ? (size_t)p->M * p->d.n_signals * (p->d.n_spectra / 32) * 4 : 0;
+}
+size_t corr_plan_power_bytes(const corr_plan_t *p) {
+    return p ? (size_t)p->d.n_signals * p->d.n_spectra * p->M * 4 : 0;
 }
 
 corr_status corr_check_device_errors(corr_plan_t *p, void *stream) {

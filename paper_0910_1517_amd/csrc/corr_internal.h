@@ -17,6 +17,9 @@ constexpr int kMaxSignals = 64;
 // Spectra per 16-byte X-layout chunk: 8 for the 8-bit precisions, 2 for FP32.
 constexpr int kChunk8 = 8;
 constexpr int kChunk32 = 2;
+// MAD flagging tiles: spectra x channels.
+constexpr int kFlagTileSpectra = 64;
+constexpr int kFlagTileChannels = 256;
 // int32 accumulator bound: 2 * 127^2 * T <= 2^31 - 1.
 constexpr int64_t kMaxInt8Spectra = 66572;
 
@@ -38,6 +41,7 @@ struct FLaunch {
     void *spec;
     const float *scale;  // HOLD-mode scales [S][C]
     float *part;         // calibration partials
+    float *power;        // optional |X|^2 output [S][T][C] (nullptr: none)
     const float2 *twp;
     const float2 *wn;
     uint32_t *err;
@@ -64,6 +68,12 @@ hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int
                           int splits, hipStream_t st);
 hipError_t launch_xpack(int precision, const void *in, void *spec, int S, int C, int T,
                         hipStream_t st);
+
+hipError_t launch_mad_flag(const float *power, int S, int T, int C, float M, uint8_t *flags, hipStream_t st);
+hipError_t launch_apply_flags(int precision, const uint8_t *flags, void *spec, uint32_t *keep, int S, int T,
+                              int C, hipStream_t st);
+hipError_t launch_pair_counts(const uint32_t *keep, const uint16_t *pairs, int S, int T, int C, int32_t *counts,
+                              hipStream_t st);
 
 hipError_t launch_integrate(int precision, void *acc, const float *scale, double *state,
                             float *vis, const uint16_t *pairs, int S, int C, int splits,

@@ -393,6 +393,8 @@ fengine_kernel(FLaunch a) {
             if constexpr (MODE == 3) {
                 pacc[j] += X.x * X.x + X.y * X.y;
             } else {
+                if (a.power && active)  // |X|^2 = |2X|^2 / 4 (the phase rotation keeps it)
+                    a.power[((int64_t)s * a.T + m) * M + tt + L * j] = 0.25f * (X.x * X.x + X.y * X.y);
                 const float2 Y = cmul(cmul(X, ramp[j]), rot);
                 if constexpr (MODE == 0) {
                     if (r & 1) {

@@ -85,16 +85,77 @@ def _analytic_block(g: np.random.Generator, B: int) -> np.ndarray:
     return Z
 
 
+class RFI:
+    """Injected radio-frequency interference (added before rounding and clipping).
+
+    * narrowband persistent tones in a fraction ``tone_frac`` of the channels of
+      an N-point channelisation, at a random frequency inside the channel, each
+      with excess power k * mu in its channel (k ~ U[tone_k]), where
+      mu = N sigma_t^2 is the mean per-cell noise power; the same channels for
+      every signal, random phase per signal;
+    * broadband bursts per antenna (both polarisations): a burst starts in a
+      spectrum with probability ``burst_p``, lasts U{burst_len} spectra and adds
+      Gaussian noise of variance k * sigma_t^2 (k ~ U[burst_k]).
+    """
+
+    def __init__(self, N: int, seed: int = BASE_SEED, tone_frac: float = 0.05, tone_k=(20.0, 200.0),
+                 burst_p: float = 0.002, burst_k=(10.0, 100.0), burst_len=(1, 8)):
+        self.N, self.seed = N, seed
+        self.tone_frac, self.tone_k = tone_frac, tone_k
+        self.burst_p, self.burst_k, self.burst_len = burst_p, burst_k, burst_len
+
+    def tones(self):
+        """(channel, frequency in cycles/sample, excess power factor k) of every tone."""
+        g = rng(self.seed, 9, self.N)
+        C = self.N // 2
+        n = max(1, int(round(self.tone_frac * C)))
+        ch = np.sort(g.choice(np.arange(2, C - 1), size=n, replace=False))
+        freq = (ch + g.uniform(-0.5, 0.5, n)) / self.N
+        k = g.uniform(*self.tone_k, n)
+        return ch, freq, k
+
+    def bursts(self, n_ant: int, n_spec: int):
+        """list per antenna of (start spectrum, length, variance factor)."""
+        out = []
+        for a in range(n_ant):
+            g = rng(self.seed, 10, a)
+            starts = np.nonzero(g.random(n_spec) < self.burst_p)[0]
+            lens = g.integers(self.burst_len[0], self.burst_len[1] + 1, starts.size)
+            ks = g.uniform(*self.burst_k, starts.size)
+            out.append(list(zip(starts.tolist(), lens.tolist(), ks.tolist())))
+        return out
+
+    def signal(self, S: int, n_samples: int, sigma_t: float, n_pol: int = 2) -> np.ndarray:
+        """The RFI-only float signal [S][n_samples]."""
+        N = self.N
+        out = np.zeros((S, n_samples))
+        n = np.arange(n_samples)
+        ch, freq, k = self.tones()
+        for s in range(S):
+            ph = rng(self.seed, 11, s).uniform(0, 2 * np.pi, ch.size)
+            amp = 2.0 * sigma_t * np.sqrt(k / N)  # (A N / 2)^2 = k N sigma_t^2
+            for c in range(ch.size):
+                out[s] += amp[c] * np.cos(2 * np.pi * freq[c] * n + ph[c])
+        for a, bl in enumerate(self.bursts(S // n_pol, n_samples // N)):
+            for (m0, ln, kk) in bl:
+                lo, hi = m0 * N, min(n_samples, (m0 + ln) * N)
+                for pol in range(n_pol):
+                    s = a * n_pol + pol
+                    out[s, lo:hi] += sigma_t * np.sqrt(kk) * rng(self.seed, 12, s, m0).standard_normal(hi - lo)
+        return out
+
+
 def voltages(S: int, n_samples: int, geom: Geom, fs: float, *, seed: int = BASE_SEED,
              rho: float = 0.3, sigma_t: float = 12.0, sideband: int = 1, n_pol: int = 2,
              tone_bin: int | None = None, tone_N: int | None = None, tone_amp: float = 4.0,
              sources: list | None = None, noise: bool = True, block: int = 1 << 20,
-             mode: str = "physical", threads: int | None = None) -> np.ndarray:
+             mode: str = "physical", threads: int | None = None, rfi: RFI | None = None) -> np.ndarray:
     """int8 [S][n_samples] streams (see module docstring).
 
     sources: list of dicts {"power": p, "dD": per-signal extra delay (samples),
     "drate": per-signal extra fringe rate (Hz)}; default one source of power
-    rho at the phase centre.
+    rho at the phase centre.  rfi: interference added before rounding (physical
+    mode only).
     """
     if sources is None:
         sources = [{"power": rho}]
@@ -133,6 +194,10 @@ def voltages(S: int, n_samples: int, geom: Geom, fs: float, *, seed: int = BASE_
                 ph = 2 * np.pi * (tone_bin / tone_N) * (n - tau) \
                     - 2 * np.pi * sideband * (geom.psi0[s] + geom.rate[s] * t)
                 acc[s] += tone_amp * np.cos(ph)
+        if rfi is not None:
+            if b == 0:
+                rfi_sig = rfi.signal(S, n_samples, sigma_t, n_pol)
+            acc += rfi_sig[:, n0:n0 + nb]
         out[:, n0:n0 + nb] = np.clip(np.rint(acc), -127, 127).astype(np.int8)
     return out
 

@@ -82,9 +82,9 @@ def test_plan_sizes_and_calls_without_workspace():
         # data-path calls before a workspace is bound are rejected on the host, before
         # any launch (the placeholder pointer is never dereferenced)
         fake = ctypes.c_void_p(1 << 20)
-        assert L.corr_fengine(h, fake, 32768 * 4096 + 64, fake, 0, fake, fake, None) == -5
+        assert L.corr_fengine(h, fake, 32768 * 4096 + 64, fake, 0, fake, fake, None, None) == -5
         assert L.corr_integrate(h, fake, fake, fake, None, 0, None) == -5
-        assert L.corr_fengine(h, None, 0, fake, 0, fake, fake, None) == -2
+        assert L.corr_fengine(h, None, 0, fake, 0, fake, fake, None, None) == -2
     finally:
         L.corr_plan_destroy(h)
 

@@ -383,3 +383,54 @@ def test_error_metric_properties():
     assert oracle.normalized_error(V, V, S) == (0.0, 0.0)
     e_max, e_fro = oracle.normalized_error(V * (1 + 1e-6), V, S)
     assert 0.9e-6 < e_max <= 1.01e-6 and abs(e_fro - 1e-6) < 1e-9
+
+
+# ---------------------------------------------------------------- MAD tiles
+def test_mad_tile_flags_worked_example():
+    # constant power with one loud spectrum (row 5) and one loud channel (col 17):
+    # every other row mean and column mean is identical, so MAD = 0 and exactly
+    # row 5 and column 17 exceed Eq. 4's threshold (strict >).
+    pw = np.ones((1, 64, 256))
+    pw[0, 5, :] *= 10
+    pw[0, :, 17] *= 10
+    fl = oracle.mad_tile_flags(pw)
+    expect = np.zeros((64, 256), dtype=np.uint8)
+    expect[5, :] = 1
+    expect[:, 17] = 1
+    assert np.array_equal(fl[0], expect)
+
+
+def test_mad_tile_flags_outliers_in_noise_and_tiling():
+    g = np.random.default_rng(3)
+    pw = g.exponential(1.0, size=(2, 128, 512))
+    pw[1, 70:72, 256:512] += 50.0       # a 2-spectrum burst in the lower-right tile of signal 1
+    pw[0, :64, 300] += 40.0             # a tone in the upper-right tile of signal 0
+    fl = oracle.mad_tile_flags(pw)
+    assert fl[1, 70:72, 256:].all() and fl[0, :64, 300].all()
+    assert not fl[1, 70:72, :256].all()  # the burst's other tile is unaffected
+    assert not fl[0, 64:, 300].all()      # the tone only lives in the first tile
+
+
+def test_mad_tile_false_flag_rate_on_clean_power():
+    # Clean per-cell power is exponential; a row statistic averages 256 cells and a column
+    # statistic 64, both close to Gaussian, so each is flagged with probability close to
+    # 2(1 - Phi(3)) = 0.27% (skew of the means makes the upper tail a little heavier).
+    g = np.random.default_rng(4)
+    pw = g.exponential(1.0, size=(4, 64 * 40, 256))
+    fl = oracle.mad_tile_flags(pw)
+    rows = fl.all(axis=2).mean()     # a flagged row flags its whole tile width
+    p = math.erfc(3 / math.sqrt(2))
+    assert 0.3 * p < rows < 3 * p
+    cols = fl.reshape(4, 40, 64, 256).all(axis=2).mean()
+    assert 0.3 * p < cols < 4 * p
+
+
+def test_pair_counts_brute_force():
+    g = np.random.default_rng(5)
+    fl = (g.random((3, 40, 4)) < 0.3).astype(np.uint8)
+    n = oracle.pair_counts(fl)
+    for k in range(4):
+        for j in range(3):
+            for i in range(j + 1):
+                assert n[k, oracle.pair_index(i, j)] == sum(
+                    1 for m in range(40) if fl[i, m, k] == 0 and fl[j, m, k] == 0)
