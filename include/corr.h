@@ -232,6 +232,59 @@ size_t corr_plan_power_bytes(const corr_plan_t *plan);
 size_t corr_plan_flags_bytes(const corr_plan_t *plan);
 size_t corr_plan_keep_bytes(const corr_plan_t *plan);
 
+/* ------------------------------------------------------------------ batch */
+
+/* Several correlations of different shapes (the paper runs sub-arrays and
+ * modes side by side, and sizes each compute node's time slice to its
+ * capability, section 2.3.2) driven as one unit: the F-engines of the
+ * sub-arrays run concurrently on forked streams, one X-engine launch covers
+ * the tasks (channel block x split) of every sub-array, then each sub-array
+ * is integrated.  INT8 with held scales only; up to 8 sub-arrays, each with
+ * T <= 66572 (one integration per run).  The whole run can be captured once
+ * into a HIP graph and replayed with a single launch; geometry, scales and
+ * data are read from the recorded device pointers at every replay. */
+typedef struct corr_batch corr_batch_t;
+
+typedef struct {
+    const int8_t *x;         /* input rows, as corr_fengine                   */
+    int64_t row_stride;
+    const corr_geom_t *geom; /* corr_geom_t[S]                                */
+    int64_t spectrum0;
+    void *spec;              /* X-layout spectra (corr_plan_spectra_bytes)     */
+    float *scale;            /* held int8 scales [S][C]                        */
+    void *acc;               /* accumulator (corr_plan_acc_bytes), zeroed      */
+    double *state;           /* integrator state                               */
+    float *vis;              /* dump (NULL unless flags has CORR_DUMP)         */
+    uint32_t flags;          /* corr_integrate flags                           */
+} corr_batch_io_t;
+
+/* Errors: NULL, INVALID (count), UNSUPPORTED (non-INT8), DEVICE, NOMEM. */
+corr_status corr_batch_create(const corr_desc_t *descs, int n, corr_batch_t **out);
+void corr_batch_destroy(corr_batch_t *batch);
+/* Sub-plan i (owned by the batch): query its sizes and bind its workspace. */
+corr_plan_t *corr_batch_plan(corr_batch_t *batch, int i);
+/* Record the buffers of sub-array i.  Errors: NULL, INVALID, ALIGN, WORKSPACE. */
+corr_status corr_batch_set_io(corr_batch_t *batch, int i, const corr_batch_io_t *io);
+/* Enqueue one batch pass on `stream`.  Errors: STATE (missing io), DEVICE. */
+corr_status corr_batch_run(corr_batch_t *batch, void *stream);
+/* Capture corr_batch_run into a HIP graph (stream must be non-NULL).
+ * Errors: NULL, INVALID, STATE, DEVICE. */
+corr_status corr_batch_capture(corr_batch_t *batch, void *stream);
+/* Replay the captured graph.  Errors: STATE (not captured), DEVICE. */
+corr_status corr_batch_launch(corr_batch_t *batch, void *stream);
+const char *corr_batch_last_error(const corr_batch_t *batch);
+
+/* --------------------------------------------------------------- autotune */
+
+/* Time the X-engine of desc for every K-split 1, 2, 4, ..., 64 that divides
+ * T/32 and return the fastest in *best_split (its time in *best_ms when non-
+ * NULL); the split goes into corr_desc_t.x_split.  Uses caller scratch of
+ * corr_autotune_scratch_bytes(desc) (256-byte aligned; contents ignored) and
+ * synchronises `stream`.  Errors: NULL, ALIGN, WORKSPACE, INVALID, DEVICE. */
+size_t corr_autotune_scratch_bytes(const corr_desc_t *desc);
+corr_status corr_autotune_x_split(const corr_desc_t *desc, void *d_scratch, size_t bytes, void *stream,
+                                  int32_t *best_split, float *best_ms);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Synchronise `stream` and report (and clear) device-side argument errors:

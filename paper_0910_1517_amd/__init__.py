@@ -63,7 +63,17 @@ SYMBOLS = [
     "corr_check_device_errors", "corr_status_string", "corr_last_error",
     "corr_mad_flag", "corr_apply_flags", "corr_pair_counts", "corr_plan_power_bytes",
     "corr_plan_flags_bytes", "corr_plan_keep_bytes",
+    "corr_batch_create", "corr_batch_destroy", "corr_batch_plan", "corr_batch_set_io", "corr_batch_run",
+    "corr_batch_capture", "corr_batch_launch", "corr_batch_last_error",
+    "corr_autotune_scratch_bytes", "corr_autotune_x_split",
 ]
+
+
+class BatchIO(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("row_stride", ctypes.c_int64), ("geom", ctypes.c_void_p),
+                ("spectrum0", ctypes.c_int64), ("spec", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("acc", ctypes.c_void_p), ("state", ctypes.c_void_p), ("vis", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32)]
 
 
 def lib():
@@ -103,6 +113,25 @@ def lib():
     L.corr_integrate.restype = st
     L.corr_check_device_errors.argtypes = [P, P]
     L.corr_check_device_errors.restype = st
+    L.corr_batch_create.argtypes = [ctypes.POINTER(CorrDesc), ctypes.c_int, ctypes.POINTER(P)]
+    L.corr_batch_create.restype = st
+    L.corr_batch_destroy.argtypes = [P]
+    L.corr_batch_destroy.restype = None
+    L.corr_batch_plan.argtypes = [P, ctypes.c_int]
+    L.corr_batch_plan.restype = P
+    L.corr_batch_set_io.argtypes = [P, ctypes.c_int, ctypes.POINTER(BatchIO)]
+    L.corr_batch_set_io.restype = st
+    for n in ("run", "capture", "launch"):
+        f = getattr(L, "corr_batch_" + n)
+        f.argtypes = [P, P]
+        f.restype = st
+    L.corr_batch_last_error.argtypes = [P]
+    L.corr_batch_last_error.restype = ctypes.c_char_p
+    L.corr_autotune_scratch_bytes.argtypes = [ctypes.POINTER(CorrDesc)]
+    L.corr_autotune_scratch_bytes.restype = sz
+    L.corr_autotune_x_split.argtypes = [ctypes.POINTER(CorrDesc), P, sz, P, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_float)]
+    L.corr_autotune_x_split.restype = st
     L.corr_status_string.argtypes = [st]
     L.corr_status_string.restype = ctypes.c_char_p
     L.corr_last_error.argtypes = [P]
@@ -139,15 +168,19 @@ class Plan:
     def __init__(self, n_signals: int, fft_len: int, n_spectra: int, *, max_delay: int = 16,
                  precision: int = FP32, sideband: int = 1, scale_mode: int = SCALE_HOLD,
                  sample_rate: float = 66.666666e6, nu_bb: float = 0.0, x_split: int = 0,
-                 device=None, bind: bool = True):
+                 device=None, bind: bool = True, _handle=None):
         L = lib()
         self.desc = make_desc(n_signals, fft_len, n_spectra, max_delay=max_delay, precision=precision,
                               sideband=sideband, scale_mode=scale_mode, sample_rate=sample_rate,
                               nu_bb=nu_bb, x_split=x_split)
-        h = ctypes.c_void_p()
-        rc = L.corr_plan_create(ctypes.byref(self.desc), ctypes.byref(h))
-        if rc != 0:
-            raise CorrError(rc, L.corr_last_error(None).decode())
+        self._owned = _handle is None
+        if _handle is None:
+            h = ctypes.c_void_p()
+            rc = L.corr_plan_create(ctypes.byref(self.desc), ctypes.byref(h))
+            if rc != 0:
+                raise CorrError(rc, L.corr_last_error(None).decode())
+        else:
+            h = ctypes.c_void_p(_handle)
         self._h = h
         self.S, self.N, self.T = n_signals, fft_len, n_spectra
         self.C = fft_len // 2
@@ -227,7 +260,8 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().corr_plan_destroy(self._h)
+            if self._owned:
+                lib().corr_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -235,6 +269,112 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Several INT8 correlations of different shapes run as one unit (corr_batch_t):
+    concurrent F-engines, one X-engine launch over all sub-arrays, integration;
+    capturable into one HIP graph."""
+
+    def __init__(self, shapes, *, device=None, **common):
+        """shapes: list of dicts with n_signals, fft_len, n_spectra (and optional x_split)."""
+        L = lib()
+        self.descs = (CorrDesc * len(shapes))()
+        kw = dict(precision=INT8, scale_mode=SCALE_HOLD)
+        kw.update(common)
+        for i, sh in enumerate(shapes):
+            self.descs[i] = make_desc(sh["n_signals"], sh["fft_len"], sh["n_spectra"],
+                                      x_split=sh.get("x_split", 0), **kw)
+        h = ctypes.c_void_p()
+        rc = L.corr_batch_create(self.descs, len(shapes), ctypes.byref(h))
+        if rc != 0:
+            raise CorrError(rc, L.corr_last_error(None).decode())
+        self._h = h
+        self.plans = []
+        for i, sh in enumerate(shapes):
+            d = self.descs[i]
+            p = Plan(d.n_signals, d.fft_len, d.n_spectra, max_delay=d.max_delay, precision=d.precision,
+                     sideband=d.sideband, scale_mode=d.scale_mode, sample_rate=d.sample_rate, nu_bb=d.nu_bb,
+                     x_split=d.x_split, device=device, _handle=L.corr_batch_plan(h, i))
+            self.plans.append(p)
+        self._keep = {}
+
+    def _check(self, rc):
+        if rc != 0:
+            raise CorrError(rc, lib().corr_batch_last_error(self._h).decode())
+
+    def set_io(self, i, *, x, geom, spec, scale, acc, state, vis=None, flags=DUMP, row_stride=None, spectrum0=0):
+        io = BatchIO(_ptr(x), x.stride(0) if row_stride is None else row_stride, _ptr(geom), spectrum0,
+                     _ptr(spec), _ptr(scale), _ptr(acc), _ptr(state), _ptr(vis), flags)
+        self._keep[i] = (x, geom, spec, scale, acc, state, vis)  # keep the tensors alive
+        self._check(lib().corr_batch_set_io(self._h, i, ctypes.byref(io)))
+
+    def run(self, stream=None):
+        self._check(lib().corr_batch_run(self._h, _stream(stream)))
+
+    def capture(self, stream):
+        self._check(lib().corr_batch_capture(self._h, _stream(stream)))
+
+    def launch(self, stream=None):
+        self._check(lib().corr_batch_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for p in self.plans:
+                p.close()
+            lib().corr_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _autotune_cache_path():
+    base = os.environ.get("CORR_AUTOTUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_0910_1517_amd", "autotune.json")
+    return base
+
+
+def autotune_x_split(n_signals, fft_len, n_spectra, *, precision=INT8, cache=True, device=None):
+    """Fastest X-engine K-split for this shape, measured on the current GPU
+    (corr_autotune_x_split) and remembered in a JSON cache keyed by device
+    architecture and shape.  Returns (split, ms)."""
+    import json
+    import torch
+    arch = torch.cuda.get_device_properties(device or 0).gcnArchName.split(":")[0]
+    key = "%s|S%d|N%d|T%d|P%d" % (arch, n_signals, fft_len, n_spectra, precision)
+    path = _autotune_cache_path()
+    table = {}
+    if cache and os.path.exists(path):
+        try:
+            table = json.load(open(path))
+        except (OSError, ValueError):
+            table = {}
+    if cache and key in table:
+        return int(table[key]["split"]), float(table[key]["ms"])
+    L = lib()
+    d = make_desc(n_signals, fft_len, n_spectra, precision=precision)
+    nbytes = int(L.corr_autotune_scratch_bytes(ctypes.byref(d)))
+    if nbytes == 0:
+        raise CorrError(-1, L.corr_last_error(None).decode())
+    scratch = torch.zeros(nbytes, dtype=torch.uint8, device=device or "cuda")
+    best = ctypes.c_int32()
+    ms = ctypes.c_float()
+    rc = L.corr_autotune_x_split(ctypes.byref(d), _ptr(scratch), nbytes, _stream(None), ctypes.byref(best),
+                                 ctypes.byref(ms))
+    if rc != 0:
+        raise CorrError(rc, L.corr_last_error(None).decode())
+    del scratch
+    if cache:
+        table[key] = {"split": best.value, "ms": ms.value}
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        json.dump(table, open(tmp, "w"), indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return best.value, ms.value
 
 
 def geom_array(D, frac, psi0, rate) -> np.ndarray:

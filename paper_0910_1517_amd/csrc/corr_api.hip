@@ -338,6 +338,215 @@ size_t corr_plan_power_bytes(const corr_plan_t *p) {
     return p ? (size_t)p->d.n_signals * p->d.n_spectra * p->M * 4 : 0;
 }
 
+/* ------------------------------------------------------------------ batch */
+
+struct corr_batch {
+    int n = 0;
+    corr_plan *plans[kMaxBatch] = {};
+    corr_batch_io_t io[kMaxBatch] = {};
+    bool io_set[kMaxBatch] = {};
+    hipStream_t side[kMaxBatch] = {};
+    hipEvent_t fork = nullptr, done[kMaxBatch] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    char err[512] = {0};
+};
+
+namespace {
+corr_status bfail(corr_batch *b, corr_status st, const char *msg) {
+    std::snprintf(b ? b->err : g_create_err, 512, "%s", msg);
+    return st;
+}
+}  // namespace
+
+corr_status corr_batch_create(const corr_desc_t *descs, int n, corr_batch_t **out) {
+    if (!descs || !out) return fail(nullptr, CORR_ERR_NULL, "descs and out must be non-null");
+    *out = nullptr;
+    if (n < 1 || n > kMaxBatch) return fail(nullptr, CORR_ERR_INVALID, "batch size %d outside 1..%d", n, kMaxBatch);
+    for (int i = 0; i < n; ++i) {
+        if (descs[i].precision != CORR_INT8)
+            return fail(nullptr, CORR_ERR_UNSUPPORTED, "batched correlation is INT8 only (entry %d)", i);
+        if (descs[i].scale_mode != CORR_SCALE_HOLD)
+            return fail(nullptr, CORR_ERR_INVALID, "batched correlation needs held scales (entry %d)", i);
+    }
+    corr_batch *b = new (std::nothrow) corr_batch;
+    if (!b) return fail(nullptr, CORR_ERR_NOMEM, "batch allocation failed");
+    b->n = n;
+    for (int i = 0; i < n; ++i) {
+        corr_status st = corr_plan_create(&descs[i], &b->plans[i]);
+        if (st != CORR_OK) {
+            corr_batch_destroy(b);
+            return st;
+        }
+    }
+    hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        corr_batch_destroy(b);
+        return fail(nullptr, CORR_ERR_DEVICE, "batch streams/events: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return CORR_OK;
+}
+
+void corr_batch_destroy(corr_batch_t *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int i = 0; i < kMaxBatch; ++i) {
+        if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+        if (b->done[i]) (void)hipEventDestroy(b->done[i]);
+        corr_plan_destroy(b->plans[i]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    delete b;
+}
+
+corr_plan_t *corr_batch_plan(corr_batch_t *b, int i) { return (b && i >= 0 && i < b->n) ? b->plans[i] : nullptr; }
+
+const char *corr_batch_last_error(const corr_batch_t *b) { return b ? b->err : g_create_err; }
+
+corr_status corr_batch_set_io(corr_batch_t *b, int i, const corr_batch_io_t *io) {
+    if (!b || !io) return bfail(b, CORR_ERR_NULL, "batch and io must be non-null");
+    if (i < 0 || i >= b->n) return bfail(b, CORR_ERR_INVALID, "sub-array index out of range");
+    corr_plan *p = b->plans[i];
+    if (!io->x || !io->geom || !io->spec || !io->scale || !io->acc || !io->state)
+        return bfail(b, CORR_ERR_NULL, "x, geom, spec, scale, acc and state are required");
+    if ((io->flags & CORR_DUMP) && !io->vis) return bfail(b, CORR_ERR_NULL, "CORR_DUMP needs vis");
+    if (!p->bound) return bfail(b, CORR_ERR_WORKSPACE, "bind the sub-plan's workspace first");
+    if (!aligned(io->x, 16) || io->row_stride % 16 || !aligned(io->spec, 256) || !aligned(io->acc, 256) ||
+        !aligned(io->state, 16) || !aligned(io->geom, 8) || !aligned(io->scale, 4))
+        return bfail(b, CORR_ERR_ALIGN, "misaligned batch buffer");
+    if (io->row_stride < (int64_t)p->d.fft_len * p->d.n_spectra + p->d.max_delay)
+        return bfail(b, CORR_ERR_INVALID, "row_stride < T*N + max_delay");
+    b->io[i] = *io;
+    b->io_set[i] = true;
+    return CORR_OK;
+}
+
+corr_status corr_batch_run(corr_batch_t *b, void *stream) {
+    if (!b) return fail(nullptr, CORR_ERR_NULL, "batch is null");
+    for (int i = 0; i < b->n; ++i)
+        if (!b->io_set[i]) return bfail(b, CORR_ERR_STATE, "every sub-array needs corr_batch_set_io");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    // fork: the F-engines of the sub-arrays run concurrently on side streams
+    if ((e = hipEventRecord(b->fork, st)) != hipSuccess) return bfail(b, CORR_ERR_DEVICE, "fork record");
+    XBatchArgs xa{};
+    xa.n = b->n;
+    xa.first[0] = 0;
+    for (int i = 0; i < b->n; ++i) {
+        corr_plan *p = b->plans[i];
+        const corr_batch_io_t &io = b->io[i];
+        if ((e = hipStreamWaitEvent(b->side[i], b->fork, 0)) != hipSuccess)
+            return bfail(b, CORR_ERR_DEVICE, "fork wait");
+        corr_status cs = corr_fengine(p, io.x, io.row_stride, io.geom, io.spectrum0, io.spec, io.scale, nullptr,
+                                      b->side[i]);
+        if (cs != CORR_OK) return bfail(b, cs, p->err);
+        if ((e = hipEventRecord(b->done[i], b->side[i])) != hipSuccess) return bfail(b, CORR_ERR_DEVICE, "join record");
+        if ((e = hipStreamWaitEvent(st, b->done[i], 0)) != hipSuccess) return bfail(b, CORR_ERR_DEVICE, "join wait");
+        xa.cor[i] = XBatchEntry{io.spec, io.acc, p->d.n_signals, p->M, (int)p->d.n_spectra, p->splits};
+        xa.first[i + 1] = xa.first[i] + (p->M / 8) * p->splits;
+    }
+    // one X-engine launch over the tasks of every sub-array
+    if ((e = launch_xengine_batch(xa, st)) != hipSuccess) return bfail(b, CORR_ERR_DEVICE, hipGetErrorString(e));
+    for (int i = 0; i < b->n; ++i) {
+        corr_plan *p = b->plans[i];
+        const corr_batch_io_t &io = b->io[i];
+        if ((e = launch_integrate(CORR_INT8, io.acc, io.scale, io.state, io.vis,
+                                  reinterpret_cast<const uint16_t *>(p->d_ws + p->ws.pairs), p->d.n_signals, p->M,
+                                  p->splits, io.flags, st)) != hipSuccess)
+            return bfail(b, CORR_ERR_DEVICE, hipGetErrorString(e));
+    }
+    return CORR_OK;
+}
+
+corr_status corr_batch_capture(corr_batch_t *b, void *stream) {
+    if (!b) return fail(nullptr, CORR_ERR_NULL, "batch is null");
+    if (!stream) return bfail(b, CORR_ERR_INVALID, "graph capture needs a non-null stream");
+    hipStream_t st = (hipStream_t)stream;
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(b, CORR_ERR_DEVICE, hipGetErrorString(e));
+    corr_status cs = corr_batch_run(b, stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (cs != CORR_OK) { if (g) (void)hipGraphDestroy(g); return cs; }
+    if (e != hipSuccess) return bfail(b, CORR_ERR_DEVICE, hipGetErrorString(e));
+    b->graph = g;
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) return bfail(b, CORR_ERR_DEVICE, hipGetErrorString(e));
+    return CORR_OK;
+}
+
+corr_status corr_batch_launch(corr_batch_t *b, void *stream) {
+    if (!b) return fail(nullptr, CORR_ERR_NULL, "batch is null");
+    if (!b->exec) return bfail(b, CORR_ERR_STATE, "capture the batch first");
+    hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    return e == hipSuccess ? CORR_OK : bfail(b, CORR_ERR_DEVICE, hipGetErrorString(e));
+}
+
+/* -------------------------------------------------------------- autotune */
+
+size_t corr_autotune_scratch_bytes(const corr_desc_t *desc) {
+    corr_plan_t *p = nullptr;
+    if (!desc) return 0;
+    corr_desc_t d = *desc;
+    d.x_split = 64;  // the largest candidate sizes the accumulator
+    if (corr_plan_create(&d, &p) != CORR_OK) return 0;
+    const size_t n = round_up(corr_plan_spectra_bytes(p), 256) + (size_t)64 * p->M * p->P * 8;
+    corr_plan_destroy(p);
+    return n;
+}
+
+corr_status corr_autotune_x_split(const corr_desc_t *desc, void *d_scratch, size_t bytes, void *stream,
+                                  int32_t *best_split, float *best_ms) {
+    if (!desc || !d_scratch || !best_split) return fail(nullptr, CORR_ERR_NULL, "desc, scratch and best_split");
+    if (!aligned(d_scratch, 256)) return fail(nullptr, CORR_ERR_ALIGN, "scratch must be 256-byte aligned");
+    if (bytes < corr_autotune_scratch_bytes(desc)) return fail(nullptr, CORR_ERR_WORKSPACE, "scratch too small");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(nullptr, CORR_ERR_DEVICE, "autotune events");
+    const int64_t steps = desc->n_spectra / 32;
+    float best = 1e30f;
+    int bsplit = 1;
+    corr_status result = CORR_OK;
+    for (int cand = 1; cand <= 64 && cand <= steps; cand *= 2) {
+        if (steps % cand) continue;
+        corr_desc_t d = *desc;
+        d.x_split = cand;
+        corr_plan_t *p = nullptr;
+        if ((result = corr_plan_create(&d, &p)) != CORR_OK) break;
+        char *spec = (char *)d_scratch;
+        char *acc = spec + round_up(corr_plan_spectra_bytes(p), 256);
+        float ms = 0.f;
+        hipError_t e = hipSuccess;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // first run warms up
+            e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = launch_xengine(d.precision, spec, acc, d.n_signals, p->M, (int)d.n_spectra, p->splits, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (rep > 0) ms += t / 2;
+        }
+        corr_plan_destroy(p);
+        if (e != hipSuccess) { result = fail(nullptr, CORR_ERR_DEVICE, "autotune run: %s", hipGetErrorString(e)); break; }
+        if (ms < best) { best = ms; bsplit = cand; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != CORR_OK) return result;
+    *best_split = bsplit;
+    if (best_ms) *best_ms = best;
+    return CORR_OK;
+}
+
 corr_status corr_check_device_errors(corr_plan_t *p, void *stream) {
     if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
     if (!p->bound) return fail(p, CORR_ERR_WORKSPACE, "no workspace bound");

@@ -66,6 +66,20 @@ hipError_t launch_calib_reduce(const float *part, int S, int C, int nparts, int 
 
 hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int C, int T,
                           int splits, hipStream_t st);
+// Batched int8 X-engine: one entry per correlation; correlation i owns the
+// workgroups [first[i], first[i+1]), one per (channel block of 8, split).
+constexpr int kMaxBatch = 8;
+struct XBatchEntry {
+    const void *spec;
+    void *acc;
+    int S, C, T, splits;
+};
+struct XBatchArgs {
+    XBatchEntry cor[kMaxBatch];
+    int first[kMaxBatch + 1];
+    int n;
+};
+hipError_t launch_xengine_batch(const XBatchArgs &a, hipStream_t st);
 hipError_t launch_xpack(int precision, const void *in, void *spec, int S, int C, int T,
                         hipStream_t st);
 

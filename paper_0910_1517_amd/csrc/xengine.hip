@@ -94,13 +94,14 @@ constexpr int x_lds_bytes() {
     return (2 * 4 * kBlk > kXWaves * NT * NT * 32 * 33 * 4) ? 2 * 4 * kBlk : kXWaves * NT * NT * 32 * 33 * 4;
 }
 
-// PREC: CORR_FP32, CORR_INT8 or CORR_FP8_E4M3; ACC: float or int32_t
+// One (channel block kb, split sp) of one correlation: PREC is CORR_FP32,
+// CORR_INT8 or CORR_FP8_E4M3; ACC float or int32_t; lds holds at least
+// x_lds_bytes<NT>() bytes.
 template <int NT, int PREC, typename ACC>
-__global__ void __launch_bounds__(64 * kXWaves)
-xengine_kernel(const uint8_t *__restrict__ spec, ACC *acc, int S, int C, int T, int splits) {
+__device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, ACC *acc, int S, int C, int T,
+                                              int splits, int kb, int sp, uint8_t *lds) {
     using V16 = typename std::conditional<PREC == CORR_INT8, v16i, v16f>::type;
-    __shared__ __attribute__((aligned(16))) uint8_t lds[x_lds_bytes<NT>()];
-    const int kb = blockIdx.x, sp = blockIdx.y, wv = threadIdx.x >> 6, c = kXWaves * kb + wv;
+    const int wv = threadIdx.x >> 6, c = kXWaves * kb + wv;
     const int lane = threadIdx.x & 63, row = lane & 31, lg = lane >> 5;
     const int G = (PREC == CORR_FP32) ? kChunk32 : kChunk8;
     const int steps = T / G / 4 / splits;
@@ -230,6 +231,33 @@ xengine_kernel(const uint8_t *__restrict__ spec, ACC *acc, int S, int C, int T, 
     // the staging buffers are free now: the epilogue's M-tile exchange reuses them
     auto *mlds = reinterpret_cast<ACC(*)[32][33]>(lds + wv * NT * NT * 32 * 33 * 4);
     x_epilogue<NT, ACC>(accR, accM, acc + ((int64_t)sp * C + c) * P * 2, S, P, mlds);
+    __syncthreads();  // the LDS may be reused by the next block of a persistent loop
+}
+
+template <int NT, int PREC, typename ACC>
+__global__ void __launch_bounds__(64 * kXWaves)
+xengine_kernel(const uint8_t *__restrict__ spec, ACC *acc, int S, int C, int T, int splits) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[x_lds_bytes<NT>()];
+    xengine_block<NT, PREC, ACC>(spec, acc, S, C, T, splits, blockIdx.x, blockIdx.y, lds);
+}
+
+// One launch over the tasks of a batch of correlations of different shapes
+// (one per sub-array).  The batch table travels by value as the kernel
+// argument, so every field is a uniform scalar; workgroup b runs task b: the
+// correlation whose task range holds b, then its (channel block, split).  All
+// tasks use the two-tile body (signals beyond S are zero rows): a one-tile
+// variant in the same kernel would double its registers, and the sub-arrays
+// with S <= 32 are small and HBM-bound.
+__global__ void __launch_bounds__(64 * kXWaves) xengine_batch_kernel(XBatchArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[x_lds_bytes<2>()];
+    const int b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < a.n && b >= a.first[i + 1]) ++i;
+    const XBatchEntry &e = a.cor[i];
+    const int local = b - a.first[i];
+    const int nkb = e.C / kXWaves;
+    xengine_block<2, CORR_INT8, int32_t>((const uint8_t *)e.spec, (int32_t *)e.acc, e.S, e.C, e.T, e.splits,
+                                         local % nkb, local / nkb, lds);
 }
 
 // --------------------------------------------------------------- xpack ----
@@ -282,6 +310,12 @@ hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int
     default:
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_xengine_batch(const XBatchArgs &a, hipStream_t st) {
+    if (a.n < 1 || a.n > kMaxBatch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(xengine_batch_kernel, dim3(a.first[a.n]), dim3(64 * kXWaves), 0, st, a);
     return hipGetLastError();
 }
 
