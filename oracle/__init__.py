@@ -66,6 +66,8 @@ def _load():
     lib.orc_mad_tile_flags.argtypes = [P, i32, i64, i64, i32, i32, dbl, P]
     lib.orc_mad_tile_flags.restype = i32
     lib.orc_pair_counts.argtypes = [P, i32, i64, i64, P]
+    lib.orc_conv3x3_fwd.argtypes = [P, P, P, i32, i32, i32, i32, i32, P]
+    lib.orc_conv3x3_bwd.argtypes = [P, P, P, i32, i32, i32, i32, i32, P, P, P]
     _lib = lib
     return lib
 
@@ -309,6 +311,130 @@ def pair_counts(flags: np.ndarray) -> np.ndarray:
 def apply_flags(Y: np.ndarray, flags: np.ndarray) -> np.ndarray:
     """Zero flagged cells (the north-star's "flagged samples are zeroed")."""
     return np.where(np.asarray(flags) != 0, 0, Y)
+
+
+# ---------------------------------------------------------------------------
+# Learned flagger: conv3x3(1->16)-ReLU-conv3x3(16->16)-ReLU-conv3x3(16->1),
+# sigmoid, binary cross-entropy against MAD labels (FP64 reference)
+# ---------------------------------------------------------------------------
+CNN_SHAPES = [(16, 1), (16, 16), (1, 16)]  # (Cout, Cin) per layer
+
+
+def cnn_param_count() -> int:
+    return sum(o * i * 9 + o for o, i in CNN_SHAPES)
+
+
+def cnn_unpack(params):
+    """Flat parameter vector -> [(w [Cout][Cin][3][3], bias [Cout]) per layer]
+    (layout: layer by layer, weights then biases)."""
+    params = np.asarray(params, dtype=np.float64)
+    out, o0 = [], 0
+    for co, ci in CNN_SHAPES:
+        w = params[o0:o0 + co * ci * 9].reshape(co, ci, 3, 3)
+        o0 += co * ci * 9
+        b = params[o0:o0 + co]
+        o0 += co
+        out.append((np.ascontiguousarray(w), np.ascontiguousarray(b)))
+    return out
+
+
+def conv3x3(x, w, b):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    B, Ci, H, W = x.shape
+    Co = w.shape[0]
+    y = np.empty((B, Co, H, W))
+    _load().orc_conv3x3_fwd(_p(x), _p(np.ascontiguousarray(w, dtype=np.float64)),
+                            _p(np.ascontiguousarray(b, dtype=np.float64)), B, Ci, Co, H, W, _p(y))
+    return y
+
+
+def conv3x3_bwd(x, w, dy, need_dx=True):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    dy = np.ascontiguousarray(dy, dtype=np.float64)
+    B, Ci, H, W = x.shape
+    Co = w.shape[0]
+    dx = np.empty_like(x) if need_dx else None
+    dw = np.empty((Co, Ci, 3, 3))
+    db = np.empty(Co)
+    _load().orc_conv3x3_bwd(_p(x), _p(np.ascontiguousarray(w, dtype=np.float64)), _p(dy), B, Ci, Co, H, W,
+                            _p(dx) if need_dx else None, _p(dw), _p(db))
+    return dx, dw, db
+
+
+def cnn_forward(params, x):
+    """x [B][1][H][W] -> logits [B][1][H][W] and the intermediate values."""
+    (w1, b1), (w2, b2), (w3, b3) = cnn_unpack(params)
+    z1 = conv3x3(x, w1, b1)
+    a1 = np.maximum(z1, 0)
+    z2 = conv3x3(a1, w2, b2)
+    a2 = np.maximum(z2, 0)
+    z3 = conv3x3(a2, w3, b3)
+    return z3, (x, z1, a1, z2, a2)
+
+
+def bce_with_logits(z, y):
+    """Mean binary cross-entropy of sigmoid(z) against labels y, in the stable
+    form max(z, 0) - z y + log(1 + exp(-|z|))."""
+    z = np.asarray(z, dtype=np.float64)
+    return float(np.mean(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
+
+
+def cnn_loss_and_grad(params, x, y):
+    """Loss and its gradient with respect to the flat parameter vector (chain rule
+    through the three convolutions and the ReLUs)."""
+    z3, (x0, z1, a1, z2, a2) = cnn_forward(params, x)
+    loss = bce_with_logits(z3, y)
+    dz3 = (1.0 / (1.0 + np.exp(-z3)) - y) / z3.size
+    (w1, _), (w2, _), (w3, _) = cnn_unpack(params)
+    da2, dw3, db3 = conv3x3_bwd(a2, w3, dz3)
+    dz2 = da2 * (z2 > 0)
+    da1, dw2, db2 = conv3x3_bwd(a1, w2, dz2)
+    dz1 = da1 * (z1 > 0)
+    _, dw1, db1 = conv3x3_bwd(x0, w1, dz1, need_dx=False)
+    g = np.concatenate([dw1.ravel(), db1, dw2.ravel(), db2, dw3.ravel(), db3])
+    return loss, g
+
+
+def cnn_tile_input(power_tile):
+    """Network input of one 64 x 256 power tile: log(1 + P / m), m = median over the
+    tile's channels of the channel's mean power over the tile's spectra."""
+    P = np.asarray(power_tile, dtype=np.float64)
+    m = median(P.mean(axis=0))
+    return np.log1p(P / m)
+
+
+def adam_step(params, m, v, g, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8):
+    """One Adam update (Kingma & Ba 2015, Algorithm 1) at step t >= 1: biased
+    moments m, v, their bias corrections 1 - beta^t, and the step
+    lr * m_hat / (sqrt(v_hat) + eps).  Returns new (params, m, v)."""
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1 - beta2) * g * g
+    m_hat = m / (1 - beta1 ** t)
+    v_hat = v / (1 - beta2 ** t)
+    return np.asarray(params, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def cnn_tile_logits(params, power, TT: int = 64, KT: int = 256):
+    """Logits of the network on every TT x KT tile of power [S][T][C] (each tile
+    its own zero-padded image), same layout as power."""
+    P = np.asarray(power, dtype=np.float64)
+    S, T, C = P.shape
+    out = np.empty_like(P)
+    tiles = []
+    for s in range(S):
+        for mt in range(T // TT):
+            for kt in range(C // KT):
+                tiles.append(cnn_tile_input(P[s, mt * TT:(mt + 1) * TT, kt * KT:(kt + 1) * KT]))
+    z, _ = cnn_forward(params, np.stack(tiles)[:, None])
+    i = 0
+    for s in range(S):
+        for mt in range(T // TT):
+            for kt in range(C // KT):
+                out[s, mt * TT:(mt + 1) * TT, kt * KT:(kt + 1) * KT] = z[i, 0]
+                i += 1
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -480,3 +480,85 @@ void orc_pair_counts(const uint8_t *flags, int S, int64_t T, int64_t C, int64_t 
                 n[k * P + (int64_t)j * (j + 1) / 2 + i] += cnt;
             }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Learned flagger (the benchmark spec's addition; the paper only notes that      */
+/* better RFI filtering has scope, section 5): 3x3 convolutions with zero     */
+/* padding ("same" size), written from the definition of a 2-D               */
+/* cross-correlation:                                                         */
+/*   y[b][o][r][c] = bias[o] + sum_i sum_{u,v in -1..1}                       */
+/*                   w[o][i][u+1][v+1] * x[b][i][r+u][c+v]                     */
+/* (x outside the H x W tile is 0).  Layouts: x [B][Cin][H][W],               */
+/* w [Cout][Cin][3][3], y [B][Cout][H][W].                                    */
+/* ------------------------------------------------------------------------ */
+void orc_conv3x3_fwd(const double *x, const double *w, const double *bias, int B, int Cin,
+                     int Cout, int H, int W, double *y)
+{
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int b = 0; b < B; ++b)
+        for (int o = 0; o < Cout; ++o)
+            for (int r = 0; r < H; ++r)
+                for (int c = 0; c < W; ++c) {
+                    double acc = bias[o];
+                    for (int i = 0; i < Cin; ++i)
+                        for (int u = -1; u <= 1; ++u)
+                            for (int v = -1; v <= 1; ++v) {
+                                int rr = r + u, cc = c + v;
+                                if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
+                                acc += w[((o * Cin + i) * 3 + u + 1) * 3 + v + 1] *
+                                       x[(((int64_t)b * Cin + i) * H + rr) * W + cc];
+                            }
+                    y[(((int64_t)b * Cout + o) * H + r) * W + c] = acc;
+                }
+}
+
+/* Gradients of the convolution above from its definition (chain rule):
+ *   dx[b][i][r][c] = sum_o sum_{u,v} w[o][i][u+1][v+1] dy[b][o][r-u][c-v]
+ *   dw[o][i][u+1][v+1] = sum_{b,r,c} dy[b][o][r][c] x[b][i][r+u][c+v]
+ *   dbias[o] = sum_{b,r,c} dy[b][o][r][c]
+ * dx may be NULL. */
+void orc_conv3x3_bwd(const double *x, const double *w, const double *dy, int B, int Cin,
+                     int Cout, int H, int W, double *dx, double *dw, double *dbias)
+{
+    if (dx) {
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int b = 0; b < B; ++b)
+            for (int i = 0; i < Cin; ++i)
+                for (int r = 0; r < H; ++r)
+                    for (int c = 0; c < W; ++c) {
+                        double acc = 0;
+                        for (int o = 0; o < Cout; ++o)
+                            for (int u = -1; u <= 1; ++u)
+                                for (int v = -1; v <= 1; ++v) {
+                                    int rr = r - u, cc = c - v;
+                                    if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
+                                    acc += w[((o * Cin + i) * 3 + u + 1) * 3 + v + 1] *
+                                           dy[(((int64_t)b * Cout + o) * H + rr) * W + cc];
+                                }
+                        dx[(((int64_t)b * Cin + i) * H + r) * W + c] = acc;
+                    }
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int o = 0; o < Cout; ++o)
+        for (int i = 0; i < Cin; ++i)
+            for (int u = -1; u <= 1; ++u)
+                for (int v = -1; v <= 1; ++v) {
+                    double acc = 0;
+                    for (int b = 0; b < B; ++b)
+                        for (int r = 0; r < H; ++r)
+                            for (int c = 0; c < W; ++c) {
+                                int rr = r + u, cc = c + v;
+                                if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
+                                acc += dy[(((int64_t)b * Cout + o) * H + r) * W + c] *
+                                       x[(((int64_t)b * Cin + i) * H + rr) * W + cc];
+                            }
+                    dw[((o * Cin + i) * 3 + u + 1) * 3 + v + 1] = acc;
+                }
+    for (int o = 0; o < Cout; ++o) {
+        double acc = 0;
+        for (int b = 0; b < B; ++b)
+            for (int r = 0; r < H; ++r)
+                for (int c = 0; c < W; ++c) acc += dy[(((int64_t)b * Cout + o) * H + r) * W + c];
+        dbias[o] = acc;
+    }
+}
