@@ -57,6 +57,7 @@ typedef int32_t corr_status;
 #define CORR_ERR_NOMEM (-8)       /* host allocation failed                     */
 #define CORR_ERR_STATE (-9)       /* call sequence not allowed in this state    */
 #define CORR_ERR_DEVICE_ARG (-10) /* a device-resident argument was invalid     */
+#define CORR_ERR_IO (-11)         /* file could not be opened, read or written  */
 
 /* Arithmetic of the spectra handed from the F- to the X-engine. */
 #define CORR_FP32 0     /* complex64 spectra, FP32 MFMA X-engine                */
@@ -284,6 +285,99 @@ const char *corr_batch_last_error(const corr_batch_t *batch);
 size_t corr_autotune_scratch_bytes(const corr_desc_t *desc);
 corr_status corr_autotune_x_split(const corr_desc_t *desc, void *d_scratch, size_t bytes, void *stream,
                                   int32_t *best_split, float *best_ms);
+
+/* ---------------------------------------------------------- learned flagger */
+
+/* A convolutional RFI flagger trained on the GPU against the MAD flags above
+ * (the paper's MAD filter of section 5, Eq. 3 and Eq. 4, is the teacher; the
+ * paper itself notes that better filtering has room to improve).  It works on
+ * the same 64 x 256 (spectra x channels) tiles of one signal's power, each
+ * tile its own zero-padded image:
+ *   x  = log(1 + P / m), m = median over the tile's 256 channels of each
+ *        channel's mean power over the tile's 64 spectra (1 if not > 0)
+ *   z1 = conv3x3(x; 1 -> 16), a1 = ReLU(z1)
+ *   z2 = conv3x3(a1; 16 -> 16), a2 = ReLU(z2)
+ *   z3 = conv3x3(a2; 16 -> 1), the logit; a cell is flagged when
+ *        sigmoid(z3) > threshold
+ * conv3x3(a)[o][r][c] = b[o] + sum_{i,u,v} w[o][i][u][v] a[i][r+u-1][c+v-1]
+ * with a = 0 outside the tile.  Training minimises the mean binary
+ * cross-entropy of sigmoid(z3) against the labels with Adam (Kingma & Ba
+ * 2015, Algorithm 1).
+ *
+ * Parameters: CORR_CNN_PARAMS floats on the device, layer by layer, each
+ * layer's weights [Cout][Cin][3][3] then its biases [Cout].  Tiles of power
+ * [S][T][C] (T a multiple of 64, C of 256) are numbered
+ * tile = (s (T/64) + m/64) (C/256) + k/256.  The training calls work on a
+ * caller-chosen list of tile numbers (device int32[n_tiles], n_tiles <=
+ * max_tiles); an out-of-range number is recorded in the workspace (reported by
+ * corr_cnn_check_device_errors) and that tile reads as zeros. */
+#define CORR_CNN_PARAMS 2625
+
+typedef struct corr_cnn corr_cnn_t;
+
+typedef struct {
+    int32_t max_tiles; /* largest tile list of a training call, 1..4096    */
+    float lr;          /* Adam step size (> 0)                              */
+    float beta1;       /* Adam moment decay rates, in [0, 1)                */
+    float beta2;
+    float eps;         /* Adam denominator offset (> 0)                     */
+    int32_t reserved[7]; /* must be zero                                    */
+} corr_cnn_desc_t;
+
+/* Errors: NULL, INVALID, NOMEM. */
+corr_status corr_cnn_create(const corr_cnn_desc_t *desc, corr_cnn_t **out);
+void corr_cnn_destroy(corr_cnn_t *cnn);
+/* Training scratch: activations and gradients of max_tiles tiles (about
+ * 4.4 MB per tile).  Bind 256-byte-aligned device memory of at least this
+ * size before the training calls.  Errors: NULL, ALIGN, WORKSPACE. */
+size_t corr_cnn_workspace_bytes(const corr_cnn_t *cnn);
+corr_status corr_cnn_bind_workspace(corr_cnn_t *cnn, void *d_ws, size_t bytes);
+
+/* FP32 forward pass of the training path: logits [n_tiles][64][256] of the
+ * listed tiles of d_power.  Errors: NULL, ALIGN, INVALID, WORKSPACE, DEVICE. */
+corr_status corr_cnn_forward(corr_cnn_t *cnn, const float *d_params, const float *d_power, int32_t S, int64_t T,
+                             int32_t C, const int32_t *d_tiles, int32_t n_tiles, float *d_logits, void *stream);
+/* Mean BCE loss (d_loss, one float) and its gradient (d_grad, CORR_CNN_PARAMS
+ * floats; NULL: kept in the workspace) over the listed tiles, labels from
+ * d_labels [S][T][C] (0 = clean, nonzero = flagged).  Errors as above. */
+corr_status corr_cnn_loss_grad(corr_cnn_t *cnn, const float *d_params, const float *d_power,
+                               const uint8_t *d_labels, int32_t S, int64_t T, int32_t C, const int32_t *d_tiles,
+                               int32_t n_tiles, float *d_loss, float *d_grad, void *stream);
+/* One Adam update of d_params with moments d_m, d_v (CORR_CNN_PARAMS floats
+ * each, zero before step 1) at step number `step` >= 1, from d_grad (NULL: the
+ * gradient the last corr_cnn_loss_grad kept in the workspace).
+ * Errors: NULL, INVALID, WORKSPACE, DEVICE. */
+corr_status corr_cnn_adam(corr_cnn_t *cnn, float *d_params, float *d_m, float *d_v, const float *d_grad,
+                          int64_t step, void *stream);
+/* corr_cnn_loss_grad followed by corr_cnn_adam. */
+corr_status corr_cnn_train_step(corr_cnn_t *cnn, float *d_params, float *d_m, float *d_v, int64_t step,
+                                const float *d_power, const uint8_t *d_labels, int32_t S, int64_t T, int32_t C,
+                                const int32_t *d_tiles, int32_t n_tiles, float *d_loss, void *stream);
+/* Synchronise `stream`; CORR_ERR_DEVICE_ARG (and clear it) if a training call
+ * saw an out-of-range tile number.  Errors: WORKSPACE, DEVICE. */
+corr_status corr_cnn_check_device_errors(corr_cnn_t *cnn, void *stream);
+
+/* Inference over every tile of d_power [S][T][C]: d_flags [S][T][C] uint8
+ * (1 = flagged when sigmoid(z3) > threshold, 0 otherwise; ready for
+ * corr_apply_flags) and optionally the logits d_logits [S][T][C] (NULL: not
+ * written).  FP16 operands with FP32 accumulation on the matrix cores, so the
+ * logits differ from the FP32 path by about 1e-3 of their scale.  Needs no
+ * handle or workspace.  Errors: NULL, ALIGN, INVALID (shape, threshold not in
+ * (0, 1)), DEVICE; messages via corr_cnn_last_error(NULL). */
+corr_status corr_cnn_infer(const float *d_params, const float *d_power, int32_t S, int64_t T, int32_t C,
+                           float threshold, uint8_t *d_flags, float *d_logits, void *stream);
+
+/* Save / load parameters and Adam state (each d_* CORR_CNN_PARAMS floats;
+ * d_m and d_v may be NULL) to a little-endian binary file: magic "CORRCNN1",
+ * int64 step, int32 count, then params, m, v as float32.  Both synchronise the
+ * null stream.  Errors: NULL, IO (open / read / write), INVALID (not such a
+ * file, or another parameter count), DEVICE (copies). */
+corr_status corr_cnn_save(const char *path, const float *d_params, const float *d_m, const float *d_v,
+                          int64_t step);
+corr_status corr_cnn_load(const char *path, float *d_params, float *d_m, float *d_v, int64_t *step);
+
+/* Last error of the handle (or of handle-free calls when cnn is NULL). */
+const char *corr_cnn_last_error(const corr_cnn_t *cnn);
 
 /* ------------------------------------------------------------------ misc */
 

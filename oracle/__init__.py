@@ -397,9 +397,13 @@ def cnn_loss_and_grad(params, x, y):
 
 def cnn_tile_input(power_tile):
     """Network input of one 64 x 256 power tile: log(1 + P / m), m = median over the
-    tile's channels of the channel's mean power over the tile's spectra."""
+    tile's channels of the channel's mean power over the tile's spectra; a tile
+    whose median is not positive (all zero) has no reference level and takes
+    m = 1, so its input is log(1 + P)."""
     P = np.asarray(power_tile, dtype=np.float64)
     m = median(P.mean(axis=0))
+    if not m > 0:
+        m = 1.0
     return np.log1p(P / m)
 
 

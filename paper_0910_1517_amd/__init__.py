@@ -23,8 +23,10 @@ MAX_INT8_SPECTRA = 66572
 
 STATUS = {
     0: "OK", -1: "INVALID", -2: "NULL", -3: "ALIGN", -4: "UNSUPPORTED", -5: "WORKSPACE",
-    -6: "OVERFLOW", -7: "DEVICE", -8: "NOMEM", -9: "STATE", -10: "DEVICE_ARG",
+    -6: "OVERFLOW", -7: "DEVICE", -8: "NOMEM", -9: "STATE", -10: "DEVICE_ARG", -11: "IO",
 }
+CNN_PARAMS = 2625
+TILE_SPECTRA, TILE_CHANNELS = 64, 256
 
 # corr_geom_t: {int32 D; float frac; double psi0; double rate} (24 bytes)
 GEOM_DTYPE = np.dtype([("D", "<i4"), ("frac", "<f4"), ("psi0", "<f8"), ("rate", "<f8")])
@@ -66,7 +68,15 @@ SYMBOLS = [
     "corr_batch_create", "corr_batch_destroy", "corr_batch_plan", "corr_batch_set_io", "corr_batch_run",
     "corr_batch_capture", "corr_batch_launch", "corr_batch_last_error",
     "corr_autotune_scratch_bytes", "corr_autotune_x_split",
+    "corr_cnn_create", "corr_cnn_destroy", "corr_cnn_workspace_bytes", "corr_cnn_bind_workspace",
+    "corr_cnn_forward", "corr_cnn_loss_grad", "corr_cnn_adam", "corr_cnn_train_step",
+    "corr_cnn_check_device_errors", "corr_cnn_infer", "corr_cnn_save", "corr_cnn_load", "corr_cnn_last_error",
 ]
+
+
+class CnnDesc(ctypes.Structure):
+    _fields_ = [("max_tiles", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("reserved", ctypes.c_int32 * 7)]
 
 
 class BatchIO(ctypes.Structure):
@@ -132,6 +142,26 @@ def lib():
     L.corr_autotune_x_split.argtypes = [ctypes.POINTER(CorrDesc), P, sz, P, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_float)]
     L.corr_autotune_x_split.restype = st
+    i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    L.corr_cnn_create.argtypes = [ctypes.POINTER(CnnDesc), ctypes.POINTER(P)]
+    L.corr_cnn_destroy.argtypes = [P]
+    L.corr_cnn_destroy.restype = None
+    L.corr_cnn_workspace_bytes.argtypes = [P]
+    L.corr_cnn_workspace_bytes.restype = sz
+    L.corr_cnn_bind_workspace.argtypes = [P, P, sz]
+    L.corr_cnn_forward.argtypes = [P, P, P, i32, i64, i32, P, i32, P, P]
+    L.corr_cnn_loss_grad.argtypes = [P, P, P, P, i32, i64, i32, P, i32, P, P, P]
+    L.corr_cnn_adam.argtypes = [P, P, P, P, P, i64, P]
+    L.corr_cnn_train_step.argtypes = [P, P, P, P, i64, P, P, i32, i64, i32, P, i32, P, P]
+    L.corr_cnn_check_device_errors.argtypes = [P, P]
+    L.corr_cnn_infer.argtypes = [P, P, i32, i64, i32, f32, P, P, P]
+    L.corr_cnn_save.argtypes = [ctypes.c_char_p, P, P, P, i64]
+    L.corr_cnn_load.argtypes = [ctypes.c_char_p, P, P, P, ctypes.POINTER(i64)]
+    for n in ("create", "bind_workspace", "forward", "loss_grad", "adam", "train_step", "check_device_errors",
+              "infer", "save", "load"):
+        getattr(L, "corr_cnn_" + n).restype = st
+    L.corr_cnn_last_error.argtypes = [P]
+    L.corr_cnn_last_error.restype = ctypes.c_char_p
     L.corr_status_string.argtypes = [st]
     L.corr_status_string.restype = ctypes.c_char_p
     L.corr_last_error.argtypes = [P]
@@ -330,6 +360,92 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _cnn_check(rc, h=None):
+    if rc != 0:
+        raise CorrError(rc, lib().corr_cnn_last_error(h).decode())
+
+
+def cnn_tiles(S: int, T: int, C: int) -> int:
+    """Number of 64 x 256 flagging tiles of power [S][T][C]."""
+    return S * (T // TILE_SPECTRA) * (C // TILE_CHANNELS)
+
+
+class CNN:
+    """Training handle of the learned flagger (corr_cnn_t) with its workspace
+    bound to device memory.  Parameters and Adam moments are caller-owned
+    device tensors of CNN_PARAMS floats."""
+
+    def __init__(self, max_tiles: int, *, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8, device=None):
+        import torch
+        L = lib()
+        self.desc = CnnDesc()
+        self.desc.max_tiles, self.desc.lr, self.desc.beta1, self.desc.beta2, self.desc.eps = (
+            max_tiles, lr, beta1, beta2, eps)
+        h = ctypes.c_void_p()
+        _cnn_check(L.corr_cnn_create(ctypes.byref(self.desc), ctypes.byref(h)))
+        self._h = h
+        self.max_tiles = max_tiles
+        n = int(L.corr_cnn_workspace_bytes(h))
+        self.workspace = torch.empty(n, dtype=torch.uint8, device=device or "cuda")
+        self._check(L.corr_cnn_bind_workspace(h, _ptr(self.workspace), n))
+
+    def _check(self, rc):
+        _cnn_check(rc, self._h)
+
+    def forward(self, params, power, tiles, logits, stream=None):
+        """FP32 logits [n][64][256] of the listed tiles of power [S][T][C]."""
+        S, T, C = power.shape
+        self._check(lib().corr_cnn_forward(self._h, _ptr(params), _ptr(power), S, T, C, _ptr(tiles),
+                                           tiles.numel(), _ptr(logits), _stream(stream)))
+
+    def loss_grad(self, params, power, labels, tiles, loss, grad=None, stream=None):
+        S, T, C = power.shape
+        self._check(lib().corr_cnn_loss_grad(self._h, _ptr(params), _ptr(power), _ptr(labels), S, T, C,
+                                             _ptr(tiles), tiles.numel(), _ptr(loss), _ptr(grad), _stream(stream)))
+
+    def adam(self, params, m, v, step: int, grad=None, stream=None):
+        self._check(lib().corr_cnn_adam(self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(grad), step, _stream(stream)))
+
+    def train_step(self, params, m, v, step: int, power, labels, tiles, loss, stream=None):
+        S, T, C = power.shape
+        self._check(lib().corr_cnn_train_step(self._h, _ptr(params), _ptr(m), _ptr(v), step, _ptr(power),
+                                              _ptr(labels), S, T, C, _ptr(tiles), tiles.numel(), _ptr(loss),
+                                              _stream(stream)))
+
+    def check_device_errors(self, stream=None):
+        self._check(lib().corr_cnn_check_device_errors(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().corr_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cnn_infer(params, power, flags, *, threshold: float = 0.5, logits=None, stream=None):
+    """Flags (and optionally logits) of every tile of power [S][T][C] from the
+    fused FP16 inference kernel."""
+    S, T, C = power.shape
+    _cnn_check(lib().corr_cnn_infer(_ptr(params), _ptr(power), S, T, C, threshold, _ptr(flags), _ptr(logits),
+                                    _stream(stream)))
+
+
+def cnn_save(path: str, params, m=None, v=None, step: int = 0):
+    _cnn_check(lib().corr_cnn_save(path.encode(), _ptr(params), _ptr(m), _ptr(v), step))
+
+
+def cnn_load(path: str, params, m=None, v=None) -> int:
+    st = ctypes.c_int64()
+    _cnn_check(lib().corr_cnn_load(path.encode(), _ptr(params), _ptr(m), _ptr(v), ctypes.byref(st)))
+    return st.value
 
 
 def _autotune_cache_path():

@@ -1,0 +1,529 @@
+// cnn.hip -- the learned RFI flagger.
+//
+// The paper removes interference with the MAD statistic (section 5, Eq. 3 and
+// Eq. 4) and notes that better filtering leaves room for improvement; this
+// flagger learns from those MAD labels.  Network, per 64 x 256 (spectra x
+// channels) tile of one signal's power P, each tile its own zero-padded image:
+//   x  = log(1 + P / m),  m = median over the tile's channels of the channel's
+//        mean power over the tile's spectra (1 when that median is not > 0)
+//   z1 = conv3x3(x; 1 -> 16),   a1 = ReLU(z1)
+//   z2 = conv3x3(a1; 16 -> 16), a2 = ReLU(z2)
+//   z3 = conv3x3(a2; 16 -> 1)   (logit; flag when sigmoid(z3) > threshold)
+// with conv3x3 the "same"-size cross-correlation
+//   y[o][r][c] = b[o] + sum_i sum_{u,v} w[o][i][u][v] a[i][r + u - 1][c + v - 1].
+// Training minimises the mean binary cross-entropy against MAD labels with
+// Adam (Kingma & Ba 2015).
+//
+// Two implementations:
+//   * training path (FP32, VALU): layer-by-layer direct convolutions on a
+//     batch of tiles with every activation kept for the backward pass, the
+//     weight gradients reduced per block and then over blocks in FP64;
+//   * inference (FP16 operands, FP32 accumulation, MFMA): one workgroup per
+//     tile runs all three layers with the activations in LDS ring buffers and
+//     writes only the flags (and optionally the logits).
+#include <algorithm>
+
+#include "corr_internal.h"
+
+namespace corr {
+namespace {
+
+constexpr int H = kFlagTileSpectra;   // 64 spectra per tile
+constexpr int W = kFlagTileChannels;  // 256 channels per tile
+constexpr int HW = kCnnPixels;
+// parameter offsets in the flat vector
+constexpr int kW1 = 0, kB1 = 144, kW2 = 160, kB2 = 2464, kW3 = 2480, kB3 = 2624;
+
+// Training blocks: 8 rows x 64 columns of one tile, staged with a one-pixel halo.
+constexpr int BR = 8, BC = 64;
+constexpr int LR = BR + 2, LC = BC + 2;
+static_assert((H / BR) * (W / BC) == kCnnBlocksPerTile, "block count");
+
+__device__ inline void tile_coords(int tile, int64_t T, int C, int &s, int64_t &m0, int &k0) {
+    const int ntk = C / W;
+    const int64_t ntm = T / H;
+    k0 = (tile % ntk) * W;
+    const int64_t rest = tile / ntk;
+    m0 = (rest % ntm) * H;
+    s = (int)(rest / ntm);
+}
+
+// ------------------------------------------------------------------ training
+
+// One workgroup per batch tile: the tile's reference level m (median of the
+// 256 channel means), then x = log(1 + P / m) and the labels as 0/1 floats.
+// A tile id outside the data is recorded in err and gives x = y = 0.
+__global__ void __launch_bounds__(256) cnn_gather_kernel(const float *__restrict__ power,
+                                                         const uint8_t *__restrict__ labels, int S, int64_t T,
+                                                         int C, const int32_t *__restrict__ tiles, float *x,
+                                                         float *y, uint32_t *err) {
+    __shared__ float v[W];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int tile = tiles[b];
+    const int64_t n_tiles = (int64_t)S * (T / H) * (C / W);
+    float *xb = x + (int64_t)b * HW, *yb = y + (int64_t)b * HW;
+    if (tile < 0 || tile >= n_tiles) {
+        if (t == 0) atomicOr(err, 1u);
+        for (int p = t; p < HW; p += 256) xb[p] = yb[p] = 0.f;
+        return;
+    }
+    int s, k0;
+    int64_t m0;
+    tile_coords(tile, T, C, s, m0, k0);
+    const int64_t base = ((int64_t)s * T + m0) * C + k0;
+    float acc = 0.f;
+    for (int r = 0; r < H; ++r) acc += power[base + (int64_t)r * C + t];
+    v[t] = acc * (1.0f / H);
+    __syncthreads();
+    block_sort(v, W);
+    const float med = 0.5f * (v[W / 2 - 1] + v[W / 2]);
+    const float lv = med > 0.f ? med : 1.f;
+    for (int r = 0; r < H; ++r) {
+        const int64_t g = base + (int64_t)r * C + t;
+        xb[r * W + t] = log1pf(power[g] / lv);
+        yb[r * W + t] = labels ? (labels[g] ? 1.f : 0.f) : 0.f;
+    }
+}
+
+// Direct 3x3 convolution over [B][CI][H][W] -> [B][CO][H][W], one 8 x 64 block
+// per workgroup, two pixels (rows t/64 and t/64 + 4) per thread.
+//   MODE 0  forward, input is the network input x
+//   MODE 1  forward, input is z of the previous layer (ReLU applied on load)
+//   MODE 2  data gradient: input is dz of the next layer, the weights are the
+//           next layer's, flipped and transposed (dx[i] = sum_o w[o][i] * dy[o]
+//           shifted), and the output is gated by z of this layer > 0.
+template <int CI, int CO, int MODE>
+__global__ void __launch_bounds__(256) cnn_conv_kernel(const float *__restrict__ in, const float *__restrict__ w,
+                                                       const float *__restrict__ bias,
+                                                       const float *__restrict__ gate, float *__restrict__ out) {
+    __shared__ float sx[CI][LR][LC];
+    const int blk = blockIdx.x % kCnnBlocksPerTile;
+    const int64_t b = blockIdx.x / kCnnBlocksPerTile;
+    const int r0 = (blk / (W / BC)) * BR, c0 = (blk % (W / BC)) * BC;
+    const int t = threadIdx.x;
+    const float *src = in + b * CI * HW;
+    for (int e = t; e < CI * LR * LC; e += 256) {
+        const int i = e / (LR * LC), rem = e % (LR * LC);
+        const int rr = rem / LC, cc = rem % LC;
+        const int r = r0 + rr - 1, c = c0 + cc - 1;
+        float v = 0.f;
+        if (r >= 0 && r < H && c >= 0 && c < W) {
+            v = src[(int64_t)i * HW + r * W + c];
+            if (MODE == 1) v = fmaxf(v, 0.f);
+        }
+        sx[i][rr][cc] = v;
+    }
+    __syncthreads();
+    const int c = t % BC, ra = t / BC;
+    float acc0[CO], acc1[CO];
+#pragma unroll
+    for (int o = 0; o < CO; ++o) acc0[o] = acc1[o] = MODE == 2 ? 0.f : bias[o];
+#pragma unroll 1
+    for (int i = 0; i < CI; ++i) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const float x0 = sx[i][ra + u][c + v], x1 = sx[i][ra + 4 + u][c + v];
+#pragma unroll
+                for (int o = 0; o < CO; ++o) {
+                    const float wv = MODE == 2 ? w[((i * CO + o) * 3 + 2 - u) * 3 + 2 - v]
+                                               : w[((o * CI + i) * 3 + u) * 3 + v];
+                    acc0[o] = fmaf(wv, x0, acc0[o]);
+                    acc1[o] = fmaf(wv, x1, acc1[o]);
+                }
+            }
+    }
+    const int p0 = (r0 + ra) * W + c0 + c, p1 = p0 + 4 * W;
+#pragma unroll
+    for (int o = 0; o < CO; ++o) {
+        const int64_t ob = (b * CO + o) * HW;
+        float v0 = acc0[o], v1 = acc1[o];
+        if (MODE == 2) {
+            v0 = gate[ob + p0] > 0.f ? v0 : 0.f;
+            v1 = gate[ob + p1] > 0.f ? v1 : 0.f;
+        }
+        out[ob + p0] = v0;
+        out[ob + p1] = v1;
+    }
+}
+
+// Weight and bias gradients of one layer over one 8 x 64 block:
+//   part[blk][(o CI + i) 9 + 3u + v] = sum_p dz[o][p] a[i][p + (u - 1, v - 1)]
+//   part[blk][CO CI 9 + o]          = sum_p dz[o][p]
+// with a = ReLU(z_prev) (RELU_IN) or the network input.  Thread t takes the
+// (o, i) pair t mod CO CI and, when there are fewer than 256 pairs, one of
+// 256 / (CO CI) slices of the block's rows; the slices are summed in LDS.
+template <int CI, int CO, bool RELU_IN>
+__global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float *__restrict__ ain, const float *__restrict__ dz,
+                                                        float *__restrict__ part) {
+    constexpr int NP = CI * CO, G = 256 / NP, E = NP * 9 + CO;
+    static_assert(NP * G == 256 && (G == 1 || G == 16), "pair count");
+    __shared__ float sa[CI][LR][LC];
+    __shared__ float sd[CO][BR][BC];
+    __shared__ float red[G > 1 ? 256 : 1][10];
+    const int blk = blockIdx.x % kCnnBlocksPerTile;
+    const int64_t b = blockIdx.x / kCnnBlocksPerTile;
+    const int r0 = (blk / (W / BC)) * BR, c0 = (blk % (W / BC)) * BC;
+    const int t = threadIdx.x;
+    for (int e = t; e < CI * LR * LC; e += 256) {
+        const int i = e / (LR * LC), rem = e % (LR * LC);
+        const int rr = rem / LC, cc = rem % LC;
+        const int r = r0 + rr - 1, c = c0 + cc - 1;
+        float v = 0.f;
+        if (r >= 0 && r < H && c >= 0 && c < W) {
+            v = ain[(b * CI + i) * HW + r * W + c];
+            if (RELU_IN) v = fmaxf(v, 0.f);
+        }
+        sa[i][rr][cc] = v;
+    }
+    for (int e = t; e < CO * BR * BC; e += 256) {
+        const int o = e / (BR * BC), rem = e % (BR * BC);
+        sd[o][rem / BC][rem % BC] = dz[(b * CO + o) * HW + (r0 + rem / BC) * W + c0 + rem % BC];
+    }
+    __syncthreads();
+    const int q = t % NP, g = t / NP;
+    const int o = q / CI, i = q % CI;
+    // rows and columns of this thread's slice
+    const int rb = G == 1 ? 0 : g / 2, re = G == 1 ? BR : g / 2 + 1;
+    const int cb = G == 1 ? 0 : (g % 2) * (BC / 2), ce = G == 1 ? BC : cb + BC / 2;
+    float acc[9], bacc = 0.f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0.f;
+    for (int rr = rb; rr < re; ++rr) {
+        float w0[3], w1[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            w0[u] = sa[i][rr + u][cb];
+            w1[u] = sa[i][rr + u][cb + 1];
+        }
+        for (int cc = cb; cc < ce; ++cc) {
+            const float d = sd[o][rr][cc];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const float w2 = sa[i][rr + u][cc + 2];
+                acc[3 * u + 0] = fmaf(d, w0[u], acc[3 * u + 0]);
+                acc[3 * u + 1] = fmaf(d, w1[u], acc[3 * u + 1]);
+                acc[3 * u + 2] = fmaf(d, w2, acc[3 * u + 2]);
+                w0[u] = w1[u];
+                w1[u] = w2;
+            }
+            bacc += d;
+        }
+    }
+    float *pb = part + (int64_t)blockIdx.x * E;
+    if constexpr (G > 1) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) red[t][k] = acc[k];
+        red[t][9] = bacc;
+        __syncthreads();
+        if (t < NP) {
+            for (int k = 0; k < 10; ++k) {
+                float sum = 0.f;
+                for (int gg = 0; gg < G; ++gg) sum += red[gg * NP + t][k];
+                if (k < 9)
+                    pb[(o * CI + i) * 9 + k] = sum;
+                else if (i == 0)
+                    pb[NP * 9 + o] = sum;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) pb[(o * CI + i) * 9 + k] = acc[k];
+        if (i == 0) pb[NP * 9 + o] = bacc;
+    }
+}
+
+// grad[e] = sum over blocks of part[blk][e], in FP64, blocks in order.
+__global__ void cnn_reduce_kernel(const float *__restrict__ part, int nparts, int E, float *grad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += part[(int64_t)k * E + e];
+    grad[e] = (float)s;
+}
+
+// Binary cross-entropy with logits: loss terms max(z, 0) - z y + log(1 + e^-|z|)
+// summed per block (FP64), dz = (sigmoid(z) - y) / n.
+__global__ void __launch_bounds__(256) cnn_bce_kernel(const float *__restrict__ z, const float *__restrict__ y,
+                                                      int64_t n, float *dz, double *lpart) {
+    __shared__ double red[256];
+    const float inv_n = (float)(1.0 / (double)n);
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const float zz = z[p], yy = y[p];
+        acc += (double)(fmaxf(zz, 0.f) - zz * yy + log1pf(expf(-fabsf(zz))));
+        dz[p] = (1.f / (1.f + expf(-zz)) - yy) * inv_n;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+__global__ void cnn_loss_final_kernel(const double *__restrict__ lpart, int nb, int64_t n, float *loss) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += lpart[k];
+    *loss = (float)(s / (double)n);
+}
+
+// Adam: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// p -= lr (m c1) / (sqrt(v c2) + eps), c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t).
+__global__ void cnn_adam_kernel(float *p, float *m, float *v, const float *__restrict__ g, int n, float lr,
+                                float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// ----------------------------------------------------------------- inference
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float float16v __attribute__((ext_vector_type(16)));
+
+constexpr int PC = W + 2;  // padded columns: zero column at each edge
+constexpr int RING = 6;    // rows kept of the layer-1 output and of the layer-3 tap sums
+constexpr int IWG = 512;   // 8 waves, one 32-column strip each
+
+// Accumulator layout of a 32 x 32 MFMA: register j of lane l holds row
+// 8 (j / 4) + 4 (l / 32) + j mod 4, column l mod 32.
+__device__ inline int acc_row(int j, int half) { return 8 * (j / 4) + 4 * half + (j & 3); }
+
+// One workgroup per tile.  Wave w owns columns 32 w .. 32 w + 31 and walks the
+// tile two rows at a time.  MFMA roles (32 x 32 x 16, FP16 in, FP32 out):
+//   layer 1: rows = (row slot, out channel) for the two rows R, R + 1;
+//            K = 4 input rows x 3 column offsets (12 of 16 used);
+//   layer 2: rows = (row slot, out channel) for rows r, r + 1; one product
+//            per (input row r - 1 .. r + 2, column offset), K = 16 channels,
+//            the weights of the taps a row slot does not use set to zero;
+//   layer 3: U[tap][q] = sum_i w3[i][tap] a2[i][q] with rows = the 9 taps, fed
+//            directly from the layer-2 accumulator (its 8 channels per lane
+//            are exactly one lane's K slots), then z3[p] = b3 + sum of U over
+//            the 9 shifted neighbours of p, read from LDS.
+__global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict__ params,
+                                                        const float *__restrict__ power, int64_t T, int C,
+                                                        float thr_logit, uint8_t *__restrict__ flags,
+                                                        float *__restrict__ logits) {
+    __shared__ _Float16 xs[H + 2][PC];
+    __shared__ __align__(16) _Float16 a1s[RING][PC][16];
+    __shared__ float us[RING][PC][9];
+    __shared__ float colv[W];
+
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int half = lane >> 5, col = lane & 31;
+    int s, k0;
+    int64_t m0;
+    tile_coords(blockIdx.x, T, C, s, m0, k0);
+    const int64_t base = ((int64_t)s * T + m0) * C + k0;
+
+    // ---- stage the tile: reference level, then x = log(1 + P / m) in FP16
+    float pv[32];
+    {
+        const int c = t & (W - 1), rh = t >> 8;  // rows rh, rh + 2, ...
+        float cs = 0.f;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            pv[q] = power[base + (int64_t)(rh + 2 * q) * C + c];
+            cs += pv[q];
+        }
+        // column sums: rows of parity 0 first, then add parity 1
+        if (rh == 0) colv[c] = cs;
+        __syncthreads();
+        if (rh == 1) colv[c] = (colv[c] + cs) * (1.0f / H);
+        __syncthreads();
+        block_sort(colv, W);
+        const float med = 0.5f * (colv[W / 2 - 1] + colv[W / 2]);
+        const float lv = med > 0.f ? med : 1.f;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) xs[rh + 2 * q + 1][c + 1] = (_Float16)log1pf(pv[q] / lv);
+        // zero borders: rows 0 and H + 1, columns 0 and W + 1 of every buffer
+        for (int e = t; e < 2 * PC; e += IWG) xs[e < PC ? 0 : H + 1][e % PC] = (_Float16)0.f;
+        for (int e = t; e < 2 * (H + 2); e += IWG) xs[e % (H + 2)][e < H + 2 ? 0 : PC - 1] = (_Float16)0.f;
+        for (int e = t; e < RING * 2 * 16; e += IWG) {
+            const int rr = e / 32, side = (e / 16) & 1, ch = e & 15;
+            a1s[rr][side ? PC - 1 : 0][ch] = (_Float16)0.f;
+        }
+        for (int e = t; e < RING * 2 * 9; e += IWG) {
+            const int rr = e / 18, side = (e / 9) & 1, k = e % 9;
+            us[rr][side ? PC - 1 : 0][k] = 0.f;
+        }
+    }
+
+    // ---- weights as MFMA A operands (lane: row = lane mod 32, K slots 8 half + j)
+    const int arow = lane & 31, aslot = arow >> 4, ao = arow & 15;
+    half8 A1, A3, A2[4][3];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int k = 8 * half + j, rho = k / 3, dv = k % 3;
+        const int u = rho - aslot;
+        A1[j] = (_Float16)((k < 12 && u >= 0 && u <= 2) ? params[kW1 + ao * 9 + u * 3 + dv] : 0.f);
+        const int ch = 8 * (j / 4) + 4 * half + (j & 3);
+        A3[j] = (_Float16)(arow < 9 ? params[kW3 + ch * 9 + arow] : 0.f);
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int dv = 0; dv < 3; ++dv)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int cin = 8 * half + j, u = p - aslot;
+                A2[p][dv][j] = (_Float16)((u >= 0 && u <= 2) ? params[kW2 + ((ao * 16 + cin) * 3 + u) * 3 + dv] : 0.f);
+            }
+    float bias1[16], bias2[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int o = acc_row(j, half) & 15;
+        bias1[j] = params[kB1 + o];
+        bias2[j] = params[kB2 + o];
+    }
+    const float b3 = params[kB3];
+    __syncthreads();
+
+    const int c0 = wv * 32;
+    const int pc = c0 + col + 1;  // padded column of this lane's pixel
+    const half8 zero8 = {};
+
+    for (int k = -1; k <= H / 2; ++k) {
+        // (1) layer 1 for rows R, R + 1 (R = 2k + 2)
+        const int R = 2 * k + 2;
+        if (R < H) {
+            half8 B;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int kk = 8 * half + j;
+                B[j] = kk < 12 ? xs[R + kk / 3][c0 + col + kk % 3] : (_Float16)0.f;
+            }
+            float16v D;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) D[j] = bias1[j];
+            D = __builtin_amdgcn_mfma_f32_32x32x16_f16(A1, B, D, 0, 0, 0);
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
+                _Float16 *dst = &a1s[(R + sl) % RING][pc][0];
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+                    half4 h4;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) h4[q] = (_Float16)fmaxf(D[8 * sl + 4 * g + q], 0.f);
+                    *reinterpret_cast<half4 *>(dst + 8 * g + 4 * half) = h4;
+                }
+            }
+        }
+        __syncthreads();
+        if (k < 0) continue;
+        if (k < H / 2) {
+            // (2) layer 2 for rows r = 2k, 2k + 1 and the layer-3 tap sums U
+            const int r = 2 * k;
+            float16v D;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) D[j] = bias2[j];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int rho = r - 1 + p;
+                const bool in = rho >= 0 && rho < H;
+#pragma unroll
+                for (int dv = 0; dv < 3; ++dv) {
+                    const half8 F =
+                        in ? *reinterpret_cast<const half8 *>(&a1s[(in ? rho : 0) % RING][pc - 1 + dv][8 * half])
+                           : zero8;
+                    D = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[p][dv], F, D, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
+                half8 Bu;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) Bu[j] = (_Float16)fmaxf(D[8 * sl + j], 0.f);
+                float16v U = {};
+                U = __builtin_amdgcn_mfma_f32_32x32x16_f16(A3, Bu, U, 0, 0, 0);
+                float *dst = &us[(r + sl) % RING][pc][0];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) dst[4 * half + j] = U[j];
+                if (half == 0) dst[8] = U[4];
+            }
+        }
+        __syncthreads();
+        // (3) output rows 2k - 2, 2k - 1 (all U rows they need are in place)
+        if (k >= 1) {
+            const int r = 2 * k - 2 + half;
+            float z = b3;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int rr = r + u - 1;
+                if (rr >= 0 && rr < H) {
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) z += us[rr % RING][pc + v - 1][3 * u + v];
+                }
+            }
+            const int64_t gp = base + (int64_t)r * C + c0 + col;
+            flags[gp] = z > thr_logit ? 1 : 0;
+            if (logits) logits[gp] = z;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_cnn_gather(const float *power, const uint8_t *labels, int S, int64_t T, int C,
+                             const int32_t *tiles, int n, const CnnTrainBufs &b, hipStream_t st) {
+    hipLaunchKernelGGL(cnn_gather_kernel, dim3(n), dim3(256), 0, st, power, labels, S, T, C, tiles, b.x, b.y, b.err);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_forward(const float *params, int n, const CnnTrainBufs &b, hipStream_t st) {
+    const dim3 grid(n * kCnnBlocksPerTile), blk(256);
+    hipLaunchKernelGGL((cnn_conv_kernel<1, 16, 0>), grid, blk, 0, st, b.x, params + kW1, params + kB1, nullptr, b.z1);
+    hipLaunchKernelGGL((cnn_conv_kernel<16, 16, 1>), grid, blk, 0, st, b.z1, params + kW2, params + kB2, nullptr, b.z2);
+    hipLaunchKernelGGL((cnn_conv_kernel<16, 1, 1>), grid, blk, 0, st, b.z2, params + kW3, params + kB3, nullptr, b.z3);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_backward(const float *params, int n, const CnnTrainBufs &b, float *grad, float *loss,
+                               hipStream_t st) {
+    const int64_t npx = (int64_t)n * HW;
+    const int nb = (int)std::min<int64_t>(kCnnLossBlocks, (npx + 255) / 256);
+    hipLaunchKernelGGL(cnn_bce_kernel, dim3(nb), dim3(256), 0, st, b.z3, b.y, npx, b.d3, b.lpart);
+    hipLaunchKernelGGL(cnn_loss_final_kernel, dim3(1), dim3(64), 0, st, b.lpart, nb, npx, loss);
+    const dim3 grid(n * kCnnBlocksPerTile), blk(256);
+    const int nparts = n * kCnnBlocksPerTile;
+    // layer 3: weights from a2 = ReLU(z2) and dz3; dz2 = (W3^T * dz3) gated by z2 > 0
+    hipLaunchKernelGGL((cnn_wgrad_kernel<16, 1, true>), grid, blk, 0, st, b.z2, b.d3, b.part);
+    hipLaunchKernelGGL(cnn_reduce_kernel, dim3(1), dim3(256), 0, st, b.part, nparts, 16 * 9 + 1, grad + kW3);
+    hipLaunchKernelGGL((cnn_conv_kernel<1, 16, 2>), grid, blk, 0, st, b.d3, params + kW3, nullptr, b.z2, b.d2);
+    // layer 2
+    hipLaunchKernelGGL((cnn_wgrad_kernel<16, 16, true>), grid, blk, 0, st, b.z1, b.d2, b.part);
+    hipLaunchKernelGGL(cnn_reduce_kernel, dim3((kCnnGradEntries + 255) / 256), dim3(256), 0, st, b.part, nparts,
+                       kCnnGradEntries, grad + kW2);
+    hipLaunchKernelGGL((cnn_conv_kernel<16, 16, 2>), grid, blk, 0, st, b.d2, params + kW2, nullptr, b.z1, b.d1);
+    // layer 1
+    hipLaunchKernelGGL((cnn_wgrad_kernel<1, 16, false>), grid, blk, 0, st, b.x, b.d1, b.part);
+    hipLaunchKernelGGL(cnn_reduce_kernel, dim3(1), dim3(256), 0, st, b.part, nparts, 16 * 9 + 16, grad + kW1);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_adam(float *params, float *m, float *v, const float *grad, float lr, float beta1,
+                           float beta2, float eps, float c1, float c2, hipStream_t st) {
+    hipLaunchKernelGGL(cnn_adam_kernel, dim3((kCnnParams + 255) / 256), dim3(256), 0, st, params, m, v, grad,
+                       kCnnParams, lr, beta1, beta2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_infer(const float *params, const float *power, int S, int64_t T, int C, float thr_logit,
+                            uint8_t *flags, float *logits, hipStream_t st) {
+    const int64_t n_tiles = (int64_t)S * (T / H) * (C / W);
+    hipLaunchKernelGGL(cnn_infer_kernel, dim3((unsigned)n_tiles), dim3(IWG), 0, st, params, power, T, C, thr_logit,
+                       flags, logits);
+    return hipGetLastError();
+}
+
+}  // namespace corr

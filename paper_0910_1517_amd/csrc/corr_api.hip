@@ -81,6 +81,7 @@ const char *corr_status_string(corr_status st) {
     case CORR_ERR_NOMEM: return "out of host memory";
     case CORR_ERR_STATE: return "call not allowed in this state";
     case CORR_ERR_DEVICE_ARG: return "invalid device-resident argument";
+    case CORR_ERR_IO: return "file I/O error";
     default: return "unknown status";
     }
 }

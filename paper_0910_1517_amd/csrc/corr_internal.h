@@ -89,8 +89,55 @@ hipError_t launch_apply_flags(int precision, const uint8_t *flags, void *spec, u
 hipError_t launch_pair_counts(const uint32_t *keep, const uint16_t *pairs, int S, int T, int C, int32_t *counts,
                               hipStream_t st);
 
+// Ascending bitonic sort of n (power of two, <= blockDim.x) floats in LDS;
+// every thread of the block must call it.
+__device__ inline void block_sort(float *v, int n) {
+    const int t = threadIdx.x;
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (t < n) {
+                const int p = t ^ j;
+                if (p > t) {
+                    const float a = v[t], b = v[p];
+                    const bool up = (t & k) == 0;
+                    if ((a > b) == up) {
+                        v[t] = b;
+                        v[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 hipError_t launch_integrate(int precision, void *acc, const float *scale, double *state,
                             float *vis, const uint16_t *pairs, int S, int C, int splits,
                             uint32_t flags, hipStream_t st);
+
+// Learned flagger (cnn.hip).  Parameters: flat FP32 vector, layer by layer,
+// weights [Cout][Cin][3][3] then biases.
+constexpr int kCnnParams = 16 * 9 + 16 + 16 * 16 * 9 + 16 + 16 * 9 + 1;  // 2625
+constexpr int kCnnPixels = kFlagTileSpectra * kFlagTileChannels;      // 16384 per tile
+// per-tile training blocks (8 x 64 pixels) and the widest per-block gradient
+constexpr int kCnnBlocksPerTile = 32;
+constexpr int kCnnGradEntries = 16 * 16 * 9 + 16;
+struct CnnTrainBufs {
+    float *x, *y, *z1, *z2, *z3, *d3, *d2, *d1, *part, *grad, *loss;
+    double *lpart;
+    uint32_t *err;
+};
+constexpr int kCnnLossBlocks = 1024;
+// FP32 training path on n tiles listed in tiles (tile id = (s ntm + mt) ntk + kt)
+hipError_t launch_cnn_gather(const float *power, const uint8_t *labels, int S, int64_t T, int C,
+                             const int32_t *tiles, int n, const CnnTrainBufs &b, hipStream_t st);
+hipError_t launch_cnn_forward(const float *params, int n, const CnnTrainBufs &b, hipStream_t st);
+hipError_t launch_cnn_backward(const float *params, int n, const CnnTrainBufs &b, float *grad, float *loss,
+                               hipStream_t st);
+hipError_t launch_cnn_adam(float *params, float *m, float *v, const float *grad, float lr, float beta1,
+                           float beta2, float eps, float c1, float c2, hipStream_t st);
+// fused FP16 MFMA inference over every tile of power [S][T][C]
+hipError_t launch_cnn_infer(const float *params, const float *power, int S, int64_t T, int C, float thr_logit,
+                            uint8_t *flags, float *logits, hipStream_t st);
 
 }  // namespace corr

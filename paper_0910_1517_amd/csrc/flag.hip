@@ -20,27 +20,6 @@ namespace {
 constexpr int TT = kFlagTileSpectra;   // 64
 constexpr int KT = kFlagTileChannels;  // 256
 
-// Ascending bitonic sort of n (power of two, <= blockDim.x) floats in LDS.
-__device__ void block_sort(float *v, int n) {
-    const int t = threadIdx.x;
-    for (int k = 2; k <= n; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (t < n) {
-                const int p = t ^ j;
-                if (p > t) {
-                    const float a = v[t], b = v[p];
-                    const bool up = (t & k) == 0;
-                    if ((a > b) == up) {
-                        v[t] = b;
-                        v[p] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
 // Eq. 3 / Eq. 4 on n values x[0..n) (x is kept; work is scratch of n floats):
 // flag[i] = |x_i - med| > M MAD / 0.6745, median of an even count = mean of
 // the two middle values.

@@ -303,3 +303,32 @@ def point_sources(S: int, n_src: int, power: float, seed: int = BASE_SEED, n_pol
             dr = np.repeat(g.uniform(-0.5, 0.5, n_ant), n_pol)
         out.append({"power": power / n_src, "dD": dD, "drate": dr})
     return out
+
+
+def power_spectra(S: int, T: int, C: int, seed: int = BASE_SEED, *, tone_frac: float = 0.05,
+                  tone_k=(2.0, 40.0), burst_p: float = 0.01, burst_k=(2.0, 20.0), burst_len=(1, 8),
+                  bandpass: bool = True) -> np.ndarray:
+    """float32 power [S][T][C] shaped like channelised noise with interference,
+    for flagger tests that do not need a voltage run: each cell is exponential
+    (the power of a complex Gaussian) with mean mu_k = a smooth bandpass,
+    persistent tones add k mu_k to a fraction of the channels (same channels
+    for every signal, k ~ U[tone_k]), and broadband bursts multiply whole
+    spectra by 1 + k (start probability burst_p per spectrum and signal, length
+    U{burst_len}, k ~ U[burst_k])."""
+    out = np.empty((S, T, C), dtype=np.float32)
+    k = np.arange(C)
+    mu = 1000.0 * (0.6 + 0.4 * np.sin(np.pi * (k + 0.5) / C)) if bandpass else np.full(C, 1000.0)
+    g = rng(seed, 20)
+    n_tone = int(round(tone_frac * C))
+    tch = g.choice(C, size=n_tone, replace=False) if n_tone else np.zeros(0, dtype=np.int64)
+    tk = g.uniform(*tone_k, n_tone)
+    for s in range(S):
+        gs = rng(seed, 21, s)
+        mean = np.broadcast_to(mu, (T, C)).copy()
+        mean[:, tch] += tk * mu[tch]
+        starts = np.nonzero(gs.random(T) < burst_p)[0]
+        for m0 in starts:
+            ln = int(gs.integers(burst_len[0], burst_len[1] + 1))
+            mean[m0:m0 + ln] *= 1.0 + gs.uniform(*burst_k)
+        out[s] = (gs.exponential(1.0, (T, C)) * mean).astype(np.float32)
+    return out

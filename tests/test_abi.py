@@ -110,3 +110,61 @@ def test_fp32_split_choice_bounds_running_sums():
         assert 16384 // sp <= 1024
     finally:
         L.corr_plan_destroy(h)
+
+
+# ----------------------------------------------------------- learned flagger
+
+def _cnn_desc(**kw):
+    d = corr.CnnDesc()
+    d.max_tiles, d.lr, d.beta1, d.beta2, d.eps = 4, 1e-3, 0.9, 0.999, 1e-8
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw", [dict(max_tiles=0), dict(max_tiles=5000), dict(lr=0.0), dict(lr=float("nan")),
+                                dict(beta1=1.0), dict(beta2=-0.1), dict(eps=0.0)])
+def test_cnn_create_rejects_bad_descriptions(kw):
+    L = corr.lib()
+    h = ctypes.c_void_p()
+    assert L.corr_cnn_create(ctypes.byref(_cnn_desc(**kw)), ctypes.byref(h)) == -1
+    assert L.corr_cnn_last_error(None)
+
+
+def test_cnn_workspace_and_unbound_calls():
+    L = corr.lib()
+    h = ctypes.c_void_p()
+    assert L.corr_cnn_create(ctypes.byref(_cnn_desc()), ctypes.byref(h)) == 0
+    try:
+        n = L.corr_cnn_workspace_bytes(h)
+        # activations of 4 tiles: 68 planes of 64 x 256 floats each, plus the gradient partials
+        assert n >= 4 * 68 * 64 * 256 * 4
+        fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below fails its checks first
+        assert L.corr_cnn_forward(h, fake, fake, 1, 64, 256, fake, 1, fake, None) == -5  # no workspace
+        assert L.corr_cnn_adam(h, fake, fake, fake, None, 1, None) == -5
+        assert L.corr_cnn_adam(h, fake, fake, fake, fake, 0, None) == -1                # step 0
+        assert L.corr_cnn_bind_workspace(h, ctypes.c_void_p(1 << 20 | 16), n) == -3
+        assert L.corr_cnn_bind_workspace(h, fake, n - 1) == -5
+    finally:
+        L.corr_cnn_destroy(h)
+
+
+@pytest.mark.parametrize("shape,thr,code", [((1, 64, 256), 0.0, -1), ((1, 64, 256), 1.0, -1),
+                                            ((1, 100, 256), 0.5, -1), ((1, 64, 300), 0.5, -1),
+                                            ((0, 64, 256), 0.5, -1)])
+def test_cnn_infer_rejects_bad_arguments(shape, thr, code):
+    L = corr.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.corr_cnn_infer(fake, fake, *shape, thr, fake, None, None) == code
+    assert L.corr_cnn_infer(None, fake, 1, 64, 256, 0.5, fake, None, None) == -2
+    assert L.corr_cnn_last_error(None)
+
+
+def test_cnn_load_rejects_missing_and_foreign_files(tmp_path):
+    L = corr.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    st = ctypes.c_int64()
+    assert L.corr_cnn_load(str(tmp_path / "none.bin").encode(), fake, None, None, ctypes.byref(st)) == -11
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTACNN!" + bytes(64))
+    assert L.corr_cnn_load(str(bad).encode(), fake, None, None, ctypes.byref(st)) == -1

@@ -1,0 +1,190 @@
+"""Learned flagger on the GPU against the FP64 oracle: FP32 training-path
+forward, loss and parameter gradient, the Adam update, and the fused FP16
+inference kernel (logits and flags), with its edge cases."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_0910_1517_amd as corr
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TH, TW = 64, 256
+
+
+def he_params(seed, scale=1.0):
+    """float32 parameters: He-normal weights (std sqrt(2 / fan_in)), small biases."""
+    g = synth.rng(seed, 30)
+    parts = []
+    for co, ci in oracle.CNN_SHAPES:
+        parts.append(g.standard_normal(co * ci * 9) * np.sqrt(2.0 / (ci * 9)) * scale)
+        parts.append(g.uniform(-0.1, 0.1, co))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def tile_slice(power, tile):
+    S, T, C = power.shape
+    ntm, ntk = T // TH, C // TW
+    s, mt, kt = tile // (ntm * ntk), (tile // ntk) % ntm, tile % ntk
+    return power[s, mt * TH:(mt + 1) * TH, kt * TW:(kt + 1) * TW]
+
+
+def oracle_inputs(power, tiles, labels=None):
+    P = power.astype(np.float64)
+    x = np.stack([oracle.cnn_tile_input(tile_slice(P, t)) for t in tiles])[:, None]
+    if labels is None:
+        return x
+    y = np.stack([tile_slice(labels, t) for t in tiles]).astype(np.float64)[:, None]
+    return x, y
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_forward_fp32_matches_oracle():
+    import torch
+    S, T, C = 2, 128, 512
+    power = synth.power_spectra(S, T, C, seed=11)
+    params = he_params(1)
+    tiles = np.array([5, 0, 3, 7, 2], dtype=np.int32)
+    cnn = corr.CNN(max_tiles=8)
+    logits = torch.empty(len(tiles), TH, TW, device="cuda")
+    cnn.forward(dev(params), dev(power), dev(tiles), logits)
+    z = logits.cpu().numpy().astype(np.float64)
+    z64, _ = oracle.cnn_forward(params.astype(np.float64), oracle_inputs(power, tiles))
+    err = np.abs(z - z64[:, 0]).max() / (1.0 + np.abs(z64).max())
+    print("FP32 forward: max |dz| / (1 + max |z|) = %.3g" % err)
+    assert err < 1e-5
+
+
+def test_loss_and_gradient_match_oracle():
+    import torch
+    S, T, C = 2, 128, 512
+    power = synth.power_spectra(S, T, C, seed=12)
+    labels = oracle.mad_tile_flags(power.astype(np.float64), 3.0)
+    params = he_params(2, scale=0.7)
+    tiles = np.array([1, 6, 4], dtype=np.int32)
+    cnn = corr.CNN(max_tiles=4)
+    loss = torch.zeros(1, device="cuda")
+    grad = torch.zeros(corr.CNN_PARAMS, device="cuda")
+    cnn.loss_grad(dev(params), dev(power), dev(labels), dev(tiles), loss, grad)
+    x, y = oracle_inputs(power, tiles, labels)
+    loss64, g64 = oracle.cnn_loss_and_grad(params.astype(np.float64), x, y)
+    g = grad.cpu().numpy().astype(np.float64)
+    lerr = abs(loss.item() - loss64) / loss64
+    gerr = np.abs(g - g64).max() / np.abs(g64).max()
+    print("loss %.6f vs %.6f (rel %.3g); gradient max err / max |g| = %.3g" % (loss.item(), loss64, lerr, gerr))
+    assert lerr < 1e-5
+    # every layer's block of the gradient, not only the largest entries
+    for lo, hi in [(0, 160), (160, 2480), (2480, 2625)]:
+        assert np.abs(g[lo:hi] - g64[lo:hi]).max() <= 1e-4 * np.abs(g64[lo:hi]).max(), (lo, hi)
+    assert gerr < 1e-5
+
+
+def test_adam_update_matches_oracle():
+    import torch
+    g = synth.rng(3, 31)
+    p, m, gr = [g.standard_normal(corr.CNN_PARAMS).astype(np.float32) for _ in range(3)]
+    v = np.abs(g.standard_normal(corr.CNN_PARAMS)).astype(np.float32)
+    cnn = corr.CNN(max_tiles=1, lr=3e-3, beta1=0.8, beta2=0.99, eps=1e-6)
+    pd, md, vd = dev(p), dev(m), dev(v)
+    cnn.adam(pd, md, vd, step=3, grad=dev(gr))
+    torch.cuda.synchronize()
+    p64, m64, v64 = oracle.adam_step(p, m, v, gr, 3, 3e-3, 0.8, 0.99, 1e-6)
+    assert np.allclose(md.cpu().numpy(), m64, rtol=1e-6, atol=1e-7)
+    assert np.allclose(vd.cpu().numpy(), v64, rtol=1e-6, atol=1e-7)
+    assert np.abs(pd.cpu().numpy() - p64).max() < 1e-6
+
+
+# Inference: FP16 operands (relative rounding 2^-11 on x, a1, a2 and the
+# weights), FP32 accumulation.  Each layer adds about 2^-11 of its output's
+# scale to the logit, so 2e-3 of (1 + max |z|) bounds the error with margin.
+INFER_TOL = 2e-3
+
+
+def _infer(params, power, threshold=0.5):
+    import torch
+    S, T, C = power.shape
+    flags = torch.full((S, T, C), 7, dtype=torch.uint8, device="cuda")
+    logits = torch.full((S, T, C), float("nan"), device="cuda")
+    corr.cnn_infer(dev(params), dev(power), flags, threshold=threshold, logits=logits)
+    torch.cuda.synchronize()
+    return flags.cpu().numpy(), logits.cpu().numpy().astype(np.float64)
+
+
+def _check_infer(params, power, threshold=0.5):
+    flags, z = _infer(params, power, threshold)
+    z64 = oracle.cnn_tile_logits(params.astype(np.float64), power.astype(np.float64))
+    scale = 1.0 + np.abs(z64).max()
+    err = np.abs(z - z64).max() / scale
+    print("FP16 inference: max |dz| / (1 + max |z|) = %.3g" % err)
+    assert err < INFER_TOL
+    # flags: identical wherever the FP64 logit is clear of the threshold by the bound
+    thr = np.log(threshold / (1 - threshold))
+    clear = np.abs(z64 - thr) > INFER_TOL * scale
+    assert np.array_equal(flags[clear], (z64[clear] > thr).astype(np.uint8))
+    assert set(np.unique(flags)) <= {0, 1}
+    return flags, z64
+
+
+def test_infer_matches_oracle_over_several_tiles():
+    power = synth.power_spectra(2, 192, 768, seed=13)  # 2 x 3 x 3 tiles
+    _check_infer(he_params(4), power)
+
+
+def test_infer_single_tile_and_thresholds():
+    power = synth.power_spectra(1, 64, 256, seed=14)
+    params = he_params(5)
+    for thr in (0.1, 0.5, 0.93):
+        _check_infer(params, power, thr)
+
+
+def test_infer_edge_tiles():
+    """An all-zero tile (no reference level: input 0 everywhere), a tile of one
+    huge value, and a constant tile."""
+    power = synth.power_spectra(1, 64, 1024, seed=15)
+    power[0, :, 0:256] = 0.0
+    power[0, 17, 300] = 3e30
+    power[0, :, 768:1024] = 5.0
+    _check_infer(he_params(6), power)
+
+
+def test_training_forward_agrees_with_inference():
+    """The FP32 training forward and the FP16 fused kernel compute the same logits."""
+    import torch
+    power = synth.power_spectra(1, 128, 512, seed=16)
+    params = he_params(7)
+    tiles = np.arange(4, dtype=np.int32)
+    cnn = corr.CNN(max_tiles=4)
+    logits = torch.empty(4, TH, TW, device="cuda")
+    cnn.forward(dev(params), dev(power), dev(tiles), logits)
+    _, z16 = _infer(params, power)
+    z32 = logits.cpu().numpy()
+    for t in tiles:
+        a, b = z32[t], tile_slice(z16, t)
+        assert np.abs(a - b).max() < INFER_TOL * (1 + np.abs(a).max())
+
+
+def test_bad_tile_number_is_reported():
+    import torch
+    power = synth.power_spectra(1, 64, 256, seed=17)
+    cnn = corr.CNN(max_tiles=2)
+    logits = torch.empty(2, TH, TW, device="cuda")
+    cnn.forward(dev(he_params(8)), dev(power), dev(np.array([0, 99], dtype=np.int32)), logits)
+    with pytest.raises(corr.CorrError) as e:
+        cnn.check_device_errors()
+    assert e.value.status == -10
+    cnn.check_device_errors()  # cleared
+
+
+def test_save_load_round_trip(tmp_path):
+    import torch
+    p, m, v = (dev(he_params(k)) for k in (9, 10, 11))
+    path = str(tmp_path / "flagger.bin")
+    corr.cnn_save(path, p, m, v, step=123)
+    q, mq, vq = (torch.zeros(corr.CNN_PARAMS, device="cuda") for _ in range(3))
+    assert corr.cnn_load(path, q, mq, vq) == 123
+    assert torch.equal(p, q) and torch.equal(m, mq) and torch.equal(v, vq)

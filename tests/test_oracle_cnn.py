@@ -165,3 +165,7 @@ def test_tile_input_invariances():
     m = np.sort(P.mean(axis=0))
     ref = 0.5 * (m[127] + m[128])
     assert np.allclose(a, np.log1p(P / ref), rtol=1e-14, atol=0)
+
+
+def test_tile_input_of_an_empty_tile_is_zero():
+    assert not oracle.cnn_tile_input(np.zeros((64, 256))).any()
