@@ -10,8 +10,10 @@ timed beside it.  One step = F-engine (held requantisation scales, set once
 on a calibration pass like the paper's gain table) + X-engine + integrate
 with dump, over one block of all 64 signals.
 
-Prints one JSON line.  Options: --steps K --warmup W --gpus 1 [--config c2|c3]
-[--no-fp32] [--no-cpu-baseline].
+Prints one JSON line.  Options: --steps K --warmup W --gpus 1
+[--config c2|c3|c4|c5] [--no-fp32] [--no-cpu-baseline].  c4 is the batched
+form (six uneven sub-arrays in one graph launch); c5 the flagged path with the
+learned RFI flagger (64 signals, 8192-pt FFT, 8192 spectra).
 """
 from __future__ import annotations
 
@@ -35,6 +37,8 @@ CONFIGS = {
 HBM_PEAK = 8.0e12           # B/s
 INT8_PEAK = 5.0e15          # dense int8 MFMA OP/s
 FP32_MFMA_PEAK = 157.3e12   # dense FP32 matrix FLOP/s
+FP16_MFMA_PEAK = 2.5e15     # dense FP16 matrix FLOP/s
+CNN_FLOP_PER_CELL = 2 * (16 * 9 + 16 * 16 * 9 + 16 * 9)  # 2592 MACs of the three 3x3 layers
 # FP32 vector peak without packed-FP32 instructions (which this library never
 # emits): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.  The 157.3
 # TFLOP/s datasheet figure assumes two FP32 FMAs per lane per cycle (packed).
@@ -224,12 +228,90 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_rfi(args):
+    """Flagged int8 path with the learned flagger: F-engine (held scales, power
+    output) -> CNN inference (fused FP16 MFMA kernel) -> zero flagged cells and
+    keep bits -> X-engine -> exact per-pair unflagged counts -> integrate.
+    Prints one JSON line."""
+    import torch
+    import paper_0910_1517_amd as corr
+    import synth
+    from paper_0910_1517_amd.flagger import init_params
+    S, N, T = 64, 8192, 8192
+    C = N // 2
+    torch.cuda.set_device(0)
+    geo = synth.make_geometry(S // 2, seed=synth.BASE_SEED + 5)
+    rs = (N * T + 16 + 255) // 256 * 256
+    log("generating %d x %d int8 samples on the GPU" % (S, rs))
+    x = synth.voltages_device(S, N * T + 16, geo, seed=synth.BASE_SEED + 5, tone_bin=37, tone_N=N, row_stride=rs)
+    g = corr.geom_to_device(corr.geom_array(geo.D, geo.f, geo.psi0, geo.rate))
+    scale = calibrate_scales(corr, torch, S, N, T, x, rs, g)
+    plan = corr.Plan(S, N, T, precision=corr.INT8, scale_mode=corr.SCALE_HOLD)
+    spec = plan.alloc("spectra", zero=False)
+    power = plan.alloc("power", zero=False).view(S, T, C)
+    flags = plan.alloc("flags", zero=False).view(S, T, C)
+    keep = plan.alloc("keep", zero=False)
+    acc, state, vis = plan.alloc("acc"), plan.alloc("state"), plan.alloc("vis")
+    counts = torch.zeros(C * plan.P, dtype=torch.int32, device="cuda")
+    params = torch.from_numpy(init_params(1)).cuda()
+    st = torch.cuda.current_stream()
+    names = ["fengine", "cnn_infer", "apply_flags", "xengine", "pair_counts", "integrate"]
+
+    def step(e=None):
+        if e: e[0].record(st)
+        plan.fengine(x, g, spec, scale, power=power, row_stride=rs, stream=st)
+        if e: e[1].record(st)
+        corr.cnn_infer(params, power, flags, threshold=0.5, stream=st)
+        if e: e[2].record(st)
+        plan.apply_flags(flags, spec, keep, stream=st)
+        if e: e[3].record(st)
+        plan.xengine(spec, acc, stream=st)
+        if e: e[4].record(st)
+        plan.pair_counts(keep, counts, stream=st)
+        if e: e[5].record(st)
+        plan.integrate(acc, state, vis, scale, flags=corr.DUMP | corr.RESET, stream=st)
+        if e: e[6].record(st)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    for e in ev:
+        step(e)
+    torch.cuda.synchronize()
+    plan.check_device_errors()
+    t = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in ev])) * 1e-3 for i, n in enumerate(names)}
+    t_step = float(np.mean([e[0].elapsed_time(e[6]) for e in ev])) * 1e-3
+    cells = S * T * C
+    cnn_flops = float(cells) * CNN_FLOP_PER_CELL
+    ach = cnn_flops / t["cnn_infer"] / 1e12
+    xops, _ = x_algorithmic(S, N, T, 2)
+    out = {
+        "metric": "correlated bandwidth (MHz) with learned RFI flagging, 64 signals",
+        "value": round(N * T / (2 * t_step) / 1e6, 3), "unit": "MHz", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int8 (X) / fp16 (CNN)",
+        "data": "synthetic (seeded Gaussian + common source + tone, generated on the GPU); "
+                "CNN weights He-normal random (the kernel's time does not depend on them)",
+        "config": {"workload": "64 signals, 8192-pt FFT (4096 ch), 8192 spectra, int8 X-engine, "
+                               "learned flagger on %d power cells (%d tiles of 64 x 256)" % (cells, cells // 16384),
+                   "parallelism": "single GPU"},
+        "ms": {n: round(v * 1e3, 4) for n, v in t.items()},
+        "x_engine_tops": round(xops / t["xengine"] / 1e12, 3),
+        "roofline": {"kernel": "cnn_infer_kernel (fused 3-layer conv, FP16 MFMA)", "bound": "mfma",
+                     "achieved": round(ach, 3), "peak": FP16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": round(ach * 1e12 / FP16_MFMA_PEAK, 4), "traffic": None,
+                     "algorithmic_flop_per_cell": CNN_FLOP_PER_CELL},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS) + ["c4"])
+    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS) + ["c4", "c5"])
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="spectra in the CPU-oracle sample")
@@ -241,6 +323,8 @@ def main():
 
     if args.config == "c4":
         return bench_batch(args)
+    if args.config == "c5":
+        return bench_rfi(args)
     import torch
     import paper_0910_1517_amd as corr
     import synth

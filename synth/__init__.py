@@ -95,14 +95,24 @@ class RFI:
       every signal, random phase per signal;
     * broadband bursts per antenna (both polarisations): a burst starts in a
       spectrum with probability ``burst_p``, lasts U{burst_len} spectra and adds
-      Gaussian noise of variance k * sigma_t^2 (k ~ U[burst_k]).
+      Gaussian noise of variance k * sigma_t^2 (k ~ U[burst_k]); a fraction
+      ``bl_frac`` of them is band-limited to a random contiguous band of
+      U[bl_width] of the channels (same excess power per cell inside it);
+    * intermittent narrowband lines per antenna: a line starts in a spectrum
+      with probability ``nb_p``, lasts U{nb_len} spectra, at a random frequency
+      with excess power k * mu in its channel (k ~ U[nb_k]).
+    The last two are off by default.
     """
 
     def __init__(self, N: int, seed: int = BASE_SEED, tone_frac: float = 0.05, tone_k=(20.0, 200.0),
-                 burst_p: float = 0.002, burst_k=(10.0, 100.0), burst_len=(1, 8)):
+                 burst_p: float = 0.002, burst_k=(10.0, 100.0), burst_len=(1, 8),
+                 bl_frac: float = 0.0, bl_width=(0.05, 0.3), nb_p: float = 0.0, nb_k=(20.0, 200.0),
+                 nb_len=(4, 32)):
         self.N, self.seed = N, seed
         self.tone_frac, self.tone_k = tone_frac, tone_k
         self.burst_p, self.burst_k, self.burst_len = burst_p, burst_k, burst_len
+        self.bl_frac, self.bl_width = bl_frac, bl_width
+        self.nb_p, self.nb_k, self.nb_len = nb_p, nb_k, nb_len
 
     def tones(self):
         """(channel, frequency in cycles/sample, excess power factor k) of every tone."""
@@ -115,18 +125,50 @@ class RFI:
         return ch, freq, k
 
     def bursts(self, n_ant: int, n_spec: int):
-        """list per antenna of (start spectrum, length, variance factor)."""
+        """list per antenna of (start spectrum, length, variance factor, band):
+        band = None (broadband) or (first, last) frequency bin of an N-point FFT."""
         out = []
+        C = self.N // 2
         for a in range(n_ant):
             g = rng(self.seed, 10, a)
             starts = np.nonzero(g.random(n_spec) < self.burst_p)[0]
             lens = g.integers(self.burst_len[0], self.burst_len[1] + 1, starts.size)
             ks = g.uniform(*self.burst_k, starts.size)
-            out.append(list(zip(starts.tolist(), lens.tolist(), ks.tolist())))
+            gb = rng(self.seed, 13, a)
+            bands = []
+            for _ in range(starts.size):
+                if gb.random() < self.bl_frac:
+                    w = max(1, int(round(gb.uniform(*self.bl_width) * C)))
+                    lo = int(gb.integers(0, C - w + 1))
+                    bands.append((lo, lo + w - 1))
+                else:
+                    bands.append(None)
+            out.append(list(zip(starts.tolist(), lens.tolist(), ks.tolist(), bands)))
+        return out
+
+    def lines(self, n_ant: int, n_spec: int):
+        """list per antenna of intermittent narrowband lines
+        (start spectrum, length, frequency in cycles/sample, excess factor k)."""
+        out = []
+        C = self.N // 2
+        for a in range(n_ant):
+            g = rng(self.seed, 14, a)
+            starts = np.nonzero(g.random(n_spec) < self.nb_p)[0]
+            lens = g.integers(self.nb_len[0], self.nb_len[1] + 1, starts.size)
+            freq = (g.integers(2, C - 1, starts.size) + g.uniform(-0.5, 0.5, starts.size)) / self.N
+            ks = g.uniform(*self.nb_k, starts.size)
+            out.append(list(zip(starts.tolist(), lens.tolist(), freq.tolist(), ks.tolist())))
         return out
 
     def signal(self, S: int, n_samples: int, sigma_t: float, n_pol: int = 2) -> np.ndarray:
-        """The RFI-only float signal [S][n_samples]."""
+        """The RFI-only float signal [S][n_samples] (the last one is cached)."""
+        key = (S, n_samples, float(sigma_t), n_pol)
+        if getattr(self, "_cache_key", None) == key:
+            return self._cache
+        self._cache_key, self._cache = key, self._signal(S, n_samples, sigma_t, n_pol)
+        return self._cache
+
+    def _signal(self, S: int, n_samples: int, sigma_t: float, n_pol: int) -> np.ndarray:
         N = self.N
         out = np.zeros((S, n_samples))
         n = np.arange(n_samples)
@@ -137,11 +179,24 @@ class RFI:
             for c in range(ch.size):
                 out[s] += amp[c] * np.cos(2 * np.pi * freq[c] * n + ph[c])
         for a, bl in enumerate(self.bursts(S // n_pol, n_samples // N)):
-            for (m0, ln, kk) in bl:
+            for (m0, ln, kk, band) in bl:
                 lo, hi = m0 * N, min(n_samples, (m0 + ln) * N)
                 for pol in range(n_pol):
                     s = a * n_pol + pol
-                    out[s, lo:hi] += sigma_t * np.sqrt(kk) * rng(self.seed, 12, s, m0).standard_normal(hi - lo)
+                    z = sigma_t * np.sqrt(kk) * rng(self.seed, 12, s, m0).standard_normal(hi - lo)
+                    if band is not None:  # keep the bins of [band] at the resolution of N-point spectra
+                        Z = np.fft.rfft(z)
+                        f = np.arange(Z.size) * N / (hi - lo)
+                        Z[(f < band[0] - 0.5) | (f > band[1] + 0.5)] = 0
+                        z = np.fft.irfft(Z, hi - lo)
+                    out[s, lo:hi] += z
+        for a, ll in enumerate(self.lines(S // n_pol, n_samples // N)):
+            for (m0, ln, fr, kk) in ll:
+                lo, hi = m0 * N, min(n_samples, (m0 + ln) * N)
+                ph = rng(self.seed, 15, a, m0).uniform(0, 2 * np.pi, n_pol)
+                for pol in range(n_pol):
+                    out[a * n_pol + pol, lo:hi] += 2.0 * sigma_t * np.sqrt(kk / N) * np.cos(
+                        2 * np.pi * fr * np.arange(lo, hi) + ph[pol])
         return out
 
 

@@ -1,0 +1,81 @@
+"""Learned flagger trained on the GPU against MAD labels, evaluated against the
+true interference mask on held-out seeds.
+
+Parity unpinned (stochastic outcome): there is no exact result to compare
+with.  The test fixes the seeds, so the run is reproducible, and checks that
+training lowers the loss and that the learned flagger makes fewer per-cell
+errors against the truth than its MAD teacher on held-out data.
+
+Truth: a cell is interference when the power of the generator's RFI-only
+signal, channelised with the same windows as the F-engine (start m N + D_s,
+N-point DFT), exceeds mu = N sigma_t^2, the mean noise power of a cell.
+
+Why the student can beat its teacher: the MAD labeller decides per tile row
+and column (whole spectra, whole channels of the tile), so it flags all of a
+row or column when interference fills only part of it, and its statistics are
+inflated in tiles crowded with tones; the network decides per cell from a 7 x 7
+neighbourhood and learns the local look of interference.
+"""
+import numpy as np
+import pytest
+
+import paper_0910_1517_amd as corr
+import synth
+from gpu_util import FS, geom_dev, upload_streams
+from paper_0910_1517_amd.flagger import Flagger
+
+pytestmark = pytest.mark.gpu
+
+N, SIGMA_T = 1024, 12.0
+MIXED = dict(bl_frac=0.5, nb_p=0.01)  # band-limited bursts, intermittent lines
+
+
+def dataset(S, T, seed, mixed):
+    """Device power [S][T][C] and MAD labels of RFI-injected voltages, and the
+    host truth mask."""
+    import torch
+    geo = synth.make_geometry(S // 2, seed=seed)
+    rfi = synth.RFI(N, seed=seed + 1, **(MIXED if mixed else {}))
+    x = synth.voltages(S, N * T + 16, geo, FS, seed=seed, sigma_t=SIGMA_T, rfi=rfi)
+    r = rfi.signal(S, N * T + 16, SIGMA_T)
+    truth = np.empty((S, T, N // 2), dtype=bool)
+    for s in range(S):
+        w = r[s, geo.D[s]:geo.D[s] + N * T].reshape(T, N)
+        truth[s] = np.abs(np.fft.rfft(w, axis=1)[:, :N // 2]) ** 2 > N * SIGMA_T ** 2
+    plan = corr.Plan(S, N, T)
+    x_dev, rs = upload_streams(x, N, T, 16)
+    spec = plan.alloc("spectra", zero=False)
+    power = plan.alloc("power", zero=False).view(S, T, N // 2)
+    plan.fengine(x_dev, geom_dev(geo), spec, power=power, row_stride=rs)
+    mad = plan.alloc("flags").view(S, T, N // 2)
+    plan.mad_flag(power, mad, 3.0)
+    torch.cuda.synchronize()
+    return power, mad, truth
+
+
+def errors(flags, truth):
+    f = flags.astype(bool)
+    fp, fn = int((f & ~truth).sum()), int((~f & truth).sum())
+    return fp, fn, fp / max(1, (~truth).sum()), fn / max(1, truth.sum())
+
+
+def test_learned_flagger_beats_its_mad_teacher_on_held_out_data():
+    import torch
+    train = dataset(8, 2048, 1000, mixed=True)
+    fl = Flagger(seed=1, batch=16, lr=2e-3)
+    losses = fl.train(train[0], train[1], 1000)
+    first, last = losses[:10].mean(), losses[-50:].mean()
+    print("loss %.4f -> %.4f" % (first, last))
+    assert np.isfinite(losses).all() and last < 0.3 * first
+    for seed, mixed in [(2100, True), (3100, False)]:
+        power, mad, truth = dataset(8, 1024, seed, mixed)
+        cnn = torch.empty_like(mad)
+        fl.infer(power, cnn, threshold=0.5)
+        torch.cuda.synchronize()
+        m = errors(mad.cpu().numpy(), truth)
+        c = errors(cnn.cpu().numpy(), truth)
+        print("seed %d (%s RFI): MAD false %.4f miss %.4f errors %d | CNN false %.4f miss %.4f errors %d"
+              % (seed, "mixed" if mixed else "tones+bursts", m[2], m[3], m[0] + m[1], c[2], c[3], c[0] + c[1]))
+        assert c[0] + c[1] < m[0] + m[1]   # fewer per-cell errors than the teacher
+        assert c[2] < m[2]                 # and less clean data thrown away
+        assert c[3] < 0.35                 # while still catching most of the interference
