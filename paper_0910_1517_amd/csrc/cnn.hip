@@ -287,21 +287,49 @@ __global__ void cnn_adam_kernel(float *p, float *m, float *v, const float *__res
 
 // ----------------------------------------------------------------- inference
 
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef short short2v __attribute__((ext_vector_type(2)));
 typedef float float16v __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int PC = W + 2;  // padded columns: zero column at each edge
-constexpr int RING = 6;    // rows kept of the layer-1 output and of the layer-3 tap sums
-constexpr int IWG = 512;   // 8 waves, one 32-column strip each
+constexpr int XCOLS = W + 4;  // input columns: zero column on the left, three on the right
+constexpr int XP = H + 2;     // input column pitch (rows, zero row at each edge); odd in dwords
+constexpr int PC = W + 2;     // activation row pitch: one zero column at each edge
+constexpr int RING = 6;     // rows kept of the layer-1 output and of the layer-3 tap sums
+constexpr int ZROW = RING;  // an all-zero row standing for rows outside the tile
+constexpr int IWG = 512;    // 8 waves, one 32-column strip each
 
 // Accumulator layout of a 32 x 32 MFMA: register j of lane l holds row
 // 8 (j / 4) + 4 (l / 32) + j mod 4, column l mod 32.
 __device__ inline int acc_row(int j, int half) { return 8 * (j / 4) + 4 * half + (j & 3); }
 
+// Two floats -> two FP16 (round to nearest even) with negatives set to +0:
+// ReLU commutes with the monotone conversion, and on FP16 bit patterns the
+// signed 16-bit max against 0 clears exactly the negative values.
+__device__ inline uint32_t relu_h2(float a, float b) {
+    const half2v h = __builtin_convertvector((float2v){a, b}, half2v);
+    const short2v m = __builtin_elementwise_max(__builtin_bit_cast(short2v, h), (short2v){0, 0});
+    return __builtin_bit_cast(uint32_t, m);
+}
+
+__device__ inline int ring_slot(int row) { return (unsigned)row < (unsigned)H ? row % RING : ZROW; }
+
+// Byte offset of the 16-byte half `h` (channels 8h .. 8h + 7) of pixel column
+// pcol in a layer-1 output row: the halves swap places by bit 2 xor bit 3 of
+// the column, so the 16-byte reads of 8 (or 16) consecutive lanes cover all 32
+// (or 64) LDS banks once.
+__device__ inline int a1_off(int pcol, int h) { return 32 * pcol + 16 * (h ^ (((pcol >> 2) ^ (pcol >> 3)) & 1)); }
+
 // One workgroup per tile.  Wave w owns columns 32 w .. 32 w + 31 and walks the
 // tile two rows at a time.  MFMA roles (32 x 32 x 16, FP16 in, FP32 out):
 //   layer 1: rows = (row slot, out channel) for the two rows R, R + 1;
-//            K = 4 input rows x 3 column offsets (12 of 16 used);
+//            K = 4 input rows x 4 column offsets, lane half h taking input
+//            rows 2h and 2h + 1, slot j = (row 2h + j mod 2, offset j / 2):
+//            with the input stored column-major each slot pair is one aligned
+//            dword (offset 3 has zero weight; the bias rides on slot 7 of
+//            half 0, set to 1);
 //   layer 2: rows = (row slot, out channel) for rows r, r + 1; one product
 //            per (input row r - 1 .. r + 2, column offset), K = 16 channels,
 //            the weights of the taps a row slot does not use set to zero;
@@ -311,61 +339,40 @@ __device__ inline int acc_row(int j, int half) { return 8 * (j / 4) + 4 * half +
 //            the 9 shifted neighbours of p, read from LDS.
 __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict__ params,
                                                         const float *__restrict__ power, int64_t T, int C,
-                                                        float thr_logit, uint8_t *__restrict__ flags,
+                                                        int n_tiles, float thr_logit, uint8_t *__restrict__ flags,
                                                         float *__restrict__ logits) {
-    __shared__ _Float16 xs[H + 2][PC];
-    __shared__ __align__(16) _Float16 a1s[RING][PC][16];
-    __shared__ float us[RING][PC][9];
+    __shared__ __align__(16) _Float16 xs[XCOLS][XP];  // column-major input
+    __shared__ __align__(16) _Float16 a1s[RING + 1][PC][16];
+    __shared__ float us[RING + 1][PC][9];
     __shared__ float colv[W];
 
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int half = lane >> 5, col = lane & 31;
-    int s, k0;
-    int64_t m0;
-    tile_coords(blockIdx.x, T, C, s, m0, k0);
-    const int64_t base = ((int64_t)s * T + m0) * C + k0;
+    const int pcx = t & (W - 1), rh = t >> 8;  // staging: column pcx, rows rh, rh + 2, ...
 
-    // ---- stage the tile: reference level, then x = log(1 + P / m) in FP16
-    float pv[32];
-    {
-        const int c = t & (W - 1), rh = t >> 8;  // rows rh, rh + 2, ...
-        float cs = 0.f;
-#pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            pv[q] = power[base + (int64_t)(rh + 2 * q) * C + c];
-            cs += pv[q];
-        }
-        // column sums: rows of parity 0 first, then add parity 1
-        if (rh == 0) colv[c] = cs;
-        __syncthreads();
-        if (rh == 1) colv[c] = (colv[c] + cs) * (1.0f / H);
-        __syncthreads();
-        block_sort(colv, W);
-        const float med = 0.5f * (colv[W / 2 - 1] + colv[W / 2]);
-        const float lv = med > 0.f ? med : 1.f;
-#pragma unroll
-        for (int q = 0; q < 32; ++q) xs[rh + 2 * q + 1][c + 1] = (_Float16)log1pf(pv[q] / lv);
-        // zero borders: rows 0 and H + 1, columns 0 and W + 1 of every buffer
-        for (int e = t; e < 2 * PC; e += IWG) xs[e < PC ? 0 : H + 1][e % PC] = (_Float16)0.f;
-        for (int e = t; e < 2 * (H + 2); e += IWG) xs[e % (H + 2)][e < H + 2 ? 0 : PC - 1] = (_Float16)0.f;
-        for (int e = t; e < RING * 2 * 16; e += IWG) {
-            const int rr = e / 32, side = (e / 16) & 1, ch = e & 15;
-            a1s[rr][side ? PC - 1 : 0][ch] = (_Float16)0.f;
-        }
-        for (int e = t; e < RING * 2 * 9; e += IWG) {
-            const int rr = e / 18, side = (e / 9) & 1, k = e % 9;
-            us[rr][side ? PC - 1 : 0][k] = 0.f;
-        }
+    // ---- zero borders and zero rows, written once (never overwritten below)
+    for (int e = t; e < 4 * XP; e += IWG) xs[(e / XP) == 0 ? 0 : W + (e / XP)][e % XP] = (_Float16)0.f;
+    for (int e = t; e < 2 * W; e += IWG) xs[1 + (e >> 1)][(e & 1) ? H + 1 : 0] = (_Float16)0.f;
+    for (int e = t; e < RING * 2 * 16; e += IWG) {
+        const int rr = e / 32, side = (e / 16) & 1, ch = e & 15;
+        a1s[rr][side ? PC - 1 : 0][ch] = (_Float16)0.f;
     }
+    for (int e = t; e < PC * 16; e += IWG) a1s[ZROW][e >> 4][e & 15] = (_Float16)0.f;
+    for (int e = t; e < RING * 2 * 9; e += IWG) {
+        const int rr = e / 18, side = (e / 9) & 1, k = e % 9;
+        us[rr][side ? PC - 1 : 0][k] = 0.f;
+    }
+    for (int e = t; e < PC * 9; e += IWG) us[ZROW][e / 9][e % 9] = 0.f;
 
     // ---- weights as MFMA A operands (lane: row = lane mod 32, K slots 8 half + j)
     const int arow = lane & 31, aslot = arow >> 4, ao = arow & 15;
     half8 A1, A3, A2[4][3];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const int k = 8 * half + j, rho = k / 3, dv = k % 3;
-        const int u = rho - aslot;
-        A1[j] = (_Float16)((k < 12 && u >= 0 && u <= 2) ? params[kW1 + ao * 9 + u * 3 + dv] : 0.f);
+        const int rho = 2 * half + (j & 1), dv = j >> 1, u = rho - aslot;
+        float w = (dv < 3 && u >= 0 && u <= 2) ? params[kW1 + ao * 9 + u * 3 + dv] : 0.f;
+        if (half == 0 && j == 7) w = params[kB1 + ao];  // constant-1 slot: the bias
+        A1[j] = (_Float16)w;
         const int ch = 8 * (j / 4) + 4 * half + (j & 3);
         A3[j] = (_Float16)(arow < 9 ? params[kW3 + ch * 9 + arow] : 0.f);
     }
@@ -378,96 +385,137 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
                 const int cin = 8 * half + j, u = p - aslot;
                 A2[p][dv][j] = (_Float16)((u >= 0 && u <= 2) ? params[kW2 + ((ao * 16 + cin) * 3 + u) * 3 + dv] : 0.f);
             }
-    float bias1[16], bias2[16];
+    float16v bias2;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int o = acc_row(j, half) & 15;
-        bias1[j] = params[kB1 + o];
-        bias2[j] = params[kB2 + o];
-    }
+    for (int j = 0; j < 16; ++j) bias2[j] = params[kB2 + (acc_row(j, half) & 15)];
     const float b3 = params[kB3];
-    __syncthreads();
+    const float16v zero16 = {};
 
     const int c0 = wv * 32;
     const int pc = c0 + col + 1;  // padded column of this lane's pixel
-    const half8 zero8 = {};
+    // this lane's input window: padded rows R + 2 half + (0, 1) (one dword per
+    // column), padded columns pc - 1 .. pc + 2
+    const uint32_t *xl = reinterpret_cast<const uint32_t *>(&xs[c0 + col][2 * half]);
+    const uint32_t bias_and = half ? 0xFFFFFFFFu : 0x0000FFFFu;  // half 0: slot 7 := 1.0
+    const uint32_t bias_or = half ? 0u : 0x3C000000u;
+    char *a1base = reinterpret_cast<char *>(&a1s[0][0][0]);
+    const int a1w0 = a1_off(pc, 0) + 8 * half, a1w1 = a1_off(pc, 1) + 8 * half;
+    int a1rd[3];
+#pragma unroll
+    for (int dv = 0; dv < 3; ++dv) a1rd[dv] = a1_off(pc - 1 + dv, half);
+    float *uw = &us[0][pc][0];
+    const float *ur = &us[0][pc - 1][0];
+    constexpr int XCOL = XP / 2, AROW = PC * 16 * 2, UROW = PC * 9;  // dwords, bytes, floats
 
-    for (int k = -1; k <= H / 2; ++k) {
-        // (1) layer 1 for rows R, R + 1 (R = 2k + 2)
-        const int R = 2 * k + 2;
-        if (R < H) {
-            half8 B;
+    // power of the first tile; later tiles are fetched while the previous one computes
+    float pv[32];
+    auto tile_base = [&](int tile) {
+        int s, k0;
+        int64_t m0;
+        tile_coords(tile, T, C, s, m0, k0);
+        return ((int64_t)s * T + m0) * C + k0;
+    };
+    int tile = blockIdx.x;
+    if (tile < n_tiles) {
+        const int64_t b0 = tile_base(tile);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int kk = 8 * half + j;
-                B[j] = kk < 12 ? xs[R + kk / 3][c0 + col + kk % 3] : (_Float16)0.f;
-            }
-            float16v D;
+        for (int q = 0; q < 32; ++q) pv[q] = power[b0 + (int64_t)(rh + 2 * q) * C + pcx];
+    }
+    for (; tile < n_tiles; tile += gridDim.x) {
+        const int64_t base = tile_base(tile);
+        // ---- stage the tile: reference level, then x = log(1 + P / m) in FP16
+        {
+            float cs = 0.f;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) D[j] = bias1[j];
-            D = __builtin_amdgcn_mfma_f32_32x32x16_f16(A1, B, D, 0, 0, 0);
+            for (int q = 0; q < 32; ++q) cs += pv[q];
+            __syncthreads();  // the previous tile is done with colv, xs, a1s and us
+            if (rh == 0) colv[pcx] = cs;
+            __syncthreads();
+            if (rh == 1) colv[pcx] = (colv[pcx] + cs) * (1.0f / H);
+            __syncthreads();
+            block_sort(colv, W);
+            const float med = 0.5f * (colv[W / 2 - 1] + colv[W / 2]);
+            const float inv = 1.0f / (med > 0.f ? med : 1.f);
 #pragma unroll
-            for (int sl = 0; sl < 2; ++sl) {
-                _Float16 *dst = &a1s[(R + sl) % RING][pc][0];
+            for (int q = 0; q < 32; ++q) xs[pcx + 1][rh + 2 * q + 1] = (_Float16)__logf(1.0f + pv[q] * inv);
+            const int next = tile + gridDim.x;
+            if (next < n_tiles) {
+                const int64_t bn = tile_base(next);
 #pragma unroll
-                for (int g = 0; g < 2; ++g) {
-                    typedef _Float16 half4 __attribute__((ext_vector_type(4)));
-                    half4 h4;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) h4[q] = (_Float16)fmaxf(D[8 * sl + 4 * g + q], 0.f);
-                    *reinterpret_cast<half4 *>(dst + 8 * g + 4 * half) = h4;
-                }
-            }
-        }
-        __syncthreads();
-        if (k < 0) continue;
-        if (k < H / 2) {
-            // (2) layer 2 for rows r = 2k, 2k + 1 and the layer-3 tap sums U
-            const int r = 2 * k;
-            float16v D;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) D[j] = bias2[j];
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int rho = r - 1 + p;
-                const bool in = rho >= 0 && rho < H;
-#pragma unroll
-                for (int dv = 0; dv < 3; ++dv) {
-                    const half8 F =
-                        in ? *reinterpret_cast<const half8 *>(&a1s[(in ? rho : 0) % RING][pc - 1 + dv][8 * half])
-                           : zero8;
-                    D = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[p][dv], F, D, 0, 0, 0);
-                }
-            }
-#pragma unroll
-            for (int sl = 0; sl < 2; ++sl) {
-                half8 Bu;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) Bu[j] = (_Float16)fmaxf(D[8 * sl + j], 0.f);
-                float16v U = {};
-                U = __builtin_amdgcn_mfma_f32_32x32x16_f16(A3, Bu, U, 0, 0, 0);
-                float *dst = &us[(r + sl) % RING][pc][0];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) dst[4 * half + j] = U[j];
-                if (half == 0) dst[8] = U[4];
+                for (int q = 0; q < 32; ++q) pv[q] = power[bn + (int64_t)(rh + 2 * q) * C + pcx];
             }
         }
         __syncthreads();
-        // (3) output rows 2k - 2, 2k - 1 (all U rows they need are in place)
-        if (k >= 1) {
-            const int r = 2 * k - 2 + half;
-            float z = b3;
+
+        for (int k = -1; k <= H / 2; ++k) {
+            // (1) layer 1 for rows R, R + 1 (R = 2k + 2)
+            const int R = 2 * k + 2;
+            if (R < H) {
+                const uint32_t *xr = xl + R / 2;
+                u32x4 bx;
 #pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                const int rr = r + u - 1;
-                if (rr >= 0 && rr < H) {
+                for (int dv = 0; dv < 4; ++dv) bx[dv] = xr[dv * XCOL];
+                bx[3] = (bx[3] & bias_and) | bias_or;
+                const float16v D =
+                    __builtin_amdgcn_mfma_f32_32x32x16_f16(A1, __builtin_bit_cast(half8, bx), zero16, 0, 0, 0);
 #pragma unroll
-                    for (int v = 0; v < 3; ++v) z += us[rr % RING][pc + v - 1][3 * u + v];
+                for (int sl = 0; sl < 2; ++sl) {
+                    char *row = a1base + ring_slot(R + sl) * AROW;
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        const int j0 = 8 * sl + 4 * g;
+                        uint2 v;
+                        v.x = relu_h2(D[j0 + 0], D[j0 + 1]);
+                        v.y = relu_h2(D[j0 + 2], D[j0 + 3]);
+                        *reinterpret_cast<uint2 *>(row + (g ? a1w1 : a1w0)) = v;
+                    }
                 }
             }
-            const int64_t gp = base + (int64_t)r * C + c0 + col;
-            flags[gp] = z > thr_logit ? 1 : 0;
-            if (logits) logits[gp] = z;
+            __syncthreads();
+            if (k < 0) continue;
+            if (k < H / 2) {
+                // (2) layer 2 for rows r = 2k, 2k + 1 and the layer-3 tap sums U
+                const int r = 2 * k;
+                float16v D = bias2;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const char *fr = a1base + ring_slot(r - 1 + p) * AROW;
+#pragma unroll
+                    for (int dv = 0; dv < 3; ++dv) {
+                        const half8 F = *reinterpret_cast<const half8 *>(fr + a1rd[dv]);
+                        D = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[p][dv], F, D, 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int sl = 0; sl < 2; ++sl) {
+                    u32x4 bu;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) bu[q] = relu_h2(D[8 * sl + 2 * q], D[8 * sl + 2 * q + 1]);
+                    const float16v U =
+                        __builtin_amdgcn_mfma_f32_32x32x16_f16(A3, __builtin_bit_cast(half8, bu), zero16, 0, 0, 0);
+                    float *dst = uw + ring_slot(r + sl) * UROW;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) dst[4 * half + j] = U[j];
+                    if (half == 0) dst[8] = U[4];
+                }
+            }
+            __syncthreads();
+            // (3) output rows 2k - 2 (lanes 0-31) and 2k - 1 (lanes 32-63)
+            if (k >= 1) {
+                const int r = 2 * k - 2 + half;
+                float z = b3;
+#pragma unroll
+                for (int u = 0; u < 3; ++u) {
+                    // rows of the two lane halves are uniform: pick the slot of this half
+                    const int s0 = ring_slot(2 * k - 3 + u), s1 = ring_slot(2 * k - 2 + u);
+                    const float *row = ur + (half ? s1 : s0) * UROW;
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) z += row[9 * v + 3 * u + v];
+                }
+                const int64_t gp = base + (int64_t)r * C + c0 + col;
+                flags[gp] = z > thr_logit ? 1 : 0;
+                if (logits) logits[gp] = z;
+            }
         }
     }
 }
@@ -520,8 +568,15 @@ hipError_t launch_cnn_adam(float *params, float *m, float *v, const float *grad,
 
 hipError_t launch_cnn_infer(const float *params, const float *power, int S, int64_t T, int C, float thr_logit,
                             uint8_t *flags, float *logits, hipStream_t st) {
-    const int64_t n_tiles = (int64_t)S * (T / H) * (C / W);
-    hipLaunchKernelGGL(cnn_infer_kernel, dim3((unsigned)n_tiles), dim3(IWG), 0, st, params, power, T, C, thr_logit,
+    const int n_tiles = (int)((int64_t)S * (T / H) * (C / W));
+    // persistent: one workgroup per compute unit (the LDS use allows one), each
+    // fetching its next tile's power while it computes the current one
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    const int grid = std::max(1, std::min(n_tiles, cus));
+    hipLaunchKernelGGL(cnn_infer_kernel, dim3(grid), dim3(IWG), 0, st, params, power, T, C, n_tiles, thr_logit,
                        flags, logits);
     return hipGetLastError();
 }

@@ -69,62 +69,55 @@ __global__ void __launch_bounds__(KT) mad_tile_kernel(const float *__restrict__ 
     for (int r = 0; r < TT; ++r) flags[base + (int64_t)r * C] = rowf[r] | cf;
 }
 
-// Zero flagged cells of the X-layout spectra in place; one thread per
-// 16-byte chunk, index g C S + (k/8) S 8 + s 8 + k mod 8.
-template <int G>
-__global__ void apply_flags_kernel(const uint8_t *__restrict__ flags, uint8_t *spec, int S, int T, int C) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)(T / G) * C * S;
-    if (idx >= total) return;
-    const int kk = (int)(idx & 7);
-    const int s = (int)((idx >> 3) % S);
-    const int64_t rest = (idx >> 3) / S;
-    const int kb = (int)(rest % (C / 8));
-    const int g = (int)(rest / (C / 8));
-    const int k = 8 * kb + kk;
-    const uint8_t *f = flags + ((int64_t)s * T + (int64_t)g * G) * C + k;
-    uint4 *chunk = reinterpret_cast<uint4 *>(spec) + idx;
-    if constexpr (G == kChunk8) {  // 8 real bytes, then 8 imaginary bytes
-        uint32_t lo = 0, hi = 0;   // keep masks for spectra 0..3 / 4..7
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            lo |= (f[(int64_t)q * C] ? 0u : 0xFFu) << (8 * q);
-            hi |= (f[(int64_t)(q + 4) * C] ? 0u : 0xFFu) << (8 * q);
-        }
-        if ((lo & hi) != 0xFFFFFFFFu) {
-            uint4 v = *chunk;
-            v.x &= lo;
-            v.y &= hi;
-            v.z &= lo;
-            v.w &= hi;
-            *chunk = v;
-        }
-    } else {  // two complex64
-        const bool f0 = f[0] != 0, f1 = f[C] != 0;
-        if (f0 || f1) {
-            uint4 v = *chunk;
-            if (f0) v.x = v.y = 0u;
-            if (f1) v.z = v.w = 0u;
-            *chunk = v;
-        }
-    }
+// Keep masks and zeroing in one pass.  A workgroup owns 32 spectra (one keep
+// word) x 256 channels of one signal.  Thread t builds the keep word of
+// channel k0 + t from the 32 flag bytes of that channel (the loads of the
+// workgroup's threads are consecutive bytes of a row), writes it to
+// keep[k][s][w] when keep is given; then the workgroup zeroes the flagged cells of its X-layout chunks (index
+// g C S + (k/8) S 8 + s 8 + k mod 8 in 16-byte units), reading and writing a
+// chunk only when one of its cells is flagged.
+__device__ inline uint32_t expand4(uint32_t b) {  // 4 bits -> 4 bytes of 0x00 / 0xFF
+    return ((b * 0x00204081u) & 0x01010101u) * 0xFFu;
 }
 
-// keep[k][s][w] bit i = 1 when cell (s, 32 w + i, k) is not flagged.
-__global__ void keep_bits_kernel(const uint8_t *__restrict__ flags, uint32_t *keep, int S, int T, int C) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int W = T / 32;
-    const int64_t total = (int64_t)W * S * C;
-    if (idx >= total) return;
-    const int k = (int)(idx % C);  // channel fastest: coalesced flag reads
-    const int64_t rest = idx / C;
-    const int s = (int)(rest % S);
-    const int w = (int)(rest / S);
+template <int G>
+__global__ void __launch_bounds__(256) apply_keep_kernel(const uint8_t *__restrict__ flags, uint8_t *spec,
+                                                         uint32_t *keep, int S, int T, int C) {
+    const int t = threadIdx.x;
+    const int nkb = C / 256, W = T / 32;
+    const int kblk = blockIdx.x % nkb;
+    const int w = (blockIdx.x / nkb) % W;
+    const int s = blockIdx.x / (nkb * W);
+    const int k = kblk * 256 + t;
     const uint8_t *f = flags + ((int64_t)s * T + (int64_t)w * 32) * C + k;
     uint32_t bits = 0;
 #pragma unroll
     for (int i = 0; i < 32; ++i) bits |= (f[(int64_t)i * C] ? 0u : 1u) << i;
-    keep[((int64_t)k * S + s) * W + w] = bits;
+    if (keep) keep[((int64_t)k * S + s) * W + w] = bits;
+    if (__syncthreads_and(bits == 0xFFFFFFFFu)) return;  // nothing flagged in this block
+    uint4 *chunks = reinterpret_cast<uint4 *>(spec);
+    constexpr int NG = 32 / G;  // chunks per channel in the block
+    // thread t walks chunks (g, channel) with channel = t; consecutive threads
+    // touch consecutive chunks of a 128-byte line
+#pragma unroll 4
+    for (int g = 0; g < NG; ++g) {
+        const uint32_t m = (bits >> (G * g)) & ((1u << G) - 1u);
+        if (m == (1u << G) - 1u) continue;
+        const int64_t gg = (int64_t)w * NG + g;
+        uint4 *c = chunks + ((gg * (C / 8) + k / 8) * S + s) * 8 + (k & 7);
+        uint4 v = *c;
+        if constexpr (G == kChunk8) {  // 8 real bytes (spectra 0..7), then 8 imaginary bytes
+            const uint32_t lo = expand4(m & 15u), hi = expand4(m >> 4);
+            v.x &= lo;
+            v.y &= hi;
+            v.z &= lo;
+            v.w &= hi;
+        } else {  // two complex64
+            if (!(m & 1u)) v.x = v.y = 0u;
+            if (!(m & 2u)) v.z = v.w = 0u;
+        }
+        *c = v;
+    }
 }
 
 // counts[k][p] += popcount over time of keep_i & keep_j; one channel per
@@ -176,17 +169,11 @@ hipError_t launch_mad_flag(const float *power, int S, int T, int C, float M, uin
 
 hipError_t launch_apply_flags(int precision, const uint8_t *flags, void *spec, uint32_t *keep, int S, int T,
                               int C, hipStream_t st) {
-    const int G = precision == CORR_FP32 ? kChunk32 : kChunk8;
-    const int64_t total = (int64_t)(T / G) * C * S;
-    const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+    const dim3 grid((unsigned)((int64_t)S * (T / 32) * (C / 256))), block(256);
     if (precision == CORR_FP32)
-        hipLaunchKernelGGL((apply_flags_kernel<kChunk32>), grid, block, 0, st, flags, (uint8_t *)spec, S, T, C);
+        hipLaunchKernelGGL((apply_keep_kernel<kChunk32>), grid, block, 0, st, flags, (uint8_t *)spec, keep, S, T, C);
     else
-        hipLaunchKernelGGL((apply_flags_kernel<kChunk8>), grid, block, 0, st, flags, (uint8_t *)spec, S, T, C);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !keep) return e;
-    const int64_t nk = (int64_t)(T / 32) * S * C;
-    hipLaunchKernelGGL(keep_bits_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, st, flags, keep, S, T, C);
+        hipLaunchKernelGGL((apply_keep_kernel<kChunk8>), grid, block, 0, st, flags, (uint8_t *)spec, keep, S, T, C);
     return hipGetLastError();
 }
 

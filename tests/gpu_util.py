@@ -5,6 +5,7 @@ from __future__ import annotations
 
 import numpy as np
 
+import oracle
 import paper_0910_1517_amd as corr
 
 FS = 66.666666e6
@@ -62,3 +63,24 @@ def pack_input(plan: corr.Plan, arr: np.ndarray):
     spec = plan.alloc("spectra", zero=False)
     plan.xpack(inp, spec)
     return spec
+
+
+def near_threshold_cells(P64, M=3.0):
+    """Cells whose row or column statistic lies within 1e-4 (relative) of Eq. 4's threshold."""
+    S, T, C = P64.shape
+    near = np.zeros(P64.shape, dtype=bool)
+    for s in range(S):
+        for m0 in range(0, T, 64):
+            for k0 in range(0, C, 256):
+                t = P64[s, m0:m0 + 64, k0:k0 + 256]
+                for axis, sl in ((1, "row"), (0, "col")):
+                    v = t.mean(axis=axis)
+                    med = oracle.median(v)
+                    mad = oracle.median(np.abs(v - med))
+                    d = np.abs(np.abs(v - med) - M * mad / 0.6745)
+                    close = d <= 1e-4 * max(M * mad / 0.6745, 1e-30)
+                    if sl == "row":
+                        near[s, m0:m0 + 64, k0:k0 + 256] |= close[:, None]
+                    else:
+                        near[s, m0:m0 + 64, k0:k0 + 256] |= close[None, :]
+    return near

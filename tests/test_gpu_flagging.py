@@ -6,7 +6,7 @@ import pytest
 import oracle
 import paper_0910_1517_amd as corr
 import synth
-from gpu_util import FS, acc_sum, geom_dev, pack_input, run_fengine, upload_streams
+from gpu_util import FS, acc_sum, geom_dev, near_threshold_cells, pack_input, run_fengine, upload_streams
 
 pytestmark = pytest.mark.gpu
 
@@ -41,27 +41,6 @@ def test_power_output_matches_oracle(prec):
     assert np.max(np.abs(pg - P64) / ref) < 1e-5
 
 
-def _near_threshold_cells(P64, M=3.0):
-    """Cells whose row or column statistic lies within 1e-4 (relative) of Eq. 4's threshold."""
-    S, T, C = P64.shape
-    near = np.zeros(P64.shape, dtype=bool)
-    for s in range(S):
-        for m0 in range(0, T, 64):
-            for k0 in range(0, C, 256):
-                t = P64[s, m0:m0 + 64, k0:k0 + 256]
-                for axis, sl in ((1, "row"), (0, "col")):
-                    v = t.mean(axis=axis)
-                    med = oracle.median(v)
-                    mad = oracle.median(np.abs(v - med))
-                    d = np.abs(np.abs(v - med) - M * mad / 0.6745)
-                    close = d <= 1e-4 * max(M * mad / 0.6745, 1e-30)
-                    if sl == "row":
-                        near[s, m0:m0 + 64, k0:k0 + 256] |= close[:, None]
-                    else:
-                        near[s, m0:m0 + 64, k0:k0 + 256] |= close[None, :]
-    return near
-
-
 def test_mad_flags_match_oracle():
     import torch
     S, N, T = 4, 1024, 256
@@ -80,7 +59,7 @@ def test_mad_flags_match_oracle():
     diff = fg != fo
     assert fg.max() <= 1
     # FP32 power and statistics vs FP64: a decision may only differ at the threshold
-    assert not np.any(diff & ~_near_threshold_cells(P64))
+    assert not np.any(diff & ~near_threshold_cells(P64))
     assert fo.mean() > 0.01  # the injected RFI is found
 
 
