@@ -129,7 +129,12 @@ def test_precision_form_int8_xengine_bit_exact_sampled_channels():
 
 def test_batched_form_sampled_channels():
     """The six uneven sub-arrays in one captured graph (autotuned splits, held
-    scales): every sub-array's sampled channels against the FP64 oracle."""
+    scales).  For every sub-array's sampled channels the oracle runs its own
+    int8 path (its scales, RNE quantisation, int64 products, FP64 scaling):
+    the GPU must reproduce those visibilities, and its error against FP64 must
+    be the quantisation's own.  int8 requantisation noise averages down as
+    T^(-1/2), so the short integrations of this form (1024-2048 spectra) sit
+    above the 1e-3 reached at 32768 spectra."""
     import torch
     sub_arrays = [(8, 256, 65536), (16, 512, 32768), (30, 1024, 16384), (48, 2048, 8192), (60, 4096, 2048),
                   (64, 8192, 1024)]
@@ -140,22 +145,31 @@ def test_batched_form_sampled_channels():
     b = corr.Batch(shapes)
     for i, sh in enumerate(shapes):
         S, N, T = sh["n_signals"], sh["fft_len"], sh["n_spectra"]
+        C = N // 2
         geo = synth.make_geometry((S + 1) // 2, seed=synth.BASE_SEED + 10 + i).subset(np.arange(S))
         rs = (N * T + 16 + 255) // 256 * 256
         x = synth.voltages_device(S, N * T + 16, geo, seed=synth.BASE_SEED + 10 + i, row_stride=rs)
         g = corr.geom_to_device(corr.geom_array(geo.D, geo.f, geo.psi0, geo.rate))
+        chans = [37, C - 1]
+        Y = oracle.fengine_channels(x.cpu().numpy(), N, T, ogeom(geo), FS, chans)
+        oscale = oracle.int8_scale(oracle.sigma(Y))
         cal = corr.Plan(S, N, T, precision=corr.INT8, scale_mode=corr.SCALE_COMPUTE)
-        scale = torch.zeros(S * (N // 2), dtype=torch.float32, device="cuda")
+        scale = torch.zeros(S * C, dtype=torch.float32, device="cuda")
         tmp = cal.alloc("spectra", zero=False)
         cal.fengine(x, g, tmp, scale, row_stride=rs)
         torch.cuda.synchronize()
         del tmp, cal
+        scale.view(S, C)[:, chans] = torch.from_numpy(oscale.astype(np.float32)).cuda()
         p = b.plans[i]
         spec = p.alloc("spectra", zero=False)
         acc, state, vis = p.alloc("acc"), p.alloc("state"), p.alloc("vis")
         b.set_io(i, x=x, row_stride=rs, geom=g, spec=spec, scale=scale, acc=acc, state=state, vis=vis,
                  flags=corr.DUMP | corr.RESET)
-        data.append((geo, x, state, vis))
+        V64 = oracle.xengine(Y)
+        q = oracle.quantize_int8(Y, oscale.astype(np.float64))
+        vq = oracle.scale_visibilities(oracle.xengine_int(q), oscale.astype(np.float64))
+        Vq = vq[..., 0] + 1j * vq[..., 1]
+        data.append((chans, V64, Vq, vis))
     stream = torch.cuda.Stream()
     b.capture(stream)
     b.launch(stream)
@@ -163,14 +177,18 @@ def test_batched_form_sampled_channels():
     for i, sh in enumerate(shapes):
         S, N, T = sh["n_signals"], sh["fft_len"], sh["n_spectra"]
         C, P = N // 2, S * (S + 1) // 2
-        geo, x, state, vis = data[i]
-        chans = [37, C - 1]
+        chans, V64, Vq, vis = data[i]
         vv = vis.view(C, P, 2)[chans].cpu().numpy().astype(np.float64)
         V = vv[..., 0] + 1j * vv[..., 1]
-        V64 = oracle.xengine(oracle.fengine_channels(x.cpu().numpy(), N, T, ogeom(geo), FS, chans))
-        e_max, e_fro = oracle.normalized_error(V, V64, S)
-        print("c4 sub-array %d (S=%d C=%d T=%d): e_fro %.3g" % (i, S, C, T, e_fro))
-        assert e_fro <= 1e-3
+        _, e_gpu = oracle.normalized_error(V, V64, S)
+        _, e_q = oracle.normalized_error(Vq, V64, S)
+        _, e_rep = oracle.normalized_error(V, Vq, S)
+        print("c4 sub-array %d (S=%d C=%d T=%d): e_fro vs FP64 %.3g (oracle int8 path %.3g), vs oracle int8 %.3g"
+              % (i, S, C, T, e_gpu, e_q, e_rep))
+        assert e_rep <= 1e-4                        # the GPU reproduces the int8 path
+        assert e_gpu <= 1.05 * e_q + 1e-5           # and its error is the quantisation's own
+        if T >= 8192:
+            assert e_gpu <= 1e-3
     b.close()
 
 
