@@ -10,13 +10,13 @@ timed beside it.  One step = F-engine (held requantisation scales, set once
 on a calibration pass like the paper's gain table) + X-engine + integrate
 with dump, over one block of all 64 signals.
 
-The value is the steady-state rate with the F-engine of block i + 1 running
-beside the X-engine of block i (two streams, two spectra buffers), the way a
-streaming correlator runs; --sequential reports the one-stream step instead.
-The per-kernel times are always those of the one-stream step.
+--streamed also times the blocks streamed, the F-engine of block i + 1
+running beside the X-engine of block i (two streams, two spectra buffers),
+and reports that rate as the value; the per-kernel times are always those of
+the one-stream step.
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus 1
-[--config c2|c3|c4|c5] [--no-fp32] [--no-cpu-baseline] [--sequential].  c4 is the batched
+[--config c2|c3|c4|c5] [--no-fp32] [--no-cpu-baseline] [--streamed].  c4 is the batched
 form (six uneven sub-arrays in one graph launch); c5 the flagged path with the
 learned RFI flagger (64 signals, 8192-pt FFT, 8192 spectra).
 """
@@ -53,8 +53,14 @@ FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
 # calibration copy, see profiles/), valid only for the kernel source they were
 # taken from: reported as `traffic` when the source hash still matches.
 MEASURED_TRAFFIC = {
-    "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine.hip", "sha256": None,
-                        "read": None, "write": None},
+    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4721834 KiB x 2.000, WRITE_SIZE 8388608 KiB x 1.000
+    "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
+                        "sha256": "b7aa213afd349f3daf0715719ac252218bc36ce86b368613d955c304b8bf279d",
+                        "read": 9.669e9, "write": 8.590e9},
+    # profiles/cnn_flagged_64sig_8192pt_8192spec.md: FETCH_SIZE 4194520 KiB x 2.000, WRITE_SIZE 2097152 KiB x 1.000
+    "cnn_infer_c5": {"source": "paper_0910_1517_amd/csrc/cnn.hip",
+                     "sha256": "1df4a694a2ec5fe763bd209b0fc65784f85bb9e00e540c37422ffe2f1c07f60c",
+                     "read": 8.590e9, "write": 2.147e9},
 }
 
 
@@ -292,6 +298,10 @@ def bench_rfi(args):
     log("generating %d x %d int8 samples on the GPU" % (S, rs))
     x = synth.voltages_device(S, N * T + 16, geo, seed=synth.BASE_SEED + 5, tone_bin=37, tone_N=N, row_stride=rs)
     g = corr.geom_to_device(corr.geom_array(geo.D, geo.f, geo.psi0, geo.rate))
+    # the 1 GiB read + 1 GiB write copy that scales a profiled run's HBM byte counters
+    src = x.view(-1)[: 1 << 30].view(torch.int32)
+    torch.neg(src, out=torch.empty_like(src))
+    del src
     scale = calibrate_scales(corr, torch, S, N, T, x, rs, g)
     plan = corr.Plan(S, N, T, precision=corr.INT8, scale_mode=corr.SCALE_HOLD)
     spec = plan.alloc("spectra", zero=False)
@@ -347,7 +357,7 @@ def bench_rfi(args):
         "x_engine_tops": round(xops / t["xengine"] / 1e12, 3),
         "roofline": {"kernel": "cnn_infer_kernel (fused 3-layer conv, FP16 MFMA)", "bound": "mfma",
                      "achieved": round(ach, 3), "peak": FP16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": round(ach * 1e12 / FP16_MFMA_PEAK, 4), "traffic": None,
+                     "frac": round(ach * 1e12 / FP16_MFMA_PEAK, 4), "traffic": measured_traffic("cnn_infer_c5"),
                      "algorithmic_flop_per_cell": CNN_FLOP_PER_CELL},
     }
     print(json.dumps(out), flush=True)
@@ -360,8 +370,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c3", choices=sorted(CONFIGS) + ["c4", "c5"])
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--sequential", action="store_true",
-                    help="report the one-stream step (F, then X, then integrate) as the value")
+    ap.add_argument("--streamed", action="store_true",
+                    help="also time blocks streamed (F of block i+1 beside X of block i) and report that as the value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="spectra in the CPU-oracle sample")
     args = ap.parse_args()
@@ -402,7 +412,7 @@ def main():
     log("int8: step %.3f ms (F %.3f, X %.3f, int %.3f)" % (r8["t_step"] * 1e3, r8["t_f"] * 1e3,
                                                           r8["t_x"] * 1e3, r8["t_int"] * 1e3))
     t8 = r8["t_step"]
-    if not args.sequential:
+    if args.streamed:
         torch.cuda.empty_cache()
         t8 = run_pipelined(corr, torch, corr.INT8, S, N, T, x_dev, rs, g_dev, args.steps, args.warmup, scale)
         log("int8 streamed (F of block i+1 beside X of block i): %.3f ms per block" % (t8 * 1e3))
@@ -416,7 +426,7 @@ def main():
         log("fp32: step %.3f ms (F %.3f, X %.3f, int %.3f)" % (r32["t_step"] * 1e3, r32["t_f"] * 1e3,
                                                               r32["t_x"] * 1e3, r32["t_int"] * 1e3))
         t32 = r32["t_step"]
-        if not args.sequential:
+        if args.streamed:
             torch.cuda.empty_cache()
             t32 = run_pipelined(corr, torch, corr.FP32, S, N, T, x_dev, rs, g_dev, max(3, args.steps // 4),
                                 min(2, args.warmup))
@@ -440,9 +450,8 @@ def main():
         "data": "synthetic (seeded Gaussian + common source + tone, generated on the GPU)",
         "config": {"workload": desc, "signals": S, "fft_len": N, "channels": C, "spectra": T,
                    "pairs": S * (S + 1) // 2, "sample_rate_hz": FS, "parallelism": "single GPU"},
-        "step_mode": "sequential" if args.sequential else
-                     "streamed: F-engine of block i+1 beside X-engine + integrate of block i (two streams, "
-                     "two spectra buffers)",
+        "step_mode": "streamed: F-engine of block i+1 beside X-engine + integrate of block i (two streams, "
+                     "two spectra buffers)" if args.streamed else "one stream: F-engine, X-engine, integrate",
         "int8": {"x_engine_tops": round(xops8 / r8["t_x"] / 1e12, 3),
                  "ms": {k: round(v * 1e3, 4) for k, v in r8.items() if k.startswith("t_")},
                  "sequential_step_ms": round(r8["t_step"] * 1e3, 4),
