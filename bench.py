@@ -172,8 +172,9 @@ def run_pipelined(corr, torch, prec, S, N, T, x_dev, rs, g_dev, steps, warmup, s
     return t
 
 
-def calibrate_scales(corr, torch, S, N, T, x_dev, rs, g_dev):
-    plan = corr.Plan(S, N, T, precision=corr.INT8, max_delay=16, scale_mode=corr.SCALE_COMPUTE)
+def calibrate_scales(corr, torch, S, N, T, x_dev, rs, g_dev, prec=None):
+    prec = corr.INT8 if prec is None else prec
+    plan = corr.Plan(S, N, T, precision=prec, max_delay=16, scale_mode=corr.SCALE_COMPUTE)
     spec = plan.alloc("spectra", zero=False)
     scale = torch.zeros(S * plan.C, dtype=torch.float32, device="cuda")
     plan.fengine(x_dev, g_dev, spec, scale, row_stride=rs)
@@ -338,6 +339,16 @@ def bench_rfi(args):
     torch.cuda.synchronize()
     plan.check_device_errors()
     t = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in ev])) * 1e-3 for i, n in enumerate(names)}
+    # the MAD flagger on the same power (the fallback and the network's teacher), timed apart
+    mad = plan.alloc("flags", zero=False)
+    em = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+    plan.mad_flag(power, mad, 3.0, stream=st)
+    for e0, e1 in em:
+        e0.record(st)
+        plan.mad_flag(power, mad, 3.0, stream=st)
+        e1.record(st)
+    torch.cuda.synchronize()
+    t_mad = float(np.mean([e0.elapsed_time(e1) for e0, e1 in em])) * 1e-3
     t_step = float(np.mean([e[0].elapsed_time(e[6]) for e in ev])) * 1e-3
     cells = S * T * C
     cnn_flops = float(cells) * CNN_FLOP_PER_CELL
@@ -354,6 +365,7 @@ def bench_rfi(args):
                                "learned flagger on %d power cells (%d tiles of 64 x 256)" % (cells, cells // 16384),
                    "parallelism": "single GPU"},
         "ms": {n: round(v * 1e3, 4) for n, v in t.items()},
+        "mad_flag_ms": round(t_mad * 1e3, 4),
         "x_engine_tops": round(xops / t["xengine"] / 1e12, 3),
         "roofline": {"kernel": "cnn_infer_kernel (fused 3-layer conv, FP16 MFMA)", "bound": "mfma",
                      "achieved": round(ach, 3), "peak": FP16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
@@ -370,6 +382,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c3", choices=sorted(CONFIGS) + ["c4", "c5"])
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--streamed", action="store_true",
                     help="also time blocks streamed (F of block i+1 beside X of block i) and report that as the value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -416,6 +429,16 @@ def main():
         torch.cuda.empty_cache()
         t8 = run_pipelined(corr, torch, corr.INT8, S, N, T, x_dev, rs, g_dev, args.steps, args.warmup, scale)
         log("int8 streamed (F of block i+1 beside X of block i): %.3f ms per block" % (t8 * 1e3))
+    r8f = None
+    if not args.no_fp8:
+        torch.cuda.empty_cache()
+        log("timing fp8 (e4m3) path")
+        scale8 = calibrate_scales(corr, torch, S, N, T, x_dev, rs, g_dev, corr.FP8_E4M3)
+        r8f = run_path(corr, torch, corr.FP8_E4M3, S, N, T, x_dev, rs, g_dev, max(3, args.steps // 2),
+                       min(2, args.warmup), scale8)
+        log("fp8: step %.3f ms (F %.3f, X %.3f, int %.3f)" % (r8f["t_step"] * 1e3, r8f["t_f"] * 1e3,
+                                                             r8f["t_x"] * 1e3, r8f["t_int"] * 1e3))
+        del scale8
     r32 = None
     t32 = None
     if not args.no_fp32:
@@ -487,6 +510,13 @@ def main():
                        "x_mfma_frac_algorithmic": round(xops32 / r32["t_x"] / FP32_MFMA_PEAK, 4),
                        "x_splits": r32["splits"]}
         out["int8_vs_fp32_speedup"] = round(t32 / t8, 3)
+    if r8f:
+        out["fp8_e4m3"] = {"correlated_bandwidth_mhz": round(bw(r8f["t_step"]), 3),
+                           "ms_per_step": round(r8f["t_step"] * 1e3, 4),
+                           "x_engine_tops": round(xops8 / r8f["t_x"] / 1e12, 3),
+                           "ms": {k: round(v * 1e3, 4) for k, v in r8f.items() if k.startswith("t_")},
+                           "x_hbm_frac": round(xin8 / r8f["t_x"] / HBM_PEAK, 4),
+                           "x_splits": r8f["splits"]}
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on %d spectra" % args.cpu_sample)
         mhz, dt, cores = cpu_baseline(S, N, args.cpu_sample)

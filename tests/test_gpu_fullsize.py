@@ -65,7 +65,8 @@ def test_gmrt_scale_fp32_sampled_channels():
 def test_precision_form_int8_sampled_channels():
     """64 signals, 4096-pt, 32768 spectra, int8 with held scales (calibration
     pass first, as the benchmark does): quantiser codes and visibilities of
-    sampled channels against the FP64 oracle."""
+    sampled channels against the FP64 oracle; then the FP8 (e4m3) variant's
+    visibilities."""
     import torch
     S, N, T = 64, 4096, 32768
     C = N // 2
@@ -101,9 +102,29 @@ def test_precision_form_int8_sampled_channels():
     print("c3 quantiser mismatches: %d of %d" % (bad.sum(), bad.size))
     assert np.abs(diff).max() <= 1 and np.all(frac[bad] < 1e-3) and bad.mean() <= 1e-4
     V = state_channels(state, C, plan.P, chans)
-    e_max, e_fro = oracle.normalized_error(V, oracle.xengine(Y), S)
+    V64 = oracle.xengine(Y)
+    e_max, e_fro = oracle.normalized_error(V, V64, S)
     print("c3 int8 sampled channels: e_max %.3g e_fro %.3g" % (e_max, e_fro))
     assert e_fro <= 1e-3
+    # the FP8 (OCP e4m3) variant of the same form: its own calibration (4 sigma -> 448)
+    del spec, acc, state, vis, plan
+    torch.cuda.empty_cache()
+    cal = corr.Plan(S, N, T, precision=corr.FP8_E4M3, scale_mode=corr.SCALE_COMPUTE)
+    scale8 = torch.zeros(S * C, dtype=torch.float32, device="cuda")
+    tmp = cal.alloc("spectra", zero=False)
+    cal.fengine(x, g, tmp, scale8, row_stride=rs)
+    torch.cuda.synchronize()
+    del tmp, cal
+    plan = corr.Plan(S, N, T, precision=corr.FP8_E4M3, scale_mode=corr.SCALE_HOLD)
+    spec = plan.alloc("spectra", zero=False)
+    acc, state, vis = plan.alloc("acc"), plan.alloc("state"), plan.alloc("vis")
+    plan.fengine(x, g, spec, scale8, row_stride=rs)
+    plan.xengine(spec, acc)
+    plan.integrate(acc, state, vis, scale8, flags=corr.DUMP)
+    plan.check_device_errors()
+    e_max8, e_fro8 = oracle.normalized_error(state_channels(state, C, plan.P, chans), V64, S)
+    print("c3 fp8 sampled channels: e_max %.3g e_fro %.3g" % (e_max8, e_fro8))
+    assert e_fro8 <= 5e-3
 
 
 def test_precision_form_int8_xengine_bit_exact_sampled_channels():
