@@ -208,7 +208,8 @@ corr_status corr_integrate(corr_plan_t *plan, void *d_acc, const float *d_scale,
  * broadband bursts, the column statistic (mean power of a channel over the
  * tile's spectra) persistent tones; a cell is flagged (1) when its row or its
  * column is.  Median of an even count = mean of the two middle values.
- *   d_flags  [S][T][C] uint8 (corr_plan_flags_bytes).
+ *   d_power  [S][T][C] float, 16-byte aligned.
+ *   d_flags  [S][T][C] uint8 (corr_plan_flags_bytes), 16-byte aligned.
  * Needs T % 64 == 0 (C = N/2 >= 256 is always a multiple of 256).
  * Errors: NULL, ALIGN, INVALID (shape, M <= 0), DEVICE. */
 corr_status corr_mad_flag(corr_plan_t *plan, const float *d_power, float M, uint8_t *d_flags,

@@ -299,7 +299,8 @@ corr_status corr_integrate(corr_plan_t *p, void *d_acc, const float *d_scale, do
 corr_status corr_mad_flag(corr_plan_t *p, const float *d_power, float M, uint8_t *d_flags, void *stream) {
     if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
     if (!d_power || !d_flags) return fail(p, CORR_ERR_NULL, "d_power and d_flags are required");
-    if (!aligned(d_power, 4)) return fail(p, CORR_ERR_ALIGN, "d_power must be 4-byte aligned");
+    if (!aligned(d_power, 16) || !aligned(d_flags, 16))
+        return fail(p, CORR_ERR_ALIGN, "d_power and d_flags must be 16-byte aligned");
     if (p->d.n_spectra % kFlagTileSpectra || p->M % kFlagTileChannels)
         return fail(p, CORR_ERR_INVALID, "flagging needs T %% %d == 0 and C %% %d == 0", kFlagTileSpectra,
                     kFlagTileChannels);

@@ -20,53 +20,147 @@ namespace {
 constexpr int TT = kFlagTileSpectra;   // 64
 constexpr int KT = kFlagTileChannels;  // 256
 
-// Eq. 3 / Eq. 4 on n values x[0..n) (x is kept; work is scratch of n floats):
-// flag[i] = |x_i - med| > M MAD / 0.6745, median of an even count = mean of
-// the two middle values.
-__device__ void mad_flags(const float *x, float *work, uint8_t *flag, int n, float M) {
-    const int t = threadIdx.x;
-    if (t < n) work[t] = x[t];
-    __syncthreads();
-    block_sort(work, n);
-    const float med = 0.5f * (work[n / 2 - 1] + work[n / 2]);
-    __syncthreads();
-    if (t < n) work[t] = fabsf(x[t] - med);
-    __syncthreads();
-    block_sort(work, n);
-    const float mad = 0.5f * (work[n / 2 - 1] + work[n / 2]);
-    if (t < n) flag[t] = fabsf(x[t] - med) > M * mad / 0.6745f;
-    __syncthreads();
+// Ascending bitonic sort of 4 x 64 = 256 floats held by one wave, element
+// 4 lane + q in v[q]: exchanges at distance >= 4 go across lanes with
+// __shfl_xor, shorter ones stay in registers.  No barriers.
+__device__ inline void wave_sort256(float (&v)[4], int lane) {
+#pragma unroll
+    for (int k = 2; k <= 256; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 4) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float o = __shfl_xor(v[q], j >> 2);
+                    const int e = 4 * lane + q;
+                    const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+                    v[q] = keep_min ? fminf(v[q], o) : fmaxf(v[q], o);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q & j) continue;
+                    const int e = 4 * lane + q;
+                    const float a = v[q], b = v[q ^ j];
+                    const bool up = (e & k) == 0;
+                    v[q] = up ? fminf(a, b) : fmaxf(a, b);
+                    v[q ^ j] = up ? fmaxf(a, b) : fminf(a, b);
+                }
+            }
+        }
+    }
+}
+
+// Ascending bitonic sort of 64 floats, one per lane of a wave.
+__device__ inline float wave_sort64(float x, int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const float o = __shfl_xor(x, j);
+            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+            x = keep_min ? fminf(x, o) : fmaxf(x, o);
+        }
+    }
+    return x;
+}
+
+// Median (mean of the two middle values) of the 256 floats of a wave.
+__device__ inline float wave_median256(float (&v)[4], int lane) {
+    wave_sort256(v, lane);
+    return 0.5f * (__shfl(v[3], 31) + __shfl(v[0], 32));  // sorted elements 127 and 128
+}
+
+// Median of 64 floats, one per lane.
+__device__ inline float wave_median64(float x, int lane) {
+    const float y = wave_sort64(x, lane);
+    return 0.5f * (__shfl(y, 31) + __shfl(y, 32));
 }
 
 // One tile (signal s, spectra m0..m0+63, channels k0..k0+255) per workgroup.
+// Eq. 3 / Eq. 4 on the 64 row means and the 256 column means:
+// flag[i] = |x_i - med| > M MAD / 0.6745, the median of an even count being
+// the mean of the two middle values.  One wave sorts the row statistic while
+// another sorts the column statistic.
 __global__ void __launch_bounds__(KT) mad_tile_kernel(const float *__restrict__ power, int S, int T, int C,
                                                       float M, uint8_t *flags) {
     __shared__ float tile[TT][KT + 1];
-    __shared__ float rowv[TT], colv[KT], work[KT];
-    __shared__ uint8_t rowf[TT], colf[KT];
+    __shared__ float rowp[KT / TT][TT];
+    __shared__ float rowv[TT], colv[KT], rdev[TT], cdev[KT];
+    __shared__ float sel[2];  // MAD of the rows, MAD of the columns
+    __shared__ uint8_t rowf[TT];
+    __shared__ __align__(16) uint8_t colf[KT];
     const int ntk = C / KT, ntm = T / TT;
     const int b = blockIdx.x;
     const int kt = b % ntk, mt = (b / ntk) % ntm, s = b / (ntk * ntm);
     const int t = threadIdx.x;
-    const int64_t base = ((int64_t)s * T + (int64_t)mt * TT) * C + (int64_t)kt * KT + t;
-    float cs = 0.f;
-    for (int r = 0; r < TT; ++r) {
-        const float v = power[base + (int64_t)r * C];
-        tile[r][t] = v;
-        cs += v;
+    const int64_t tbase = ((int64_t)s * T + (int64_t)mt * TT) * C + (int64_t)kt * KT;  // tile corner
+    {  // 16-byte loads: columns 4 (t mod 64) .. + 3 of rows t / 64 + 4 i
+        const int cq = t & 63, r0 = t >> 6;
+#pragma unroll
+        for (int i = 0; i < TT / 4; ++i) {
+            const int r = r0 + 4 * i;
+            const float4 v = *reinterpret_cast<const float4 *>(power + tbase + (int64_t)r * C + 4 * cq);
+            tile[r][4 * cq + 0] = v.x;
+            tile[r][4 * cq + 1] = v.y;
+            tile[r][4 * cq + 2] = v.z;
+            tile[r][4 * cq + 3] = v.w;
+        }
     }
-    colv[t] = cs / (float)TT;
     __syncthreads();
-    if (t < TT) {
+    {
+        float cs = 0.f;
+        for (int r = 0; r < TT; ++r) cs += tile[r][t];
+        colv[t] = cs / (float)TT;
+    }
+    __syncthreads();
+    {  // partial row sums: row t mod 64 over a quarter of the columns
+        const int r = t % TT, q = t / TT;
         float rs = 0.f;
-        for (int k = 0; k < KT; ++k) rs += tile[t][k];
-        rowv[t] = rs / (float)KT;
+        for (int k = 0; k < TT; ++k) rs += tile[r][q * TT + k];
+        rowp[q][r] = rs;
     }
     __syncthreads();
-    mad_flags(rowv, work, rowf, TT, M);
-    mad_flags(colv, work, colf, KT, M);
-    const uint8_t cf = colf[t];
-    for (int r = 0; r < TT; ++r) flags[base + (int64_t)r * C] = rowf[r] | cf;
+    if (t < TT) rowv[t] = (rowp[0][t] + rowp[1][t] + rowp[2][t] + rowp[3][t]) / (float)KT;
+    __syncthreads();
+    // Eq. 3 on the rows (wave 0) and on the columns (wave 1), side by side
+    const int lane = t & 63, wv = t >> 6;
+    if (wv == 0) {
+        const float x = rowv[lane];
+        const float med = wave_median64(x, lane);
+        const float d = fabsf(x - med);
+        const float mad = wave_median64(d, lane);
+        rdev[lane] = d;
+        if (lane == 0) sel[0] = mad;
+    } else if (wv == 1) {
+        float v[4], w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = colv[4 * lane + q];
+        const float med = wave_median256(v, lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            cdev[4 * lane + q] = w[q] = fabsf(colv[4 * lane + q] - med);
+        }
+        const float mad = wave_median256(w, lane);
+        if (lane == 0) sel[1] = mad;
+    }
+    __syncthreads();
+    const float madr = sel[0], madc = sel[1];
+    colf[t] = cdev[t] > M * madc / 0.6745f;
+    if (t < TT) rowf[t] = rdev[t] > M * madr / 0.6745f;
+    __syncthreads();
+    // 16-byte stores: chunk c = t + 256 j covers row c / 16, columns 16 (c mod 16) .. + 15
+#pragma unroll
+    for (int j = 0; j < TT * KT / 16 / KT; ++j) {
+        const int c = t + KT * j, r = c >> 4, c16 = c & 15;
+        const uint32_t rb = rowf[r] * 0x01010101u;
+        uint4 f = *reinterpret_cast<const uint4 *>(&colf[16 * c16]);
+        f.x |= rb;
+        f.y |= rb;
+        f.z |= rb;
+        f.w |= rb;
+        *reinterpret_cast<uint4 *>(flags + tbase + (int64_t)r * C + 16 * c16) = f;
+    }
 }
 
 // Keep masks and zeroing in one pass.  A workgroup owns 32 spectra (one keep
