@@ -201,7 +201,8 @@ __device__ __forceinline__ float2 *result_buffer(float2 *b0, float2 *b1) {
     else return ((FCfg<LOGM>::NPASS - 1) & 1) ? b1 : b0;
 }
 
-// Round to OCP e4m3 (bias 7, max 448), nearest-even, saturating to +-448.
+// Round to OCP e4m3 (bias 7, max 448), nearest-even, saturating to +-448; a
+// value that rounds to zero is encoded as +0 whatever its sign.
 __device__ __forceinline__ uint32_t e4m3_rne_sat(float v) {
     const uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
     const float a = fminf(fabsf(v), 448.0f);
@@ -213,7 +214,7 @@ __device__ __forceinline__ uint32_t e4m3_rne_sat(float v) {
         b += 0x7FFFFu + ((b >> 20) & 1u);
         code = ((((b >> 23) - 120u) << 3) | ((b >> 20) & 7u)) & 0x7Fu;
     }
-    return sign | code;
+    return code ? (sign | code) : 0u;
 }
 
 // int8 code of an already-scaled value: clamp to [-127, 127] (integers, so the

@@ -174,6 +174,39 @@ def test_fengine_int8_quantizer_matches_oracle():
     assert qg.min() >= -127
 
 
+def test_fengine_fp8_quantizer_matches_oracle():
+    """e4m3 codes of the F-engine against the oracle's (RNE to the nearest OCP
+    e4m3 value, saturating at 448, +0 for anything that rounds to zero): a
+    code may differ only to the adjacent code, and only where the exact value
+    sits at their midpoint to within the FP32 F-engine's error (2e-5 of the
+    spectrum's RMS, or 1e-3 of the step between the two codes)."""
+    import torch
+    S, N, T = 8, 1024, 256
+    geo, x = fx_case(S, N, T, seed=23)
+    Y = oracle.fengine(x, N, T, ogeom(geo), FS)
+    scale = oracle.fp8_scale(oracle.sigma(Y))
+    plan = corr.Plan(S, N, T, precision=corr.FP8_E4M3)
+    x_dev, rs = upload_streams(x, N, T, 16)
+    spec = run_fengine(plan, x_dev, rs, geom_dev(geo), torch.from_numpy(scale.ravel()).cuda())
+    qg = corr.unpack_spectra(spec, corr.FP8_E4M3, S, plan.C, T)
+    qo = oracle.quantize_fp8(Y, scale.astype(np.float64))
+    table = oracle.e4m3_decode_table()
+    bad = qg != qo
+    print("fp8 code mismatches: %d of %d" % (bad.sum(), bad.size))
+    assert bad.mean() <= 1e-4
+    uall = np.stack([Y.real, Y.imag], -1) / scale.astype(np.float64)[:, None, :, None]
+    u = uall[bad]
+    a, b = table[qg[bad]], table[qo[bad]]
+    assert np.all(np.sign(a) * np.sign(b) >= 0)                      # same side of zero
+    assert np.all(np.abs(np.abs(qg[bad].astype(int) & 0x7F) - (qo[bad].astype(int) & 0x7F)) == 1)  # adjacent
+    mid, step = 0.5 * (a + b), np.abs(a - b)
+    # the FP32 F-engine's error is absolute, a fraction (< 2e-5) of the spectrum's RMS,
+    # so near zero, where e4m3 steps are 2^-9, it is measured against that RMS
+    rms = np.sqrt(np.mean(uall ** 2))
+    assert np.all(np.abs(u - mid) <= np.maximum(1e-3 * step, 2e-5 * rms))
+    assert 0x80 not in np.unique(qg)                                 # zero is +0
+
+
 def test_calibration_scales_match_oracle():
     import torch
     S, N, T = 8, 1024, 256
