@@ -363,8 +363,9 @@ corr_status corr_cnn_check_device_errors(corr_cnn_t *cnn, void *stream);
  * corr_apply_flags) and optionally the logits d_logits [S][T][C] (NULL: not
  * written).  FP16 operands with FP32 accumulation on the matrix cores, so the
  * logits differ from the FP32 path by about 1e-3 of their scale.  Needs no
- * handle or workspace.  Errors: NULL, ALIGN, INVALID (shape, threshold not in
- * (0, 1)), DEVICE; messages via corr_cnn_last_error(NULL). */
+ * handle or workspace.  C is at most 2^22 (offsets inside a tile are 32-bit).
+ * Errors: NULL, ALIGN, INVALID (shape, C above 2^22, threshold not in (0, 1)),
+ * DEVICE; messages via corr_cnn_last_error(NULL). */
 corr_status corr_cnn_infer(const float *d_params, const float *d_power, int32_t S, int64_t T, int32_t C,
                            float threshold, uint8_t *d_flags, float *d_logits, void *stream);
 

@@ -295,11 +295,10 @@ typedef float float16v __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int XCOLS = W + 4;  // input columns: zero column on the left, three on the right
-constexpr int XP = H + 2;     // input column pitch (rows, zero row at each edge); odd in dwords
 constexpr int PC = W + 2;     // activation row pitch: one zero column at each edge
-constexpr int RING = 6;     // rows kept of the layer-1 output and of the layer-3 tap sums
-constexpr int ZROW = RING;  // an all-zero row standing for rows outside the tile
-constexpr int IWG = 512;    // 8 waves, one 32-column strip each
+constexpr int RX = 8;         // rows kept of the input, of the layer-1 output and of the tap sums
+constexpr int XPITCH = 10;    // halves per input column: RX rows + 2 pad (odd dword stride)
+constexpr int IWG = 512;      // 8 waves, one 32-column strip each
 
 // Accumulator layout of a 32 x 32 MFMA: register j of lane l holds row
 // 8 (j / 4) + 4 (l / 32) + j mod 4, column l mod 32.
@@ -314,55 +313,61 @@ __device__ inline uint32_t relu_h2(float a, float b) {
     return __builtin_bit_cast(uint32_t, m);
 }
 
-__device__ inline int ring_slot(int row) { return (unsigned)row < (unsigned)H ? row % RING : ZROW; }
-
 // Byte offset of the 16-byte half `h` (channels 8h .. 8h + 7) of pixel column
 // pcol in a layer-1 output row: the halves swap places by bit 2 xor bit 3 of
 // the column, so the 16-byte reads of 8 (or 16) consecutive lanes cover all 32
 // (or 64) LDS banks once.
 __device__ inline int a1_off(int pcol, int h) { return 32 * pcol + 16 * (h ^ (((pcol >> 2) ^ (pcol >> 3)) & 1)); }
 
-// One workgroup per tile.  Wave w owns columns 32 w .. 32 w + 31 and walks the
-// tile two rows at a time.  MFMA roles (32 x 32 x 16, FP16 in, FP32 out):
-//   layer 1: rows = (row slot, out channel) for the two rows R, R + 1;
-//            K = 4 input rows x 4 column offsets, lane half h taking input
-//            rows 2h and 2h + 1, slot j = (row 2h + j mod 2, offset j / 2):
-//            with the input stored column-major each slot pair is one aligned
-//            dword (offset 3 has zero weight; the bias rides on slot 7 of
-//            half 0, set to 1);
-//   layer 2: rows = (row slot, out channel) for rows r, r + 1; one product
-//            per (input row r - 1 .. r + 2, column offset), K = 16 channels,
-//            the weights of the taps a row slot does not use set to zero;
+// One workgroup per compute unit, looping over tiles.  Wave w owns columns
+// 32 w .. 32 w + 31 and walks the tile two rows at a time in a software
+// pipeline with one barrier per step j:
+//   x rows 2j + 5, 2j + 6 = log(1 + P / m) (FP16) into the input ring,
+//   layer 1 for rows 2j + 2, 2j + 3,
+//   layer 2 and the layer-3 tap sums for rows 2j - 2, 2j - 1,
+//   the logits of rows 2j - 6, 2j - 5,
+// each stage reading only what earlier steps wrote, from rings of 8 rows.
+// Layer 2 of a row pair reads layer-1 rows 2j - 3 .. 2j; the first two were
+// read by the previous step and stay in registers.  Layer-1 rows -1 and 64
+// are zero rows in the ring.  Steps run four at a time (the ring period), so
+// every ring slot is a constant.  While a tile is processed, the column sums
+// of the next tile and the input rows its first step needs are fetched.
+// MFMA roles (32 x 32 x 16, FP16 in, FP32 out):
+//   layer 1: rows = (row slot, out channel) for two rows; K = 4 input rows x 4
+//            column offsets, lane half h taking input rows 2h and 2h + 1,
+//            slot j = (row 2h + j mod 2, offset j / 2): with the input stored
+//            column-major each slot pair is one aligned dword (offset 3 has
+//            zero weight; the bias rides on slot 7 of half 0, set to 1);
+//   layer 2: rows = (row slot, out channel); one product per (input row,
+//            column offset), K = 16 channels, the weights of the taps a row
+//            slot does not use set to zero;
 //   layer 3: U[tap][q] = sum_i w3[i][tap] a2[i][q] with rows = the 9 taps, fed
 //            directly from the layer-2 accumulator (its 8 channels per lane
 //            are exactly one lane's K slots), then z3[p] = b3 + sum of U over
-//            the 9 shifted neighbours of p, read from LDS.
+//            the 9 shifted neighbours of p.
 __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict__ params,
                                                         const float *__restrict__ power, int64_t T, int C,
                                                         int n_tiles, float thr_logit, uint8_t *__restrict__ flags,
                                                         float *__restrict__ logits) {
-    __shared__ __align__(16) _Float16 xs[XCOLS][XP];  // column-major input
-    __shared__ __align__(16) _Float16 a1s[RING + 1][PC][16];
-    __shared__ float us[RING + 1][PC][9];
-    __shared__ float colv[W];
+    __shared__ __align__(16) _Float16 xs[XCOLS][XPITCH];  // column-major input ring (slot = (row + 1) mod 8)
+    __shared__ __align__(16) _Float16 a1s[RX][PC][16];   // layer-1 ring (slot = row mod 8)
+    __shared__ float us[RX][PC][9];                      // tap-sum ring (slot = row mod 8)
+    __shared__ float colv[2][W];                         // column sums of even / odd rows
 
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int half = lane >> 5, col = lane & 31;
-    const int pcx = t & (W - 1), rh = t >> 8;  // staging: column pcx, rows rh, rh + 2, ...
+    const int xc = t & (W - 1), xh = t >> 8;  // input staging: column xc, rows of parity xh
 
-    // ---- zero borders and zero rows, written once (never overwritten below)
-    for (int e = t; e < 4 * XP; e += IWG) xs[(e / XP) == 0 ? 0 : W + (e / XP)][e % XP] = (_Float16)0.f;
-    for (int e = t; e < 2 * W; e += IWG) xs[1 + (e >> 1)][(e & 1) ? H + 1 : 0] = (_Float16)0.f;
-    for (int e = t; e < RING * 2 * 16; e += IWG) {
+    // ---- zero border columns, written once (never overwritten below)
+    for (int e = t; e < 4 * XPITCH; e += IWG) xs[(e / XPITCH) == 0 ? 0 : W + (e / XPITCH)][e % XPITCH] = (_Float16)0.f;
+    for (int e = t; e < RX * 2 * 16; e += IWG) {
         const int rr = e / 32, side = (e / 16) & 1, ch = e & 15;
         a1s[rr][side ? PC - 1 : 0][ch] = (_Float16)0.f;
     }
-    for (int e = t; e < PC * 16; e += IWG) a1s[ZROW][e >> 4][e & 15] = (_Float16)0.f;
-    for (int e = t; e < RING * 2 * 9; e += IWG) {
+    for (int e = t; e < RX * 2 * 9; e += IWG) {
         const int rr = e / 18, side = (e / 9) & 1, k = e % 9;
         us[rr][side ? PC - 1 : 0][k] = 0.f;
     }
-    for (int e = t; e < PC * 9; e += IWG) us[ZROW][e / 9][e % 9] = 0.f;
 
     // ---- weights as MFMA A operands (lane: row = lane mod 32, K slots 8 half + j)
     const int arow = lane & 31, aslot = arow >> 4, ao = arow & 15;
@@ -390,12 +395,11 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
     for (int j = 0; j < 16; ++j) bias2[j] = params[kB2 + (acc_row(j, half) & 15)];
     const float b3 = params[kB3];
     const float16v zero16 = {};
+    const half8 zero8 = {};
 
     const int c0 = wv * 32;
     const int pc = c0 + col + 1;  // padded column of this lane's pixel
-    // this lane's input window: padded rows R + 2 half + (0, 1) (one dword per
-    // column), padded columns pc - 1 .. pc + 2
-    const uint32_t *xl = reinterpret_cast<const uint32_t *>(&xs[c0 + col][2 * half]);
+    const uint32_t *xl = reinterpret_cast<const uint32_t *>(&xs[c0 + col][0]);
     const uint32_t bias_and = half ? 0xFFFFFFFFu : 0x0000FFFFu;  // half 0: slot 7 := 1.0
     const uint32_t bias_or = half ? 0u : 0x3C000000u;
     char *a1base = reinterpret_cast<char *>(&a1s[0][0][0]);
@@ -405,62 +409,90 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
     for (int dv = 0; dv < 3; ++dv) a1rd[dv] = a1_off(pc - 1 + dv, half);
     float *uw = &us[0][pc][0];
     const float *ur = &us[0][pc - 1][0];
-    constexpr int XCOL = XP / 2, AROW = PC * 16 * 2, UROW = PC * 9;  // dwords, bytes, floats
+    constexpr int AROW = PC * 16 * 2, UROW = PC * 9;  // bytes, floats
 
-    // power of the first tile; later tiles are fetched while the previous one computes
-    float pv[32];
-    auto tile_base = [&](int tile) {
+    auto tile_base = [&](int tl) {
         int s, k0;
         int64_t m0;
-        tile_coords(tile, T, C, s, m0, k0);
+        tile_coords(tl, T, C, s, m0, k0);
         return ((int64_t)s * T + m0) * C + k0;
     };
+    // First tile: column sums of rows xh, xh + 2, ... and the input rows -1 + xh,
+    // 1 + xh, 3 + xh of its first steps.  Later tiles get these during the previous one.
+    // Offsets inside a tile (row r, column c: r C + c < 2^24) are 32-bit;
+    // tile bases are uniform 64-bit pointers.
+    auto roff = [&](int r, int c) { return __umul24((uint32_t)r, (uint32_t)C) + (uint32_t)c; };
     int tile = blockIdx.x;
+    float csum = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f;
     if (tile < n_tiles) {
-        const int64_t b0 = tile_base(tile);
-#pragma unroll
-        for (int q = 0; q < 32; ++q) pv[q] = power[b0 + (int64_t)(rh + 2 * q) * C + pcx];
+        const float *tb = power + tile_base(tile);
+#pragma unroll 8
+        for (int q = 0; q < 32; ++q) csum += tb[roff(2 * q + xh, xc)];
+        p0 = xh ? tb[xc] : 0.f;
+        p1 = tb[roff(1 + xh, xc)];
+        p2 = tb[roff(3 + xh, xc)];
     }
     for (; tile < n_tiles; tile += gridDim.x) {
         const int64_t base = tile_base(tile);
-        // ---- stage the tile: reference level, then x = log(1 + P / m) in FP16
-        {
-            float cs = 0.f;
+        const float *tb = power + base;
+        const bool has_next = tile + (int)gridDim.x < n_tiles;
+        const float *tn = has_next ? power + tile_base(tile + gridDim.x) : tb;
+        uint8_t *fb = flags + base;
+        float *lb = logits ? logits + base : nullptr;
+
+        // ---- reference level: median over the 256 channels of each channel's mean power
+        colv[xh][xc] = csum;
+        for (int e = t; e < PC * 2; e += IWG)  // layer-1 row -1 (slot 7): zero
+            reinterpret_cast<uint4 *>(a1base + (RX - 1) * AROW)[e] = make_uint4(0u, 0u, 0u, 0u);
+        __syncthreads();
+        float cv[4];
 #pragma unroll
-            for (int q = 0; q < 32; ++q) cs += pv[q];
-            __syncthreads();  // the previous tile is done with colv, xs, a1s and us
-            if (rh == 0) colv[pcx] = cs;
-            __syncthreads();
-            if (rh == 1) colv[pcx] = (colv[pcx] + cs) * (1.0f / H);
-            __syncthreads();
-            block_sort(colv, W);
-            const float med = 0.5f * (colv[W / 2 - 1] + colv[W / 2]);
-            const float inv = 1.0f / (med > 0.f ? med : 1.f);
-#pragma unroll
-            for (int q = 0; q < 32; ++q) xs[pcx + 1][rh + 2 * q + 1] = (_Float16)__logf(1.0f + pv[q] * inv);
-            const int next = tile + gridDim.x;
-            if (next < n_tiles) {
-                const int64_t bn = tile_base(next);
-#pragma unroll
-                for (int q = 0; q < 32; ++q) pv[q] = power[bn + (int64_t)(rh + 2 * q) * C + pcx];
-            }
-        }
+        for (int q = 0; q < 4; ++q) cv[q] = (colv[0][4 * lane + q] + colv[1][4 * lane + q]) * (1.0f / H);
+        const float med = wave_median256(cv, lane);
+        const float inv = 1.0f / (med > 0.f ? med : 1.f);
+        // x of tile row r -> input ring slot (r + 1) mod 8, zero outside the tile
+        auto x_put = [&](int r, float pv) {
+            const float v = (r >= 0 && r < H) ? __logf(1.0f + pv * inv) : 0.f;
+            xs[xc + 1][(r + 1) & (RX - 1)] = (_Float16)v;
+        };
+        x_put(-1 + xh, p0);
+        x_put(1 + xh, p1);
+        float xnext = p2, cnext = 0.f;
+        csum = 0.f;
         __syncthreads();
 
-        for (int k = -1; k <= H / 2; ++k) {
-            // (1) layer 1 for rows R, R + 1 (R = 2k + 2)
-            const int R = 2 * k + 2;
+        half8 Fa[3], Fb[3];  // layer-1 operands of rows 2j - 3, 2j - 2, read by the previous step
+#pragma unroll
+        for (int dv = 0; dv < 3; ++dv) Fa[dv] = Fb[dv] = zero8;
+
+        auto step = [&](const int j) {
+            // (a) input row 2j + 5 + xh; row 2j + 7 + xh is fetched for the next step, and row
+            //     2j + 2 + xh of the next tile for its column sums (added one step later)
+            {
+                const int r = 2 * j + 5 + xh;
+                x_put(r, xnext);
+                xnext = (r + 2 < H) ? tb[roff(r + 2, xc)] : 0.f;
+                if (j >= 0 && j <= H / 2 - 1) csum += cnext;
+                if (j <= H / 2 - 2) cnext = has_next ? tn[roff(2 * j + 2 + xh, xc)] : 0.f;
+                if (j == H / 2 && has_next) {
+                    p0 = xh ? tn[xc] : 0.f;
+                    p1 = tn[roff(1 + xh, xc)];
+                    p2 = tn[roff(3 + xh, xc)];
+                }
+            }
+            // (b) layer 1 for rows R, R + 1, R = 2j + 2 (input rows R - 1 .. R + 2); row 64 is zero
+            const int R = 2 * j + 2;
             if (R < H) {
-                const uint32_t *xr = xl + R / 2;
+                const uint32_t *xr = xl + (((R + 2 * half) & (RX - 1)) >> 1);
                 u32x4 bx;
 #pragma unroll
-                for (int dv = 0; dv < 4; ++dv) bx[dv] = xr[dv * XCOL];
+                for (int dv = 0; dv < 4; ++dv) bx[dv] = xr[dv * (XPITCH / 2)];
                 bx[3] = (bx[3] & bias_and) | bias_or;
                 const float16v D =
                     __builtin_amdgcn_mfma_f32_32x32x16_f16(A1, __builtin_bit_cast(half8, bx), zero16, 0, 0, 0);
 #pragma unroll
                 for (int sl = 0; sl < 2; ++sl) {
-                    char *row = a1base + ring_slot(R + sl) * AROW;
+                    char *row = a1base + ((R + sl) & (RX - 1)) * AROW;
 #pragma unroll
                     for (int g = 0; g < 2; ++g) {
                         const int j0 = 8 * sl + 4 * g;
@@ -470,52 +502,78 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
                         *reinterpret_cast<uint2 *>(row + (g ? a1w1 : a1w0)) = v;
                     }
                 }
+            } else if (R == H) {
+                char *row = a1base + (R & (RX - 1)) * AROW;
+                *reinterpret_cast<uint2 *>(row + a1w0) = make_uint2(0u, 0u);
+                *reinterpret_cast<uint2 *>(row + a1w1) = make_uint2(0u, 0u);
             }
-            __syncthreads();
-            if (k < 0) continue;
-            if (k < H / 2) {
-                // (2) layer 2 for rows r = 2k, 2k + 1 and the layer-3 tap sums U
-                const int r = 2 * k;
-                float16v D = bias2;
+            // (c) layer 2 and the tap sums for rows r2, r2 + 1, r2 = 2j - 2 (layer-1 rows r2 - 1 .. r2 + 2)
+            if (j >= 0 && j <= H / 2) {
+                half8 Fc[3], Fd[3];  // layer-1 rows 2j - 1, 2j
+                const char *fc = a1base + ((2 * j - 1) & (RX - 1)) * AROW;
+                const char *fd = a1base + ((2 * j) & (RX - 1)) * AROW;
 #pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    const char *fr = a1base + ring_slot(r - 1 + p) * AROW;
+                for (int dv = 0; dv < 3; ++dv) {
+                    Fc[dv] = *reinterpret_cast<const half8 *>(fc + a1rd[dv]);
+                    Fd[dv] = *reinterpret_cast<const half8 *>(fd + a1rd[dv]);
+                }
+                if (j >= 1) {
+                    const int r2 = 2 * j - 2;
+                    float16v D = bias2;
 #pragma unroll
-                    for (int dv = 0; dv < 3; ++dv) {
-                        const half8 F = *reinterpret_cast<const half8 *>(fr + a1rd[dv]);
-                        D = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[p][dv], F, D, 0, 0, 0);
+                    for (int dv = 0; dv < 3; ++dv) D = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[0][dv], Fa[dv], D, 0, 0, 0);
+#pragma unroll
+                    for (int dv = 0; dv < 3; ++dv) D = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[1][dv], Fb[dv], D, 0, 0, 0);
+#pragma unroll
+                    for (int dv = 0; dv < 3; ++dv) D = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[2][dv], Fc[dv], D, 0, 0, 0);
+#pragma unroll
+                    for (int dv = 0; dv < 3; ++dv) D = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[3][dv], Fd[dv], D, 0, 0, 0);
+#pragma unroll
+                    for (int sl = 0; sl < 2; ++sl) {
+                        u32x4 bu;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) bu[q] = relu_h2(D[8 * sl + 2 * q], D[8 * sl + 2 * q + 1]);
+                        const float16v U =
+                            __builtin_amdgcn_mfma_f32_32x32x16_f16(A3, __builtin_bit_cast(half8, bu), zero16, 0, 0, 0);
+                        float *dst = uw + ((r2 + sl) & (RX - 1)) * UROW;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dst[4 * half + q] = U[q];
+                        if (half == 0) dst[8] = U[4];
                     }
                 }
 #pragma unroll
-                for (int sl = 0; sl < 2; ++sl) {
-                    u32x4 bu;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) bu[q] = relu_h2(D[8 * sl + 2 * q], D[8 * sl + 2 * q + 1]);
-                    const float16v U =
-                        __builtin_amdgcn_mfma_f32_32x32x16_f16(A3, __builtin_bit_cast(half8, bu), zero16, 0, 0, 0);
-                    float *dst = uw + ring_slot(r + sl) * UROW;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) dst[4 * half + j] = U[j];
-                    if (half == 0) dst[8] = U[4];
+                for (int dv = 0; dv < 3; ++dv) {
+                    Fa[dv] = Fc[dv];
+                    Fb[dv] = Fd[dv];
                 }
             }
-            __syncthreads();
-            // (3) output rows 2k - 2 (lanes 0-31) and 2k - 1 (lanes 32-63)
-            if (k >= 1) {
-                const int r = 2 * k - 2 + half;
+            // (d) logits of rows 2j - 6 (lanes 0-31) and 2j - 5 (lanes 32-63)
+            const int r3 = 2 * j - 6;
+            if (r3 >= 0 && r3 < H) {
+                const int r = r3 + half;
                 float z = b3;
 #pragma unroll
                 for (int u = 0; u < 3; ++u) {
-                    // rows of the two lane halves are uniform: pick the slot of this half
-                    const int s0 = ring_slot(2 * k - 3 + u), s1 = ring_slot(2 * k - 2 + u);
-                    const float *row = ur + (half ? s1 : s0) * UROW;
+                    const int rr = r + u - 1;
+                    const float *row = ur + (rr & (RX - 1)) * UROW;
+                    float zu = 0.f;
 #pragma unroll
-                    for (int v = 0; v < 3; ++v) z += row[9 * v + 3 * u + v];
+                    for (int v = 0; v < 3; ++v) zu += row[9 * v + 3 * u + v];
+                    z += (rr >= 0 && rr < H) ? zu : 0.f;
                 }
-                const int64_t gp = base + (int64_t)r * C + c0 + col;
-                flags[gp] = z > thr_logit ? 1 : 0;
-                if (logits) logits[gp] = z;
+                const uint32_t gp = roff(r, c0 + col);
+                fb[gp] = z > thr_logit ? 1 : 0;
+                if (lb) lb[gp] = z;
             }
+            __syncthreads();
+        };
+        // steps -1 .. 34, four at a time: 2j mod 8 is fixed within each group
+        for (int i = 0; i < (H / 2 + 4) / 4; ++i) {
+            const int jb = 4 * i - 1;
+            step(jb);
+            step(jb + 1);
+            step(jb + 2);
+            step(jb + 3);
         }
     }
 }

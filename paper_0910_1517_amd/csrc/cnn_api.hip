@@ -233,6 +233,8 @@ corr_status corr_cnn_infer(const float *d_params, const float *d_power, int32_t 
     if (!(threshold > 0.f && threshold < 1.f)) return fail(nullptr, CORR_ERR_INVALID, "threshold must lie in (0, 1)");
     corr_status r = check_shape(nullptr, S, T, C);
     if (r != CORR_OK) return r;
+    if (C > kCnnMaxInferChannels)
+        return fail(nullptr, CORR_ERR_INVALID, "C=%d above the inference limit %d", C, kCnnMaxInferChannels);
     // sigmoid(z) > thr  <=>  z > log(thr / (1 - thr))
     const float thr_logit = (float)std::log((double)threshold / (1.0 - (double)threshold));
     hipError_t e = launch_cnn_infer(d_params, d_power, S, T, C, thr_logit, d_flags, d_logits, (hipStream_t)stream);

@@ -111,6 +111,43 @@ __device__ inline void block_sort(float *v, int n) {
     }
 }
 
+// Ascending bitonic sort of 4 x 64 = 256 floats held by one wave, element
+// 4 lane + q in v[q]: exchanges at distance >= 4 go across lanes with
+// __shfl_xor, shorter ones stay in registers.  No barriers.
+__device__ inline void wave_sort256(float (&v)[4], int lane) {
+#pragma unroll
+    for (int k = 2; k <= 256; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 4) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float o = __shfl_xor(v[q], j >> 2);
+                    const int e = 4 * lane + q;
+                    const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+                    v[q] = keep_min ? fminf(v[q], o) : fmaxf(v[q], o);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q & j) continue;
+                    const int e = 4 * lane + q;
+                    const float a = v[q], b = v[q ^ j];
+                    const bool up = (e & k) == 0;
+                    v[q] = up ? fminf(a, b) : fmaxf(a, b);
+                    v[q ^ j] = up ? fmaxf(a, b) : fminf(a, b);
+                }
+            }
+        }
+    }
+}
+
+// Median (mean of the two middle values) of the 256 floats of a wave.
+__device__ inline float wave_median256(float (&v)[4], int lane) {
+    wave_sort256(v, lane);
+    return 0.5f * (__shfl(v[3], 31) + __shfl(v[0], 32));  // sorted elements 127 and 128
+}
+
 hipError_t launch_integrate(int precision, void *acc, const float *scale, double *state,
                             float *vis, const uint16_t *pairs, int S, int C, int splits,
                             uint32_t flags, hipStream_t st);
@@ -118,6 +155,8 @@ hipError_t launch_integrate(int precision, void *acc, const float *scale, double
 // Learned flagger (cnn.hip).  Parameters: flat FP32 vector, layer by layer,
 // weights [Cout][Cin][3][3] then biases.
 constexpr int kCnnParams = 16 * 9 + 16 + 16 * 16 * 9 + 16 + 16 * 9 + 1;  // 2625
+// inference addresses a tile's cells with 32-bit offsets r C + c (r <= 66)
+constexpr int kCnnMaxInferChannels = 1 << 22;
 constexpr int kCnnPixels = kFlagTileSpectra * kFlagTileChannels;      // 16384 per tile
 // per-tile training blocks (8 x 64 pixels) and the widest per-block gradient
 constexpr int kCnnBlocksPerTile = 32;

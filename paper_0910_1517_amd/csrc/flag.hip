@@ -20,37 +20,6 @@ namespace {
 constexpr int TT = kFlagTileSpectra;   // 64
 constexpr int KT = kFlagTileChannels;  // 256
 
-// Ascending bitonic sort of 4 x 64 = 256 floats held by one wave, element
-// 4 lane + q in v[q]: exchanges at distance >= 4 go across lanes with
-// __shfl_xor, shorter ones stay in registers.  No barriers.
-__device__ inline void wave_sort256(float (&v)[4], int lane) {
-#pragma unroll
-    for (int k = 2; k <= 256; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= 4) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float o = __shfl_xor(v[q], j >> 2);
-                    const int e = 4 * lane + q;
-                    const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
-                    v[q] = keep_min ? fminf(v[q], o) : fmaxf(v[q], o);
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (q & j) continue;
-                    const int e = 4 * lane + q;
-                    const float a = v[q], b = v[q ^ j];
-                    const bool up = (e & k) == 0;
-                    v[q] = up ? fminf(a, b) : fmaxf(a, b);
-                    v[q ^ j] = up ? fmaxf(a, b) : fminf(a, b);
-                }
-            }
-        }
-    }
-}
-
 // Ascending bitonic sort of 64 floats, one per lane of a wave.
 __device__ inline float wave_sort64(float x, int lane) {
 #pragma unroll
@@ -65,11 +34,6 @@ __device__ inline float wave_sort64(float x, int lane) {
     return x;
 }
 
-// Median (mean of the two middle values) of the 256 floats of a wave.
-__device__ inline float wave_median256(float (&v)[4], int lane) {
-    wave_sort256(v, lane);
-    return 0.5f * (__shfl(v[3], 31) + __shfl(v[0], 32));  // sorted elements 127 and 128
-}
 
 // Median of 64 floats, one per lane.
 __device__ inline float wave_median64(float x, int lane) {

@@ -151,7 +151,7 @@ def test_cnn_workspace_and_unbound_calls():
 
 @pytest.mark.parametrize("shape,thr,code", [((1, 64, 256), 0.0, -1), ((1, 64, 256), 1.0, -1),
                                             ((1, 100, 256), 0.5, -1), ((1, 64, 300), 0.5, -1),
-                                            ((0, 64, 256), 0.5, -1)])
+                                            ((0, 64, 256), 0.5, -1), ((1, 64, (1 << 22) + 256), 0.5, -1)])
 def test_cnn_infer_rejects_bad_arguments(shape, thr, code):
     L = corr.lib()
     fake = ctypes.c_void_p(1 << 20)
