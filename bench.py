@@ -53,14 +53,14 @@ FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
 # calibration copy, see profiles/), valid only for the kernel source they were
 # taken from: reported as `traffic` when the source hash still matches.
 MEASURED_TRAFFIC = {
-    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4721834 KiB x 2.000, WRITE_SIZE 8388608 KiB x 1.000
+    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4721670 KiB x 2.000, WRITE_SIZE 8388610 KiB x 1.000
     "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
-                        "sha256": "b7aa213afd349f3daf0715719ac252218bc36ce86b368613d955c304b8bf279d",
-                        "read": 9.669e9, "write": 8.590e9},
-    # profiles/cnn_flagged_64sig_8192pt_8192spec.md: FETCH_SIZE 4194520 KiB x 2.000, WRITE_SIZE 2097152 KiB x 1.000
+                        "sha256": "5a7f3999543a3c286c15ef1861eccdca35eca58b0b5fd3e573d53e9ce9e29011",
+                        "read": 9.670e9, "write": 8.590e9},
+    # profiles/cnn_flagged_64sig_8192pt_8192spec.md: FETCH_SIZE 6622270 KiB x 2.000, WRITE_SIZE 2097150 KiB x 1.000
     "cnn_infer_c5": {"source": "paper_0910_1517_amd/csrc/cnn.hip",
-                     "sha256": "1df4a694a2ec5fe763bd209b0fc65784f85bb9e00e540c37422ffe2f1c07f60c",
-                     "read": 8.590e9, "write": 2.147e9},
+                     "sha256": "11897de3ea8f1fed2ff75202bd8832f9f067f1821c5b36ebff85b1240076a554",
+                     "read": 13.562e9, "write": 2.147e9},
 }
 
 

@@ -309,6 +309,8 @@ fengine_kernel(FLaunch a) {
     };
     const uint32_t sh = (uint32_t)(D & 3);
     if (active) fetch(m0);
+    const double t_spec = (double)N / a.fs;             // seconds per spectrum
+    const double c_bb = a.nu_bb * (double)g.frac / a.fs;  // baseband term of the phase, cycles
 
     // corner-turn staging: one 16-byte chunk per channel
     //   INT8/FP8: dwords {re 0-3, re 4-7, im 0-3, im 4-7}; FP32: 2 complex64
@@ -363,8 +365,8 @@ fengine_kernel(FLaunch a) {
         // 3. phase of this spectrum (FP64 reduction, FP32 sincos)
         float2 rot = make_float2(1.f, 0.f);
         if constexpr (MODE != 3) {
-            const double tm = ((double)(a.spectrum0 + m) + 0.5) * (double)N / a.fs;
-            double c = a.nu_bb * (double)g.frac / a.fs + (double)a.sideband * (g.psi0 + g.rate * tm);
+            const double tm = ((double)(a.spectrum0 + m) + 0.5) * t_spec;
+            double c = c_bb + (double)a.sideband * (g.psi0 + g.rate * tm);
             c -= floor(c);
             float sn, cs;
             sincospif(2.0f * (float)c, &sn, &cs);

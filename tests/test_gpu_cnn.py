@@ -135,6 +135,44 @@ def test_infer_matches_oracle_over_several_tiles():
     _check_infer(he_params(4), power)
 
 
+def test_infer_many_tiles_per_workgroup():
+    """1280 tiles, several per workgroup (one workgroup per compute unit, each
+    walking its tiles as one stream): sampled tiles against the oracle, and
+    every sampled tile bit-identical to the same tile inferred on its own (a
+    tile's result may not depend on its neighbours in the stream)."""
+    import torch
+    S, T, C = 2, 4096, 2560
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.BASE_SEED + 31)
+    power = torch.empty(S, T, C, device="cuda").exponential_(1.0, generator=gen)
+    power[1, :, 777] *= 30.0  # a tone column crossing many tiles of one stream
+    params = he_params(7)
+    pd = dev(params)
+    flags = torch.empty(S, T, C, dtype=torch.uint8, device="cuda")
+    logits = torch.empty(S, T, C, device="cuda")
+    corr.cnn_infer(pd, power, flags, logits=logits)
+    torch.cuda.synchronize()
+    ntm, ntk = T // TH, C // TW
+    n = S * ntm * ntk
+    rng = np.random.default_rng(3)
+    sample = sorted(set([0, 1, 255, 256, 257, n - 1] + rng.integers(0, n, 34).tolist()))
+    for k, tile in enumerate(sample):
+        s, rest = divmod(tile, ntm * ntk)
+        mt, kt = divmod(rest, ntk)
+        sl = (s, slice(mt * TH, mt * TH + TH), slice(kt * TW, kt * TW + TW))
+        one = power[sl].contiguous().view(1, TH, TW)
+        f1 = torch.empty(1, TH, TW, dtype=torch.uint8, device="cuda")
+        z1 = torch.empty(1, TH, TW, device="cuda")
+        corr.cnn_infer(pd, one, f1, logits=z1)
+        torch.cuda.synchronize()
+        assert torch.equal(z1[0], logits[sl]) and torch.equal(f1[0], flags[sl]), tile
+        if k % 5 == 0 or tile in (0, n - 1):
+            P = one[0].cpu().numpy().astype(np.float64)
+            z64, _ = oracle.cnn_forward(params.astype(np.float64), oracle.cnn_tile_input(P)[None, None])
+            scale = 1.0 + np.abs(z64).max()
+            assert np.abs(logits[sl].cpu().numpy() - z64[0, 0]).max() < INFER_TOL * scale, tile
+
+
 def test_infer_single_tile_and_thresholds():
     power = synth.power_spectra(1, 64, 256, seed=14)
     params = he_params(5)
