@@ -53,11 +53,11 @@ FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
 # calibration copy, see profiles/), valid only for the kernel source they were
 # taken from: reported as `traffic` when the source hash still matches.
 MEASURED_TRAFFIC = {
-    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4721670 KiB x 2.000, WRITE_SIZE 8388610 KiB x 1.000
+    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4721674 KiB x 2.000, WRITE_SIZE 8388608 KiB x 1.000
     "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
                         "sha256": "5a7f3999543a3c286c15ef1861eccdca35eca58b0b5fd3e573d53e9ce9e29011",
                         "read": 9.670e9, "write": 8.590e9},
-    # profiles/cnn_flagged_64sig_8192pt_8192spec.md: FETCH_SIZE 6622270 KiB x 2.000, WRITE_SIZE 2097150 KiB x 1.000
+    # profiles/cnn_flagged_64sig_8192pt_8192spec.md: FETCH_SIZE 6622274 KiB x 2.000, WRITE_SIZE 2097152 KiB x 1.000
     "cnn_infer_c5": {"source": "paper_0910_1517_amd/csrc/cnn.hip",
                      "sha256": "11897de3ea8f1fed2ff75202bd8832f9f067f1821c5b36ebff85b1240076a554",
                      "read": 13.562e9, "write": 2.147e9},
@@ -389,7 +389,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2048, help="spectra in the CPU-oracle sample")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

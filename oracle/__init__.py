@@ -309,7 +309,7 @@ def pair_counts(flags: np.ndarray) -> np.ndarray:
 
 
 def apply_flags(Y: np.ndarray, flags: np.ndarray) -> np.ndarray:
-    """Zero flagged cells (the north-star's "flagged samples are zeroed")."""
+    """Zero the flagged cells of the spectra: a flagged sample contributes nothing."""
     return np.where(np.asarray(flags) != 0, 0, Y)
 
 

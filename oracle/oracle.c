@@ -482,7 +482,7 @@ void orc_pair_counts(const uint8_t *flags, int S, int64_t T, int64_t C, int64_t 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Learned flagger (the benchmark spec's addition; the paper only notes that      */
+/* Learned flagger (an addition to the paper, which only notes that          */
 /* better RFI filtering has scope, section 5): 3x3 convolutions with zero     */
 /* padding ("same" size), written from the definition of a 2-D               */
 /* cross-correlation:                                                         */
