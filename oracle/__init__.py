@@ -51,6 +51,7 @@ def _load():
     lib.orc_fengine_channels.restype = i32
     lib.orc_xengine_f64.argtypes = [P, i32, i64, i64, P]
     lib.orc_xengine_int.argtypes = [P, i32, i64, i64, P]
+    lib.orc_beamform.argtypes = [P, i32, i64, i64, P, P, i32, i32, i32, P, P]
     lib.orc_sigma.argtypes = [P, i32, i64, i64, P]
     lib.orc_quantize_int8.argtypes = [P, P, i32, i64, i64, P]
     lib.orc_quantize_fp8.argtypes = [P, P, i32, i64, i64, P]
@@ -192,6 +193,36 @@ def xengine_int(q: np.ndarray, A: np.ndarray | None = None) -> np.ndarray:
         A = np.zeros((C, n_pairs(S), 2), dtype=np.int64)
     _load().orc_xengine_int(_p(q), S, T, C, _p(A))
     return A
+
+
+# ---------------------------------------------------------------------------
+# Array beams (section 3)
+# ---------------------------------------------------------------------------
+BEAM_INTENSITY, BEAM_FULLPOL, BEAM_VOLTAGE = 0, 1, 2
+
+
+def beamform(Y: np.ndarray, w=None, c=None, mode: int = BEAM_FULLPOL, tint: int = 1):
+    """Incoherent beam (detected intensities of the selected signals added,
+    weights w [S]) and coherent beams (voltages added with complex weights
+    c [nb][S], then detected: |V_0|^2, |V_1|^2 and, full-polar, V_0 conj(V_1);
+    or the voltages), the two beamformer modes of section 3.  Y: complex
+    [S][T][C]; signal s = 2a + pol.  Returns (inc [2][T/tint][C] or None,
+    coh [nb][planes][T/tint][C] or None), sums over tint spectra."""
+    Y = np.ascontiguousarray(Y, dtype=np.complex128)
+    S, T, C = Y.shape
+    To = T // tint
+    inc = np.zeros((2, To, C)) if w is not None else None
+    nb = 0 if c is None else len(c)
+    coh = None
+    if nb:
+        c = np.ascontiguousarray(c, dtype=np.complex128).reshape(nb, S)
+        coh = (np.zeros((nb, 2, T, C), dtype=np.complex128) if mode == BEAM_VOLTAGE
+               else np.zeros((nb, 4 if mode == BEAM_FULLPOL else 2, To, C)))
+    wv = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    _load().orc_beamform(_p(Y), S, T, C, _p(wv) if wv is not None else None,
+                         _p(c) if nb else None, nb, mode, tint,
+                         _p(inc) if inc is not None else None, _p(coh) if coh is not None else None)
+    return inc, coh
 
 
 # ---------------------------------------------------------------------------

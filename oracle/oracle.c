@@ -482,6 +482,54 @@ void orc_pair_counts(const uint8_t *flags, int S, int64_t T, int64_t C, int64_t 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Array beams (section 3).  Signal s = 2a + pol.  Per spectrum m, channel k: */
+/*   incoherent  I_pol  = sum over s of pol of  w_s |Y_s|^2                  */
+/*   coherent    V_b,pol = sum over s of pol of  c_b,s Y_s                    */
+/* and the coherent products by mode: 0 |V_0|^2, |V_1|^2; 1 those and Re, Im  */
+/* of V_0 conj(V_1); 2 the voltages V_0, V_1 themselves.  Outputs are sums    */
+/* over tint consecutive spectra.  Y [S][T][C] complex (re, im); w [S] or     */
+/* NULL; c [nb][S] complex; inc [2][T/tint][C] (+=); coh [nb][planes][T/tint] */
+/* [C] (+=; complex for mode 2, tint = 1).                                   */
+void orc_beamform(const double *Y, int S, int64_t T, int64_t C, const double *w, const double *c, int nb,
+                  int mode, int tint, double *inc, double *coh)
+{
+    int64_t To = T / tint;
+    for (int64_t m = 0; m < T; ++m)
+        for (int64_t k = 0; k < C; ++k) {
+            int64_t o = m / tint;
+            if (w && inc)
+                for (int s = 0; s < S; ++s) {
+                    const double *y = Y + 2 * (((int64_t)s * T + m) * C + k);
+                    inc[((int64_t)(s % 2) * To + o) * C + k] += w[s] * (y[0] * y[0] + y[1] * y[1]);
+                }
+            for (int b = 0; b < nb; ++b) {
+                double vr[2] = {0.0, 0.0}, vi[2] = {0.0, 0.0};
+                for (int s = 0; s < S; ++s) {
+                    const double *y = Y + 2 * (((int64_t)s * T + m) * C + k);
+                    const double *cs = c + 2 * ((int64_t)b * S + s);
+                    vr[s % 2] += cs[0] * y[0] - cs[1] * y[1];
+                    vi[s % 2] += cs[0] * y[1] + cs[1] * y[0];
+                }
+                if (mode == 2) {
+                    for (int p = 0; p < 2; ++p) {
+                        double *out = coh + 2 * (((int64_t)(2 * b + p) * T + m) * C + k);
+                        out[0] += vr[p];
+                        out[1] += vi[p];
+                    }
+                    continue;
+                }
+                int np = mode == 1 ? 4 : 2;
+                double prod[4];
+                prod[0] = vr[0] * vr[0] + vi[0] * vi[0];
+                prod[1] = vr[1] * vr[1] + vi[1] * vi[1];
+                prod[2] = vr[0] * vr[1] + vi[0] * vi[1]; /* Re V0 conj(V1) */
+                prod[3] = vi[0] * vr[1] - vr[0] * vi[1]; /* Im V0 conj(V1) */
+                for (int q = 0; q < np; ++q) coh[(((int64_t)b * np + q) * To + o) * C + k] += prod[q];
+            }
+        }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Learned flagger (an addition to the paper, which only notes that          */
 /* better RFI filtering has scope, section 5): 3x3 convolutions with zero     */
 /* padding ("same" size), written from the definition of a 2-D               */
