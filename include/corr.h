@@ -187,6 +187,42 @@ corr_status corr_xpack(corr_plan_t *plan, const void *d_in, void *d_spec, void *
  */
 corr_status corr_xengine(corr_plan_t *plan, const void *d_spec, void *d_acc, void *stream);
 
+/* ------------------------------------------------------------- beamformer */
+
+/*
+ * Array beams from X-layout spectra: the two beamformer modes of section 3,
+ * on the F-engine output as in section 4 (one incoherent and coherent beams
+ * at the raw FFT time resolution, optionally summed over a few spectra).
+ * Per spectrum m, channel k and polarisation pol (signals s = 2a + pol; an
+ * odd S leaves the last antenna with polarisation 0 only), with Y_s the
+ * spectra (INT8 / FP8 codes times d_scale[s][k]; FP32 as stored):
+ *   incoherent     I_pol = sum_s w_s |Y_s|^2 over the signals of pol
+ *                  (d_w[S] >= 0; 0 leaves a signal out)
+ *   coherent b     V_b,pol = sum_s c_b,s Y_s over the signals of pol
+ *                  (d_c[n_beams][S] complex as (re, im) float pairs: gain and
+ *                  antenna-based phase of beam b)
+ * Coherent outputs by mode:
+ *   CORR_BEAM_INTENSITY  2 planes: |V_b,0|^2, |V_b,1|^2
+ *   CORR_BEAM_FULLPOL    4 planes: |V_b,0|^2, |V_b,1|^2, Re and Im of
+ *                        V_b,0 conj(V_b,1) (every product the Stokes
+ *                        parameters need)
+ *   CORR_BEAM_VOLTAGE    2 planes of complex64: V_b,0, V_b,1 (tint = 1)
+ * Every plane is [T/tint][C], summed over tint = 1, 2, 4 or 8 consecutive
+ * spectra.  d_inc: [2][T/tint][C] float (NULL: no incoherent beam; d_w is
+ * then unused).  d_coh: [n_beams][planes][T/tint][C] (unused if n_beams = 0).
+ * n_beams 0..CORR_MAX_BEAMS; at least one beam of either kind.  d_scale is
+ * required for INT8 / FP8 and ignored for FP32.  d_spec 256-byte aligned,
+ * the rest 4-byte aligned (d_coh 8-byte aligned for VOLTAGE).
+ * Errors: NULL, ALIGN, INVALID, DEVICE.
+ */
+#define CORR_MAX_BEAMS 4
+#define CORR_BEAM_INTENSITY 0
+#define CORR_BEAM_FULLPOL 1
+#define CORR_BEAM_VOLTAGE 2
+corr_status corr_beamform(corr_plan_t *plan, const void *d_spec, const float *d_scale, const float *d_w,
+                          float *d_inc, const float *d_c, int32_t n_beams, int32_t mode, float *d_coh,
+                          int32_t tint, void *stream);
+
 /* -------------------------------------------------------------- integrate */
 
 /*

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libcorr.so")
 FP32, INT8, FP8_E4M3 = 0, 1, 2
 SCALE_HOLD, SCALE_COMPUTE = 0, 1
 DUMP, RESET = 1, 2
+BEAM_INTENSITY, BEAM_FULLPOL, BEAM_VOLTAGE = 0, 1, 2  # coherent beam products (corr_beamform)
+MAX_BEAMS = 4
 MAX_INT8_SPECTRA = 66572
 
 STATUS = {
@@ -64,7 +66,7 @@ SYMBOLS = [
     "corr_plan_bind_workspace", "corr_fengine", "corr_xpack", "corr_xengine", "corr_integrate",
     "corr_check_device_errors", "corr_status_string", "corr_last_error",
     "corr_mad_flag", "corr_apply_flags", "corr_pair_counts", "corr_plan_power_bytes",
-    "corr_plan_flags_bytes", "corr_plan_keep_bytes",
+    "corr_plan_flags_bytes", "corr_plan_keep_bytes", "corr_beamform",
     "corr_batch_create", "corr_batch_destroy", "corr_batch_plan", "corr_batch_set_io", "corr_batch_run",
     "corr_batch_capture", "corr_batch_launch", "corr_batch_last_error",
     "corr_autotune_scratch_bytes", "corr_autotune_x_split",
@@ -119,6 +121,8 @@ def lib():
     L.corr_xpack.restype = st
     L.corr_xengine.argtypes = [P, P, P, P]
     L.corr_xengine.restype = st
+    L.corr_beamform.argtypes = [P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P]
+    L.corr_beamform.restype = st
     L.corr_integrate.argtypes = [P, P, P, P, P, ctypes.c_uint32, P]
     L.corr_integrate.restype = st
     L.corr_check_device_errors.argtypes = [P, P]
@@ -280,6 +284,15 @@ class Plan:
 
     def xengine(self, spec, acc, stream=None):
         self._check(lib().corr_xengine(self._h, _ptr(spec), _ptr(acc), _stream(stream)))
+
+    def beamform(self, spec, scale=None, w=None, inc=None, c=None, coh=None, mode=None, tint=1, stream=None):
+        """Incoherent beam (w [S] float -> inc [2][T/tint][C]) and coherent beams
+        (c [n_beams][S][2] float as (re, im) -> coh [n_beams][planes][T/tint][C],
+        complex64 [n_beams][2][T][C] for BEAM_VOLTAGE); see corr_beamform."""
+        n_beams = 0 if c is None else int(c.shape[0])
+        mode = BEAM_FULLPOL if mode is None else mode
+        self._check(lib().corr_beamform(self._h, _ptr(spec), _ptr(scale), _ptr(w), _ptr(inc), _ptr(c), n_beams,
+                                        mode, _ptr(coh), tint, _stream(stream)))
 
     def integrate(self, acc, state, vis=None, scale=None, flags=DUMP, stream=None):
         self._check(lib().corr_integrate(self._h, _ptr(acc), _ptr(scale), _ptr(state), _ptr(vis), flags,

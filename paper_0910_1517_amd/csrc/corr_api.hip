@@ -260,6 +260,33 @@ corr_status corr_xpack(corr_plan_t *p, const void *d_in, void *d_spec, void *str
     return e == hipSuccess ? CORR_OK : hip_fail(p, e, "xpack launch");
 }
 
+corr_status corr_beamform(corr_plan_t *p, const void *d_spec, const float *d_scale, const float *d_w, float *d_inc,
+                          const float *d_c, int32_t n_beams, int32_t mode, float *d_coh, int32_t tint,
+                          void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (n_beams < 0 || n_beams > CORR_MAX_BEAMS)
+        return fail(p, CORR_ERR_INVALID, "n_beams %d outside 0..%d", n_beams, CORR_MAX_BEAMS);
+    if (mode != CORR_BEAM_INTENSITY && mode != CORR_BEAM_FULLPOL && mode != CORR_BEAM_VOLTAGE)
+        return fail(p, CORR_ERR_INVALID, "unknown coherent beam mode %d", mode);
+    if (tint != 1 && tint != 2 && tint != 4 && tint != 8)
+        return fail(p, CORR_ERR_INVALID, "tint %d is not 1, 2, 4 or 8", tint);
+    if (mode == CORR_BEAM_VOLTAGE && n_beams > 0 && tint != 1)
+        return fail(p, CORR_ERR_INVALID, "voltage beams are not summed over time (tint must be 1)");
+    if (!d_inc && n_beams == 0) return fail(p, CORR_ERR_INVALID, "no beam requested");
+    if (!d_spec) return fail(p, CORR_ERR_NULL, "d_spec is required");
+    if (d_inc && !d_w) return fail(p, CORR_ERR_NULL, "the incoherent beam needs d_w");
+    if (n_beams > 0 && (!d_c || !d_coh)) return fail(p, CORR_ERR_NULL, "coherent beams need d_c and d_coh");
+    if (p->d.precision != CORR_FP32 && !d_scale) return fail(p, CORR_ERR_NULL, "INT8 / FP8 spectra need d_scale");
+    if (!aligned(d_spec, 256)) return fail(p, CORR_ERR_ALIGN, "d_spec must be 256-byte aligned");
+    if (!aligned(d_scale, 4) || !aligned(d_w, 4) || !aligned(d_inc, 4) || !aligned(d_c, 4) ||
+        !aligned(d_coh, mode == CORR_BEAM_VOLTAGE ? 8 : 4))
+        return fail(p, CORR_ERR_ALIGN, "beam weights and outputs must be 4-byte aligned (8 for voltage beams)");
+    hipError_t e = launch_beamform(p->d.precision, d_spec, d_scale, d_w, d_c, n_beams, p->d.n_signals, p->M,
+                                   p->d.n_spectra, tint, mode, d_inc, n_beams > 0 ? d_coh : nullptr,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? CORR_OK : hip_fail(p, e, "beamformer launch");
+}
+
 corr_status corr_xengine(corr_plan_t *p, const void *d_spec, void *d_acc, void *stream) {
     if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
     if (!d_spec || !d_acc) return fail(p, CORR_ERR_NULL, "d_spec and d_acc are required");

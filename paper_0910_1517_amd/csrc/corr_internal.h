@@ -148,6 +148,9 @@ __device__ inline float wave_median256(float (&v)[4], int lane) {
     return 0.5f * (__shfl(v[3], 31) + __shfl(v[0], 32));  // sorted elements 127 and 128
 }
 
+hipError_t launch_beamform(int precision, const void *spec, const float *scale, const float *w, const float *cb,
+                           int n_beams, int S, int C, int64_t T, int tint, int mode, float *inc, float *coh,
+                           hipStream_t st);
 hipError_t launch_integrate(int precision, void *acc, const float *scale, double *state,
                             float *vis, const uint16_t *pairs, int S, int C, int splits,
                             uint32_t flags, hipStream_t st);

@@ -168,3 +168,33 @@ def test_cnn_load_rejects_missing_and_foreign_files(tmp_path):
     bad = tmp_path / "bad.bin"
     bad.write_bytes(b"NOTACNN!" + bytes(64))
     assert L.corr_cnn_load(str(bad).encode(), fake, None, None, ctypes.byref(st)) == -1
+
+
+def test_beamform_rejects_bad_arguments():
+    """Every call below fails a host-side check before any launch (the
+    placeholder pointers are never dereferenced)."""
+    L = corr.lib()
+    rc, h = create(n_signals=8, fft_len=512, n_spectra=32, precision=corr.INT8)
+    assert rc == 0
+    try:
+        f = ctypes.c_void_p(1 << 20)  # 256-byte aligned placeholder
+
+        def bf(spec=f, scale=f, w=f, inc=f, c=f, nb=1, mode=corr.BEAM_FULLPOL, coh=f, tint=1):
+            return L.corr_beamform(h, spec, scale, w, inc, c, nb, mode, coh, tint, None)
+
+        assert bf(nb=5) == -1 and bf(nb=-1) == -1
+        assert bf(mode=7) == -1
+        assert bf(tint=3) == -1 and bf(tint=16) == -1 and bf(tint=0) == -1
+        assert bf(mode=corr.BEAM_VOLTAGE, tint=2) == -1  # voltages are not summed over time
+        assert bf(inc=None, nb=0) == -1                   # no beam requested
+        assert bf(spec=None) == -2
+        assert bf(w=None) == -2                           # incoherent beam without weights
+        assert bf(c=None) == -2 and bf(coh=None) == -2
+        assert bf(scale=None) == -2                       # INT8 spectra need their scales
+        assert bf(spec=ctypes.c_void_p((1 << 20) + 16)) == -3
+        assert bf(coh=ctypes.c_void_p((1 << 20) + 2)) == -3
+        assert bf(mode=corr.BEAM_VOLTAGE, coh=ctypes.c_void_p((1 << 20) + 4)) == -3
+        assert L.corr_beamform(None, f, f, f, f, f, 1, 0, f, 1, None) == -2
+        assert L.corr_last_error(h)
+    finally:
+        L.corr_plan_destroy(h)
