@@ -61,6 +61,10 @@ MEASURED_TRAFFIC = {
     "cnn_infer_c5": {"source": "paper_0910_1517_amd/csrc/cnn.hip",
                      "sha256": "11897de3ea8f1fed2ff75202bd8832f9f067f1821c5b36ebff85b1240076a554",
                      "read": 13.562e9, "write": 2.147e9},
+    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4201819 KiB x 2.000, WRITE_SIZE 1572864 KiB x 1.000
+    "beam_int8_c3": {"source": "paper_0910_1517_amd/csrc/beam.hip",
+                     "sha256": "c4b752f8785e1887ba24a549df17dcb04d350f6aef77a9cf576275e4ed864124",
+                     "read": 8.606e9, "write": 1.611e9},
 }
 
 
@@ -375,6 +379,36 @@ def bench_rfi(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_beamformer(corr, torch, S, N, T, x_dev, rs, g_dev, scale, steps, warmup):
+    """B-engine on the int8 spectra of one F-engine call: one incoherent beam and
+    one full-polar coherent beam at the raw FFT time resolution (the paper's
+    beamformer outputs).  Returns (ms per call, algorithmic bytes per call)."""
+    C = N // 2
+    plan = corr.Plan(S, N, T, precision=corr.INT8, scale_mode=corr.SCALE_HOLD)
+    spec = plan.alloc("spectra", zero=False)
+    plan.fengine(x_dev, g_dev, spec, scale, row_stride=rs)
+    w = torch.ones(S, device="cuda")
+    ph = torch.rand(S, device="cuda", generator=torch.Generator(device="cuda").manual_seed(7)) * 6.283185
+    c = torch.stack([torch.cos(ph), torch.sin(ph)], -1).view(1, S, 2).contiguous()
+    inc = torch.empty(2, T, C, device="cuda")
+    coh = torch.empty(1, 4, T, C, device="cuda")
+    f = lambda: plan.beamform(spec, scale, w, inc, c, coh, mode=corr.BEAM_FULLPOL, tint=1)
+    for _ in range(warmup):
+        f()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nbytes = S * C * T * 2 + S * C * 4 + (2 + 4) * T * C * 4
+    del spec, inc, coh, plan
+    torch.cuda.empty_cache()
+    return ms, nbytes
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -429,6 +463,10 @@ def main():
         torch.cuda.empty_cache()
         t8 = run_pipelined(corr, torch, corr.INT8, S, N, T, x_dev, rs, g_dev, args.steps, args.warmup, scale)
         log("int8 streamed (F of block i+1 beside X of block i): %.3f ms per block" % (t8 * 1e3))
+    torch.cuda.empty_cache()
+    log("timing the beamformer (one incoherent + one full-polar coherent beam)")
+    tb_ms, tb_bytes = bench_beamformer(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
+    log("beamformer: %.3f ms per call" % tb_ms)
     r8f = None
     if not args.no_fp8:
         torch.cuda.empty_cache()
@@ -501,6 +539,12 @@ def main():
     out["roofline"] = {"kernel": kern, "bound": bound, "achieved": round(ach, 3), "peak": round(peak, 2),
                        "unit": unit, "frac": round(ach / peak, 4), "traffic": traffic,
                        "f_engine": f_part, "x_engine": x_part}
+    out["beamformer"] = {"kernel": "beam_kernel<int8, 1 beam> (B-engine)", "bound": "hbm",
+                         "beams": "1 incoherent (2 pol) + 1 coherent full-polar (4 products), tint 1",
+                         "ms": round(tb_ms, 4), "achieved_gbs": round(tb_bytes / tb_ms / 1e6, 1),
+                         "hbm_frac": round(tb_bytes / tb_ms / 1e6 / (HBM_PEAK / 1e9), 4),
+                         "algorithmic_bytes": tb_bytes,
+                         "traffic": measured_traffic("beam_int8_%s" % args.config)}
     if r32:
         xops32, xin32 = x_algorithmic(S, N, T, 8)
         out["fp32"] = {"correlated_bandwidth_mhz": round(bw(t32), 3), "ms_per_step": round(t32 * 1e3, 4),

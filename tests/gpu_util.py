@@ -84,3 +84,52 @@ def near_threshold_cells(P64, M=3.0):
                     else:
                         near[s, m0:m0 + 64, k0:k0 + 256] |= close[None, :]
     return near
+
+
+# Beamformer tolerance (FP32 accumulation of at most 64 terms, the scale folded
+# into the weights in FP32): per cell, |error| <= 1e-5 of the sum of the
+# magnitudes of the terms -- sum_s w_s |Y_s|^2 for the incoherent beam,
+# B_p = sum_s |c_s| |Y_s| per polarisation for a voltage, B_p^2 for |V_p|^2 and
+# B_0 B_1 for V_0 conj(V_1).
+BEAM_TOL = 1e-5
+
+
+def beam_bounds(Y, w, c, tint):
+    """Per-cell error scales: incoherent sum_s w |Y|^2 [2][T/tint][C]; coherent
+    B [nb][2][T][C] = sum over the signals of each polarisation of |c| |Y|."""
+    S, T, C = Y.shape
+    pol = np.arange(S) % 2
+    A = np.abs(Y)
+    inc_b = None
+    if w is not None:
+        inc_b = np.stack([np.tensordot(w * (pol == p), A ** 2, axes=1) for p in (0, 1)])
+        inc_b = inc_b.reshape(2, T // tint, tint, C).sum(axis=2)
+    coh_b = None
+    if c is not None:
+        coh_b = np.stack([np.stack([np.tensordot(np.abs(cb) * (pol == p), A, axes=1) for p in (0, 1)])
+                          for cb in c])
+    return inc_b, coh_b
+
+
+def check_beams(got_inc, got_coh, ref_inc, ref_coh, inc_b, coh_b, mode, tint):
+    if ref_inc is not None:
+        assert np.all(np.isfinite(got_inc))
+        err = np.abs(got_inc - ref_inc)
+        assert np.all(err <= BEAM_TOL * inc_b + 1e-30), err.max()
+    if ref_coh is None:
+        return
+    assert np.all(np.isfinite(got_coh))
+    nb = ref_coh.shape[0]
+    B = coh_b  # [nb][2][T][C]
+    if mode == corr.BEAM_VOLTAGE:
+        err = np.abs(got_coh - ref_coh)
+        assert np.all(err <= BEAM_TOL * B + 1e-30), err.max()
+        return
+    T, C = B.shape[2], B.shape[3]
+    fold = lambda x: x.reshape(nb, T // tint, tint, C).sum(axis=2)
+    bounds = [fold(B[:, 0] ** 2), fold(B[:, 1] ** 2)]
+    if mode == corr.BEAM_FULLPOL:
+        bounds += [fold(B[:, 0] * B[:, 1])] * 2
+    for q, bq in enumerate(bounds):
+        err = np.abs(got_coh[:, q] - ref_coh[:, q])
+        assert np.all(err <= BEAM_TOL * bq + 1e-30), (q, err.max())

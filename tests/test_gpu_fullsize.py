@@ -10,7 +10,7 @@ import pytest
 import oracle
 import paper_0910_1517_amd as corr
 import synth
-from gpu_util import FS, near_threshold_cells
+from gpu_util import FS, beam_bounds, check_beams, near_threshold_cells
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -125,6 +125,42 @@ def test_precision_form_int8_sampled_channels():
     e_max8, e_fro8 = oracle.normalized_error(state_channels(state, C, plan.P, chans), V64, S)
     print("c3 fp8 sampled channels: e_max %.3g e_fro %.3g" % (e_max8, e_fro8))
     assert e_fro8 <= 5e-3
+
+
+def test_beamformer_at_the_precision_form_sampled_channels():
+    """Array beams at the precision form's shape (64 signals, 4096-pt, 32768
+    spectra, int8 from the F-engine with computed scales) in bench.py's
+    configuration: one incoherent beam and one full-polar coherent beam at the
+    raw FFT time resolution.  Sampled channels against the oracle on the same
+    int8 codes and scales."""
+    import torch
+    S, N, T = 64, 4096, 32768
+    C = N // 2
+    geo, x, rs, g = workload(S, N, T, synth.BASE_SEED + 2)
+    plan = corr.Plan(S, N, T, precision=corr.INT8, scale_mode=corr.SCALE_COMPUTE)
+    scale = torch.zeros(S * C, dtype=torch.float32, device="cuda")
+    spec = plan.alloc("spectra", zero=False)
+    plan.fengine(x, g, spec, scale, row_stride=rs)
+    del x
+    rng = np.random.default_rng(5)
+    w = rng.uniform(0.5, 1.5, S).astype(np.float32)
+    w[9] = 0.0  # one signal left out of the incoherent sum
+    c = np.exp(2j * np.pi * rng.uniform(size=S)).astype(np.complex64)  # antenna phases
+    inc = torch.empty(2, T, C, device="cuda")
+    coh = torch.empty(1, 4, T, C, device="cuda")
+    cw = torch.from_numpy(np.stack([c.real, c.imag], -1)[None].copy()).cuda()
+    plan.beamform(spec, scale, torch.from_numpy(w).cuda(), inc, cw, coh, mode=corr.BEAM_FULLPOL, tint=1)
+    torch.cuda.synchronize()
+    chans = [37, 1500]
+    q = int8_channels(spec, S, C, T, chans).astype(np.float64)  # [S][T][2 ch][2]
+    sc = scale.view(S, C)[:, chans].cpu().numpy().astype(np.float64)
+    Y = (q[..., 0] + 1j * q[..., 1]) * sc[:, None, :]
+    w64, c64 = w.astype(np.float64), c.astype(np.complex128)[None]
+    ref_inc, ref_coh = oracle.beamform(Y, w=w64, c=c64, mode=oracle.BEAM_FULLPOL)
+    inc_b, coh_b = beam_bounds(Y, w64, c64, 1)
+    got_inc = inc[:, :, chans].cpu().numpy()
+    got_coh = coh[:, :, :, chans].cpu().numpy()
+    check_beams(got_inc, got_coh, ref_inc, ref_coh, inc_b, coh_b, corr.BEAM_FULLPOL, 1)
 
 
 def test_precision_form_int8_xengine_bit_exact_sampled_channels():
