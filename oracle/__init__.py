@@ -24,10 +24,11 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c with gcc (no fast-math) into liboracle.so."""
+    """Compile oracle.c with gcc (no fast-math, no contraction into FMA) into
+    liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-shared", "-fPIC", "-std=c11",
                                _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -67,6 +68,10 @@ def _load():
     lib.orc_mad_tile_flags.argtypes = [P, i32, i64, i64, i32, i32, dbl, P]
     lib.orc_mad_tile_flags.restype = i32
     lib.orc_pair_counts.argtypes = [P, i32, i64, i64, P]
+    u32 = ctypes.c_uint32
+    lib.orc_philox4x32_10.argtypes = [P, P, P]
+    lib.orc_blank_noise_table.argtypes = [ctypes.c_uint64, i32, i64, P]
+    lib.orc_mad_blank.argtypes = [P, i64, i32, i64, i64, dbl, P, i64, i64, P, P, P]
     lib.orc_conv3x3_fwd.argtypes = [P, P, P, i32, i32, i32, i32, i32, P]
     lib.orc_conv3x3_bwd.argtypes = [P, P, P, i32, i32, i32, i32, i32, P, P, P]
     _lib = lib
@@ -223,6 +228,48 @@ def beamform(Y: np.ndarray, w=None, c=None, mode: int = BEAM_FULLPOL, tint: int 
                          _p(c) if nb else None, nb, mode, tint,
                          _p(inc) if inc is not None else None, _p(coh) if coh is not None else None)
     return inc, coh
+
+
+# ---------------------------------------------------------------------------
+# Time-domain MAD voltage blanker (section 5, Eq. 3 and 4)
+# ---------------------------------------------------------------------------
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """One Philox4x32-10 block (Salmon et al., SC'11): 4 counter words and 2
+    key words in, 4 words out."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(4)
+    k = np.ascontiguousarray(key, dtype=np.uint32).reshape(2)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def blank_noise_table(seed: int, S: int, L: int) -> np.ndarray:
+    """Precomputed replacement noise [S][L] (float32, mean 0, variance 1):
+    Irwin-Hall sums of twelve 16-bit uniforms from Philox4x32-10, one
+    independent row per signal."""
+    t = np.zeros((S, L), dtype=np.float32)
+    _load().orc_blank_noise_table(int(seed) & 0xFFFFFFFFFFFFFFFF, S, L, _p(t))
+    return t
+
+
+def mad_blank(x: np.ndarray, B: int, M: float, table: np.ndarray, sample0: int = 0):
+    """Blank voltage outliers per block of B samples of each row of x (int8
+    [S][n]): samples with |x - median| > M MAD / 0.6745 become
+    rint(median + MAD / 0.6745 * z) clamped to int8, z from the signal's row
+    of the noise table at (sample0 + i) mod L.  Returns (out, counts
+    [S][nblocks], stats [S][nblocks][2] = (2 median, 4 MAD))."""
+    x = np.ascontiguousarray(x, dtype=np.int8)
+    S, n = x.shape
+    table = np.ascontiguousarray(table, dtype=np.float32)
+    assert table.shape[0] == S
+    L = table.shape[1]
+    assert L > 0 and L & (L - 1) == 0
+    nb = (n + B - 1) // B
+    out = np.empty_like(x)
+    counts = np.zeros((S, nb), dtype=np.int32)
+    stats = np.zeros((S, nb, 2), dtype=np.int32)
+    _load().orc_mad_blank(_p(x), n, S, n, B, float(M), _p(table), L, sample0, _p(out), _p(counts), _p(stats))
+    return out, counts, stats
 
 
 # ---------------------------------------------------------------------------

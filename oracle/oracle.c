@@ -21,14 +21,20 @@
  *   requantisation       section 4.1 (fixed-point pipeline up to the MAC,
  *                        32-bit products, float long-term accumulation)
  *   MAD statistic        Eq. 3 and Eq. 4 of section 5
+ *   array beams          section 3 (incoherent and coherent beamformer)
+ *   voltage blanker      section 5 (Eq. 3 and 4 on voltage blocks, outliers
+ *                        replaced by precomputed Gaussian noise, one table
+ *                        per signal from Philox4x32-10)
  *
  * Readings where the paper is silent (FFT sign, bins kept, time stamp of a
  * spectrum, sign convention of Eq. 2, requantisation scale, e4m3 format) are
  * the ones listed in the design notes of the repository and are restated at
  * each function below.
  *
- * Build: gcc -O2 -fopenmp -shared -fPIC oracle.c -o liboracle.so -lm
- * (no -ffast-math: every operation is the plain IEEE one).
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC oracle.c
+ *        -o liboracle.so -lm
+ * (no -ffast-math and no FMA contraction: every operation is the plain IEEE
+ * one).
  */
 #include <complex.h>
 #include <math.h>
@@ -527,6 +533,122 @@ void orc_beamform(const double *Y, int S, int64_t T, int64_t C, const double *w,
                 for (int q = 0; q < np; ++q) coh[(((int64_t)b * np + q) * To + o) * C + k] += prod[q];
             }
         }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time-domain MAD voltage blanker (section 5, Eq. 3 and 4).  Per block of B */
+/* consecutive samples of one signal: x~ = median, MAD = median |x - x~|; a   */
+/* sample with |x - x~| > M MAD / 0.6745 is replaced by a precomputed         */
+/* Gaussian noise sample, the tables being independent per signal (so per    */
+/* antenna).  The replacement has the block's robust statistics (mean x~,     */
+/* sigma = MAD / 0.6745): rint(x~ + sigma z), clamped to the int8 range.  A   */
+/* block with MAD = 0 has no scale estimate and is passed unchanged.  Medians */
+/* are kept exactly as integers: med2 = 2 x~, mad4 = 4 MAD.                   */
+/*                                                                            */
+/* Noise table: z[s][j] for j < L is the Irwin-Hall sum of twelve 16-bit      */
+/* uniforms (U + 1/2) / 65536 minus 6 (mean 0, variance 1), the uniforms      */
+/* being the 16-bit halves of two Philox4x32-10 outputs (Salmon, Moraes,      */
+/* Dror and Shaw, SC'11) keyed by the seed at counters (j, 0, s, 0) and       */
+/* (j, 0, s, 1): halves low then high of words 0..3 of the first and words    */
+/* 0..1 of the second.  Sample p of a row uses z[s][p mod L].                 */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { /* key schedule: Weyl increments between rounds */
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+    }
+    for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+/* table[s * L + j], float (every value is a multiple of 2^-16 below 6: exact) */
+void orc_blank_noise_table(uint64_t seed, int S, int64_t L, float *table)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int s = 0; s < S; ++s)
+        for (int64_t j = 0; j < L; ++j) {
+            uint32_t a[4], b[4];
+            uint32_t c0[4] = {(uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)s, 0u};
+            uint32_t c1[4] = {(uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)s, 1u};
+            orc_philox4x32_10(c0, key, a);
+            orc_philox4x32_10(c1, key, b);
+            uint32_t w[6] = {a[0], a[1], a[2], a[3], b[0], b[1]};
+            int64_t sum = 0;
+            for (int q = 0; q < 6; ++q) sum += (int64_t)(w[q] & 0xFFFFu) + (int64_t)(w[q] >> 16);
+            /* sum of (U + 1/2) / 65536 over 12, minus 6 */
+            table[(int64_t)s * L + j] = (float)((double)(sum + 6 - 6 * 65536) / 65536.0);
+        }
+}
+
+static int cmp_int(const void *a, const void *b)
+{
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* 2 x median of v[0 .. n-1] (sorts v): the middle value, or the sum of the two */
+/* middle values for even n */
+static int median2(int *v, int64_t n)
+{
+    qsort(v, (size_t)n, sizeof(int), cmp_int);
+    return (n & 1) ? 2 * v[n / 2] : v[n / 2 - 1] + v[n / 2];
+}
+
+/* x: S rows of n samples, row s at x + s * row_stride; out: same layout (may */
+/* be x).  table [S][L] (L a power of two), sample i of a row uses entry      */
+/* (sample0 + i) mod L.  counts [S][ceil(n / B)] blanked samples and stats    */
+/* [S][ceil(n / B)][2] = (med2, mad4), each optional (NULL).                  */
+void orc_mad_blank(const int8_t *x, int64_t row_stride, int S, int64_t n, int64_t B, double M, const float *table,
+                   int64_t L, int64_t sample0, int8_t *out, int32_t *counts, int32_t *stats)
+{
+    int64_t nb = (n + B - 1) / B;
+    int *v = (int *)malloc(sizeof(int) * (size_t)B);
+    int *d = (int *)malloc(sizeof(int) * (size_t)B);
+    for (int s = 0; s < S; ++s)
+        for (int64_t b = 0; b < nb; ++b) {
+            int64_t i0 = b * B, len = (i0 + B <= n) ? B : n - i0;
+            const int8_t *xr = x + (int64_t)s * row_stride + i0;
+            int8_t *o = out + (int64_t)s * row_stride + i0;
+            for (int64_t i = 0; i < len; ++i) v[i] = xr[i];
+            int med2 = median2(v, len);                            /* Eq. 3: x~ */
+            for (int64_t i = 0; i < len; ++i) d[i] = abs(2 * (int)xr[i] - med2);
+            int mad4 = median2(d, len);                            /* Eq. 3: MAD */
+            double mad = (double)mad4 * 0.25;
+            double thr = (double)M * mad / 0.6745;                 /* Eq. 4 */
+            double sigma = mad / 0.6745;
+            int32_t cnt = 0;
+            for (int64_t i = 0; i < len; ++i) {
+                int xi = xr[i];
+                double dev = 0.5 * (double)abs(2 * xi - med2);     /* |x - x~| */
+                if (mad4 > 0 && dev > thr) {
+                    double z = (double)table[(int64_t)s * L + ((sample0 + i0 + i) & (L - 1))];
+                    double r = rint(0.5 * (double)med2 + sigma * z);
+                    if (r < -128.0) r = -128.0;
+                    if (r > 127.0) r = 127.0;
+                    o[i] = (int8_t)r;
+                    ++cnt;
+                } else {
+                    o[i] = (int8_t)xi;
+                }
+            }
+            if (counts) counts[(int64_t)s * nb + b] = cnt;
+            if (stats) {
+                stats[((int64_t)s * nb + b) * 2] = med2;
+                stats[((int64_t)s * nb + b) * 2 + 1] = mad4;
+            }
+        }
+    free(v);
+    free(d);
 }
 
 /* ------------------------------------------------------------------------ */
