@@ -270,6 +270,59 @@ size_t corr_plan_power_bytes(const corr_plan_t *plan);
 size_t corr_plan_flags_bytes(const corr_plan_t *plan);
 size_t corr_plan_keep_bytes(const corr_plan_t *plan);
 
+/* ------------------------------------------------------- voltage blanker */
+
+/* Time-domain RFI blanker on the pre-detected voltages (section 5, Eq. 3 and
+ * Eq. 4).  It runs on the int8 sample rows corr_fengine reads, before the FFT.
+ * Each block of `block` consecutive samples of a row is handled on its own
+ * (the last block of a row may be shorter): x~ = median, MAD = median
+ * |x - x~| (median of an even count = mean of the two middle values).  A
+ * sample with |x - x~| > M MAD / 0.6745 is replaced by
+ * rint(x~ + (MAD / 0.6745) z), clamped to [-128, 127] (rint: nearest, ties to
+ * even).  z is entry (sample0 + i) mod table_len of the signal's row of a
+ * precomputed Gaussian noise table (corr_blank_noise_table), so the
+ * replacements are independent between antennas.  A block with MAD = 0 has
+ * no scale estimate and passes unchanged.  The median and the MAD are exact,
+ * and the threshold and the replacements are evaluated in FP64, so the
+ * output is one definite array.
+ *   d_x        S rows of int8 samples, row s at d_x + s*row_stride, n samples
+ *              each; row_stride a multiple of 16 and >= n; 16-byte aligned.
+ *              Whole 16-byte chunks are read, so each row must be addressable
+ *              up to n rounded up to 16 (true for S full rows of row_stride).
+ *   block      multiple of 16 in [16, 65536] (the paper leaves the block
+ *              length to the user; a few thousand samples suit impulsive RFI).
+ *   M          threshold, finite and > 0 (2.5 to 3.0 in the paper).
+ *   d_table    [S][table_len] float, table_len a power of two <= 2^31.
+ *   sample0    absolute index of each row's first sample (>= 0), so that
+ *              consecutive calls on a stream draw consecutive table entries.
+ *   d_out      same layout as d_x.  Either d_x itself (in place: only 16-byte
+ *              chunks holding a blanked sample are written), or a buffer that
+ *              does not overlap it (every sample is written).
+ *   d_counts   optional [S][ceil(n / block)] int32: samples blanked per block.
+ *   d_stats    optional [S][ceil(n / block)][2] int32: (2 x~, 4 MAD) per block,
+ *              both integers for int8 data.
+ * n == 0 enqueues nothing.  Calls that overlap on the same buffers race.
+ * Errors: NULL, ALIGN, INVALID (S outside [1, 65535], n < 0, row_stride,
+ * block, M, table_len, sample0 < 0, more than 2^31 - 1 blocks), DEVICE;
+ * messages via corr_blank_last_error. */
+corr_status corr_blank_voltages(const int8_t *d_x, int64_t row_stride, int32_t S, int64_t n, int32_t block,
+                                float M, const float *d_table, int64_t table_len, int64_t sample0, int8_t *d_out,
+                                int32_t *d_counts, int32_t *d_stats, void *stream);
+
+/* Fill d_table [S][L] (float, 4-byte aligned; L a power of two <= 2^31) with
+ * the blanker's precomputed Gaussian noise (section 5): entry j of signal s is
+ * the sum of twelve uniforms (U + 1/2) / 65536 minus 6 (mean 0, variance 1,
+ * the Irwin-Hall approximation of a normal deviate, |z| < 6).  The U are the
+ * 16-bit halves, low then high, of words 0..3 of Philox4x32-10 (Salmon et al.,
+ * SC'11) at counter (j mod 2^32, j / 2^32, s, 0) and words 0..1 at counter
+ * (.., s, 1), with key (seed mod 2^32, seed / 2^32).  One row per signal makes
+ * the replacements of different antennas independent.  Every value is exact
+ * in float.  Errors: NULL, ALIGN, INVALID (S outside [1, 65535], L), DEVICE. */
+corr_status corr_blank_noise_table(uint64_t seed, int32_t S, int64_t L, float *d_table, void *stream);
+
+/* Message of the last failed blanker call on this thread ("" after success). */
+const char *corr_blank_last_error(void);
+
 /* ------------------------------------------------------------------ batch */
 
 /* Several correlations of different shapes (the paper runs sub-arrays and

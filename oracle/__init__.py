@@ -68,9 +68,10 @@ def _load():
     lib.orc_mad_tile_flags.argtypes = [P, i32, i64, i64, i32, i32, dbl, P]
     lib.orc_mad_tile_flags.restype = i32
     lib.orc_pair_counts.argtypes = [P, i32, i64, i64, P]
-    u32 = ctypes.c_uint32
     lib.orc_philox4x32_10.argtypes = [P, P, P]
     lib.orc_blank_noise_table.argtypes = [ctypes.c_uint64, i32, i64, P]
+    lib.orc_blank_noise_entry.argtypes = [ctypes.c_uint64, i32, i64]
+    lib.orc_blank_noise_entry.restype = ctypes.c_float
     lib.orc_mad_blank.argtypes = [P, i64, i32, i64, i64, dbl, P, i64, i64, P, P, P]
     lib.orc_conv3x3_fwd.argtypes = [P, P, P, i32, i32, i32, i32, i32, P]
     lib.orc_conv3x3_bwd.argtypes = [P, P, P, i32, i32, i32, i32, i32, P, P, P]
@@ -250,6 +251,11 @@ def blank_noise_table(seed: int, S: int, L: int) -> np.ndarray:
     t = np.zeros((S, L), dtype=np.float32)
     _load().orc_blank_noise_table(int(seed) & 0xFFFFFFFFFFFFFFFF, S, L, _p(t))
     return t
+
+
+def blank_noise_entry(seed: int, s: int, j: int) -> float:
+    """Entry j of signal s's noise-table row, computed on its own."""
+    return float(_load().orc_blank_noise_entry(int(seed) & 0xFFFFFFFFFFFFFFFF, s, j))
 
 
 def mad_blank(x: np.ndarray, B: int, M: float, table: np.ndarray, sample0: int = 0):

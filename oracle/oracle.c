@@ -571,23 +571,27 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
     for (int i = 0; i < 4; ++i) out[i] = c[i];
 }
 
-/* table[s * L + j], float (every value is a multiple of 2^-16 below 6: exact) */
-void orc_blank_noise_table(uint64_t seed, int S, int64_t L, float *table)
+/* entry j of signal s's table row (a multiple of 2^-16 below 6: exact in float) */
+float orc_blank_noise_entry(uint64_t seed, int s, int64_t j)
 {
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t a[4], b[4];
+    uint32_t c0[4] = {(uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)s, 0u};
+    uint32_t c1[4] = {(uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)s, 1u};
+    orc_philox4x32_10(c0, key, a);
+    orc_philox4x32_10(c1, key, b);
+    uint32_t w[6] = {a[0], a[1], a[2], a[3], b[0], b[1]};
+    int64_t sum = 0;
+    for (int q = 0; q < 6; ++q) sum += (int64_t)(w[q] & 0xFFFFu) + (int64_t)(w[q] >> 16);
+    /* sum of (U + 1/2) / 65536 over 12, minus 6 */
+    return (float)((double)(sum + 6 - 6 * 65536) / 65536.0);
+}
+
+/* table[s * L + j] */
+void orc_blank_noise_table(uint64_t seed, int S, int64_t L, float *table)
+{
     for (int s = 0; s < S; ++s)
-        for (int64_t j = 0; j < L; ++j) {
-            uint32_t a[4], b[4];
-            uint32_t c0[4] = {(uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)s, 0u};
-            uint32_t c1[4] = {(uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)s, 1u};
-            orc_philox4x32_10(c0, key, a);
-            orc_philox4x32_10(c1, key, b);
-            uint32_t w[6] = {a[0], a[1], a[2], a[3], b[0], b[1]};
-            int64_t sum = 0;
-            for (int q = 0; q < 6; ++q) sum += (int64_t)(w[q] & 0xFFFFu) + (int64_t)(w[q] >> 16);
-            /* sum of (U + 1/2) / 65536 over 12, minus 6 */
-            table[(int64_t)s * L + j] = (float)((double)(sum + 6 - 6 * 65536) / 65536.0);
-        }
+        for (int64_t j = 0; j < L; ++j) table[(int64_t)s * L + j] = orc_blank_noise_entry(seed, s, j);
 }
 
 static int cmp_int(const void *a, const void *b)

@@ -73,6 +73,7 @@ SYMBOLS = [
     "corr_cnn_create", "corr_cnn_destroy", "corr_cnn_workspace_bytes", "corr_cnn_bind_workspace",
     "corr_cnn_forward", "corr_cnn_loss_grad", "corr_cnn_adam", "corr_cnn_train_step",
     "corr_cnn_check_device_errors", "corr_cnn_infer", "corr_cnn_save", "corr_cnn_load", "corr_cnn_last_error",
+    "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
 ]
 
 
@@ -166,6 +167,12 @@ def lib():
         getattr(L, "corr_cnn_" + n).restype = st
     L.corr_cnn_last_error.argtypes = [P]
     L.corr_cnn_last_error.restype = ctypes.c_char_p
+    L.corr_blank_voltages.argtypes = [P, i64, i32, i64, i32, f32, P, i64, i64, P, P, P, P]
+    L.corr_blank_voltages.restype = st
+    L.corr_blank_noise_table.argtypes = [ctypes.c_uint64, i32, i64, P, P]
+    L.corr_blank_noise_table.restype = st
+    L.corr_blank_last_error.argtypes = []
+    L.corr_blank_last_error.restype = ctypes.c_char_p
     L.corr_status_string.argtypes = [st]
     L.corr_status_string.restype = ctypes.c_char_p
     L.corr_last_error.argtypes = [P]
@@ -459,6 +466,33 @@ def cnn_load(path: str, params, m=None, v=None) -> int:
     st = ctypes.c_int64()
     _cnn_check(lib().corr_cnn_load(path.encode(), _ptr(params), _ptr(m), _ptr(v), ctypes.byref(st)))
     return st.value
+
+
+def _blank_check(rc):
+    if rc != 0:
+        raise CorrError(rc, lib().corr_blank_last_error().decode())
+
+
+def blank_noise_table(seed: int, table, stream=None):
+    """Fill table (float32 [S][L], L a power of two) with the blanker's
+    precomputed Gaussian noise; see corr_blank_noise_table."""
+    S, L = table.shape
+    _blank_check(lib().corr_blank_noise_table(int(seed) & 0xFFFFFFFFFFFFFFFF, S, L, _ptr(table), _stream(stream)))
+
+
+def blank_voltages(x, table, *, block: int, M: float = 3.0, out=None, counts=None, stats=None, sample0: int = 0,
+                   n: int | None = None, stream=None):
+    """MAD voltage blanker on int8 rows x [S][row_stride] (first n samples of
+    each row, default all); out is x (in place, the default) or a tensor of
+    the same shape; counts int32 [S][nblocks] and stats int32
+    [S][nblocks][2] optional.  See corr_blank_voltages."""
+    S, rs = x.shape
+    if out is None:
+        out = x
+    _blank_check(lib().corr_blank_voltages(_ptr(x), x.stride(0), S, rs if n is None else n, block, M, _ptr(table),
+                                           table.shape[1], sample0, _ptr(out), _ptr(counts), _ptr(stats),
+                                           _stream(stream)))
+    return out
 
 
 def _autotune_cache_path():

@@ -387,3 +387,72 @@ def power_spectra(S: int, T: int, C: int, seed: int = BASE_SEED, *, tone_frac: f
             mean[m0:m0 + ln] *= 1.0 + gs.uniform(*burst_k)
         out[s] = (gs.exponential(1.0, (T, C)) * mean).astype(np.float32)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Impulsive voltage interference (the broadband, power-line spark RFI that the
+# time-domain blanker of section 5 targets)
+# ---------------------------------------------------------------------------
+def impulse_bursts(n_samples: int, seed: int = BASE_SEED, *, duty: float = 0.025, burst_len=(16, 512),
+                   k=(4.0, 40.0)):
+    """Bursts common to every antenna: (start sample, length, variance factor)
+    arrays.  Starts are uniform over the stream (count Poisson with mean
+    duty * n / mean length, so about a fraction ``duty`` of the samples lie in
+    a burst), each moved past the end of the previous burst so that no two
+    overlap; lengths U{burst_len}, variance factors k ~ U[k] in units of
+    sigma_t^2."""
+    g = rng(seed, 30, n_samples)
+    mean_len = 0.5 * (burst_len[0] + burst_len[1])
+    nb = int(g.poisson(duty * n_samples / mean_len))
+    starts = np.sort(g.integers(0, max(1, n_samples), nb))
+    lens = g.integers(burst_len[0], burst_len[1] + 1, nb)
+    ks = g.uniform(k[0], k[1], nb)
+    before = np.concatenate([[0], np.cumsum(lens)[:-1]])      # samples in earlier bursts
+    starts = np.maximum.accumulate(starts - before) + before  # start_i >= end_{i-1}
+    return starts, lens, ks
+
+
+def add_impulses(x, geom: Geom, n_samples: int, *, sigma_t: float = 12.0, seed: int = BASE_SEED,
+                 duty: float = 0.025, burst_len=(16, 512), k=(4.0, 40.0), n_pol: int = 2):
+    """Add impulsive RFI to int8 streams x [S][>= n_samples] in place (numpy
+    array or torch tensor, on any device): each burst is one Gaussian waveform
+    per polarisation (std sqrt(k) sigma_t), received by every antenna with its
+    integer delay D (sample n of the waveform lands on sample n + D), so it
+    correlates between antennas like a terrestrial source; then
+    x = clip(x + rint(w), -127, 127).  Returns the boolean mask (numpy
+    [S][n_samples]) of the samples a burst touched only for numpy input, else
+    None."""
+    starts, lens, ks = impulse_bursts(n_samples, seed, duty=duty, burst_len=burst_len, k=k)
+    total = int(lens.sum())
+    if total == 0:
+        return np.zeros(x.shape[0:1] + (n_samples,), bool) if isinstance(x, np.ndarray) else None
+    pos = np.repeat(starts - np.cumsum(np.concatenate([[0], lens[:-1]])), lens) + np.arange(total)
+    amp = np.repeat(np.sqrt(ks) * sigma_t, lens).astype(np.float32)
+    S = x.shape[0]
+    if isinstance(x, np.ndarray):
+        mask = np.zeros((S, n_samples), bool)
+        for pol in range(n_pol):
+            w = np.rint(rng(seed, 31, pol).standard_normal(total, dtype=np.float32) * amp)
+            for s in range(pol, S, n_pol):
+                p = pos + int(geom.D[s])
+                keep = p < n_samples
+                v = x[s, p[keep]].astype(np.float32) + w[keep]
+                x[s, p[keep]] = np.clip(v, -127, 127).astype(np.int8)
+                mask[s, p[keep]] = True
+        return mask
+    import torch
+    dev = x.device
+    pos_d = torch.from_numpy(pos).to(dev)
+    amp_d = torch.from_numpy(amp).to(dev)
+    gen = torch.Generator(device=dev)
+    for pol in range(n_pol):
+        gen.manual_seed((int(seed) * 1000003 + 31 * pol + 5) & 0x7FFFFFFFFFFFFFFF)
+        w = torch.randn(total, generator=gen, device=dev, dtype=torch.float32).mul_(amp_d).round_()
+        for s in range(pol, S, n_pol):
+            p = pos_d + int(geom.D[s])
+            keep = p < n_samples
+            pk = p[keep]
+            v = x[s, pk].float().add_(w[keep])
+            x[s, pk] = v.clamp_(-127, 127).to(torch.int8)
+        del w
+    return None

@@ -198,3 +198,33 @@ def test_beamform_rejects_bad_arguments():
         assert L.corr_last_error(h)
     finally:
         L.corr_plan_destroy(h)
+
+
+def test_blanker_rejects_bad_arguments():
+    """Host-side checks of the voltage blanker and its noise table; every call
+    returns before any launch (placeholder pointers, never dereferenced)."""
+    L = corr.lib()
+    f = ctypes.c_void_p(1 << 20)
+
+    def bv(x=f, rs=1024, S=4, n=1000, block=256, M=3.0, table=f, tl=1024, s0=0, out=f, counts=f, stats=f):
+        return L.corr_blank_voltages(x, rs, S, n, block, M, table, tl, s0, out, counts, stats, None)
+
+    assert bv(x=None) == -2 and bv(table=None) == -2 and bv(out=None) == -2
+    assert bv(x=ctypes.c_void_p((1 << 20) + 8)) == -3 and bv(out=ctypes.c_void_p((1 << 20) + 4)) == -3
+    assert bv(table=ctypes.c_void_p((1 << 20) + 2)) == -3 and bv(stats=ctypes.c_void_p((1 << 20) + 1)) == -3
+    assert bv(S=0) == -1 and bv(S=65536) == -1
+    assert bv(n=-1) == -1 and bv(rs=1000) == -1 and bv(rs=992) == -1      # not a multiple of 16 / below n
+    assert bv(block=8) == -1 and bv(block=100) == -1 and bv(block=65552) == -1
+    assert bv(M=0.0) == -1 and bv(M=-1.0) == -1 and bv(M=float("inf")) == -1 and bv(M=float("nan")) == -1
+    assert bv(tl=0) == -1 and bv(tl=1000) == -1 and bv(tl=1 << 32) == -1
+    assert bv(s0=-1) == -1
+    assert bv(n=1 << 40, rs=1 << 40, block=16) == -1                     # 2^36 blocks per row
+    assert L.corr_blank_last_error()
+    assert bv(n=0, counts=None, stats=None) == 0                         # nothing to do, nothing launched
+    assert L.corr_blank_last_error() == b""
+
+    def nt(seed=1, S=4, n=1024, t=f):
+        return L.corr_blank_noise_table(seed, S, n, t, None)
+
+    assert nt(t=None) == -2 and nt(t=ctypes.c_void_p((1 << 20) + 2)) == -3
+    assert nt(S=0) == -1 and nt(n=0) == -1 and nt(n=3) == -1 and nt(n=1 << 32) == -1
