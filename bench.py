@@ -65,6 +65,14 @@ MEASURED_TRAFFIC = {
     "beam_int8_c3": {"source": "paper_0910_1517_amd/csrc/beam.hip",
                      "sha256": "c4b752f8785e1887ba24a549df17dcb04d350f6aef77a9cf576275e4ed864124",
                      "read": 8.606e9, "write": 1.611e9},
+    # profiles/blank_int8_64sig_134Msamples.md: out of place FETCH_SIZE 4211175 KiB x 2.000, WRITE_SIZE 9624595 KiB
+    "blank_out_c3": {"source": "paper_0910_1517_amd/csrc/blank.hip",
+                     "sha256": "a5e5a8dd867d35691113d8813f8fb217c46eb115a3e2554b2ca5b362d3108911",
+                     "read": 8.624e9, "write": 9.856e9},
+    # same profile, in place: FETCH_SIZE 4211023 KiB x 2.000, WRITE_SIZE 900710 KiB
+    "blank_in_c3": {"source": "paper_0910_1517_amd/csrc/blank.hip",
+                    "sha256": "a5e5a8dd867d35691113d8813f8fb217c46eb115a3e2554b2ca5b362d3108911",
+                    "read": 8.624e9, "write": 0.922e9},
 }
 
 
@@ -409,6 +417,46 @@ def bench_beamformer(corr, torch, S, N, T, x_dev, rs, g_dev, scale, steps, warmu
     return ms, nbytes
 
 
+def bench_blanker(corr, torch, synth, S, n, x_dev, geo, steps, warmup, block=16384, M=3.0, table_len=1 << 16):
+    """Time-domain MAD voltage blanker on the F-engine's input rows (S rows of
+    n samples) after adding impulsive bursts to about 2.5 % of the samples
+    (on a copy; x_dev is left as it is).  Out of place (reads and writes every
+    sample: 2 bytes per sample) back to back; in place (reads every sample,
+    writes back only the 16-byte chunks holding a blanked one) on a fresh copy
+    per call, the copy outside the timed events.  Returns a dict."""
+    x_rfi = x_dev.clone()
+    synth.add_impulses(x_rfi, geo, n, seed=synth.BASE_SEED + 3)
+    table = torch.empty(S, table_len, device="cuda")
+    corr.blank_noise_table(0x5EED, table)
+    nb = -(-n // block)
+    counts = torch.zeros(S, nb, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x_rfi)
+    f = lambda: corr.blank_voltages(x_rfi, table, block=block, M=M, out=y, n=n)
+    for _ in range(warmup):
+        f()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_out = e0.elapsed_time(e1) / steps
+    ms_in = []
+    for i in range(max(2, steps // 4)):
+        y.copy_(x_rfi)
+        e0.record()
+        corr.blank_voltages(y, table, block=block, M=M, counts=counts, n=n)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_in.append(e0.elapsed_time(e1))
+    frac = counts.sum().item() / (S * n)
+    del x_rfi, y, table, counts
+    torch.cuda.empty_cache()
+    return {"ms_out_of_place": ms_out, "ms_in_place": float(np.mean(ms_in[1:])), "blanked_fraction": frac,
+            "bytes_out_of_place": 2.0 * S * n, "bytes_read": 1.0 * S * n}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,6 +515,11 @@ def main():
     log("timing the beamformer (one incoherent + one full-polar coherent beam)")
     tb_ms, tb_bytes = bench_beamformer(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
     log("beamformer: %.3f ms per call" % tb_ms)
+    torch.cuda.empty_cache()
+    log("timing the voltage blanker (blocks of 16384 samples, M = 3, impulsive bursts on a copy of the input)")
+    rb = bench_blanker(corr, torch, synth, S, N * T + 16, x_dev, geo, args.steps, args.warmup)
+    log("blanker: %.3f ms out of place, %.3f ms in place, %.4f of the samples blanked"
+        % (rb["ms_out_of_place"], rb["ms_in_place"], rb["blanked_fraction"]))
     r8f = None
     if not args.no_fp8:
         torch.cuda.empty_cache()
@@ -545,6 +598,18 @@ def main():
                          "hbm_frac": round(tb_bytes / tb_ms / 1e6 / (HBM_PEAK / 1e9), 4),
                          "algorithmic_bytes": tb_bytes,
                          "traffic": measured_traffic("beam_int8_%s" % args.config)}
+    gbs = rb["bytes_out_of_place"] / rb["ms_out_of_place"] / 1e6
+    out["voltage_blanker"] = {
+        "kernel": "blank_kernel<4> (MAD blanker, blocks of 16384 samples)", "bound": "hbm",
+        "input": "the int8 input rows with impulsive bursts added to about 2.5 % of the samples",
+        "blanked_fraction": round(rb["blanked_fraction"], 5),
+        "ms_out_of_place": round(rb["ms_out_of_place"], 4), "achieved_gbs": round(gbs, 1),
+        "hbm_frac": round(gbs / (HBM_PEAK / 1e9), 4), "algorithmic_bytes": rb["bytes_out_of_place"],
+        "traffic": measured_traffic("blank_out_%s" % args.config),
+        "ms_in_place": round(rb["ms_in_place"], 4),
+        "in_place_read_gbs": round(rb["bytes_read"] / rb["ms_in_place"] / 1e6, 1),
+        "traffic_in_place": measured_traffic("blank_in_%s" % args.config),
+        "share_of_step": round(rb["ms_in_place"] / (t8 * 1e3), 4)}
     if r32:
         xops32, xin32 = x_algorithmic(S, N, T, 8)
         out["fp32"] = {"correlated_bandwidth_mhz": round(bw(t32), 3), "ms_per_step": round(t32 * 1e3, 4),

@@ -15,6 +15,10 @@
  *              over time (the MAC of sections 2.3.2 and 3.4).
  *   integrate  long-term accumulation in floating point (section 4.1) and
  *              dump of the visibilities.
+ *   RFI        the MAD statistic of section 5 (Eq. 3 and 4) on power tiles
+ *              with zeroing and exact pair counts, a learned flagger, and
+ *              the time-domain voltage blanker with noise replacement.
+ *   B-engine   incoherent and coherent array beams (section 3).
  *
  * Conventions used everywhere below
  *   S   number of signals (antenna a, polarisation pol -> s = 2a + pol)

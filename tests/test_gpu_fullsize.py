@@ -163,6 +163,47 @@ def test_beamformer_at_the_precision_form_sampled_channels():
     check_beams(got_inc, got_coh, ref_inc, ref_coh, inc_b, coh_b, corr.BEAM_FULLPOL, 1)
 
 
+def test_voltage_blanker_at_the_fx_input_sampled_blocks():
+    """The time-domain blanker on the precision form's input (64 signals x
+    (4096 x 32768 + 16) samples) with impulsive bursts on about 2.5 % of the
+    samples, in bench.py's configuration (blocks of 16384, M = 3, a 2^16-entry
+    table per signal).  Out of place over the whole input, then in place:
+    the two results are identical.  Sampled blocks (first, middle, the ragged
+    last one) of three rows, their counts and statistics equal the oracle's,
+    each block computed on its own."""
+    import torch
+    S, N, T = 64, 4096, 32768
+    B, M, L, seed = 16384, 3.0, 1 << 16, 0x5EED
+    geo, x, rs, _ = workload(S, N, T, synth.BASE_SEED + 2)
+    n = N * T + 16
+    synth.add_impulses(x, geo, n, seed=synth.BASE_SEED + 3)
+    nb = -(-n // B)
+    rows, blocks = [0, 33, 63], [0, nb // 2, nb - 1]
+    before = {(s, b): x[s, b * B:min(n, (b + 1) * B)].cpu().numpy() for s in rows for b in blocks}
+    table = torch.empty(S, L, device="cuda")
+    corr.blank_noise_table(seed, table)
+    y = torch.empty_like(x)
+    counts = torch.empty(S, nb, dtype=torch.int32, device="cuda")
+    stats = torch.empty(S, nb, 2, dtype=torch.int32, device="cuda")
+    corr.blank_voltages(x, table, block=B, M=M, out=y, n=n)
+    corr.blank_voltages(x, table, block=B, M=M, counts=counts, stats=stats, n=n)
+    torch.cuda.synchronize()
+    assert torch.equal(x[:, :n], y[:, :n])
+    frac = counts.sum().item() / (S * n)
+    print("blanked fraction %.4f" % frac)
+    assert 0.01 < frac < 0.05
+    ref_table = oracle.blank_noise_table(seed, S, L)
+    assert np.array_equal(table.cpu().numpy(), ref_table)
+    for s in rows:
+        trow = ref_table[s:s + 1]
+        for b in blocks:
+            xb = before[(s, b)]
+            ref, rc, rst = oracle.mad_blank(xb[None], B, M, trow, sample0=b * B)
+            got = x[s, b * B:b * B + xb.size].cpu().numpy()
+            assert np.array_equal(got, ref[0]), (s, b)
+            assert counts[s, b].item() == rc[0, 0] and stats[s, b].tolist() == rst[0, 0].tolist(), (s, b)
+
+
 def test_precision_form_int8_xengine_bit_exact_sampled_channels():
     """The int8 X-engine at 64 x 2048 x 32768 in the benchmark's split, on
     seeded int8 codes: sampled channels equal the int64 triple loop exactly."""
