@@ -68,6 +68,7 @@ def _load():
     lib.orc_mad_tile_flags.argtypes = [P, i32, i64, i64, i32, i32, dbl, P]
     lib.orc_mad_tile_flags.restype = i32
     lib.orc_pair_counts.argtypes = [P, i32, i64, i64, P]
+    lib.orc_adc_unpack.argtypes = [P, i64, i32, i64, i32, P, i64]
     lib.orc_philox4x32_10.argtypes = [P, P, P]
     lib.orc_blank_noise_table.argtypes = [ctypes.c_uint64, i32, i64, P]
     lib.orc_blank_noise_entry.argtypes = [ctypes.c_uint64, i32, i64]
@@ -229,6 +230,22 @@ def beamform(Y: np.ndarray, w=None, c=None, mode: int = BEAM_FULLPOL, tint: int 
                          _p(c) if nb else None, nb, mode, tint,
                          _p(inc) if inc is not None else None, _p(coh) if coh is not None else None)
     return inc, coh
+
+
+# ---------------------------------------------------------------------------
+# ADC input formats (sections 2.3.2 and 3.3)
+# ---------------------------------------------------------------------------
+def adc_unpack(raw: np.ndarray, n: int, bits: int) -> np.ndarray:
+    """Demultiplex and unpack the raw streams of acquisition cards (uint8
+    [cards][bytes], time-major, 4 inputs per time sample, 8-bit bytes or
+    4-bit nibbles low first, two's complement) into int8 rows [4 cards][n]
+    (row 4 c + i = input i of card c)."""
+    raw = np.ascontiguousarray(raw, dtype=np.uint8)
+    cards = raw.shape[0]
+    assert bits in (4, 8) and raw.shape[1] >= n * 4 * bits // 8
+    x = np.zeros((4 * cards, n), dtype=np.int8)
+    _load().orc_adc_unpack(_p(raw), raw.shape[1], cards, n, bits, _p(x), n)
+    return x
 
 
 # ---------------------------------------------------------------------------

@@ -22,6 +22,8 @@
  *                        32-bit products, float long-term accumulation)
  *   MAD statistic        Eq. 3 and Eq. 4 of section 5
  *   array beams          section 3 (incoherent and coherent beamformer)
+ *   ADC unpacking        sections 2.3.2 and 3.3 (four-input demultiplexing,
+ *                        4-bit samples to 8 bits)
  *   voltage blanker      section 5 (Eq. 3 and 4 on voltage blocks, outliers
  *                        replaced by precomputed Gaussian noise, one table
  *                        per signal from Philox4x32-10)
@@ -533,6 +535,33 @@ void orc_beamform(const double *Y, int S, int64_t T, int64_t C, const double *w,
                 for (int q = 0; q < np; ++q) coh[(((int64_t)b * np + q) * To + o) * C + k] += prod[q];
             }
         }
+}
+
+/* ------------------------------------------------------------------------ */
+/* ADC input formats (section 2.3.2 and 3.3): each acquisition card digitises */
+/* four inputs, either 8-bit (16 MHz mode) or 4-bit (33 MHz mode), and the    */
+/* compute nodes demultiplex the four streams and unpack 4-bit samples to     */
+/* 8 bits.  Raw stream of a card: time-major, the four inputs of a time       */
+/* sample together; 8-bit: byte 4t + i is input i; 4-bit: byte 2t + i/2,      */
+/* nibble i mod 2 (low nibble first).  Samples are two's complement, 4-bit    */
+/* ones sign-extended to int8 (value kept).  Output row 4 c + i holds input i */
+/* of card c.                                                                 */
+void orc_adc_unpack(const uint8_t *raw, int64_t raw_stride, int n_cards, int64_t n, int bits, int8_t *x,
+                    int64_t row_stride)
+{
+    for (int c = 0; c < n_cards; ++c)
+        for (int64_t t = 0; t < n; ++t)
+            for (int i = 0; i < 4; ++i) {
+                const uint8_t *r = raw + (int64_t)c * raw_stride;
+                int v;
+                if (bits == 8) {
+                    v = (int8_t)r[4 * t + i];
+                } else {
+                    int nib = (r[2 * t + i / 2] >> (4 * (i % 2))) & 0xF;
+                    v = nib >= 8 ? nib - 16 : nib;
+                }
+                x[(int64_t)(4 * c + i) * row_stride + t] = (int8_t)v;
+            }
 }
 
 /* ------------------------------------------------------------------------ */
