@@ -457,6 +457,35 @@ def bench_blanker(corr, torch, synth, S, n, x_dev, geo, steps, warmup, block=163
             "bytes_out_of_place": 2.0 * S * n, "bytes_read": 1.0 * S * n}
 
 
+def bench_adc(corr, torch, S, n, steps, warmup):
+    """Demultiplex and unpack S / 4 acquisition-card streams of n time samples
+    into the F-engine's S int8 rows, in the 4-bit (33 MHz) and the 8-bit
+    (16 MHz) mode.  Returns {bits: (ms per call, algorithmic bytes)}."""
+    cards = S // 4
+    rs = (n + 255) // 256 * 256
+    x = torch.empty(S, rs, dtype=torch.int8, device="cuda")
+    out = {}
+    for bits in (4, 8):
+        rrs = (n * bits // 2 + 255) // 256 * 256
+        g = torch.Generator(device="cuda").manual_seed(bits)
+        raw = torch.randint(0, 256, (cards, rrs), dtype=torch.uint8, device="cuda", generator=g)
+        f = lambda: corr.adc_unpack(raw, x, bits=bits, n=n)
+        for _ in range(warmup):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        out[bits] = (e0.elapsed_time(e1) / steps, float(cards) * n * bits / 2 + float(S) * n)
+        del raw
+    del x
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -520,6 +549,9 @@ def main():
     rb = bench_blanker(corr, torch, synth, S, N * T + 16, x_dev, geo, args.steps, args.warmup)
     log("blanker: %.3f ms out of place, %.3f ms in place, %.4f of the samples blanked"
         % (rb["ms_out_of_place"], rb["ms_in_place"], rb["blanked_fraction"]))
+    log("timing the ADC demultiplexing and unpacking (4-bit and 8-bit card streams)")
+    ra = bench_adc(corr, torch, S, N * T + 16, args.steps, args.warmup)
+    log("adc unpack: %.3f ms (4-bit), %.3f ms (8-bit)" % (ra[4][0], ra[8][0]))
     r8f = None
     if not args.no_fp8:
         torch.cuda.empty_cache()
@@ -610,6 +642,12 @@ def main():
         "in_place_read_gbs": round(rb["bytes_read"] / rb["ms_in_place"] / 1e6, 1),
         "traffic_in_place": measured_traffic("blank_in_%s" % args.config),
         "share_of_step": round(rb["ms_in_place"] / (t8 * 1e3), 4)}
+    out["adc_unpack"] = {
+        "kernel": "adc_unpack_kernel<bits> (4-input demultiplexing, 4-bit to 8-bit)", "bound": "hbm",
+        "cards": S // 4,
+        **{"bits%d" % b: {"ms": round(ra[b][0], 4), "algorithmic_bytes": ra[b][1],
+                           "achieved_gbs": round(ra[b][1] / ra[b][0] / 1e6, 1),
+                           "hbm_frac": round(ra[b][1] / ra[b][0] / 1e6 / (HBM_PEAK / 1e9), 4)} for b in (4, 8)}}
     if r32:
         xops32, xin32 = x_algorithmic(S, N, T, 8)
         out["fp32"] = {"correlated_bandwidth_mhz": round(bw(t32), 3), "ms_per_step": round(t32 * 1e3, 4),

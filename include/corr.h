@@ -274,6 +274,32 @@ size_t corr_plan_power_bytes(const corr_plan_t *plan);
 size_t corr_plan_flags_bytes(const corr_plan_t *plan);
 size_t corr_plan_keep_bytes(const corr_plan_t *plan);
 
+/* ------------------------------------------------------------- ADC input */
+
+/* Demultiplex and unpack the raw streams of the acquisition cards (sections
+ * 2.3.2 and 3.3): each card digitises four inputs, 8-bit (16 MHz mode) or
+ * 4-bit (33 MHz mode), and the compute side separates the four streams and
+ * unpacks 4-bit samples to 8 bits before the FFT.
+ *   d_raw       card c's stream at d_raw + c*raw_stride, time-major with the
+ *               four inputs of a time sample together: 8-bit, byte 4t + i is
+ *               input i; 4-bit, byte 2t + i/2, nibble i mod 2 (low nibble
+ *               first).  Two's complement.  16-byte aligned; raw_stride a
+ *               multiple of 16 and >= n*bits/2.
+ *   n           time samples per card (0 enqueues nothing; at most 2^40).
+ *   d_x         int8 rows, row 4c + i (input i of card c) at
+ *               d_x + (4c + i)*row_stride, n samples each: the layout
+ *               corr_fengine reads.  4-bit samples are sign-extended (value
+ *               kept, -8..7).  16-byte aligned; row_stride a multiple of 16
+ *               and >= n.  Must not overlap d_raw.  Bytes of a row past n are
+ *               not written.
+ * Errors: NULL, ALIGN, INVALID (bits not 4 or 8, n_cards outside
+ * [1, 16383], n, strides), DEVICE; messages via corr_adc_last_error. */
+corr_status corr_adc_unpack(const uint8_t *d_raw, int64_t raw_stride, int32_t n_cards, int64_t n, int32_t bits,
+                            int8_t *d_x, int64_t row_stride, void *stream);
+
+/* Message of the last failed corr_adc_unpack call on this thread. */
+const char *corr_adc_last_error(void);
+
 /* ------------------------------------------------------- voltage blanker */
 
 /* Time-domain RFI blanker on the pre-detected voltages (section 5, Eq. 3 and

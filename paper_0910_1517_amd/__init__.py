@@ -74,6 +74,7 @@ SYMBOLS = [
     "corr_cnn_forward", "corr_cnn_loss_grad", "corr_cnn_adam", "corr_cnn_train_step",
     "corr_cnn_check_device_errors", "corr_cnn_infer", "corr_cnn_save", "corr_cnn_load", "corr_cnn_last_error",
     "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
+    "corr_adc_unpack", "corr_adc_last_error",
 ]
 
 
@@ -173,6 +174,10 @@ def lib():
     L.corr_blank_noise_table.restype = st
     L.corr_blank_last_error.argtypes = []
     L.corr_blank_last_error.restype = ctypes.c_char_p
+    L.corr_adc_unpack.argtypes = [P, i64, i32, i64, i32, P, i64, P]
+    L.corr_adc_unpack.restype = st
+    L.corr_adc_last_error.argtypes = []
+    L.corr_adc_last_error.restype = ctypes.c_char_p
     L.corr_status_string.argtypes = [st]
     L.corr_status_string.restype = ctypes.c_char_p
     L.corr_last_error.argtypes = [P]
@@ -466,6 +471,20 @@ def cnn_load(path: str, params, m=None, v=None) -> int:
     st = ctypes.c_int64()
     _cnn_check(lib().corr_cnn_load(path.encode(), _ptr(params), _ptr(m), _ptr(v), ctypes.byref(st)))
     return st.value
+
+
+def adc_unpack(raw, x, *, bits: int, n: int | None = None, stream=None):
+    """Demultiplex and unpack card streams raw (uint8 [cards][raw_stride]) into
+    int8 rows x [4 cards][row_stride] (first n samples; default the row
+    length); see corr_adc_unpack."""
+    cards, rs_raw = raw.shape
+    rows, rs = x.shape
+    assert rows == 4 * cards
+    rc = lib().corr_adc_unpack(_ptr(raw), raw.stride(0), cards, rs if n is None else n, bits, _ptr(x), x.stride(0),
+                               _stream(stream))
+    if rc != 0:
+        raise CorrError(rc, lib().corr_adc_last_error().decode())
+    return x
 
 
 def _blank_check(rc):

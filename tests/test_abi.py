@@ -228,3 +228,22 @@ def test_blanker_rejects_bad_arguments():
 
     assert nt(t=None) == -2 and nt(t=ctypes.c_void_p((1 << 20) + 2)) == -3
     assert nt(S=0) == -1 and nt(n=0) == -1 and nt(n=3) == -1 and nt(n=1 << 32) == -1
+
+
+def test_adc_unpack_rejects_bad_arguments():
+    L = corr.lib()
+    f = ctypes.c_void_p(1 << 20)
+
+    def au(raw=f, rrs=2048, cards=2, n=512, bits=4, x=f, rs=512):
+        return L.corr_adc_unpack(raw, rrs, cards, n, bits, x, rs, None)
+
+    assert au(raw=None) == -2 and au(x=None) == -2
+    assert au(raw=ctypes.c_void_p((1 << 20) + 8)) == -3 and au(x=ctypes.c_void_p((1 << 20) + 4)) == -3
+    assert au(bits=2) == -1 and au(bits=16) == -1
+    assert au(cards=0) == -1 and au(cards=16384) == -1
+    assert au(n=-1) == -1 and au(n=(1 << 40) + 1, rrs=1 << 44, rs=1 << 44) == -1
+    assert au(rrs=1008) == -1 and au(rrs=1000) == -1               # below n*bits/2, not a multiple of 16
+    assert au(bits=8, rrs=2032) == -1                              # 8-bit needs 4 n bytes
+    assert au(rs=496) == -1 and au(rs=520) == -1
+    assert L.corr_adc_last_error()
+    assert au(n=0) == 0 and L.corr_adc_last_error() == b""

@@ -204,6 +204,26 @@ def test_voltage_blanker_at_the_fx_input_sampled_blocks():
             assert counts[s, b].item() == rc[0, 0] and stats[s, b].tolist() == rst[0, 0].tolist(), (s, b)
 
 
+def test_adc_unpack_at_the_fx_input_sampled_ranges():
+    """4-bit, 33 MHz-mode card streams for the precision form's input: 16
+    cards x 4 inputs = 64 rows of 4096 x 32768 + 16 samples, in bench.py's
+    configuration.  Sampled ranges of three cards (first, middle, last with
+    the row's end) equal the oracle's unpacking of the same raw bytes."""
+    import torch
+    cards, n = 16, 4096 * 32768 + 16
+    rrs = (2 * n + 255) // 256 * 256
+    rs = (n + 255) // 256 * 256
+    g = torch.Generator(device="cuda").manual_seed(11)
+    raw = torch.randint(0, 256, (cards, rrs), dtype=torch.uint8, device="cuda", generator=g)
+    x = torch.empty(4 * cards, rs, dtype=torch.int8, device="cuda")
+    corr.adc_unpack(raw, x, bits=4, n=n)
+    torch.cuda.synchronize()
+    for c in (0, 7, 15):
+        for t0, t1 in ((0, 4096), (n // 2 - 33, n // 2 + 4000), (n - 4100, n)):
+            ref = oracle.adc_unpack(raw[c:c + 1, 2 * t0:2 * t1].cpu().numpy(), t1 - t0, 4)
+            assert np.array_equal(x[4 * c:4 * c + 4, t0:t1].cpu().numpy(), ref), (c, t0)
+
+
 def test_precision_form_int8_xengine_bit_exact_sampled_channels():
     """The int8 X-engine at 64 x 2048 x 32768 in the benchmark's split, on
     seeded int8 codes: sampled channels equal the int64 triple loop exactly."""
