@@ -457,6 +457,36 @@ def bench_blanker(corr, torch, synth, S, n, x_dev, geo, steps, warmup, block=163
             "bytes_out_of_place": 2.0 * S * n, "bytes_read": 1.0 * S * n}
 
 
+def bench_gated(corr, torch, S, N, T, x_dev, rs, g_dev, scale, steps, warmup, period=1.5578e-3):
+    """Gated int8 X-engine on the spectra of one F-engine call: two gates (the
+    on and off halves of a pulsar period of 1.5578 ms, about 25 spectra), one
+    launch.  Each timed call is bracketed by its own events; both gates are
+    integrated (and their accumulators zeroed) outside them.  Returns ms per
+    call."""
+    plan = corr.Plan(S, N, T, precision=corr.INT8, scale_mode=corr.SCALE_HOLD)
+    spec = plan.alloc("spectra", zero=False)
+    plan.fengine(x_dev, g_dev, spec, scale, row_stride=rs)
+    gate, _ = corr.pulsar_gates(0, T, N, FS, 0.0, period, 2)
+    gate_d = torch.from_numpy(gate).cuda()
+    words = plan.acc_bytes // 4
+    acc = torch.zeros(2 * words, dtype=torch.int32, device="cuda")
+    states = [plan.alloc("state") for _ in range(2)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for i in range(warmup + steps):
+        if i >= warmup:
+            ev[i - warmup][0].record()
+        plan.xengine_gated(spec, gate_d, 2, acc)
+        if i >= warmup:
+            ev[i - warmup][1].record()
+        for b in range(2):
+            plan.integrate(acc[b * words:(b + 1) * words], states[b], None, scale, flags=0)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    del spec, acc, states, plan
+    torch.cuda.empty_cache()
+    return ms
+
+
 def bench_adc(corr, torch, S, n, steps, warmup):
     """Demultiplex and unpack S / 4 acquisition-card streams of n time samples
     into the F-engine's S int8 rows, in the 4-bit (33 MHz) and the 8-bit
@@ -549,6 +579,9 @@ def main():
     rb = bench_blanker(corr, torch, synth, S, N * T + 16, x_dev, geo, args.steps, args.warmup)
     log("blanker: %.3f ms out of place, %.3f ms in place, %.4f of the samples blanked"
         % (rb["ms_out_of_place"], rb["ms_in_place"], rb["blanked_fraction"]))
+    log("timing the gated X-engine (two pulse-phase gates)")
+    tg_ms = bench_gated(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
+    log("gated X-engine: %.3f ms per call (ungated %.3f ms)" % (tg_ms, r8["t_x"] * 1e3))
     log("timing the ADC demultiplexing and unpacking (4-bit and 8-bit card streams)")
     ra = bench_adc(corr, torch, S, N * T + 16, args.steps, args.warmup)
     log("adc unpack: %.3f ms (4-bit), %.3f ms (8-bit)" % (ra[4][0], ra[8][0]))
@@ -642,6 +675,12 @@ def main():
         "in_place_read_gbs": round(rb["bytes_read"] / rb["ms_in_place"] / 1e6, 1),
         "traffic_in_place": measured_traffic("blank_in_%s" % args.config),
         "share_of_step": round(rb["ms_in_place"] / (t8 * 1e3), 4)}
+    out["gated_xengine"] = {
+        "kernel": "xengine_gated_kernel<2, int8> (two pulse-phase gates, one launch)", "bound": "hbm",
+        "ms": round(tg_ms, 4), "ungated_ms": round(r8["t_x"] * 1e3, 4),
+        "achieved_gbs": round(xin8 / (tg_ms * 1e-3) / 1e9, 1),
+        "hbm_frac": round(xin8 / (tg_ms * 1e-3) / HBM_PEAK, 4),
+        "mfma_frac_issued": round(2 * xops8 / (tg_ms * 1e-3) / INT8_PEAK, 4)}
     out["adc_unpack"] = {
         "kernel": "adc_unpack_kernel<bits> (4-input demultiplexing, 4-bit to 8-bit)", "bound": "hbm",
         "cards": S // 4,

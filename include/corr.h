@@ -191,6 +191,40 @@ corr_status corr_xpack(corr_plan_t *plan, const void *d_in, void *d_spec, void *
  */
 corr_status corr_xengine(corr_plan_t *plan, const void *d_spec, void *d_acc, void *stream);
 
+/* ------------------------------------------------------- gated correlator */
+
+/* Gated correlator (section 5: the pulsar-gated mode, for off-pulse emission
+ * and pulsars as phase calibrators): accumulator set b sums only the spectra
+ * whose gate is b,
+ *   d_acc_b[split][k][p] += sum over m with gate[m] == b of Y_i conj(Y_j),
+ * for b = 0 .. n_bins-1, in one launch that reads the spectra once (every
+ * product's second operand is masked per spectrum in registers).  The sum of
+ * all sets is the ungated corr_xengine result (exactly for INT8).
+ *   d_gate   uint8 [T], the bin of each spectrum of the call; a value
+ *            >= n_bins leaves the spectrum out of every set.  16-byte aligned.
+ *   d_acc    n_bins consecutive accumulators of corr_plan_acc_bytes each
+ *            (set b at d_acc + b * corr_plan_acc_bytes), 256-byte aligned,
+ *            zeroed before the first call like corr_xengine's.
+ * Integrate each set with corr_integrate.  The INT8 bound and the COMPUTE
+ * scale rule are those of corr_xengine, counted per call: integrate every set
+ * before 66572 spectra have accumulated.
+ * Errors: NULL, ALIGN, INVALID (n_bins outside [1, CORR_MAX_GATE_BINS]),
+ * OVERFLOW, STATE, DEVICE. */
+#define CORR_MAX_GATE_BINS 255
+corr_status corr_xengine_gated(corr_plan_t *plan, const void *d_spec, const uint8_t *d_gate, int32_t n_bins,
+                               void *d_acc, void *stream);
+
+/* Gates of spectra spectrum0 .. spectrum0 + n_spectra - 1 from a pulsar's
+ * period (host arithmetic, FP64, like the delay model): spectrum m is taken
+ * at its window centre t = (m + 1/2) fft_len / sample_rate (the time stamp of
+ * the fringe phase), its pulse phase is frac((t - t0) / period), and
+ * h_gate[m - spectrum0] = floor(phase * n_bins) (at most n_bins - 1).
+ * h_counts (optional, int64 [n_bins], host) gets each bin's spectra added.
+ * Errors: NULL, INVALID (negative counts, fft_len < 1, non-finite or
+ * non-positive rate or period, n_bins); messages via corr_last_error(NULL). */
+corr_status corr_pulsar_gates(int64_t spectrum0, int64_t n_spectra, int32_t fft_len, double sample_rate, double t0,
+                              double period, int32_t n_bins, uint8_t *h_gate, int64_t *h_counts);
+
 /* ------------------------------------------------------------- beamformer */
 
 /*

@@ -233,6 +233,37 @@ def beamform(Y: np.ndarray, w=None, c=None, mode: int = BEAM_FULLPOL, tint: int 
 
 
 # ---------------------------------------------------------------------------
+# Gated correlator (section 5)
+# ---------------------------------------------------------------------------
+def pulsar_gates(spectrum0: int, n: int, N: int, fs: float, t0: float, period: float, n_bins: int) -> np.ndarray:
+    """Gate bin of spectra spectrum0 .. spectrum0 + n - 1: the pulse phase
+    frac((t - t0) / P) at the window centre t = (m + 1/2) N / fs, in n_bins
+    equal bins (FP64, each operation rounded on its own)."""
+    out = np.empty(n, dtype=np.uint8)
+    t_spec = float(N) / float(fs)
+    for i in range(n):
+        t = (float(spectrum0 + i) + 0.5) * t_spec
+        x = (t - t0) / period
+        phase = x - np.floor(x)
+        b = int(np.floor(phase * float(n_bins)))
+        out[i] = min(max(b, 0), n_bins - 1)
+    return out
+
+
+def xengine_gated(Y: np.ndarray, gate, n_bins: int) -> np.ndarray:
+    """V_b = sum over the spectra with gate == b of Y_i conj(Y_j): the X
+    oracle on each bin's spectra ([n_bins][C][P] complex128)."""
+    gate = np.asarray(gate)
+    return np.stack([xengine(np.ascontiguousarray(Y[:, gate == b, :])) for b in range(n_bins)])
+
+
+def xengine_int_gated(q: np.ndarray, gate, n_bins: int) -> np.ndarray:
+    """The int64 X oracle on each bin's int8 spectra ([n_bins][C][P][2])."""
+    gate = np.asarray(gate)
+    return np.stack([xengine_int(np.ascontiguousarray(q[:, gate == b])) for b in range(n_bins)])
+
+
+# ---------------------------------------------------------------------------
 # ADC input formats (sections 2.3.2 and 3.3)
 # ---------------------------------------------------------------------------
 def adc_unpack(raw: np.ndarray, n: int, bits: int) -> np.ndarray:

@@ -74,7 +74,7 @@ SYMBOLS = [
     "corr_cnn_forward", "corr_cnn_loss_grad", "corr_cnn_adam", "corr_cnn_train_step",
     "corr_cnn_check_device_errors", "corr_cnn_infer", "corr_cnn_save", "corr_cnn_load", "corr_cnn_last_error",
     "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
-    "corr_adc_unpack", "corr_adc_last_error",
+    "corr_adc_unpack", "corr_adc_last_error", "corr_xengine_gated", "corr_pulsar_gates",
 ]
 
 
@@ -174,6 +174,10 @@ def lib():
     L.corr_blank_noise_table.restype = st
     L.corr_blank_last_error.argtypes = []
     L.corr_blank_last_error.restype = ctypes.c_char_p
+    L.corr_xengine_gated.argtypes = [P, P, P, i32, P, P]
+    L.corr_xengine_gated.restype = st
+    L.corr_pulsar_gates.argtypes = [i64, i64, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32, P, P]
+    L.corr_pulsar_gates.restype = st
     L.corr_adc_unpack.argtypes = [P, i64, i32, i64, i32, P, i64, P]
     L.corr_adc_unpack.restype = st
     L.corr_adc_last_error.argtypes = []
@@ -296,6 +300,11 @@ class Plan:
 
     def xengine(self, spec, acc, stream=None):
         self._check(lib().corr_xengine(self._h, _ptr(spec), _ptr(acc), _stream(stream)))
+
+    def xengine_gated(self, spec, gate, n_bins, acc, stream=None):
+        """Gated X-engine: acc holds n_bins accumulators of acc_bytes each;
+        gate is a uint8 device tensor [T]; see corr_xengine_gated."""
+        self._check(lib().corr_xengine_gated(self._h, _ptr(spec), _ptr(gate), n_bins, _ptr(acc), _stream(stream)))
 
     def beamform(self, spec, scale=None, w=None, inc=None, c=None, coh=None, mode=None, tint=1, stream=None):
         """Incoherent beam (w [S] float -> inc [2][T/tint][C]) and coherent beams
@@ -485,6 +494,20 @@ def adc_unpack(raw, x, *, bits: int, n: int | None = None, stream=None):
     if rc != 0:
         raise CorrError(rc, lib().corr_adc_last_error().decode())
     return x
+
+
+def pulsar_gates(spectrum0: int, n_spectra: int, fft_len: int, sample_rate: float, t0: float, period: float,
+                 n_bins: int):
+    """(gate uint8 [n_spectra], counts int64 [n_bins]) of consecutive spectra
+    from a pulsar's period; see corr_pulsar_gates (host arithmetic)."""
+    import numpy as np
+    gate = np.zeros(n_spectra, dtype=np.uint8)
+    counts = np.zeros(n_bins, dtype=np.int64)
+    rc = lib().corr_pulsar_gates(spectrum0, n_spectra, fft_len, sample_rate, t0, period, n_bins,
+                                 gate.ctypes.data_as(ctypes.c_void_p), counts.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise CorrError(rc, lib().corr_last_error(None).decode())
+    return gate, counts
 
 
 def _blank_check(rc):

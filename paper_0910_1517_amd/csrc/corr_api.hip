@@ -304,6 +304,52 @@ corr_status corr_xengine(corr_plan_t *p, const void *d_spec, void *d_acc, void *
     return CORR_OK;
 }
 
+corr_status corr_xengine_gated(corr_plan_t *p, const void *d_spec, const uint8_t *d_gate, int32_t n_bins, void *d_acc,
+                               void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_spec || !d_gate || !d_acc) return fail(p, CORR_ERR_NULL, "d_spec, d_gate and d_acc are required");
+    if (!aligned(d_spec, 256) || !aligned(d_acc, 256) || !aligned(d_gate, 16))
+        return fail(p, CORR_ERR_ALIGN, "d_spec/d_acc 256-byte, d_gate 16-byte alignment");
+    if (n_bins < 1 || n_bins > CORR_MAX_GATE_BINS)
+        return fail(p, CORR_ERR_INVALID, "n_bins=%d outside [1, %d]", n_bins, CORR_MAX_GATE_BINS);
+    if (p->d.precision == CORR_INT8 && p->acc_spectra + p->d.n_spectra > kMaxInt8Spectra)
+        return fail(p, CORR_ERR_OVERFLOW, "%lld spectra since the last integrate would exceed the int32 bound (%lld)",
+                    (long long)(p->acc_spectra + p->d.n_spectra), (long long)kMaxInt8Spectra);
+    if (p->d.precision != CORR_FP32 && p->d.scale_mode == CORR_SCALE_COMPUTE && p->x_calls > 0)
+        return fail(p, CORR_ERR_STATE, "COMPUTE scales change per call: integrate before the next X-engine call");
+    const int64_t acc_elems = (int64_t)p->splits * p->M * ((int64_t)p->d.n_signals * (p->d.n_signals + 1) / 2) * 2;
+    hipError_t e = launch_xengine_gated(p->d.precision, d_spec, d_gate, n_bins, d_acc, acc_elems, p->d.n_signals,
+                                        p->M, (int)p->d.n_spectra, p->splits, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(p, e, "gated X-engine launch");
+    p->acc_spectra += p->d.n_spectra;
+    p->x_calls += 1;
+    return CORR_OK;
+}
+
+corr_status corr_pulsar_gates(int64_t spectrum0, int64_t n_spectra, int32_t fft_len, double sample_rate, double t0,
+                              double period, int32_t n_bins, uint8_t *h_gate, int64_t *h_counts) {
+    if (!h_gate) return fail(nullptr, CORR_ERR_NULL, "h_gate is required");
+    if (n_spectra < 0 || spectrum0 < 0 || fft_len < 1 || !(sample_rate > 0) || !std::isfinite(sample_rate) ||
+        !(period > 0) || !std::isfinite(period) || !std::isfinite(t0))
+        return fail(nullptr, CORR_ERR_INVALID, "n_spectra, spectrum0 >= 0, fft_len >= 1, finite sample_rate, "
+                                               "period > 0 and t0 required");
+    if (n_bins < 1 || n_bins > CORR_MAX_GATE_BINS)
+        return fail(nullptr, CORR_ERR_INVALID, "n_bins=%d outside [1, %d]", n_bins, CORR_MAX_GATE_BINS);
+    const double t_spec = (double)fft_len / sample_rate;
+    for (int64_t m = 0; m < n_spectra; ++m) {
+        // window centre of spectrum spectrum0 + m, then its pulse phase in [0, 1)
+        const double t = ((double)(spectrum0 + m) + 0.5) * t_spec;
+        const double x = (t - t0) / period;
+        const double phase = x - std::floor(x);
+        int b = (int)std::floor(phase * (double)n_bins);
+        if (b >= n_bins) b = n_bins - 1;  // phase * n_bins rounded up to n_bins
+        if (b < 0) b = 0;
+        h_gate[m] = (uint8_t)b;
+        if (h_counts) h_counts[b] += 1;
+    }
+    return CORR_OK;
+}
+
 corr_status corr_integrate(corr_plan_t *p, void *d_acc, const float *d_scale, double *d_state, float *d_vis_out,
                            uint32_t flags, void *stream) {
     if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");

@@ -66,6 +66,10 @@ hipError_t launch_calib_reduce(const float *part, int S, int C, int nparts, int 
 
 hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int C, int T,
                           int splits, hipStream_t st);
+// Gated X-engine: accumulator set b (acc_elems elements apart) sums the
+// spectra m with gate[m] == b, for b < n_bins.
+hipError_t launch_xengine_gated(int precision, const void *spec, const uint8_t *gate, int n_bins, void *acc,
+                                int64_t acc_elems, int S, int C, int T, int splits, hipStream_t st);
 // Batched int8 X-engine: one entry per correlation; correlation i owns the
 // workgroups [first[i], first[i+1]), one per (channel block of 8, split).
 constexpr int kMaxBatch = 8;

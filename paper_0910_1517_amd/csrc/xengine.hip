@@ -36,6 +36,8 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int ntri(int nt) { return nt * (nt + 1) / 2; }
+constexpr int kXcds = 8;  // MI355X: workgroups are dealt to its 8 XCDs in turn
+
 // index of tile pair (a <= b) in the upper triangle
 __device__ __forceinline__ constexpr int tri_idx(int a, int b) { return b * (b + 1) / 2 + a; }
 
@@ -94,12 +96,21 @@ constexpr int x_lds_bytes() {
     return (2 * 4 * kBlk > kXWaves * NT * NT * 32 * 33 * 4) ? 2 * 4 * kBlk : kXWaves * NT * NT * 32 * 33 * 4;
 }
 
+// 0xFF in every byte of w that equals b (exact zero-byte test of w ^ b).
+__device__ inline uint32_t eq_bytes(uint32_t w, uint32_t b4) {
+    const uint32_t x = w ^ b4;
+    const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);  // 0x80 in zero bytes
+    return (z << 1) - (z >> 7);                                                   // 0x80 -> 0xFF
+}
+
 // One (channel block kb, split sp) of one correlation: PREC is CORR_FP32,
 // CORR_INT8 or CORR_FP8_E4M3; ACC float or int32_t; lds holds at least
-// x_lds_bytes<NT>() bytes.
-template <int NT, int PREC, typename ACC>
+// x_lds_bytes<NT>() bytes.  GATED: only the spectra m with gate[m] == bin
+// are summed (the B operand of every product is masked per spectrum).
+template <int NT, int PREC, typename ACC, bool GATED = false>
 __device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, ACC *acc, int S, int C, int T,
-                                              int splits, int kb, int sp, uint8_t *lds) {
+                                              int splits, int kb, int sp, uint8_t *lds,
+                                              const uint8_t *__restrict__ gate = nullptr, int bin = 0) {
     using V16 = typename std::conditional<PREC == CORR_INT8, v16i, v16f>::type;
     const int wv = threadIdx.x >> 6, c = kXWaves * kb + wv;
     const int lane = threadIdx.x & 63, row = lane & 31, lg = lane >> 5;
@@ -155,20 +166,54 @@ __device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, 
             c0[a] = valid[a] ? *reinterpret_cast<const v4i *>(b) : v4i{0};
             c1[a] = valid[a] ? *reinterpret_cast<const v4i *>(b + 2 * kBlk) : v4i{0};
         }
+        // B operands: masked to the gate's spectra when GATED
+        v4i b0[NT], b1[NT];
+        if constexpr (GATED) {
+            // this lane's chunks are g0 + lg and g0 + 2 + lg, g0 = 4 (sp steps + st)
+            const int64_t g = 4 * ((int64_t)sp * steps + st) + lg;
+            const uint32_t b4 = (uint32_t)bin * 0x01010101u;
+            if constexpr (PREC == CORR_FP32) {  // 2 spectra per chunk: one mask word per spectrum
+                const uint16_t q0 = *reinterpret_cast<const uint16_t *>(gate + 2 * g);
+                const uint16_t q1 = *reinterpret_cast<const uint16_t *>(gate + 2 * (g + 2));
+                const int m00 = (q0 & 0xFF) == bin ? -1 : 0, m01 = (q0 >> 8) == bin ? -1 : 0;
+                const int m10 = (q1 & 0xFF) == bin ? -1 : 0, m11 = (q1 >> 8) == bin ? -1 : 0;
+#pragma unroll
+                for (int a = 0; a < NT; ++a) {
+                    b0[a] = v4i{c0[a].x & m00, c0[a].y & m00, c0[a].z & m01, c0[a].w & m01};
+                    b1[a] = v4i{c1[a].x & m10, c1[a].y & m10, c1[a].z & m11, c1[a].w & m11};
+                }
+            } else {  // 8 spectra per chunk: real bytes 0-7, imaginary bytes 8-15
+                const uint2 q0 = *reinterpret_cast<const uint2 *>(gate + 8 * g);
+                const uint2 q1 = *reinterpret_cast<const uint2 *>(gate + 8 * (g + 2));
+                const int m0l = (int)eq_bytes(q0.x, b4), m0h = (int)eq_bytes(q0.y, b4);
+                const int m1l = (int)eq_bytes(q1.x, b4), m1h = (int)eq_bytes(q1.y, b4);
+#pragma unroll
+                for (int a = 0; a < NT; ++a) {
+                    b0[a] = v4i{c0[a].x & m0l, c0[a].y & m0h, c0[a].z & m0l, c0[a].w & m0h};
+                    b1[a] = v4i{c1[a].x & m1l, c1[a].y & m1h, c1[a].z & m1l, c1[a].w & m1h};
+                }
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < NT; ++a) {
+                b0[a] = c0[a];
+                b1[a] = c1[a];
+            }
+        }
         if constexpr (PREC == CORR_INT8) {
-            v4i im[NT], re[NT];  // imaginary / real bytes of both chunks
+            v4i im[NT], re[NT];  // imaginary bytes (A side) / real bytes (B side) of both chunks
 #pragma unroll
             for (int a = 0; a < NT; ++a) {
                 im[a] = v4i{c0[a].z, c0[a].w, c1[a].z, c1[a].w};
-                re[a] = v4i{c0[a].x, c0[a].y, c1[a].x, c1[a].y};
+                re[a] = v4i{b0[a].x, b0[a].y, b1[a].x, b1[a].y};
             }
 #pragma unroll
             for (int b = 0; b < NT; ++b) {
 #pragma unroll
                 for (int a = 0; a <= b; ++a) {
                     V16 &d = accR[tri_idx(a, b)];
-                    d = __builtin_amdgcn_mfma_i32_32x32x32_i8(c0[a], c0[b], d, 0, 0, 0);
-                    d = __builtin_amdgcn_mfma_i32_32x32x32_i8(c1[a], c1[b], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_i32_32x32x32_i8(c0[a], b0[b], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_i32_32x32x32_i8(c1[a], b1[b], d, 0, 0, 0);
                 }
 #pragma unroll
                 for (int a = 0; a < NT; ++a)
@@ -177,47 +222,53 @@ __device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, 
         } else if constexpr (PREC == CORR_FP8_E4M3) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                long re[NT], im[NT];
+                long re[NT], im[NT], reB[NT], imB[NT];  // A side, and the (masked) B side
 #pragma unroll
                 for (int a = 0; a < NT; ++a) {
                     const v4i v = h ? c1[a] : c0[a];
+                    const v4i w = h ? b1[a] : b0[a];
                     re[a] = (long)(((unsigned long)(unsigned)v.y << 32) | (unsigned)v.x);
                     im[a] = (long)(((unsigned long)(unsigned)v.w << 32) | (unsigned)v.z);
+                    reB[a] = (long)(((unsigned long)(unsigned)w.y << 32) | (unsigned)w.x);
+                    imB[a] = (long)(((unsigned long)(unsigned)w.w << 32) | (unsigned)w.z);
                 }
 #pragma unroll
                 for (int b = 0; b < NT; ++b) {
 #pragma unroll
                     for (int a = 0; a <= b; ++a) {
                         V16 &d = accR[tri_idx(a, b)];
-                        d = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(re[a], re[b], d, 0, 0, 0);
-                        d = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(im[a], im[b], d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(re[a], reB[b], d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(im[a], imB[b], d, 0, 0, 0);
                     }
 #pragma unroll
                     for (int a = 0; a < NT; ++a)
-                        accM[a * NT + b] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(im[a], re[b], accM[a * NT + b], 0, 0, 0);
+                        accM[a * NT + b] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(im[a], reB[b], accM[a * NT + b], 0, 0, 0);
                 }
             }
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {  // spectra (chunk 0: 0, 1; chunk 1: 2, 3)
-                float rr[NT], qq[NT];
+                float rr[NT], qq[NT], rrB[NT], qqB[NT];  // A side, and the (masked) B side
 #pragma unroll
                 for (int a = 0; a < NT; ++a) {
                     const v4i v = (q < 2) ? c0[a] : c1[a];
+                    const v4i w = (q < 2) ? b0[a] : b1[a];
                     rr[a] = __int_as_float((q & 1) ? v.z : v.x);
                     qq[a] = __int_as_float((q & 1) ? v.w : v.y);
+                    rrB[a] = __int_as_float((q & 1) ? w.z : w.x);
+                    qqB[a] = __int_as_float((q & 1) ? w.w : w.y);
                 }
 #pragma unroll
                 for (int b = 0; b < NT; ++b) {
 #pragma unroll
                     for (int a = 0; a <= b; ++a) {
                         V16 &d = accR[tri_idx(a, b)];
-                        d = __builtin_amdgcn_mfma_f32_32x32x2f32(rr[a], rr[b], d, 0, 0, 0);
-                        d = __builtin_amdgcn_mfma_f32_32x32x2f32(qq[a], qq[b], d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_32x32x2f32(rr[a], rrB[b], d, 0, 0, 0);
+                        d = __builtin_amdgcn_mfma_f32_32x32x2f32(qq[a], qqB[b], d, 0, 0, 0);
                     }
 #pragma unroll
                     for (int a = 0; a < NT; ++a)
-                        accM[a * NT + b] = __builtin_amdgcn_mfma_f32_32x32x2f32(qq[a], rr[b], accM[a * NT + b], 0, 0, 0);
+                        accM[a * NT + b] = __builtin_amdgcn_mfma_f32_32x32x2f32(qq[a], rrB[b], accM[a * NT + b], 0, 0, 0);
                 }
             }
         }
@@ -239,6 +290,26 @@ __global__ void __launch_bounds__(64 * kXWaves)
 xengine_kernel(const uint8_t *__restrict__ spec, ACC *acc, int S, int C, int T, int splits) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[x_lds_bytes<NT>()];
     xengine_block<NT, PREC, ACC>(spec, acc, S, C, T, splits, blockIdx.x, blockIdx.y, lds);
+}
+
+// Gated correlation: one workgroup per (task, bin), task = (channel block kb,
+// split sp); it sums the spectra of gate bin `bin` into accumulator set
+// `bin` (acc_elems elements apart).  Every bin reads the same spectra, so the
+// bins of one task are given ids 8 apart: workgroups go to the 8 XCDs in
+// turn, so those land on the same XCD, run side by side and share its L2
+// (the later reads hit).  w -> xcd = w mod 8, j = w / 8, bin = j mod n_bins,
+// task = 8 (j / n_bins) + xcd.
+template <int NT, int PREC, typename ACC>
+__global__ void __launch_bounds__(64 * kXWaves)
+xengine_gated_kernel(const uint8_t *__restrict__ spec, const uint8_t *__restrict__ gate, ACC *acc, int64_t acc_elems,
+                     int S, int C, int T, int splits, int n_bins) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[x_lds_bytes<NT>()];
+    const int w = blockIdx.x, xcd = w & (kXcds - 1), j = w / kXcds;
+    const int bin = j % n_bins, task = kXcds * (j / n_bins) + xcd;
+    const int nkb = C / kXWaves;
+    if (task >= nkb * splits) return;  // padding of the last group of 8 tasks
+    xengine_block<NT, PREC, ACC, true>(spec, acc + bin * acc_elems, S, C, T, splits, task % nkb, task / nkb, lds, gate,
+                                       bin);
 }
 
 // One launch over the tasks of a batch of correlations of different shapes
@@ -306,6 +377,31 @@ hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int
     case CORR_FP32:
         if (two) hipLaunchKernelGGL((xengine_kernel<2, CORR_FP32, float>), grid, block, 0, st, sp8, (float *)acc, S, C, T, splits);
         else hipLaunchKernelGGL((xengine_kernel<1, CORR_FP32, float>), grid, block, 0, st, sp8, (float *)acc, S, C, T, splits);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_xengine_gated(int precision, const void *spec, const uint8_t *gate, int n_bins, void *acc,
+                                int64_t acc_elems, int S, int C, int T, int splits, hipStream_t st) {
+    const int tasks = (C / kXWaves) * splits;
+    const dim3 grid((unsigned)((tasks + kXcds - 1) / kXcds * kXcds * n_bins)), block(64 * kXWaves);
+    const uint8_t *sp8 = (const uint8_t *)spec;
+    const bool two = S > 32;
+    switch (precision) {
+    case CORR_INT8:
+        if (two) hipLaunchKernelGGL((xengine_gated_kernel<2, CORR_INT8, int32_t>), grid, block, 0, st, sp8, gate, (int32_t *)acc, acc_elems, S, C, T, splits, n_bins);
+        else hipLaunchKernelGGL((xengine_gated_kernel<1, CORR_INT8, int32_t>), grid, block, 0, st, sp8, gate, (int32_t *)acc, acc_elems, S, C, T, splits, n_bins);
+        break;
+    case CORR_FP8_E4M3:
+        if (two) hipLaunchKernelGGL((xengine_gated_kernel<2, CORR_FP8_E4M3, float>), grid, block, 0, st, sp8, gate, (float *)acc, acc_elems, S, C, T, splits, n_bins);
+        else hipLaunchKernelGGL((xengine_gated_kernel<1, CORR_FP8_E4M3, float>), grid, block, 0, st, sp8, gate, (float *)acc, acc_elems, S, C, T, splits, n_bins);
+        break;
+    case CORR_FP32:
+        if (two) hipLaunchKernelGGL((xengine_gated_kernel<2, CORR_FP32, float>), grid, block, 0, st, sp8, gate, (float *)acc, acc_elems, S, C, T, splits, n_bins);
+        else hipLaunchKernelGGL((xengine_gated_kernel<1, CORR_FP32, float>), grid, block, 0, st, sp8, gate, (float *)acc, acc_elems, S, C, T, splits, n_bins);
         break;
     default:
         return hipErrorInvalidValue;

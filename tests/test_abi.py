@@ -247,3 +247,26 @@ def test_adc_unpack_rejects_bad_arguments():
     assert au(rs=496) == -1 and au(rs=520) == -1
     assert L.corr_adc_last_error()
     assert au(n=0) == 0 and L.corr_adc_last_error() == b""
+
+
+def test_gated_xengine_and_gates_reject_bad_arguments():
+    L = corr.lib()
+    rc, h = create(n_signals=8, fft_len=512, n_spectra=32, precision=corr.INT8)
+    assert rc == 0
+    try:
+        f = ctypes.c_void_p(1 << 20)
+        gx = lambda spec=f, gate=f, nb=2, acc=f: L.corr_xengine_gated(h, spec, gate, nb, acc, None)
+        assert gx(spec=None) == -2 and gx(gate=None) == -2 and gx(acc=None) == -2
+        assert gx(spec=ctypes.c_void_p((1 << 20) + 16)) == -3 and gx(gate=ctypes.c_void_p((1 << 20) + 8)) == -3
+        assert gx(nb=0) == -1 and gx(nb=256) == -1
+        assert L.corr_xengine_gated(None, f, f, 1, f, None) == -2
+    finally:
+        L.corr_plan_destroy(h)
+    g = (ctypes.c_uint8 * 8)()
+    pg = lambda s0=0, n=8, N=512, fs=1e6, t0=0.0, P=1e-3, nb=2, gate=g: \
+        L.corr_pulsar_gates(s0, n, N, fs, t0, P, nb, gate, None)
+    assert pg() == 0
+    assert pg(gate=None) == -2
+    assert pg(n=-1) == -1 and pg(s0=-1) == -1 and pg(N=0) == -1 and pg(fs=0.0) == -1 and pg(fs=float("inf")) == -1
+    assert pg(P=0.0) == -1 and pg(P=float("nan")) == -1 and pg(t0=float("nan")) == -1
+    assert pg(nb=0) == -1 and pg(nb=256) == -1

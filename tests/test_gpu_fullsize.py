@@ -245,6 +245,32 @@ def test_precision_form_int8_xengine_bit_exact_sampled_channels():
     assert np.array_equal(a, oracle.xengine_int(qh))
 
 
+def test_gated_int8_xengine_bit_exact_sampled_channels():
+    """The gated X-engine at 64 x 2048 x 32768 in bench.py's configuration
+    (two gates: the halves of a 1.5578 ms pulsar period), on seeded int8
+    codes: sampled channels of both gates equal the int64 triple loop over
+    each gate's spectra exactly."""
+    import torch
+    S, N, T = 64, 4096, 32768
+    C = N // 2
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.BASE_SEED + 78)
+    q = torch.randint(-127, 128, (S, T, C, 2), generator=gen, device="cuda", dtype=torch.int16).to(torch.int8)
+    plan = corr.Plan(S, N, T, precision=corr.INT8)
+    spec = plan.alloc("spectra", zero=False)
+    plan.xpack(q, spec)
+    gate, counts = corr.pulsar_gates(0, T, N, FS, 0.0, 1.5578e-3, 2)
+    acc = torch.zeros(2 * plan.acc_bytes // 4, dtype=torch.int32, device="cuda")
+    plan.xengine_gated(spec, torch.from_numpy(gate).cuda(), 2, acc)
+    torch.cuda.synchronize()
+    chans = [5, 1100, 2046]
+    qh = q[:, :, chans].cpu().numpy()
+    ref = oracle.xengine_int_gated(qh, gate, 2)
+    a = acc.view(2, plan.splits, C, plan.P, 2)[:, :, chans].cpu().numpy().astype(np.int64).sum(1)
+    assert np.array_equal(a, ref)
+    assert counts.min() > 0.45 * T
+
+
 def test_batched_form_sampled_channels():
     """The six uneven sub-arrays in one captured graph (autotuned splits, held
     scales).  For every sub-array's sampled channels the oracle runs its own
