@@ -46,6 +46,7 @@ def _load():
     lib.orc_fft.argtypes = [P, i64]
     lib.orc_fft.restype = i32
     lib.orc_fengine.argtypes = [P, i64, i32, i64, i64, i64, P, P, P, P, dbl, dbl, i32, i32, P]
+    lib.orc_fengine_lut.argtypes = [P, i64, i32, i64, i64, i64, P, P, P, P, dbl, dbl, i32, P]
     lib.orc_fengine.restype = i32
     lib.orc_fengine_channels.argtypes = [P, i64, i32, i64, i64, i64, P, P, P, P, dbl, dbl, i32,
                                          P, i32, P]
@@ -136,6 +137,23 @@ def fengine(x: np.ndarray, N: int, T: int, geom: Geometry, fs: float, nu_bb: flo
                              1 if method == "dft" else 0, _p(Y))
     if rc != 0:
         raise ValueError("orc_fengine failed (%d)" % rc)
+    return Y
+
+
+def fengine_lut(x: np.ndarray, N: int, T: int, geom: Geometry, fs: float, nu_bb: float = 0.0,
+                sideband: int = 1, spectrum0: int = 0) -> np.ndarray:
+    """F-engine with the phase from the 1440-step sin/cos table of section
+    2.3.2 (each channel's Eq. 2 phase rounded to the nearest 0.25 degree
+    step); returns Y[S][T][C] complex128."""
+    x = np.ascontiguousarray(x, dtype=np.int8)
+    S, stride = x.shape
+    if np.any(geom.D < 0) or np.any(T * N + geom.D > stride):
+        raise ValueError("delay window runs past the row")
+    Y = np.empty((S, T, N // 2), dtype=np.complex128)
+    rc = _load().orc_fengine_lut(_p(x), stride, S, N, T, spectrum0, _p(geom.D), _p(geom.f), _p(geom.psi0),
+                                 _p(geom.rate), fs, nu_bb, sideband, _p(Y))
+    if rc != 0:
+        raise ValueError("orc_fengine_lut failed (%d)" % rc)
     return Y
 
 

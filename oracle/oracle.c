@@ -178,6 +178,50 @@ int orc_fengine(const int8_t *x, int64_t row_stride, int S, int64_t N,
     return bad ? -2 : 0;
 }
 
+/* F-engine with the phase taken from the 1440-step sin/cos table of section  */
+/* 2.3.2 (0.25 degree steps).  The phase of Eq. 2 in cycles is formed per     */
+/* channel and spectrum as                                                    */
+/*   c   = nu_BB f / fs + sigma (psi + r t_m),  t_m = (spectrum + 1/2)(N/fs), */
+/*   c  -= floor(c),                                                          */
+/*   phi = c + k (f / N),                                                     */
+/* each operation rounded on its own in FP64 (the table index is an integer   */
+/* decision, so the reading fixes this order), and the table entry is         */
+/* j = rint(1440 phi) mod 1440: Y[k] = X[k] exp(2 pi i j / 1440).             */
+int orc_fengine_lut(const int8_t *x, int64_t row_stride, int S, int64_t N, int64_t T, int64_t spectrum0,
+                    const int32_t *D, const double *f, const double *psi0, const double *rate, double fs,
+                    double nu_bb, int sideband, double *Y)
+{
+    if (!is_pow2(N) || S <= 0 || T < 0) return -1;
+    int64_t C = N / 2;
+    int bad = 0;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int s = 0; s < S; ++s) {
+        for (int64_t m = 0; m < T; ++m) {
+            cplx *X = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+            if (!X) { bad = 1; continue; }
+            const int8_t *row = x + (int64_t)s * row_stride;
+            for (int64_t n = 0; n < N; ++n) X[n] = (double)row[m * N + D[s] + n];
+            fft_inplace(X, N);
+            double t_spec = (double)N / fs;
+            double tm = ((double)(spectrum0 + m) + 0.5) * t_spec;
+            double c = nu_bb * f[s] / fs + (double)sideband * (psi0[s] + rate[s] * tm);
+            c -= floor(c);
+            double fn = f[s] / (double)N;
+            double *out = Y + (((int64_t)s * T + m) * C) * 2;
+            for (int64_t k = 0; k < C; ++k) {
+                double phi = c + (double)k * fn;
+                int64_t j = (int64_t)rint(phi * 1440.0) % 1440;
+                double th = 2.0 * M_PI * (double)j / 1440.0;
+                cplx y = X[k] * (cos(th) + I * sin(th));
+                out[2 * k] = creal(y);
+                out[2 * k + 1] = cimag(y);
+            }
+            free(X);
+        }
+    }
+    return bad ? -2 : 0;
+}
+
 /* Same F-engine for a list of channels only, by the direct DFT sum of the
  * definition (used to check sampled outputs of full-size runs).
  * Y layout: [S][T][nk][2]. */
