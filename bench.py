@@ -487,6 +487,28 @@ def bench_gated(corr, torch, S, N, T, x_dev, rs, g_dev, scale, steps, warmup, pe
     return ms
 
 
+def bench_table_phase(corr, torch, S, N, T, x_dev, rs, g_dev, scale, steps, warmup):
+    """The int8 F-engine with the phase from the 1440-step table of section
+    2.3.2 instead of direct sincos, same input and scales.  Returns ms per
+    call."""
+    plan = corr.Plan(S, N, T, precision=corr.INT8, scale_mode=corr.SCALE_HOLD, phase_lut=1)
+    spec = plan.alloc("spectra", zero=False)
+    f = lambda: plan.fengine(x_dev, g_dev, spec, scale, row_stride=rs)
+    for _ in range(warmup):
+        f()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del spec, plan
+    torch.cuda.empty_cache()
+    return ms
+
+
 def bench_adc(corr, torch, S, n, steps, warmup):
     """Demultiplex and unpack S / 4 acquisition-card streams of n time samples
     into the F-engine's S int8 rows, in the 4-bit (33 MHz) and the 8-bit
@@ -582,6 +604,9 @@ def main():
     log("timing the gated X-engine (two pulse-phase gates)")
     tg_ms = bench_gated(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
     log("gated X-engine: %.3f ms per call (ungated %.3f ms)" % (tg_ms, r8["t_x"] * 1e3))
+    log("timing the int8 F-engine with the 1440-step phase table")
+    tt_ms = bench_table_phase(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
+    log("table-phase F-engine: %.3f ms (direct sincos %.3f ms)" % (tt_ms, r8["t_f"] * 1e3))
     log("timing the ADC demultiplexing and unpacking (4-bit and 8-bit card streams)")
     ra = bench_adc(corr, torch, S, N * T + 16, args.steps, args.warmup)
     log("adc unpack: %.3f ms (4-bit), %.3f ms (8-bit)" % (ra[4][0], ra[8][0]))
@@ -681,6 +706,10 @@ def main():
         "achieved_gbs": round(xin8 / (tg_ms * 1e-3) / 1e9, 1),
         "hbm_frac": round(xin8 / (tg_ms * 1e-3) / HBM_PEAK, 4),
         "mfma_frac_issued": round(2 * xops8 / (tg_ms * 1e-3) / INT8_PEAK, 4)}
+    out["table_phase_fengine"] = {
+        "kernel": "fengine_kernel<log2M, 5> (int8, phase from the 1440-step table)", "bound": "alu",
+        "ms": round(tt_ms, 4), "direct_sincos_ms": round(r8["t_f"] * 1e3, 4),
+        "alu_frac": round(ff8 / (tt_ms * 1e-3) / FP32_VALU_PEAK, 4)}
     out["adc_unpack"] = {
         "kernel": "adc_unpack_kernel<bits> (4-input demultiplexing, 4-bit to 8-bit)", "bound": "hbm",
         "cards": S // 4,

@@ -91,7 +91,13 @@ typedef struct {
     double sample_rate;   /* fs in Hz (> 0)                                      */
     double nu_bb;         /* baseband frequency of the band's lower edge (Hz)    */
     int32_t x_split;      /* X-engine K-splits (0 = library choice)              */
-    int32_t reserved[7];  /* must be zero                                        */
+    int32_t phase_lut;    /* 0: FSTC/fringe phase evaluated directly (FP32     */
+                          /* sincos); 1: the paper's 1440-step sin/cos table    */
+                          /* (section 2.3.2): the phase k f/N + c_m of Eq. 2 is */
+                          /* formed in FP64 per channel and spectrum, rounded   */
+                          /* to the nearest 0.25 degree step, and that step's   */
+                          /* FP32 cos and sin are used (error <= 0.125 deg)     */
+    int32_t reserved[6];  /* must be zero                                        */
 } corr_desc_t;
 
 /*

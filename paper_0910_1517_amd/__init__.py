@@ -47,7 +47,8 @@ class CorrDesc(ctypes.Structure):
         ("sample_rate", ctypes.c_double),
         ("nu_bb", ctypes.c_double),
         ("x_split", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("phase_lut", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -204,11 +205,11 @@ def _stream(stream):
 
 
 def make_desc(n_signals, fft_len, n_spectra, *, max_delay=16, precision=FP32, sideband=1,
-              scale_mode=SCALE_HOLD, sample_rate=66.666666e6, nu_bb=0.0, x_split=0) -> CorrDesc:
+              scale_mode=SCALE_HOLD, sample_rate=66.666666e6, nu_bb=0.0, x_split=0, phase_lut=0) -> CorrDesc:
     d = CorrDesc()
     d.n_signals, d.fft_len, d.n_spectra = n_signals, fft_len, n_spectra
     d.max_delay, d.precision, d.sideband, d.scale_mode = max_delay, precision, sideband, scale_mode
-    d.sample_rate, d.nu_bb, d.x_split = sample_rate, nu_bb, x_split
+    d.sample_rate, d.nu_bb, d.x_split, d.phase_lut = sample_rate, nu_bb, x_split, phase_lut
     return d
 
 
@@ -217,12 +218,12 @@ class Plan:
 
     def __init__(self, n_signals: int, fft_len: int, n_spectra: int, *, max_delay: int = 16,
                  precision: int = FP32, sideband: int = 1, scale_mode: int = SCALE_HOLD,
-                 sample_rate: float = 66.666666e6, nu_bb: float = 0.0, x_split: int = 0,
+                 sample_rate: float = 66.666666e6, nu_bb: float = 0.0, x_split: int = 0, phase_lut: int = 0,
                  device=None, bind: bool = True, _handle=None):
         L = lib()
         self.desc = make_desc(n_signals, fft_len, n_spectra, max_delay=max_delay, precision=precision,
                               sideband=sideband, scale_mode=scale_mode, sample_rate=sample_rate,
-                              nu_bb=nu_bb, x_split=x_split)
+                              nu_bb=nu_bb, x_split=x_split, phase_lut=phase_lut)
         self._owned = _handle is None
         if _handle is None:
             h = ctypes.c_void_p()

@@ -113,7 +113,9 @@ corr_status corr_plan_create(const corr_desc_t *desc, corr_plan_t **out) {
         return fail(nullptr, CORR_ERR_INVALID, "sample_rate must be finite and > 0, nu_bb finite");
     if (d.x_split < 0 || d.x_split > 4096)
         return fail(nullptr, CORR_ERR_INVALID, "x_split %d outside 0..4096", d.x_split);
-    for (int i = 0; i < 7; ++i)
+    if (d.phase_lut != 0 && d.phase_lut != 1)
+        return fail(nullptr, CORR_ERR_INVALID, "phase_lut must be 0 or 1 (got %d)", d.phase_lut);
+    for (int i = 0; i < 6; ++i)
         if (d.reserved[i]) return fail(nullptr, CORR_ERR_INVALID, "reserved[%d] must be zero", i);
 
     corr_plan *p = new (std::nothrow) corr_plan;
@@ -133,6 +135,7 @@ corr_status corr_plan_create(const corr_desc_t *desc, corr_plan_t **out) {
     w.wn = o; o = round_up(o + sizeof(float2) * p->M, 256);
     w.pairs = o; o = round_up(o + sizeof(uint16_t) * 2 * p->P, 256);
     w.err = o; o = round_up(o + 16, 256);
+    w.lut = o; o = round_up(o + sizeof(float2) * kLutSteps, 256);
     w.part = o;
     if (d.precision != CORR_FP32 && d.scale_mode == CORR_SCALE_COMPUTE)
         o = round_up(o + sizeof(float) * d.n_signals * (d.n_spectra / 16) * p->M, 256);
@@ -180,6 +183,12 @@ corr_status corr_plan_bind_workspace(corr_plan_t *p, void *d_ws, size_t bytes, v
         const double b = -2.0 * M_PI * (double)n / (double)N;
         wn[n] = make_float2((float)std::cos(b), (float)std::sin(b));
     }
+    // phase table: cos and sin of 2 pi j / 1440 in FP64, rounded once to FP32
+    std::vector<float2> lut(kLutSteps);
+    for (int j = 0; j < kLutSteps; ++j) {
+        const double b = 2.0 * M_PI * (double)j / (double)kLutSteps;
+        lut[j] = make_float2((float)std::cos(b), (float)std::sin(b));
+    }
     std::vector<uint16_t> pairs(2 * p->P);
     for (int j = 0; j < p->d.n_signals; ++j)
         for (int i = 0; i <= j; ++i) {
@@ -193,6 +202,7 @@ corr_status corr_plan_bind_workspace(corr_plan_t *p, void *d_ws, size_t bytes, v
         (e = hipMemcpyAsync(ws + p->ws.wn, wn.data(), sizeof(float2) * M, hipMemcpyHostToDevice, st)) ||
         (e = hipMemcpyAsync(ws + p->ws.pairs, pairs.data(), sizeof(uint16_t) * pairs.size(),
                             hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(ws + p->ws.lut, lut.data(), sizeof(float2) * kLutSteps, hipMemcpyHostToDevice, st)) ||
         (e = hipMemsetAsync(ws + p->ws.err, 0, 16, st)) || (e = hipStreamSynchronize(st)))
         return hip_fail(p, e, "uploading plan tables");
     p->d_ws = ws;
@@ -237,6 +247,7 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
     a.sideband = p->d.sideband;
     a.fs = p->d.sample_rate;
     a.nu_bb = p->d.nu_bb;
+    a.lut = reinterpret_cast<const float2 *>(p->d_ws + p->ws.lut);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (q8 && p->d.scale_mode == CORR_SCALE_COMPUTE) {
@@ -246,7 +257,7 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
             return hip_fail(p, e, "calibration reduce");
     }
     a.power = d_power;
-    const int mode = p->d.precision == CORR_FP32 ? 0 : (p->d.precision == CORR_INT8 ? 1 : 2);
+    const int mode = (p->d.precision == CORR_FP32 ? 0 : (p->d.precision == CORR_INT8 ? 1 : 2)) + (p->d.phase_lut ? 4 : 0);
     if ((e = launch_fengine(p->log2m, mode, a, st)) != hipSuccess) return hip_fail(p, e, "F-engine launch");
     return CORR_OK;
 }

@@ -30,6 +30,7 @@ struct WsLayout {
     size_t pairs;     // uint16[2P]  (i, j) of each pair index
     size_t err;       // uint32[4]   device error words
     size_t part;      // float[S][nblk*fpar][C] calibration partial sums
+    size_t lut;       // float2[kLutSteps] cos, sin of 2 pi j / kLutSteps (table mode)
     size_t total;
 };
 
@@ -51,9 +52,14 @@ struct FLaunch {
     int sideband;
     double fs;
     double nu_bb;
+    const float2 *lut;   // phase table (table mode only)
 };
 
-// mode: 0 FP32 spectra, 1 INT8, 2 FP8, 3 calibration partial sums
+// Phase look-up table of section 2.3.2: 1440 steps of 0.25 degrees.
+constexpr int kLutSteps = 1440;
+// mode: 0 FP32 spectra, 1 INT8, 2 FP8, 3 calibration partial sums; 4..6 = the
+// first three with the phase from the table
+
 hipError_t launch_fengine(int log2m, int mode, const FLaunch &a, hipStream_t st);
 // geometry of the F-engine launch: spectra handled per workgroup, workgroups per signal
 int fengine_spectra_per_block(int log2m);

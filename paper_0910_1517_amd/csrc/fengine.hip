@@ -21,7 +21,10 @@
 //  3. FSTC and fringe stop (Eq. 2): Y[k] = X[k] exp(2 pi i (k f/N + c_m)),
 //     c_m = nu_BB f/fs + sideband (psi0 + rate t_m) reduced mod 1 in FP64 once
 //     per spectrum; the per-channel ramp exp(2 pi i k f / N) is computed once
-//     per workgroup.
+//     per workgroup.  Table mode (the paper's 1440-step sin/cos look-up table,
+//     section 2.3.2): the phase k f/N + c_m is formed in FP64 per channel and
+//     spectrum and rounded to the nearest of 1440 steps, whose FP32 cos and sin
+//     replace the direct evaluation.
 //  4. requantisation (section 4.1's fixed point up to the MAC): int8
 //     clamp(rne(Y/scale), +-127) or OCP e4m3 RNE satfinite; FP32 keeps Y.
 //  5. corner turn: a thread owns channels k = t + L*j (j = 0..7) of every
@@ -245,14 +248,34 @@ __device__ __forceinline__ int opaque_zero() {
     return z;
 }
 
+// Phase of the 1440-step table (section 2.3.2): the cycles of spectrum m,
+// c = nu_BB f / fs + sideband (psi0 + rate t_m), t_m = (m + 1/2) N / fs,
+// reduced mod 1, each operation rounded on its own (the table index is an
+// integer decision, so the arithmetic is pinned down).
+__device__ inline double lut_spectrum_phase(double c_bb, int sideband, double psi0, double rate, int64_t m,
+                                            double t_spec) {
+#pragma clang fp contract(off)
+    const double tm = ((double)m + 0.5) * t_spec;
+    double c = c_bb + (double)sideband * (psi0 + rate * tm);
+    return c - floor(c);
+}
+// table entry of channel phase c + k f / N: nearest of the 1440 steps
+__device__ inline int lut_index(double c, double kfn) {
+#pragma clang fp contract(off)
+    const int i = (int)rint((c + kfn) * (double)kLutSteps);
+    return i % kLutSteps;
+}
+
 template <int LOGM, int MODE>
 // 4 waves per SIMD: <= 128 VGPRs, which the kernel meets without scratch.
 __global__ void __launch_bounds__(FCfg<LOGM>::WG) __attribute__((amdgpu_waves_per_eu(4, 8)))
 fengine_kernel(FLaunch a) {
     using C = FCfg<LOGM>;
+    constexpr int BM = MODE & 3;          // 0 FP32, 1 INT8, 2 FP8, 3 calibration
+    constexpr bool PL = (MODE & 4) != 0;  // phase from the 1440-step table
     constexpr int M = C::M, N = C::N, L = C::L, FPAR = C::FPAR;
     constexpr int SPB = 16 * FPAR;  // spectra per workgroup
-    constexpr int G = (MODE == 0) ? kChunk32 : kChunk8;  // spectra per X-layout chunk
+    constexpr int G = (BM == 0) ? kChunk32 : kChunk8;  // spectra per X-layout chunk
     __shared__ __attribute__((aligned(16))) uint32_t lds_in[FPAR][N / 4];
     __shared__ __attribute__((aligned(16))) float2 lds_w[FPAR][C::NBUF][C::PADM];
 
@@ -279,18 +302,21 @@ fengine_kernel(FLaunch a) {
     // per-thread channel constants, k_j = t + L j: FSTC ramp exp(2 pi i k f / N)
     // and the inverse requantisation scale
     float2 ramp[8];
+    const double fn = (double)g.frac / (double)N;  // table mode: channel k adds k fn cycles
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int k = t + L * j;
         // the post-process below forms 2 X[k]; the factor 1/2 is folded (exactly)
         // into the ramp
-        if constexpr (MODE != 3) {
+        if constexpr (PL) {
+            ramp[j] = make_float2(0.5f, 0.f);
+        } else if constexpr (BM != 3) {
             float sn, cs;
             sincospif(2.0f * ((float)k * (g.frac / (float)N)), &sn, &cs);
             ramp[j] = make_float2(0.5f * cs, 0.5f * sn);
         }
         // requantised output: the ramp also carries 1 / scale, so Y arrives scaled
-        if constexpr (MODE == 1 || MODE == 2) {
+        if constexpr (BM == 1 || BM == 2) {
             const float inv = 1.0f / a.scale[(int64_t)s * M + k];
             ramp[j] = make_float2(ramp[j].x * inv, ramp[j].y * inv);
         }
@@ -362,9 +388,13 @@ fengine_kernel(FLaunch a) {
         const float2 *Z = result_buffer<LOGM>(b0, b1);
         const float2 *wn = a.wn;
 
-        // 3. phase of this spectrum (FP64 reduction, FP32 sincos)
+        // 3. phase of this spectrum (FP64 reduction, FP32 sincos; LUT mode:
+        //    the reduced cycles c, to which each channel adds k f / N)
         float2 rot = make_float2(1.f, 0.f);
-        if constexpr (MODE != 3) {
+        double c_lut = 0.0;
+        if constexpr (PL) {
+            c_lut = lut_spectrum_phase(c_bb, a.sideband, g.psi0, g.rate, a.spectrum0 + m, t_spec);
+        } else if constexpr (BM != 3) {
             const double tm = ((double)(a.spectrum0 + m) + 0.5) * t_spec;
             double c = c_bb + (double)a.sideband * (g.psi0 + g.rate * tm);
             c -= floor(c);
@@ -393,13 +423,19 @@ fengine_kernel(FLaunch a) {
             float2 X;
             X.x = sm.x + (w.x * df.y + w.y * df.x);
             X.y = sm.y - (w.x * df.x - w.y * df.y);
-            if constexpr (MODE == 3) {
+            if constexpr (BM == 3) {
                 pacc[j] += X.x * X.x + X.y * X.y;
             } else {
                 if (a.power && active)  // |X|^2 = |2X|^2 / 4 (the phase rotation keeps it)
                     a.power[((int64_t)s * a.T + m) * M + tt + L * j] = 0.25f * (X.x * X.x + X.y * X.y);
-                const float2 Y = cmul(cmul(X, ramp[j]), rot);
-                if constexpr (MODE == 0) {
+                float2 Y;
+                if constexpr (PL) {  // table entry nearest the channel's phase; ramp = 1/2 (x 1/scale)
+                    const float2 e = a.lut[lut_index(c_lut, (double)(tt + L * j) * fn)];
+                    Y = make_float2(ramp[j].x * (X.x * e.x - X.y * e.y), ramp[j].x * (X.x * e.y + X.y * e.x));
+                } else {
+                    Y = cmul(cmul(X, ramp[j]), rot);
+                }
+                if constexpr (BM == 0) {
                     if (r & 1) {
                         if (active) {
                             float4 *dst = reinterpret_cast<float4 *>(a.spec) + obase + (int64_t)j * L * a.S;
@@ -410,7 +446,7 @@ fengine_kernel(FLaunch a) {
                     }
                 } else {
                     uint32_t qr, qi;
-                    if constexpr (MODE == 1) {
+                    if constexpr (BM == 1) {
                         qr = quant_i8(Y.x);
                         qi = quant_i8(Y.y);
                     } else {
@@ -433,7 +469,7 @@ fengine_kernel(FLaunch a) {
         }
     }
 
-    if constexpr (MODE == 3) {
+    if constexpr (BM == 3) {
         if (active) {
             // slot m0/16 of T/16 per signal: the active slots are exactly the first T/16
             float *dst = a.part + ((int64_t)s * (a.T / 16) + (m0 >> 4)) * M;
@@ -454,6 +490,9 @@ hipError_t launch_one(int mode, const FLaunch &a, hipStream_t st) {
     case 1: hipLaunchKernelGGL((fengine_kernel<LOGM, 1>), grid, block, 0, st, a); break;
     case 2: hipLaunchKernelGGL((fengine_kernel<LOGM, 2>), grid, block, 0, st, a); break;
     case 3: hipLaunchKernelGGL((fengine_kernel<LOGM, 3>), grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((fengine_kernel<LOGM, 4>), grid, block, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((fengine_kernel<LOGM, 5>), grid, block, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((fengine_kernel<LOGM, 6>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -50,7 +50,7 @@ def create(**kw):
     (dict(fft_len=256), -1), (dict(fft_len=32768), -1), (dict(n_spectra=48), -1),
     (dict(n_spectra=0), -1), (dict(max_delay=-1), -1), (dict(precision=7), -1),
     (dict(sideband=0), -1), (dict(scale_mode=3), -1), (dict(sample_rate=0.0), -1),
-    (dict(sample_rate=float("nan")), -1), (dict(x_split=-2), -1),
+    (dict(sample_rate=float("nan")), -1), (dict(x_split=-2), -1), (dict(phase_lut=2), -1),
 ])
 def test_plan_create_rejects_bad_descriptions(kw, code):
     rc, h = create(**kw)
