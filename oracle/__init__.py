@@ -251,6 +251,62 @@ def beamform(Y: np.ndarray, w=None, c=None, mode: int = BEAM_FULLPOL, tint: int 
 
 
 # ---------------------------------------------------------------------------
+# Coherent dedispersion of phased-array voltages (section 4.3)
+# ---------------------------------------------------------------------------
+K_DM = 4.148808e15  # dispersion constant, Hz^2 s / (pc cm^-3): delay = K_DM DM / nu^2
+
+
+def baseband_series(V: np.ndarray) -> np.ndarray:
+    """Broadband complex time series of channel voltages V [..][T][C]: per
+    spectrum the inverse DFT over the channels, z[m C + n] = sum_k
+    V[m, k] exp(+2 pi i k n / C) (unnormalised); the channels k fs/N of the
+    band become a complex baseband signal at fs/2 samples per second."""
+    V = np.asarray(V, dtype=np.complex128)
+    C = V.shape[-1]
+    z = np.fft.ifft(V, axis=-1) * C
+    return z.reshape(V.shape[:-2] + (V.shape[-2] * C,))
+
+
+def dispersion_phase_cycles(f: np.ndarray, nu0: float, dm: float) -> np.ndarray:
+    """Phase (cycles) of the cold-plasma transfer function at sky frequency
+    nu0 + f, referenced to nu0: K_DM DM (1/nu - 1/nu0 + (nu - nu0)/nu0^2) =
+    K_DM DM f^2 / (nu0^2 (nu0 + f)).  Its group delay is K_DM DM (nu^-2 -
+    nu0^-2), the dispersion delay relative to nu0 (a pure delay and a
+    constant phase dropped)."""
+    f = np.asarray(f, dtype=np.float64)
+    return K_DM * dm * f * f / (nu0 * nu0 * (nu0 + f))
+
+
+def dedisperse(V: np.ndarray, fs: float, nu0: float, dm: float, n_int: int) -> np.ndarray:
+    """Coherent dedispersion of phased-array voltages V [npol][T][C] (upper
+    sideband, channel k at sky frequency nu0 + k fs/N, N = 2C) as in section
+    4.3: the broadband series of each polarisation (inverse FFT of its
+    spectra), its Fourier transform multiplied by the inverse dispersion
+    transfer function exp(-2 pi i phase(f)), f = q fs / (2 L) for bin q of L =
+    T C, the inverse transform (divided by L), intensities |z|^2 added over
+    polarisations and summed over n_int samples: I [L / n_int].  The
+    transform is circular: the first K_DM DM (nu0^-2 - (nu0 + fs/2)^-2) fs/2
+    samples wrap around and are not valid."""
+    V = np.asarray(V, dtype=np.complex128)
+    npol, T, C = V.shape
+    L = T * C
+    z = baseband_series(V)
+    f = np.arange(L, dtype=np.float64) * (fs / (2.0 * L))
+    ph = dispersion_phase_cycles(f, nu0, dm)
+    ph = ph - np.floor(ph)
+    H = np.exp(-2j * np.pi * ph)
+    zd = np.fft.ifft(np.fft.fft(z, axis=-1) * H, axis=-1)
+    I = (np.abs(zd) ** 2).sum(0)
+    return I.reshape(L // n_int, n_int).sum(1)
+
+
+def smear_samples(fs: float, nu0: float, dm: float) -> int:
+    """Dispersion sweep across the band [nu0, nu0 + fs/2] in complex samples
+    at fs/2."""
+    return int(np.ceil(K_DM * dm * (1.0 / nu0 ** 2 - 1.0 / (nu0 + fs / 2) ** 2) * fs / 2))
+
+
+# ---------------------------------------------------------------------------
 # Gated correlator (section 5)
 # ---------------------------------------------------------------------------
 def pulsar_gates(spectrum0: int, n: int, N: int, fs: float, t0: float, period: float, n_bins: int) -> np.ndarray:
