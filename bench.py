@@ -509,6 +509,42 @@ def bench_table_phase(corr, torch, S, N, T, x_dev, rs, g_dev, scale, steps, warm
     return ms
 
 
+def bench_dedisperse(corr, torch, N, T, steps, warmup, dm=71.0, nu0=325e6, n_int=1024):
+    """Coherent dedispersion of one beam's two polarisations of channel
+    voltages, the shape of one block of the step (T spectra x N/2 channels:
+    L = T N/2 complex samples per polarisation, T N / FS seconds): DM 71 pc
+    cm^-3 at 325 MHz, as for the paper's B1937+21, whose sweep across the band
+    fits in the block.  Random voltages (the cost does not depend on them).
+    Returns (ms per call, HBM bytes of its passes, block seconds, valid
+    fraction)."""
+    import math
+    C = N // 2
+    L = T * C
+    g = torch.Generator(device="cuda").manual_seed(5)
+    v = torch.randn(2, T, C, dtype=torch.complex64, device="cuda", generator=g)
+    work = torch.empty(2, L, dtype=torch.complex64, device="cuda")
+    out = torch.empty(L // n_int, dtype=torch.float32, device="cuda")
+    f = lambda: corr.dedisperse(v, sample_rate=FS, nu0=nu0, dm=dm, n_int=n_int, work=work, out=out)
+    for _ in range(warmup):
+        f()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    npass = math.ceil(math.log2(L) / 8)
+    # inverse DFT per spectrum, forward and inverse passes, chirp: read + write
+    # each; the detection reads once
+    nbytes = 2.0 * L * 8 * (2 * (1 + 2 * npass + 1) + 1)
+    sweep = 4.148808e15 * dm * (nu0 ** -2 - (nu0 + FS / 2) ** -2) * FS / 2
+    del v, work, out
+    torch.cuda.empty_cache()
+    return ms, nbytes, L / (FS / 2), 1.0 - sweep / L
+
+
 def bench_adc(corr, torch, S, n, steps, warmup):
     """Demultiplex and unpack S / 4 acquisition-card streams of n time samples
     into the F-engine's S int8 rows, in the 4-bit (33 MHz) and the 8-bit
@@ -607,6 +643,9 @@ def main():
     log("timing the int8 F-engine with the 1440-step phase table")
     tt_ms = bench_table_phase(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
     log("table-phase F-engine: %.3f ms (direct sincos %.3f ms)" % (tt_ms, r8["t_f"] * 1e3))
+    log("timing coherent dedispersion of one beam (DM 71 at 325 MHz)")
+    rd = bench_dedisperse(corr, torch, N, T, max(2, args.steps // 2), min(1, args.warmup))
+    log("dedispersion: %.3f ms per %.2f s block (%.0fx real time)" % (rd[0], rd[2], rd[2] / (rd[0] * 1e-3)))
     log("timing the ADC demultiplexing and unpacking (4-bit and 8-bit card streams)")
     ra = bench_adc(corr, torch, S, N * T + 16, args.steps, args.warmup)
     log("adc unpack: %.3f ms (4-bit), %.3f ms (8-bit)" % (ra[4][0], ra[8][0]))
@@ -710,6 +749,13 @@ def main():
         "kernel": "fengine_kernel<log2M, 5> (int8, phase from the 1440-step table)", "bound": "alu",
         "ms": round(tt_ms, 4), "direct_sincos_ms": round(r8["t_f"] * 1e3, 4),
         "alu_frac": round(ff8 / (tt_ms * 1e-3) / FP32_VALU_PEAK, 4)}
+    out["coherent_dedispersion"] = {
+        "kernel": "dd_fft_kernel<log2R> passes + chirp + detection (one beam, two polarisations)", "bound": "hbm",
+        "block": "%d spectra x %d channels = 2^%d complex samples per polarisation" % (T, N // 2, int(np.log2(T * N // 2))),
+        "dm": 71.0, "nu0_hz": 325e6, "ms": round(rd[0], 4), "block_seconds": round(rd[2], 4),
+        "real_time_factor": round(rd[2] / (rd[0] * 1e-3), 1), "valid_fraction": round(rd[3], 4),
+        "pass_bytes": rd[1], "achieved_gbs": round(rd[1] / rd[0] / 1e6, 1),
+        "hbm_frac": round(rd[1] / rd[0] / 1e6 / (HBM_PEAK / 1e9), 4)}
     out["adc_unpack"] = {
         "kernel": "adc_unpack_kernel<bits> (4-input demultiplexing, 4-bit to 8-bit)", "bound": "hbm",
         "cards": S // 4,

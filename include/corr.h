@@ -314,6 +314,39 @@ size_t corr_plan_power_bytes(const corr_plan_t *plan);
 size_t corr_plan_flags_bytes(const corr_plan_t *plan);
 size_t corr_plan_keep_bytes(const corr_plan_t *plan);
 
+/* ------------------------------------------------- coherent dedispersion */
+
+/* Coherent dedispersion of phased-array voltages (section 4.3: the coherent
+ * beam's pre-detected voltages converted to a broadband series by inverse
+ * FFT, multiplied by the inverse of the interstellar dispersion kernel in the
+ * Fourier domain, detected, polarisations added, integrated).
+ *   d_v      complex64 [npol][T][C]: the channel voltages of one beam (for
+ *            example corr_beamform's CORR_BEAM_VOLTAGE output of one beam),
+ *            upper sideband, channel k at sky frequency nu0 + k fs/N, N = 2C.
+ *            Not modified.  8-byte aligned.
+ *   Steps: z[m C + n] = sum_k V[m][k] exp(+2 pi i k n / C) (complex baseband
+ *   at fs/2); its L = T C point transform times
+ *   exp(-2 pi i K DM f^2 / (nu0^2 (nu0 + f))), f = q fs / (2L), K =
+ *   4.148808e15 Hz^2 s / (pc cm^-3) (group delay K DM (nu^-2 - nu0^-2): every
+ *   frequency is aligned to its arrival at nu0); the inverse transform / L;
+ *   I[j] = sum over polarisations and samples j n_int .. j n_int + n_int - 1
+ *   of |z|^2.
+ *   The transform is circular: the first K DM (nu0^-2 - (nu0 + fs/2)^-2) fs/2
+ *   output samples (the sweep across the band) are not valid; consecutive
+ *   blocks should overlap by that many samples.
+ *   npol     1 or 2.  C a power of two in [16, 8192]; T a power of two;
+ *            T C in [4096, 2^28].  n_int a power of two <= T C.
+ *   d_work   corr_dedisperse_workspace_bytes(npol, T, C) bytes, 8-byte
+ *            aligned, not d_v; holds the dedispersed voltages afterwards.
+ *   d_out    float [T C / n_int].
+ * FP32 transforms (error about 1e-6 of the rms at T C = 2^24), the chirp
+ * phase in FP64 reduced mod 1.  Errors: NULL, ALIGN, INVALID, DEVICE;
+ * messages via corr_dedisperse_last_error. */
+corr_status corr_dedisperse(const float *d_v, int32_t npol, int64_t T, int32_t C, double sample_rate, double nu0,
+                            double dm, int32_t n_int, float *d_work, float *d_out, void *stream);
+size_t corr_dedisperse_workspace_bytes(int32_t npol, int64_t T, int32_t C);
+const char *corr_dedisperse_last_error(void);
+
 /* ------------------------------------------------------------- ADC input */
 
 /* Demultiplex and unpack the raw streams of the acquisition cards (sections

@@ -76,6 +76,7 @@ SYMBOLS = [
     "corr_cnn_check_device_errors", "corr_cnn_infer", "corr_cnn_save", "corr_cnn_load", "corr_cnn_last_error",
     "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
     "corr_adc_unpack", "corr_adc_last_error", "corr_xengine_gated", "corr_pulsar_gates",
+    "corr_dedisperse", "corr_dedisperse_workspace_bytes", "corr_dedisperse_last_error",
 ]
 
 
@@ -179,6 +180,12 @@ def lib():
     L.corr_xengine_gated.restype = st
     L.corr_pulsar_gates.argtypes = [i64, i64, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32, P, P]
     L.corr_pulsar_gates.restype = st
+    L.corr_dedisperse.argtypes = [P, i32, i64, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32, P, P, P]
+    L.corr_dedisperse.restype = st
+    L.corr_dedisperse_workspace_bytes.argtypes = [i32, i64, i32]
+    L.corr_dedisperse_workspace_bytes.restype = ctypes.c_size_t
+    L.corr_dedisperse_last_error.argtypes = []
+    L.corr_dedisperse_last_error.restype = ctypes.c_char_p
     L.corr_adc_unpack.argtypes = [P, i64, i32, i64, i32, P, i64, P]
     L.corr_adc_unpack.restype = st
     L.corr_adc_last_error.argtypes = []
@@ -509,6 +516,25 @@ def pulsar_gates(spectrum0: int, n_spectra: int, fft_len: int, sample_rate: floa
     if rc != 0:
         raise CorrError(rc, lib().corr_last_error(None).decode())
     return gate, counts
+
+
+def dedisperse(v, *, sample_rate: float, nu0: float, dm: float, n_int: int, work=None, out=None, stream=None):
+    """Coherent dedispersion of one beam's voltages v (complex64 device tensor
+    [npol][T][C]); returns the detected, integrated series (float [T C /
+    n_int]) and the workspace (the dedispersed voltages).  See
+    corr_dedisperse."""
+    import torch
+    npol, T, C = v.shape
+    L = T * C
+    if work is None:
+        work = torch.empty(npol, L, dtype=torch.complex64, device=v.device)
+    if out is None:
+        out = torch.empty(L // n_int, dtype=torch.float32, device=v.device)
+    rc = lib().corr_dedisperse(_ptr(v), npol, T, C, sample_rate, nu0, dm, n_int, _ptr(work), _ptr(out),
+                               _stream(stream))
+    if rc != 0:
+        raise CorrError(rc, lib().corr_dedisperse_last_error().decode())
+    return out, work
 
 
 def _blank_check(rc):

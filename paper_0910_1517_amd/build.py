@@ -12,7 +12,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcorr.so")
-SOURCES = ["corr_api.hip", "fengine.hip", "xengine.hip", "integrate.hip", "flag.hip", "cnn.hip", "cnn_api.hip", "beam.hip", "blank.hip", "adc.hip"]
+SOURCES = ["corr_api.hip", "fengine.hip", "xengine.hip", "integrate.hip", "flag.hip", "cnn.hip", "cnn_api.hip", "beam.hip", "blank.hip", "adc.hip", "dedisp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -packed-fp32-ops: never emit v_pk_{add,mul,fma}_f32 (plain FP32 VALU only).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -270,3 +270,22 @@ def test_gated_xengine_and_gates_reject_bad_arguments():
     assert pg(n=-1) == -1 and pg(s0=-1) == -1 and pg(N=0) == -1 and pg(fs=0.0) == -1 and pg(fs=float("inf")) == -1
     assert pg(P=0.0) == -1 and pg(P=float("nan")) == -1 and pg(t0=float("nan")) == -1
     assert pg(nb=0) == -1 and pg(nb=256) == -1
+
+
+def test_dedisperse_rejects_bad_arguments():
+    L = corr.lib()
+    f = ctypes.c_void_p(1 << 20)
+
+    def dd(v=f, npol=2, T=1024, C=64, fs=33e6, nu0=325e6, dm=1.0, n=16, work=ctypes.c_void_p(1 << 21), out=f):
+        return L.corr_dedisperse(v, npol, T, C, fs, nu0, dm, n, work, out, None)
+
+    assert dd(v=None) == -2 and dd(work=None) == -2 and dd(out=None) == -2
+    assert dd(v=ctypes.c_void_p((1 << 20) + 4)) == -3 and dd(out=ctypes.c_void_p((1 << 20) + 2)) == -3
+    assert dd(npol=0) == -1 and dd(npol=3) == -1
+    assert dd(C=8) == -1 and dd(C=100) == -1 and dd(C=16384) == -1
+    assert dd(T=1000) == -1 and dd(T=16) == -1 and dd(T=1 << 22, C=128) == -1  # T C below 4096 / above 2^28
+    assert dd(n=3) == -1 and dd(n=0) == -1
+    assert dd(fs=0.0) == -1 and dd(nu0=-1.0) == -1 and dd(dm=-0.5) == -1 and dd(dm=float("nan")) == -1
+    assert dd(work=f) == -1  # the input must not be the workspace
+    assert L.corr_dedisperse_last_error()
+    assert L.corr_dedisperse_workspace_bytes(2, 1024, 64) == 2 * 1024 * 64 * 8

@@ -271,6 +271,25 @@ def test_gated_int8_xengine_bit_exact_sampled_channels():
     assert counts.min() > 0.45 * T
 
 
+def test_coherent_dedispersion_at_the_bench_block():
+    """Coherent dedispersion in bench.py's configuration: two polarisations of
+    32768 spectra x 2048 channels (2^26 complex samples each, a four-pass
+    transform), DM 71 at 325 MHz, 1024 samples per output.  Every output
+    against the oracle's FP64 transforms."""
+    import torch
+    T, C, dm, n_int = 32768, 2048, 71.0, 1024
+    g = torch.Generator(device="cuda").manual_seed(5)
+    v = torch.randn(2, T, C, dtype=torch.complex64, device="cuda", generator=g)
+    out, _ = corr.dedisperse(v, sample_rate=FS, nu0=325e6, dm=dm, n_int=n_int)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.dedisperse(v.cpu().numpy().astype(np.complex128), FS, 325e6, dm, n_int)
+    rms = np.sqrt(np.mean(ref ** 2))
+    err = np.abs(got - ref)
+    print("dedispersion 2^26: max err %.3g, rms err %.3g of rms" % (err.max() / rms, np.sqrt(np.mean(err ** 2)) / rms))
+    assert np.sqrt(np.mean(err ** 2)) <= 2e-5 * rms and err.max() <= 2e-4 * rms
+
+
 def test_batched_form_sampled_channels():
     """The six uneven sub-arrays in one captured graph (autotuned splits, held
     scales).  For every sub-array's sampled channels the oracle runs its own
