@@ -15,15 +15,16 @@
 // streams blocks that overlap by that much, as it does for the integer delays.
 //
 // One LDS kernel does all the transforms: W instances of an R-point DFT
-// (radix-2 Stockham stages in LDS, natural order in and out), loaded from
-// and stored to the instance's elements.  The per-spectrum inverse DFT is
+// (radix-4 Stockham stages in LDS, one radix-2 stage for odd log2 R, natural
+// order in and out, twiddles from an LDS table), loaded from and stored to
+// the instance's elements; a tile holds 4096 points.  The per-spectrum inverse DFT is
 // that kernel with R = C.  The long transform is a sequence of passes of a
 // decimation-in-frequency decomposition: pass j splits blocks of Bp samples
 // into R_j strided sub-sequences (stride s = Bp / R_j), takes their R_j-point
 // DFTs and multiplies output k of column b by exp(-2 pi i b k / Bp).  A small
 // radix goes first and then radix 256, so the stride is either >= the tile
-// width (a tile is 16 adjacent columns: 128-byte rows) or 1 (a tile is
-// contiguous).  The result is in digit-reversed order; the chirp kernel maps
+// width (a tile is 4096 / R adjacent columns: rows of at least 128 bytes) or
+// 1 (a tile is contiguous).  The result is in digit-reversed order; the chirp kernel maps
 // each position to its frequency, and the inverse passes (the mirror image:
 // conjugate twiddle, then the inverse DFT, in reverse order) restore time
 // order.  All passes run in place: a workgroup reads its whole tile into LDS
@@ -48,9 +49,13 @@ struct DdPasses {
     int lr[kDdMaxPasses];      // log2 radix of each pass, in forward order
 };
 
-// Instances per workgroup: a 4096-point tile up to R = 4096, one instance above.
+// Instances per workgroup: a 4096-point tile up to R = 4096, one instance
+// above.  (Every pass with R < 4096 has stride 1 or >= 4096 / R.)
 template <int LOGR>
-constexpr int dd_w() { return LOGR >= 12 ? 1 : (1 << (12 - LOGR)) > 16 ? 16 : (1 << (12 - LOGR)); }
+constexpr int dd_w() { return LOGR >= 12 ? 1 : (1 << (12 - LOGR)); }
+// R <= 4096: twiddles exp(dir 2 pi i t / R), t < R, from an LDS table
+template <int LOGR>
+constexpr bool dd_table() { return LOGR <= 12; }
 
 // W instances of an R-point DFT.  Instance i = tile * W + w covers block
 // beta = i / s, column b = i mod s; its point a is element beta Bp + a s + b.
@@ -62,7 +67,7 @@ __global__ __launch_bounds__(kDdThreads) void dd_fft_kernel(const float2 *in, fl
                                                             int dir, int twid) {
     constexpr int R = 1 << LOGR, W = dd_w<LOGR>(), RP = R + 1;
     extern __shared__ float2 dd_lds[];
-    float2 *A = dd_lds, *B = dd_lds + W * RP;
+    float2 *A = dd_lds, *B = dd_lds + W * RP, *tw = dd_lds + 2 * W * RP;
     const int tid = threadIdx.x;
     const int64_t s = Bp >> LOGR;
     const int64_t tile = blockIdx.x;
@@ -71,14 +76,33 @@ __global__ __launch_bounds__(kDdThreads) void dd_fft_kernel(const float2 *in, fl
     float2 *dst = out + pol_off;
     const float sgn = (float)dir;
 
-    // element (w, a) of the tile <-> global index
+    // element (w, a) of the tile <-> global index.  With s > 1, W divides s
+    // (both powers of two, s >= W), so the tile's W instances are adjacent
+    // columns b0 + w of one block beta.
+    const int64_t i0 = tile * W;
+    const int64_t beta = s == 1 ? 0 : i0 / s, b0 = s == 1 ? 0 : i0 - beta * s;
+    const int64_t base = s == 1 ? i0 * R : beta * Bp + b0;
     auto gidx = [&](int w, int a) -> int64_t {
-        if (s == 1) return (tile * W + w) * (int64_t)R + a;
-        const int64_t i = tile * W + w;
-        const int64_t beta = i / s, b = i - beta * s;
-        return beta * Bp + (int64_t)a * s + b;
+        return s == 1 ? base + (int64_t)w * R + a : base + (int64_t)a * s + w;
     };
-    auto colb = [&](int w) -> int64_t { return s == 1 ? 0 : (tile * W + w) % s; };
+    auto colb = [&](int w) -> int64_t { return s == 1 ? 0 : b0 + w; };
+    // exp(dir 2 pi i t / R)
+    auto rot = [&](int t) -> float2 {
+        if constexpr (dd_table<LOGR>()) {
+            return tw[t & (R - 1)];
+        } else {
+            float sn, cs;
+            sincospif(sgn * 2.0f * (float)(t & (R - 1)) / (float)R, &sn, &cs);
+            return make_float2(cs, sn);
+        }
+    };
+    if constexpr (dd_table<LOGR>()) {
+        for (int t = tid; t < R; t += kDdThreads) {
+            float sn, cs;
+            sincospif(sgn * 2.0f * (float)t / (float)R, &sn, &cs);
+            tw[t] = make_float2(cs, sn);
+        }
+    }
 
     // load (coalesced: s == 1 -> contiguous, else rows of W adjacent columns)
     for (int e = tid; e < W * R; e += kDdThreads) {
@@ -87,7 +111,7 @@ __global__ __launch_bounds__(kDdThreads) void dd_fft_kernel(const float2 *in, fl
         else { w = e % W; a = e / W; }
         float2 v = src[gidx(w, a)];
         if (twid && dir > 0) {  // inverse: conjugate twiddle of input k = a first
-            const int64_t bk = (colb(w) * a) % Bp;
+            const int64_t bk = colb(w) * a;  // < s R = Bp
             float sn, cs;
             sincospif(2.0f * (float)((double)bk / (double)Bp), &sn, &cs);
             v = make_float2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
@@ -96,25 +120,57 @@ __global__ __launch_bounds__(kDdThreads) void dd_fft_kernel(const float2 *in, fl
     }
     __syncthreads();
 
-    // radix-2 Stockham stages: out[(j / ns) 2 ns + k] = a + w b, [.. + ns] = a - w b,
-    // a = in[j], b = in[j + R/2], k = j mod ns, w = exp(dir 2 pi i k / (2 ns))
+    // Stockham stages (natural order in and out): one radix-2 stage when
+    // log2 R is odd, then radix 4.  A radix-P stage with span ns reads
+    // v_q = in[j + q R/P] (j < R/P), rotates v_q by exp(dir 2 pi i q k / (P ns)),
+    // k = j mod ns, takes the P-point DFT V_r and writes
+    // out[(j / ns) P ns + k + r ns] = V_r.
     float2 *X = A, *Y = B;
-    for (int ns = 1; ns < R; ns <<= 1) {
+    if constexpr (LOGR & 1) {
         for (int e = tid; e < W * (R / 2); e += kDdThreads) {
             const int w = e / (R / 2), j = e % (R / 2);
-            const int k = j & (ns - 1);
             const float2 a = X[w * RP + j], b = X[w * RP + j + R / 2];
-            float sn, cs;
-            sincospif(sgn * (float)k / (float)ns, &sn, &cs);
-            const float2 wb = make_float2(b.x * cs - b.y * sn, b.x * sn + b.y * cs);
-            const int o = (j / ns) * 2 * ns + k;
-            Y[w * RP + o] = make_float2(a.x + wb.x, a.y + wb.y);
-            Y[w * RP + o + ns] = make_float2(a.x - wb.x, a.y - wb.y);
+            Y[w * RP + 2 * j] = make_float2(a.x + b.x, a.y + b.y);
+            Y[w * RP + 2 * j + 1] = make_float2(a.x - b.x, a.y - b.y);
         }
         __syncthreads();
         float2 *t = X;
         X = Y;
         Y = t;
+    }
+    if constexpr (LOGR >= 2) {
+        constexpr int Q = R / 4;
+#pragma unroll 1
+        for (int lns = LOGR & 1; lns < LOGR; lns += 2) {  // span ns = 2^lns
+            const int ns = 1 << lns;
+            const int lstep = LOGR - 2 - lns;  // exp(dir 2 pi i k / (4 ns)) = rot(k << lstep)
+            for (int e = tid; e < W * Q; e += kDdThreads) {
+                const int w = e / Q, j = e % Q;
+                const int k = j & (ns - 1);
+                const float2 *x = X + w * RP;
+                float2 v0 = x[j], v1 = x[j + Q], v2 = x[j + 2 * Q], v3 = x[j + 3 * Q];
+                if (lns > 0) {
+                    const int t = k << lstep;
+                    const float2 w1 = rot(t), w2 = rot(2 * t), w3 = rot(3 * t);
+                    v1 = make_float2(v1.x * w1.x - v1.y * w1.y, v1.x * w1.y + v1.y * w1.x);
+                    v2 = make_float2(v2.x * w2.x - v2.y * w2.y, v2.x * w2.y + v2.y * w2.x);
+                    v3 = make_float2(v3.x * w3.x - v3.y * w3.y, v3.x * w3.y + v3.y * w3.x);
+                }
+                // 4-point DFT with exp(dir 2 pi i q r / 4) = (dir i)^(q r)
+                const float2 s02 = make_float2(v0.x + v2.x, v0.y + v2.y), d02 = make_float2(v0.x - v2.x, v0.y - v2.y);
+                const float2 s13 = make_float2(v1.x + v3.x, v1.y + v3.y), d13 = make_float2(v1.x - v3.x, v1.y - v3.y);
+                const float2 jd13 = make_float2(-sgn * d13.y, sgn * d13.x);  // (dir i) (v1 - v3)
+                float2 *y = Y + w * RP + ((j >> lns) << (lns + 2)) + k;
+                y[0] = make_float2(s02.x + s13.x, s02.y + s13.y);
+                y[ns] = make_float2(d02.x + jd13.x, d02.y + jd13.y);
+                y[2 * ns] = make_float2(s02.x - s13.x, s02.y - s13.y);
+                y[3 * ns] = make_float2(d02.x - jd13.x, d02.y - jd13.y);
+            }
+            __syncthreads();
+            float2 *t = X;
+            X = Y;
+            Y = t;
+        }
     }
 
     // store (forward: twiddle of output k = a last)
@@ -124,7 +180,7 @@ __global__ __launch_bounds__(kDdThreads) void dd_fft_kernel(const float2 *in, fl
         else { w = e % W; a = e / W; }
         float2 v = X[w * RP + a];
         if (twid && dir < 0) {
-            const int64_t bk = (colb(w) * a) % Bp;
+            const int64_t bk = colb(w) * a;  // < s R = Bp
             float sn, cs;
             sincospif(-2.0f * (float)((double)bk / (double)Bp), &sn, &cs);
             v = make_float2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
@@ -177,7 +233,7 @@ template <int LOGR>
 hipError_t dd_fft(const float2 *in, float2 *out, int npol, int64_t L, int64_t Bp, int dir, int twid,
                   hipStream_t st) {
     constexpr int R = 1 << LOGR, W = dd_w<LOGR>();
-    const size_t lds = sizeof(float2) * 2 * W * (R + 1);
+    const size_t lds = sizeof(float2) * (2 * W * (R + 1) + (dd_table<LOGR>() ? R : 0));
     static bool attr = false;  // per process: raise the dynamic LDS limit once
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)dd_fft_kernel<LOGR>,
