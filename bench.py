@@ -536,9 +536,10 @@ def bench_dedisperse(corr, torch, N, T, steps, warmup, dm=71.0, nu0=325e6, n_int
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     npass = math.ceil(math.log2(L) / 8)
-    # inverse DFT per spectrum, forward and inverse passes, chirp: read + write
-    # each; the detection reads once
-    nbytes = 2.0 * L * 8 * (2 * (1 + 2 * npass + 1) + 1)
+    # read + write each: the inverse DFT per spectrum, the forward passes but
+    # the last, the last forward pass fused with the chirp and the first
+    # inverse pass, the other inverse passes; the detection reads once
+    nbytes = 2.0 * L * 8 * (2 * (1 + (npass - 1) + 1 + (npass - 1)) + 1)
     sweep = 4.148808e15 * dm * (nu0 ** -2 - (nu0 + FS / 2) ** -2) * FS / 2
     del v, work, out
     torch.cuda.empty_cache()

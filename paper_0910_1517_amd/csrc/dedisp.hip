@@ -14,27 +14,33 @@
 // (K DM (nu0^-2 - (nu0 + fs/2)^-2) fs/2 samples) wraps around, so a caller
 // streams blocks that overlap by that much, as it does for the integer delays.
 //
-// One LDS kernel does all the transforms: W instances of an R-point DFT
-// (radix-4 Stockham stages in LDS, one radix-2 stage for odd log2 R, natural
-// order in and out, twiddles from an LDS table), loaded from and stored to
-// the instance's elements; a tile holds 4096 points.  The per-spectrum inverse DFT is
-// that kernel with R = C.  The long transform is a sequence of passes of a
+// One kernel does all the transforms: a workgroup of 256 threads takes W
+// instances of an R-point DFT (a tile of max(4096, R) points), each thread
+// 16 (32 at R = 8192) points in registers.  The DFT is a Stockham sequence of
+// radix-16 stages (a radix-2/4/8 stage first when log2 R is not a multiple of
+// 4), each an in-register DFT after a twiddle; stages exchange points through
+// one LDS buffer (one pad per 16 points), the first reads global memory and
+// the last writes it.  The per-spectrum inverse DFT is that kernel with
+// R = C.  The long transform is a sequence of passes of a
 // decimation-in-frequency decomposition: pass j splits blocks of Bp samples
 // into R_j strided sub-sequences (stride s = Bp / R_j), takes their R_j-point
 // DFTs and multiplies output k of column b by exp(-2 pi i b k / Bp).  A small
 // radix goes first and then radix 256, so the stride is either >= the tile
 // width (a tile is 4096 / R adjacent columns: rows of at least 128 bytes) or
-// 1 (a tile is contiguous).  The result is in digit-reversed order; the chirp kernel maps
-// each position to its frequency, and the inverse passes (the mirror image:
-// conjugate twiddle, then the inverse DFT, in reverse order) restore time
-// order.  All passes run in place: a workgroup reads its whole tile into LDS
-// before it writes it back.
+// 1 (a tile is contiguous).  The result is in digit-reversed order.  The last
+// forward pass (blocks of 256, contiguous) also multiplies each position by
+// the transfer function at its frequency and takes the inverse DFT of the
+// same tile; the remaining inverse passes (the mirror image: conjugate
+// twiddle, then the inverse DFT, in reverse order) restore time order.  All
+// passes run in place: a workgroup reads its whole tile before it writes it
+// back.
 
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <type_traits>
 
 #include "corr_internal.h"
 
@@ -49,219 +55,389 @@ struct DdPasses {
     int lr[kDdMaxPasses];      // log2 radix of each pass, in forward order
 };
 
-// Instances per workgroup: a 4096-point tile up to R = 4096, one instance
-// above.  (Every pass with R < 4096 has stride 1 or >= 4096 / R.)
+// Shape of one R-point transform kernel: a tile of max(4096, R) points
+// (W instances), 256 threads, NPT points per thread in registers.  Stages:
+// radix 2^LREM first when log2 R is not a multiple of 4, then radix 16.
 template <int LOGR>
-constexpr int dd_w() { return LOGR >= 12 ? 1 : (1 << (12 - LOGR)); }
-// R <= 4096: twiddles exp(dir 2 pi i t / R), t < R, from an LDS table
-template <int LOGR>
-constexpr bool dd_table() { return LOGR <= 12; }
+struct DdShape {
+    static constexpr int R = 1 << LOGR;
+    static constexpr int TILE = R > 4096 ? R : 4096;
+    static constexpr int W = TILE / R;
+    static constexpr int NPT = TILE / kDdThreads;
+    static constexpr int LREM = LOGR % 4;
+    static constexpr int NST = LOGR / 4 + (LREM ? 1 : 0);
+    static constexpr int RP = R + R / 16 + 1;  // LDS row pitch (float2): one pad per 16, plus one
+    static constexpr size_t lds_bytes = NST > 1 ? sizeof(float2) * W * RP : 0;
+};
 
-// W instances of an R-point DFT.  Instance i = tile * W + w covers block
-// beta = i / s, column b = i mod s; its point a is element beta Bp + a s + b.
-// dir = -1: forward (exp(-2 pi i ...)), +1: inverse (exp(+...), unscaled).
-// twid: forward, multiply output k by exp(-2 pi i b k / Bp) after the DFT;
-// inverse, multiply input k by exp(+2 pi i b k / Bp) before it.
-template <int LOGR>
-__global__ __launch_bounds__(kDdThreads) void dd_fft_kernel(const float2 *in, float2 *out, int64_t L, int64_t Bp,
-                                                            int dir, int twid) {
-    constexpr int R = 1 << LOGR, W = dd_w<LOGR>(), RP = R + 1;
-    extern __shared__ float2 dd_lds[];
-    float2 *A = dd_lds, *B = dd_lds + W * RP, *tw = dd_lds + 2 * W * RP;
-    const int tid = threadIdx.x;
-    const int64_t s = Bp >> LOGR;
-    const int64_t tile = blockIdx.x;
-    const int64_t pol_off = (int64_t)blockIdx.y * L;
-    const float2 *src = in + pol_off;
-    float2 *dst = out + pol_off;
-    const float sgn = (float)dir;
+// radix and log2 span (ns = 2^LNS: product of the earlier radices) of stage ST
+template <int LOGR, int ST>
+struct DdStage {
+    static constexpr int LREM = DdShape<LOGR>::LREM;
+    static constexpr int LP = (ST == 0 && LREM) ? LREM : 4;
+    static constexpr int P = 1 << LP;
+    static constexpr int LNS = ST == 0 ? 0 : (LREM ? LREM : 4) + 4 * (ST - 1);
+    static constexpr int Q = (1 << LOGR) / P;  // butterflies per instance
+    static constexpr int NB = DdShape<LOGR>::NPT / P;  // butterflies per thread
+};
 
-    // element (w, a) of the tile <-> global index.  With s > 1, W divides s
-    // (both powers of two, s >= W), so the tile's W instances are adjacent
-    // columns b0 + w of one block beta.
-    const int64_t i0 = tile * W;
-    const int64_t beta = s == 1 ? 0 : i0 / s, b0 = s == 1 ? 0 : i0 - beta * s;
-    const int64_t base = s == 1 ? i0 * R : beta * Bp + b0;
-    auto gidx = [&](int w, int a) -> int64_t {
-        return s == 1 ? base + (int64_t)w * R + a : base + (int64_t)a * s + w;
-    };
-    auto colb = [&](int w) -> int64_t { return s == 1 ? 0 : b0 + w; };
-    // exp(dir 2 pi i t / R)
-    auto rot = [&](int t) -> float2 {
-        if constexpr (dd_table<LOGR>()) {
-            return tw[t & (R - 1)];
-        } else {
-            float sn, cs;
-            sincospif(sgn * 2.0f * (float)(t & (R - 1)) / (float)R, &sn, &cs);
-            return make_float2(cs, sn);
-        }
-    };
-    if constexpr (dd_table<LOGR>()) {
-        for (int t = tid; t < R; t += kDdThreads) {
-            float sn, cs;
-            sincospif(sgn * 2.0f * (float)t / (float)R, &sn, &cs);
-            tw[t] = make_float2(cs, sn);
-        }
-    }
+__device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// (SG i) a
+template <int SG>
+__device__ inline float2 cjmul(float2 a) { return SG > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x); }
+__device__ inline float2 cis_turns(float t) {  // exp(2 pi i t)
+    float sn, cs;
+    sincospif(2.0f * t, &sn, &cs);
+    return make_float2(cs, sn);
+}
 
-    // load (coalesced: s == 1 -> contiguous, else rows of W adjacent columns)
-    for (int e = tid; e < W * R; e += kDdThreads) {
-        int w, a;
-        if (s == 1) { w = e >> LOGR; a = e & (R - 1); }
-        else { w = e % W; a = e / W; }
-        float2 v = src[gidx(w, a)];
-        if (twid && dir > 0) {  // inverse: conjugate twiddle of input k = a first
-            const int64_t bk = colb(w) * a;  // < s R = Bp
-            float sn, cs;
-            sincospif(2.0f * (float)((double)bk / (double)Bp), &sn, &cs);
-            v = make_float2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+// In-register P-point DFT, X_r = sum_q x_q exp(SG 2 pi i q r / P), natural
+// order in and out.  P = 8 and 16 are 2 x 4 and 4 x 4 (index n = n1 + m n2,
+// k = k2 + 4 k1, inner twiddle exp(SG 2 pi i n1 k2 / P)).
+template <int SG>
+__device__ inline void dft4(float2 &x0, float2 &x1, float2 &x2, float2 &x3) {
+    const float2 s02 = cadd(x0, x2), d02 = csub(x0, x2), s13 = cadd(x1, x3), j13 = cjmul<SG>(csub(x1, x3));
+    x0 = cadd(s02, s13);
+    x1 = cadd(d02, j13);
+    x2 = csub(s02, s13);
+    x3 = csub(d02, j13);
+}
+template <int P, int SG>
+__device__ inline void dft(float2 *x) {
+    if constexpr (P == 2) {
+        const float2 a = x[0], b = x[1];
+        x[0] = cadd(a, b);
+        x[1] = csub(a, b);
+    } else if constexpr (P == 4) {
+        dft4<SG>(x[0], x[1], x[2], x[3]);
+    } else if constexpr (P == 8) {
+        constexpr float h = 0.70710678118654752f;  // cos(pi/4)
+        dft4<SG>(x[0], x[2], x[4], x[6]);
+        dft4<SG>(x[1], x[3], x[5], x[7]);
+        // y1[k2] *= exp(SG 2 pi i k2 / 8)
+        x[3] = cmul(x[3], make_float2(h, SG * h));
+        x[5] = cjmul<SG>(x[5]);
+        x[7] = cmul(x[7], make_float2(-h, SG * h));
+        float2 y[8];
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            y[k2] = cadd(x[2 * k2], x[2 * k2 + 1]);
+            y[k2 + 4] = csub(x[2 * k2], x[2 * k2 + 1]);
         }
-        A[w * RP + a] = v;
-    }
-    __syncthreads();
-
-    // Stockham stages (natural order in and out): one radix-2 stage when
-    // log2 R is odd, then radix 4.  A radix-P stage with span ns reads
-    // v_q = in[j + q R/P] (j < R/P), rotates v_q by exp(dir 2 pi i q k / (P ns)),
-    // k = j mod ns, takes the P-point DFT V_r and writes
-    // out[(j / ns) P ns + k + r ns] = V_r.
-    float2 *X = A, *Y = B;
-    if constexpr (LOGR & 1) {
-        for (int e = tid; e < W * (R / 2); e += kDdThreads) {
-            const int w = e / (R / 2), j = e % (R / 2);
-            const float2 a = X[w * RP + j], b = X[w * RP + j + R / 2];
-            Y[w * RP + 2 * j] = make_float2(a.x + b.x, a.y + b.y);
-            Y[w * RP + 2 * j + 1] = make_float2(a.x - b.x, a.y - b.y);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = y[k];
+    } else {
+        static_assert(P == 16, "radix 2, 4, 8 or 16");
+        constexpr float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
+        // y_{n1}[k2] = DFT4 over n2 of x[n1 + 4 n2], held in x[n1 + 4 k2]
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) dft4<SG>(x[n1], x[n1 + 4], x[n1 + 8], x[n1 + 12]);
+        // twiddles exp(SG 2 pi i m / 16), m = n1 k2
+        x[5] = cmul(x[5], make_float2(c1, SG * s1));     // m = 1
+        x[9] = cmul(x[9], make_float2(h, SG * h));       // 2
+        x[13] = cmul(x[13], make_float2(s1, SG * c1));   // 3
+        x[6] = cmul(x[6], make_float2(h, SG * h));       // 2
+        x[10] = cjmul<SG>(x[10]);                        // 4
+        x[14] = cmul(x[14], make_float2(-h, SG * h));    // 6
+        x[7] = cmul(x[7], make_float2(s1, SG * c1));     // 3
+        x[11] = cmul(x[11], make_float2(-h, SG * h));    // 6
+        x[15] = cmul(x[15], make_float2(-c1, -SG * s1)); // 9
+        // X[k2 + 4 k1] = DFT4 over n1 of x[n1 + 4 k2]
+        float2 y[16];
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            float2 a = x[4 * k2], b = x[4 * k2 + 1], c = x[4 * k2 + 2], d = x[4 * k2 + 3];
+            dft4<SG>(a, b, c, d);
+            y[k2] = a;
+            y[k2 + 4] = b;
+            y[k2 + 8] = c;
+            y[k2 + 12] = d;
         }
-        __syncthreads();
-        float2 *t = X;
-        X = Y;
-        Y = t;
-    }
-    if constexpr (LOGR >= 2) {
-        constexpr int Q = R / 4;
-#pragma unroll 1
-        for (int lns = LOGR & 1; lns < LOGR; lns += 2) {  // span ns = 2^lns
-            const int ns = 1 << lns;
-            const int lstep = LOGR - 2 - lns;  // exp(dir 2 pi i k / (4 ns)) = rot(k << lstep)
-            for (int e = tid; e < W * Q; e += kDdThreads) {
-                const int w = e / Q, j = e % Q;
-                const int k = j & (ns - 1);
-                const float2 *x = X + w * RP;
-                float2 v0 = x[j], v1 = x[j + Q], v2 = x[j + 2 * Q], v3 = x[j + 3 * Q];
-                if (lns > 0) {
-                    const int t = k << lstep;
-                    const float2 w1 = rot(t), w2 = rot(2 * t), w3 = rot(3 * t);
-                    v1 = make_float2(v1.x * w1.x - v1.y * w1.y, v1.x * w1.y + v1.y * w1.x);
-                    v2 = make_float2(v2.x * w2.x - v2.y * w2.y, v2.x * w2.y + v2.y * w2.x);
-                    v3 = make_float2(v3.x * w3.x - v3.y * w3.y, v3.x * w3.y + v3.y * w3.x);
-                }
-                // 4-point DFT with exp(dir 2 pi i q r / 4) = (dir i)^(q r)
-                const float2 s02 = make_float2(v0.x + v2.x, v0.y + v2.y), d02 = make_float2(v0.x - v2.x, v0.y - v2.y);
-                const float2 s13 = make_float2(v1.x + v3.x, v1.y + v3.y), d13 = make_float2(v1.x - v3.x, v1.y - v3.y);
-                const float2 jd13 = make_float2(-sgn * d13.y, sgn * d13.x);  // (dir i) (v1 - v3)
-                float2 *y = Y + w * RP + ((j >> lns) << (lns + 2)) + k;
-                y[0] = make_float2(s02.x + s13.x, s02.y + s13.y);
-                y[ns] = make_float2(d02.x + jd13.x, d02.y + jd13.y);
-                y[2 * ns] = make_float2(s02.x - s13.x, s02.y - s13.y);
-                y[3 * ns] = make_float2(d02.x - jd13.x, d02.y - jd13.y);
-            }
-            __syncthreads();
-            float2 *t = X;
-            X = Y;
-            Y = t;
-        }
-    }
-
-    // store (forward: twiddle of output k = a last)
-    for (int e = tid; e < W * R; e += kDdThreads) {
-        int w, a;
-        if (s == 1) { w = e >> LOGR; a = e & (R - 1); }
-        else { w = e % W; a = e / W; }
-        float2 v = X[w * RP + a];
-        if (twid && dir < 0) {
-            const int64_t bk = colb(w) * a;  // < s R = Bp
-            float sn, cs;
-            sincospif(-2.0f * (float)((double)bk / (double)Bp), &sn, &cs);
-            v = make_float2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
-        }
-        dst[gidx(w, a)] = v;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) x[k] = y[k];
     }
 }
 
-// Inverse dispersion transfer function at every position of the forward
-// transform's digit-reversed order, with the 1/L of the inverse transform.
-__global__ __launch_bounds__(256) void dd_chirp_kernel(float2 *z, int64_t L, int lgL, DdPasses ps, double df,
-                                                       double nu0, double kdm) {
-    const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (P >= L) return;
-    // position -> frequency index: digits of the passes, first pass least significant
+// LDS position of point a of instance w: one pad per 16 points
+__device__ inline int dd_pad(int w, int a, int rp) { return w * rp + a + (a >> 4); }
+
+// The inverse dispersion transfer function with the 1/L of the inverse
+// transform, at frequency index k (f = k df).  Position P of the forward
+// transform's digit-reversed order holds frequency index: the digits of the
+// passes, the first pass's least significant.
+struct DdChirp {
+    DdPasses ps;
+    int lgL;
+    double df, nu0, kdm_nu0sq;  // kdm_nu0sq = K DM / nu0^2
+    float inv_l;
+};
+__device__ inline int64_t dd_freq_index(const DdChirp &c, int64_t P) {
     int64_t k = 0, rem = P;
-    int sh = lgL, mult = 0;
-    for (int j = 0; j < ps.n; ++j) {
-        sh -= ps.lr[j];
+    int sh = c.lgL, mult = 0;
+    for (int j = 0; j < c.ps.n; ++j) {
+        sh -= c.ps.lr[j];
         const int64_t digit = rem >> sh;
         rem &= ((int64_t)1 << sh) - 1;
         k += digit << mult;
-        mult += ps.lr[j];
+        mult += c.ps.lr[j];
     }
-    const double f = (double)k * df;
-    double c = kdm * f * f / (nu0 * nu0 * (nu0 + f));
-    c -= floor(c);
-    float sn, cs;
-    sincospif(-2.0f * (float)c, &sn, &cs);
-    const float inv = 1.0f / (float)L;
-    const int64_t off = (int64_t)blockIdx.y * L + P;
-    const float2 v = z[off];
-    z[off] = make_float2(inv * (v.x * cs - v.y * sn), inv * (v.x * sn + v.y * cs));
+    return k;
+}
+__device__ inline float2 dd_chirp_at(const DdChirp &c, int64_t k) {
+    const double f = (double)k * c.df;
+    double ph = c.kdm_nu0sq * f * f / (c.nu0 + f);
+    ph -= floor(ph);
+    const float2 e = cis_turns(-(float)ph);
+    return make_float2(c.inv_l * e.x, c.inv_l * e.y);
+}
+
+// One thread's butterflies in a stage: butterfly i is b = tid + 256 i, at
+// instance w, index j < Q.  Contiguous instances (s == 1) put j fastest
+// across the lanes, strided ones put w (adjacent columns) fastest, so that
+// the global loads and stores of the first and last stages are coalesced.
+template <int LOGR, int ST>
+__device__ inline void dd_bf(int i, bool contig, int &w, int &j) {
+    using S = DdStage<LOGR, ST>;
+    const int b = threadIdx.x + kDdThreads * i;
+    if (contig) {
+        w = b / S::Q;
+        j = b % S::Q;
+    } else {
+        w = b % DdShape<LOGR>::W;
+        j = b / DdShape<LOGR>::W;
+    }
+}
+
+// stage ST on registers: twiddle exp(SG 2 pi i q k / (P ns)), k = j mod ns, then the P-point DFT
+template <int LOGR, int ST, int SG>
+__device__ inline void dd_stage(float2 *v, bool contig) {
+    using S = DdStage<LOGR, ST>;
+#pragma unroll
+    for (int i = 0; i < S::NB; ++i) {
+        float2 *x = v + i * S::P;
+        if constexpr (S::LNS > 0) {
+            static_assert(S::P == 16, "twiddled stages are radix 16");
+            int w, j;
+            dd_bf<LOGR, ST>(i, contig, w, j);
+            const int k = j & ((1 << S::LNS) - 1);
+            const float t = (float)(SG * k) * (1.0f / (float)(16 << S::LNS));  // exact
+            const float2 w1 = cis_turns(t), w4 = cis_turns(4.0f * t);
+            const float2 w2 = cmul(w1, w1), w3 = cmul(w2, w1), w8 = cmul(w4, w4), w12 = cmul(w8, w4);
+            const float2 lo[4] = {make_float2(1.f, 0.f), w1, w2, w3};
+            const float2 hi[4] = {make_float2(1.f, 0.f), w4, w8, w12};
+#pragma unroll
+            for (int q = 1; q < 16; ++q) {
+                const float2 tw = (q & 3) == 0 ? hi[q >> 2] : (q >> 2) == 0 ? lo[q & 3] : cmul(hi[q >> 2], lo[q & 3]);
+                x[q] = cmul(x[q], tw);
+            }
+        }
+        dft<S::P, SG>(x);
+    }
+}
+
+template <int LOGR, int ST>
+__device__ inline void dd_read_lds(float2 *v, const float2 *X, bool contig) {
+    using S = DdStage<LOGR, ST>;
+#pragma unroll
+    for (int i = 0; i < S::NB; ++i) {
+        int w, j;
+        dd_bf<LOGR, ST>(i, contig, w, j);
+#pragma unroll
+        for (int q = 0; q < S::P; ++q) v[i * S::P + q] = X[dd_pad(w, j + q * S::Q, DdShape<LOGR>::RP)];
+    }
+}
+
+// Stockham write: output r of butterfly (w, j) goes to (j / ns) P ns + k + r ns
+template <int LOGR, int ST>
+__device__ inline void dd_write_lds(const float2 *v, float2 *X, bool contig) {
+    using S = DdStage<LOGR, ST>;
+#pragma unroll
+    for (int i = 0; i < S::NB; ++i) {
+        int w, j;
+        dd_bf<LOGR, ST>(i, contig, w, j);
+        const int o = ((j >> S::LNS) << (S::LNS + S::LP)) + (j & ((1 << S::LNS) - 1));
+#pragma unroll
+        for (int r = 0; r < S::P; ++r) X[dd_pad(w, o + (r << S::LNS), DdShape<LOGR>::RP)] = v[i * S::P + r];
+    }
+}
+
+// exp(SG 2 pi i (base + r m) / Bp) for r < P, with base, m integers: three
+// sincos and products (at most two per factor)
+template <int P, int SG>
+__device__ inline void dd_ramp(int64_t base, int64_t m, int64_t Bp, float inv_bp, float2 *t) {
+    const int64_t msk = Bp - 1;
+    const float2 u = cis_turns((float)SG * (float)(base & msk) * inv_bp);
+    const float2 m1 = cis_turns((float)SG * (float)(m & msk) * inv_bp);
+    const float2 m4 = cis_turns((float)SG * (float)((4 * m) & msk) * inv_bp);
+    const float2 m2 = cmul(m1, m1), m3 = cmul(m2, m1), m8 = cmul(m4, m4), m12 = cmul(m8, m4);
+    const float2 lo[4] = {u, cmul(u, m1), cmul(u, m2), cmul(u, m3)};
+    const float2 hi[4] = {make_float2(1.f, 0.f), m4, m8, m12};
+#pragma unroll
+    for (int r = 0; r < P; ++r) t[r] = (r >> 2) == 0 ? lo[r & 3] : cmul(hi[r >> 2], lo[r & 3]);
+}
+
+// W instances of an R-point DFT per workgroup.  Instance i = tile W + w
+// covers block beta = i / s, column b = i mod s (s = Bp / R); its point a is
+// element beta Bp + a s + b.
+// MODE 0, forward (exp(-2 pi i ...)): the DFT, then output k of column b
+//   times exp(-2 pi i b k / Bp).
+// MODE 1, inverse (exp(+...), unscaled): input k times exp(+2 pi i b k / Bp),
+//   then the DFT.
+// MODE 2 (R = Bp = 256): the forward DFT, the dispersion chirp and 1/L at the
+//   forward transform's position, then the inverse DFT, on one tile.
+template <int LOGR, int MODE>
+__global__ __launch_bounds__(kDdThreads) void dd_fft_kernel(const float2 *in, float2 *out, int64_t L, int64_t Bp,
+                                                            DdChirp ch) {
+    using Sh = DdShape<LOGR>;
+    constexpr int R = Sh::R, W = Sh::W, NST = Sh::NST, LAST = NST - 1;
+    using S0 = DdStage<LOGR, 0>;
+    using SL = DdStage<LOGR, LAST>;
+    static_assert(MODE != 2 || (LOGR == 8 && S0::P == SL::P), "fused pass: radix 16 x 16");
+    constexpr int SG0 = MODE == 1 ? 1 : -1;
+    extern __shared__ float2 dd_lds[];
+    const int64_t s = Bp >> LOGR;
+    const bool contig = s == 1;
+    const int64_t i0 = (int64_t)blockIdx.x * W;
+    const int64_t beta = contig ? 0 : i0 / s, b0 = contig ? 0 : i0 - beta * s;
+    const int64_t base = contig ? i0 * R : beta * Bp + b0;
+    const int64_t pol_off = (int64_t)blockIdx.y * L;
+    const float2 *src = in + pol_off;
+    float2 *dst = out + pol_off;
+    const float inv_bp = 1.0f / (float)Bp;  // Bp is a power of two
+    auto gidx = [&](int w, int a) -> int64_t {
+        return contig ? base + (int64_t)w * R + a : base + (int64_t)a * s + w;
+    };
+
+    float2 v[Sh::NPT];
+    // stage 0 inputs from global memory (inverse: the conjugate pass twiddle)
+#pragma unroll
+    for (int i = 0; i < S0::NB; ++i) {
+        int w, j;
+        dd_bf<LOGR, 0>(i, contig, w, j);
+#pragma unroll
+        for (int q = 0; q < S0::P; ++q) v[i * S0::P + q] = src[gidx(w, j + q * S0::Q)];
+        if (MODE == 1 && !contig) {
+            float2 t[S0::P];
+            dd_ramp<S0::P, 1>((b0 + w) * j, (b0 + w) * S0::Q, Bp, inv_bp, t);
+#pragma unroll
+            for (int q = 0; q < S0::P; ++q) v[i * S0::P + q] = cmul(v[i * S0::P + q], t[q]);
+        }
+    }
+    auto run = [&](auto sg_tag) {
+        constexpr int SG = decltype(sg_tag)::value;
+        dd_stage<LOGR, 0, SG>(v, contig);
+        if constexpr (NST > 1) {
+            dd_write_lds<LOGR, 0>(v, dd_lds, contig);
+            __syncthreads();
+            if constexpr (NST > 2) {
+                dd_read_lds<LOGR, 1>(v, dd_lds, contig);
+                dd_stage<LOGR, 1, SG>(v, contig);
+                __syncthreads();
+                dd_write_lds<LOGR, 1>(v, dd_lds, contig);
+                __syncthreads();
+            }
+            if constexpr (NST > 3) {
+                dd_read_lds<LOGR, 2>(v, dd_lds, contig);
+                dd_stage<LOGR, 2, SG>(v, contig);
+                __syncthreads();
+                dd_write_lds<LOGR, 2>(v, dd_lds, contig);
+                __syncthreads();
+            }
+            static_assert(NST <= 4, "at most four stages (R <= 2^13)");
+            dd_read_lds<LOGR, LAST>(v, dd_lds, contig);
+            dd_stage<LOGR, LAST, SG>(v, contig);
+        }
+    };
+    run(std::integral_constant<int, SG0>{});
+    if constexpr (MODE == 2) {
+        // chirp at the forward transform's positions (this pass's digit, the
+        // point index within the instance, is the frequency index's most
+        // significant), then the inverse on the same registers
+#pragma unroll
+        for (int i = 0; i < SL::NB; ++i) {
+            int w, j;
+            dd_bf<LOGR, LAST>(i, contig, w, j);
+            const int64_t k0 = dd_freq_index(ch, gidx(w, 0));
+#pragma unroll
+            for (int r = 0; r < SL::P; ++r)
+                v[i * SL::P + r] =
+                    cmul(v[i * SL::P + r], dd_chirp_at(ch, k0 + ((int64_t)(j + r * SL::Q) << (ch.lgL - LOGR))));
+        }
+        __syncthreads();  // the forward's last LDS reads are done
+        run(std::integral_constant<int, 1>{});
+    }
+    // last stage outputs to global memory (forward: the pass twiddle)
+#pragma unroll
+    for (int i = 0; i < SL::NB; ++i) {
+        int w, j;
+        dd_bf<LOGR, LAST>(i, contig, w, j);
+        if (MODE == 0 && !contig) {
+            float2 t[SL::P];
+            dd_ramp<SL::P, -1>((b0 + w) * j, (b0 + w) * SL::Q, Bp, inv_bp, t);
+#pragma unroll
+            for (int r = 0; r < SL::P; ++r) v[i * SL::P + r] = cmul(v[i * SL::P + r], t[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < SL::P; ++r) dst[gidx(w, j + r * SL::Q)] = v[i * SL::P + r];
+    }
 }
 
 // I[j] = sum over polarisations and the n_int samples of bin j of |z|^2.
-__global__ __launch_bounds__(256) void dd_detect_kernel(const float2 *z, int npol, int64_t L, int n_int,
+// G = min(n_int, 64) adjacent lanes share a bin (lane l sums samples l, l + G,
+// ...), so a wave reads 64 consecutive samples at a time, then a butterfly
+// reduction over the G lanes.
+__global__ __launch_bounds__(256) void dd_detect_kernel(const float2 *z, int npol, int64_t L, int n_int, int lg_g,
                                                         float *out) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= L / n_int) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int G = 1 << lg_g;
+    const int64_t j = t >> lg_g;
+    const int l = (int)(t & (G - 1));
+    const bool live = j < L / n_int;
     float acc = 0.f;
-    for (int p = 0; p < npol; ++p) {
-        const float2 *r = z + (int64_t)p * L + j * n_int;
-        for (int i = 0; i < n_int; ++i) acc += r[i].x * r[i].x + r[i].y * r[i].y;
+    if (live) {
+        for (int p = 0; p < npol; ++p) {
+            const float2 *r = z + (int64_t)p * L + j * n_int;
+            for (int i = l; i < n_int; i += G) acc += r[i].x * r[i].x + r[i].y * r[i].y;
+        }
     }
-    out[j] = acc;
+    for (int m = G >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    if (live && l == 0) out[j] = acc;
 }
 
-template <int LOGR>
-hipError_t dd_fft(const float2 *in, float2 *out, int npol, int64_t L, int64_t Bp, int dir, int twid,
-                  hipStream_t st) {
-    constexpr int R = 1 << LOGR, W = dd_w<LOGR>();
-    const size_t lds = sizeof(float2) * (2 * W * (R + 1) + (dd_table<LOGR>() ? R : 0));
+template <int LOGR, int MODE>
+hipError_t dd_fft(const float2 *in, float2 *out, int npol, int64_t L, int64_t Bp, const DdChirp &ch, hipStream_t st) {
+    using Sh = DdShape<LOGR>;
     static bool attr = false;  // per process: raise the dynamic LDS limit once
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)dd_fft_kernel<LOGR>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (!attr && Sh::lds_bytes > 0) {
+        hipError_t e = hipFuncSetAttribute((const void *)dd_fft_kernel<LOGR, MODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)Sh::lds_bytes);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const dim3 grid((unsigned)(L / ((int64_t)R * W)), (unsigned)npol);
-    hipLaunchKernelGGL(dd_fft_kernel<LOGR>, grid, dim3(kDdThreads), lds, st, in, out, L, Bp, dir, twid);
+    const dim3 grid((unsigned)(L / Sh::TILE), (unsigned)npol);
+    hipLaunchKernelGGL((dd_fft_kernel<LOGR, MODE>), grid, dim3(kDdThreads), Sh::lds_bytes, st, in, out, L, Bp, ch);
     return hipGetLastError();
 }
 
-hipError_t dd_fft_any(int lr, const float2 *in, float2 *out, int npol, int64_t L, int64_t Bp, int dir, int twid,
-                      hipStream_t st) {
+template <int MODE>
+hipError_t dd_fft_mode(int lr, const float2 *in, float2 *out, int npol, int64_t L, int64_t Bp, const DdChirp &ch,
+                       hipStream_t st) {
     switch (lr) {
-    case 1: return dd_fft<1>(in, out, npol, L, Bp, dir, twid, st);
-    case 2: return dd_fft<2>(in, out, npol, L, Bp, dir, twid, st);
-    case 3: return dd_fft<3>(in, out, npol, L, Bp, dir, twid, st);
-    case 4: return dd_fft<4>(in, out, npol, L, Bp, dir, twid, st);
-    case 5: return dd_fft<5>(in, out, npol, L, Bp, dir, twid, st);
-    case 6: return dd_fft<6>(in, out, npol, L, Bp, dir, twid, st);
-    case 7: return dd_fft<7>(in, out, npol, L, Bp, dir, twid, st);
-    case 8: return dd_fft<8>(in, out, npol, L, Bp, dir, twid, st);
-    case 9: return dd_fft<9>(in, out, npol, L, Bp, dir, twid, st);
-    case 10: return dd_fft<10>(in, out, npol, L, Bp, dir, twid, st);
-    case 11: return dd_fft<11>(in, out, npol, L, Bp, dir, twid, st);
-    case 12: return dd_fft<12>(in, out, npol, L, Bp, dir, twid, st);
-    case 13: return dd_fft<13>(in, out, npol, L, Bp, dir, twid, st);
+    case 1: return dd_fft<1, MODE>(in, out, npol, L, Bp, ch, st);
+    case 2: return dd_fft<2, MODE>(in, out, npol, L, Bp, ch, st);
+    case 3: return dd_fft<3, MODE>(in, out, npol, L, Bp, ch, st);
+    case 4: return dd_fft<4, MODE>(in, out, npol, L, Bp, ch, st);
+    case 5: return dd_fft<5, MODE>(in, out, npol, L, Bp, ch, st);
+    case 6: return dd_fft<6, MODE>(in, out, npol, L, Bp, ch, st);
+    case 7: return dd_fft<7, MODE>(in, out, npol, L, Bp, ch, st);
+    case 8: return dd_fft<8, MODE>(in, out, npol, L, Bp, ch, st);
+    case 9: return dd_fft<9, MODE>(in, out, npol, L, Bp, ch, st);
+    case 10: return dd_fft<10, MODE>(in, out, npol, L, Bp, ch, st);
+    case 11: return dd_fft<11, MODE>(in, out, npol, L, Bp, ch, st);
+    case 12: return dd_fft<12, MODE>(in, out, npol, L, Bp, ch, st);
+    case 13: return dd_fft<13, MODE>(in, out, npol, L, Bp, ch, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -313,32 +489,36 @@ corr_status corr_dedisperse(const float *d_v, int32_t npol, int64_t T, int32_t C
     const float2 *v = reinterpret_cast<const float2 *>(d_v);
     float2 *z = reinterpret_cast<float2 *>(d_work);
     // 1. broadband series: inverse C-point DFT of every spectrum
-    hipError_t e = dd_fft_any(ilog2(C), v, z, npol, L, C, +1, 0, st);
-    // 2. forward transform over the block: a small radix first, then radix 256
     const int lgL = ilog2(L);
-    DdPasses ps{};
-    if (lgL % 8) ps.lr[ps.n++] = lgL % 8;
-    for (int i = 0; i < lgL / 8; ++i) ps.lr[ps.n++] = 8;
+    DdChirp ch{};
+    if (lgL % 8) ch.ps.lr[ch.ps.n++] = lgL % 8;
+    for (int i = 0; i < lgL / 8; ++i) ch.ps.lr[ch.ps.n++] = 8;
+    ch.lgL = lgL;
+    ch.df = sample_rate / (2.0 * (double)L);
+    ch.nu0 = nu0;
+    ch.kdm_nu0sq = kDmConst * dm / (nu0 * nu0);
+    ch.inv_l = 1.0f / (float)L;
+    hipError_t e = dd_fft_mode<1>(ilog2(C), v, z, npol, L, C, ch, st);
+    // 2. forward transform over the block: a small radix first, then radix
+    // 256; the last pass (blocks of 256) also applies the inverse dispersion
+    // transfer function and starts the inverse transform: 3. the inverse
+    // passes, in reverse order
+    const DdPasses &ps = ch.ps;
     int64_t Bp = L;
     int64_t bps[kDdMaxPasses];
-    for (int j = 0; j < ps.n && e == hipSuccess; ++j) {
+    for (int j = 0; j < ps.n - 1 && e == hipSuccess; ++j) {
         bps[j] = Bp;
-        e = dd_fft_any(ps.lr[j], z, z, npol, L, Bp, -1, 1, st);
+        e = dd_fft_mode<0>(ps.lr[j], z, z, npol, L, Bp, ch, st);
         Bp >>= ps.lr[j];
     }
-    // 3. inverse dispersion transfer function (and 1/L)
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(dd_chirp_kernel, dim3((unsigned)((L + 255) / 256), (unsigned)npol), dim3(256), 0, st, z, L,
-                           lgL, ps, sample_rate / (2.0 * (double)L), nu0, kDmConst * dm);
-        e = hipGetLastError();
-    }
-    // 4. inverse transform, passes in reverse order
-    for (int j = ps.n - 1; j >= 0 && e == hipSuccess; --j) e = dd_fft_any(ps.lr[j], z, z, npol, L, bps[j], +1, 1, st);
+    if (e == hipSuccess) e = dd_fft<8, 2>(z, z, npol, L, Bp, ch, st);  // Bp == 256 here
+    for (int j = ps.n - 2; j >= 0 && e == hipSuccess; --j) e = dd_fft_mode<1>(ps.lr[j], z, z, npol, L, bps[j], ch, st);
     // 5. detection, both polarisations, n_int samples per output
     if (e == hipSuccess) {
-        const int64_t nout = L / n_int;
-        hipLaunchKernelGGL(dd_detect_kernel, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, st, z, npol, L, n_int,
-                           d_out);
+        const int lg_g = ilog2(n_int < 64 ? n_int : 64);
+        const int64_t nthr = (L / n_int) << lg_g;
+        hipLaunchKernelGGL(dd_detect_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st, z, npol, L, n_int,
+                           lg_g, d_out);
         e = hipGetLastError();
     }
     return e == hipSuccess ? CORR_OK : dd_fail(CORR_ERR_DEVICE, "dedispersion launch: %s", hipGetErrorString(e));
