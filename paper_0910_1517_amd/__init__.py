@@ -204,6 +204,55 @@ def _ptr(t) -> int | None:
     return t.data_ptr()
 
 
+def _avail(t, rows: bool = False) -> int:
+    """Bytes a call may use from t.data_ptr(): the tensor's own extent (a 2-D
+    array of rows: up to the last row's end rounded to a 16-byte chunk),
+    never past the end of its storage."""
+    el = t.element_size()
+    store = t.untyped_storage().nbytes() - t.storage_offset() * el
+    if rows and t.dim() == 2 and t.shape[0] > 0:
+        view = (t.shape[0] - 1) * t.stride(0) * el + (t.shape[1] * el + 15) // 16 * 16
+    else:
+        view = t.numel() * el
+    return min(store, view)
+
+
+def _need(t, name: str, nbytes: int, dtype=None, *, optional: bool = False, rows: bool = False):
+    """Check a caller buffer before its raw pointer crosses the C-ABI (which
+    cannot see sizes): a device tensor, of dtype when given (a dtype or a
+    tuple of them), dense -- contiguous, or with rows=True a 2-D array of rows
+    with unit stride along a row (or a contiguous flat buffer that the call's
+    row stride divides into rows) -- and with at least nbytes addressable
+    from its data pointer.  None passes when optional."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError("%s is required" % name)
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("%s must be a device tensor" % name)
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if rows and t.dim() == 2:
+        if t.shape[1] > 1 and t.stride(1) != 1:
+            raise ValueError("%s must be a 2-D array of rows with unit stride along a row" % name)
+    elif rows and t.dim() != 1:
+        raise ValueError("%s must be a 2-D array of rows or a flat buffer" % name)
+    elif not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    have = _avail(t, rows)
+    if have < nbytes:
+        raise ValueError("%s holds %d bytes, needs %d" % (name, have, nbytes))
+
+
+def _rows_bytes(n_rows: int, row_stride: int, row_len: int, elsize: int = 1) -> int:
+    """Bytes from the first row's start to the end of the last row's row_len
+    elements, rounded up to whole 16-byte chunks (the kernels read whole
+    chunks)."""
+    if n_rows <= 0:
+        return 0
+    return ((n_rows - 1) * row_stride * elsize + row_len * elsize + 15) // 16 * 16
+
+
 def _stream(stream):
     import torch
     if stream is None:
@@ -290,40 +339,79 @@ class Plan:
     # ---------------------------------------------------------------- calls
     def fengine(self, x, geom, spec, scale=None, *, power=None, row_stride=None, spectrum0=0, stream=None):
         """x: int8 device tensor [S][row_stride]; geom: uint8 device tensor holding corr_geom_t[S]."""
+        import torch
         rs = x.stride(0) if row_stride is None else row_stride
+        _need(x, "x", _rows_bytes(self.S, rs, self.T * self.N + self.max_delay), (torch.int8, torch.uint8),
+              rows=True)
+        _need(geom, "geom", 24 * self.S)
+        _need(spec, "spec", self.spectra_bytes)
+        _need(scale, "scale", 4 * self.S * self.C, torch.float32, optional=self.precision == FP32)
+        _need(power, "power", self._size("power"), torch.float32, optional=True)
         self._check(lib().corr_fengine(self._h, _ptr(x), rs, _ptr(geom), spectrum0, _ptr(spec),
                                        _ptr(scale), _ptr(power), _stream(stream)))
 
     def mad_flag(self, power, flags, M=3.0, stream=None):
+        import torch
+        _need(power, "power", self._size("power"), torch.float32)
+        _need(flags, "flags", self._size("flags"), torch.uint8)
         self._check(lib().corr_mad_flag(self._h, _ptr(power), M, _ptr(flags), _stream(stream)))
 
     def apply_flags(self, flags, spec, keep=None, stream=None):
+        _need(flags, "flags", self._size("flags"))
+        _need(spec, "spec", self.spectra_bytes)
+        _need(keep, "keep", self._size("keep"), optional=True)
         self._check(lib().corr_apply_flags(self._h, _ptr(flags), _ptr(spec), _ptr(keep), _stream(stream)))
 
     def pair_counts(self, keep, counts, stream=None):
+        import torch
+        _need(keep, "keep", self._size("keep"))
+        _need(counts, "counts", 4 * self.C * self.P, torch.int32)
         self._check(lib().corr_pair_counts(self._h, _ptr(keep), _ptr(counts), _stream(stream)))
 
     def xpack(self, inp, spec, stream=None):
+        _need(inp, "inp", self.S * self.T * self.C * 2 * (4 if self.precision == FP32 else 1))
+        _need(spec, "spec", self.spectra_bytes)
         self._check(lib().corr_xpack(self._h, _ptr(inp), _ptr(spec), _stream(stream)))
 
     def xengine(self, spec, acc, stream=None):
+        _need(spec, "spec", self.spectra_bytes)
+        _need(acc, "acc", self.acc_bytes)
         self._check(lib().corr_xengine(self._h, _ptr(spec), _ptr(acc), _stream(stream)))
 
     def xengine_gated(self, spec, gate, n_bins, acc, stream=None):
         """Gated X-engine: acc holds n_bins accumulators of acc_bytes each;
         gate is a uint8 device tensor [T]; see corr_xengine_gated."""
+        import torch
+        _need(spec, "spec", self.spectra_bytes)
+        _need(gate, "gate", self.T, torch.uint8)
+        _need(acc, "acc", max(int(n_bins), 0) * self.acc_bytes)
         self._check(lib().corr_xengine_gated(self._h, _ptr(spec), _ptr(gate), n_bins, _ptr(acc), _stream(stream)))
 
     def beamform(self, spec, scale=None, w=None, inc=None, c=None, coh=None, mode=None, tint=1, stream=None):
         """Incoherent beam (w [S] float -> inc [2][T/tint][C]) and coherent beams
         (c [n_beams][S][2] float as (re, im) -> coh [n_beams][planes][T/tint][C],
         complex64 [n_beams][2][T][C] for BEAM_VOLTAGE); see corr_beamform."""
+        import torch
         n_beams = 0 if c is None else int(c.shape[0])
         mode = BEAM_FULLPOL if mode is None else mode
+        tt = self.T // max(int(tint), 1)
+        _need(spec, "spec", self.spectra_bytes)
+        _need(scale, "scale", 4 * self.S * self.C, torch.float32, optional=self.precision == FP32)
+        _need(inc, "inc", 4 * 2 * tt * self.C, torch.float32, optional=True)
+        _need(w, "w", 4 * self.S, torch.float32, optional=inc is None)
+        if n_beams:
+            _need(c, "c", 4 * 2 * n_beams * self.S, torch.float32)
+            per = {BEAM_INTENSITY: 2 * 4 * tt, BEAM_FULLPOL: 4 * 4 * tt, BEAM_VOLTAGE: 2 * 8 * self.T}.get(mode, 0)
+            _need(coh, "coh", n_beams * per * self.C, (torch.float32, torch.complex64))
         self._check(lib().corr_beamform(self._h, _ptr(spec), _ptr(scale), _ptr(w), _ptr(inc), _ptr(c), n_beams,
                                         mode, _ptr(coh), tint, _stream(stream)))
 
     def integrate(self, acc, state, vis=None, scale=None, flags=DUMP, stream=None):
+        import torch
+        _need(acc, "acc", self.acc_bytes)
+        _need(state, "state", self.state_bytes, torch.float64)
+        _need(vis, "vis", self.vis_bytes, (torch.float32, torch.complex64), optional=True)
+        _need(scale, "scale", 4 * self.S * self.C, torch.float32, optional=self.precision == FP32)
         self._check(lib().corr_integrate(self._h, _ptr(acc), _ptr(scale), _ptr(state), _ptr(vis), flags,
                                          _stream(stream)))
 
@@ -376,6 +464,16 @@ class Batch:
             raise CorrError(rc, lib().corr_batch_last_error(self._h).decode())
 
     def set_io(self, i, *, x, geom, spec, scale, acc, state, vis=None, flags=DUMP, row_stride=None, spectrum0=0):
+        import torch
+        p = self.plans[i]
+        rs = x.stride(0) if row_stride is None else row_stride
+        _need(x, "x", _rows_bytes(p.S, rs, p.T * p.N + p.max_delay), (torch.int8, torch.uint8), rows=True)
+        _need(geom, "geom", 24 * p.S)
+        _need(spec, "spec", p.spectra_bytes)
+        _need(scale, "scale", 4 * p.S * p.C, torch.float32)
+        _need(acc, "acc", p.acc_bytes)
+        _need(state, "state", p.state_bytes, torch.float64)
+        _need(vis, "vis", p.vis_bytes, (torch.float32, torch.complex64), optional=True)
         io = BatchIO(_ptr(x), x.stride(0) if row_stride is None else row_stride, _ptr(geom), spectrum0,
                      _ptr(spec), _ptr(scale), _ptr(acc), _ptr(state), _ptr(vis), flags)
         self._keep[i] = (x, geom, spec, scale, acc, state, vis)  # keep the tensors alive
@@ -409,6 +507,18 @@ def _cnn_check(rc, h=None):
         raise CorrError(rc, lib().corr_cnn_last_error(h).decode())
 
 
+def _cnn_args(params, power, tiles, labels=None):
+    """Buffers shared by the CNN training calls: parameters, power [S][T][C],
+    the int32 tile list and, for the loss, labels [S][T][C]."""
+    import torch
+    _need(params, "params", 4 * CNN_PARAMS, torch.float32)
+    S, T, C = power.shape
+    _need(power, "power", 4 * S * T * C, torch.float32)
+    _need(tiles, "tiles", 4 * tiles.numel(), torch.int32)
+    if labels is not None:
+        _need(labels, "labels", S * T * C, (torch.uint8, torch.bool))
+
+
 def cnn_tiles(S: int, T: int, C: int) -> int:
     """Number of 64 x 256 flagging tiles of power [S][T][C]."""
     return S * (T // TILE_SPECTRA) * (C // TILE_CHANNELS)
@@ -439,20 +549,36 @@ class CNN:
 
     def forward(self, params, power, tiles, logits, stream=None):
         """FP32 logits [n][64][256] of the listed tiles of power [S][T][C]."""
+        import torch
         S, T, C = power.shape
+        _cnn_args(params, power, tiles)
+        _need(logits, "logits", 4 * tiles.numel() * TILE_SPECTRA * TILE_CHANNELS, torch.float32)
         self._check(lib().corr_cnn_forward(self._h, _ptr(params), _ptr(power), S, T, C, _ptr(tiles),
                                            tiles.numel(), _ptr(logits), _stream(stream)))
 
     def loss_grad(self, params, power, labels, tiles, loss, grad=None, stream=None):
+        import torch
         S, T, C = power.shape
+        _cnn_args(params, power, tiles, labels)
+        _need(loss, "loss", 4, torch.float32)
+        _need(grad, "grad", 4 * CNN_PARAMS, torch.float32, optional=True)
         self._check(lib().corr_cnn_loss_grad(self._h, _ptr(params), _ptr(power), _ptr(labels), S, T, C,
                                              _ptr(tiles), tiles.numel(), _ptr(loss), _ptr(grad), _stream(stream)))
 
     def adam(self, params, m, v, step: int, grad=None, stream=None):
+        import torch
+        for t, nm in ((params, "params"), (m, "m"), (v, "v")):
+            _need(t, nm, 4 * CNN_PARAMS, torch.float32)
+        _need(grad, "grad", 4 * CNN_PARAMS, torch.float32, optional=True)
         self._check(lib().corr_cnn_adam(self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(grad), step, _stream(stream)))
 
     def train_step(self, params, m, v, step: int, power, labels, tiles, loss, stream=None):
+        import torch
         S, T, C = power.shape
+        _cnn_args(params, power, tiles, labels)
+        for t, nm in ((m, "m"), (v, "v")):
+            _need(t, nm, 4 * CNN_PARAMS, torch.float32)
+        _need(loss, "loss", 4, torch.float32)
         self._check(lib().corr_cnn_train_step(self._h, _ptr(params), _ptr(m), _ptr(v), step, _ptr(power),
                                               _ptr(labels), S, T, C, _ptr(tiles), tiles.numel(), _ptr(loss),
                                               _stream(stream)))
@@ -475,16 +601,29 @@ class CNN:
 def cnn_infer(params, power, flags, *, threshold: float = 0.5, logits=None, stream=None):
     """Flags (and optionally logits) of every tile of power [S][T][C] from the
     fused FP16 inference kernel."""
+    import torch
     S, T, C = power.shape
+    _need(params, "params", 4 * CNN_PARAMS, torch.float32)
+    _need(power, "power", 4 * S * T * C, torch.float32)
+    _need(flags, "flags", S * T * C, torch.uint8)
+    _need(logits, "logits", 4 * S * T * C, torch.float32, optional=True)
     _cnn_check(lib().corr_cnn_infer(_ptr(params), _ptr(power), S, T, C, threshold, _ptr(flags), _ptr(logits),
                                     _stream(stream)))
 
 
 def cnn_save(path: str, params, m=None, v=None, step: int = 0):
+    import torch
+    _need(params, "params", 4 * CNN_PARAMS, torch.float32)
+    _need(m, "m", 4 * CNN_PARAMS, torch.float32, optional=True)
+    _need(v, "v", 4 * CNN_PARAMS, torch.float32, optional=True)
     _cnn_check(lib().corr_cnn_save(path.encode(), _ptr(params), _ptr(m), _ptr(v), step))
 
 
 def cnn_load(path: str, params, m=None, v=None) -> int:
+    import torch
+    _need(params, "params", 4 * CNN_PARAMS, torch.float32)
+    _need(m, "m", 4 * CNN_PARAMS, torch.float32, optional=True)
+    _need(v, "v", 4 * CNN_PARAMS, torch.float32, optional=True)
     st = ctypes.c_int64()
     _cnn_check(lib().corr_cnn_load(path.encode(), _ptr(params), _ptr(m), _ptr(v), ctypes.byref(st)))
     return st.value
@@ -494,9 +633,14 @@ def adc_unpack(raw, x, *, bits: int, n: int | None = None, stream=None):
     """Demultiplex and unpack card streams raw (uint8 [cards][raw_stride]) into
     int8 rows x [4 cards][row_stride] (first n samples; default the row
     length); see corr_adc_unpack."""
+    import torch
     cards, rs_raw = raw.shape
     rows, rs = x.shape
-    assert rows == 4 * cards
+    if rows != 4 * cards:
+        raise ValueError("x has %d rows, needs 4 per card (%d)" % (rows, 4 * cards))
+    nn = rs if n is None else int(n)
+    _need(raw, "raw", _rows_bytes(cards, raw.stride(0), nn * bits // 2), torch.uint8, rows=True)
+    _need(x, "x", _rows_bytes(rows, x.stride(0), nn), torch.int8, rows=True)
     rc = lib().corr_adc_unpack(_ptr(raw), raw.stride(0), cards, rs if n is None else n, bits, _ptr(x), x.stride(0),
                                _stream(stream))
     if rc != 0:
@@ -529,7 +673,10 @@ def dedisperse(v, *, sample_rate: float, nu0: float, dm: float, n_int: int, work
     if work is None:
         work = torch.empty(npol, L, dtype=torch.complex64, device=v.device)
     if out is None:
-        out = torch.empty(L // n_int, dtype=torch.float32, device=v.device)
+        out = torch.empty(L // max(int(n_int), 1), dtype=torch.float32, device=v.device)
+    _need(v, "v", 8 * npol * L, torch.complex64)
+    _need(work, "work", 8 * npol * L, torch.complex64)
+    _need(out, "out", 4 * (L // max(int(n_int), 1)), torch.float32)
     rc = lib().corr_dedisperse(_ptr(v), npol, T, C, sample_rate, nu0, dm, n_int, _ptr(work), _ptr(out),
                                _stream(stream))
     if rc != 0:
@@ -545,7 +692,9 @@ def _blank_check(rc):
 def blank_noise_table(seed: int, table, stream=None):
     """Fill table (float32 [S][L], L a power of two) with the blanker's
     precomputed Gaussian noise; see corr_blank_noise_table."""
+    import torch
     S, L = table.shape
+    _need(table, "table", 4 * S * L, torch.float32)
     _blank_check(lib().corr_blank_noise_table(int(seed) & 0xFFFFFFFFFFFFFFFF, S, L, _ptr(table), _stream(stream)))
 
 
@@ -555,9 +704,19 @@ def blank_voltages(x, table, *, block: int, M: float = 3.0, out=None, counts=Non
     each row, default all); out is x (in place, the default) or a tensor of
     the same shape; counts int32 [S][nblocks] and stats int32
     [S][nblocks][2] optional.  See corr_blank_voltages."""
+    import torch
     S, rs = x.shape
     if out is None:
         out = x
+    nn = rs if n is None else int(n)
+    nblk = -(-nn // block) if block > 0 else 0
+    _need(x, "x", _rows_bytes(S, x.stride(0), nn), torch.int8, rows=True)
+    _need(out, "out", _rows_bytes(S, x.stride(0), nn), torch.int8, rows=True)
+    if out.stride(0) != x.stride(0):
+        raise ValueError("out must have the row stride of x")
+    _need(table, "table", 4 * S * table.shape[1], torch.float32)
+    _need(counts, "counts", 4 * S * nblk, torch.int32, optional=True)
+    _need(stats, "stats", 8 * S * nblk, torch.int32, optional=True)
     _blank_check(lib().corr_blank_voltages(_ptr(x), x.stride(0), S, rs if n is None else n, block, M, _ptr(table),
                                            table.shape[1], sample0, _ptr(out), _ptr(counts), _ptr(stats),
                                            _stream(stream)))
