@@ -399,6 +399,7 @@ __global__ __launch_bounds__(256) void dd_detect_kernel(const float2 *z, int npo
     if (live) {
         for (int p = 0; p < npol; ++p) {
             const float2 *r = z + (int64_t)p * L + j * n_int;
+#pragma unroll 4
             for (int i = l; i < n_int; i += G) acc += r[i].x * r[i].x + r[i].y * r[i].y;
         }
     }
