@@ -1,7 +1,8 @@
 """Coherent dedispersion (section 4.3) through the C ABI against the oracle
 (numpy FP64 transforms): the detected, integrated output of the GPU's FP32
-transforms for block lengths whose transform takes 2 to 4 passes, channel
-counts from 64 to 8192 (the per-spectrum inverse DFT at its largest), one and
+transforms for block lengths whose transform takes 2 to 4 passes (every first-pass
+radix and every per-spectrum size the library instantiates), channel
+counts from 16 to 8192 (the per-spectrum inverse DFT at its largest), one and
 two polarisations, several integrations, zero DM; and a dispersed impulse put
 back into one sample."""
 import numpy as np
@@ -40,6 +41,26 @@ def test_dedispersion_matches_oracle(npol, T, C, dm, n_int):
     print("  max err %.3g rms err %.3g of rms" % (err.max() / rms, np.sqrt(np.mean(err ** 2)) / rms), flush=True)
     # FP32 transforms of up to 2^24 points: the error of each voltage is about
     # 1e-6 of the rms, of each intensity 2e-6 of its size
+    assert np.sqrt(np.mean(err ** 2)) <= 2e-5 * rms
+    assert err.max() <= 2e-4 * rms * max(1.0, ref.max() / rms)
+
+
+# Every shape of transform kernel the library instantiates: the block length's
+# first pass takes log2 L mod 8 = 4 (the smallest block, whose stride equals
+# the tile width), 5, 6, 7, 0, 2, 3, 5, 6, 7 bits, and the per-spectrum
+# transform every C from 16 (one in-register stage) to 8192 (four stages, a
+# whole workgroup per spectrum).
+@pytest.mark.parametrize("T,C", [(256, 16), (256, 32), (128, 128), (64, 512), (32, 2048), (16, 4096), (8, 8192),
+                                 (1024, 256), (2048, 256), (8192, 256), (16384, 256), (32768, 256)])
+def test_every_transform_shape_matches_oracle(T, C):
+    print("dedisp shape", T, C, flush=True)
+    V = voltages(2, T, C, 7 * T + C)
+    dm, n_int = 0.01, 16
+    got = run(V, dm, n_int)
+    ref = oracle.dedisperse(V.astype(np.complex128), FS, NU0, dm, n_int)
+    rms = np.sqrt(np.mean(ref ** 2))
+    err = np.abs(got - ref)
+    print("  max err %.3g rms err %.3g of rms" % (err.max() / rms, np.sqrt(np.mean(err ** 2)) / rms), flush=True)
     assert np.sqrt(np.mean(err ** 2)) <= 2e-5 * rms
     assert err.max() <= 2e-4 * rms * max(1.0, ref.max() / rms)
 
