@@ -67,11 +67,12 @@ MEASURED_TRAFFIC = {
                      "read": 8.606e9, "write": 1.611e9},
     # profiles/blank_int8_64sig_134Msamples.md: out of place FETCH_SIZE 4211175 KiB x 2.000, WRITE_SIZE 9624595 KiB
     "blank_out_c3": {"source": "paper_0910_1517_amd/csrc/blank.hip",
-                     "sha256": "a5e5a8dd867d35691113d8813f8fb217c46eb115a3e2554b2ca5b362d3108911",
+                     "sha256": "932989e03f2c17f7f9787d198612f4ac306c305cc65e08067a953112c19261bd",
                      "read": 8.624e9, "write": 9.856e9},
-    # same profile, in place: FETCH_SIZE 4211023 KiB x 2.000, WRITE_SIZE 900710 KiB
+    # same profile, in place: FETCH_SIZE 4211023 KiB x 2.000, WRITE_SIZE 900710 KiB.  (The record follows a
+    # host-side change to blank.hip whose device code compiles to the same instructions.)
     "blank_in_c3": {"source": "paper_0910_1517_amd/csrc/blank.hip",
-                    "sha256": "a5e5a8dd867d35691113d8813f8fb217c46eb115a3e2554b2ca5b362d3108911",
+                    "sha256": "932989e03f2c17f7f9787d198612f4ac306c305cc65e08067a953112c19261bd",
                     "read": 8.624e9, "write": 0.922e9},
 }
 

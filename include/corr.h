@@ -406,7 +406,8 @@ const char *corr_adc_last_error(void);
  *              both integers for int8 data.
  * n == 0 enqueues nothing.  Calls that overlap on the same buffers race.
  * Errors: NULL, ALIGN, INVALID (S outside [1, 65535], n < 0, row_stride,
- * block, M, table_len, sample0 < 0, more than 2^31 - 1 blocks), DEVICE;
+ * block, M, table_len, sample0 < 0 or sample0 + n above 2^63 - 1, more than
+ * 2^31 - 1 blocks), DEVICE;
  * messages via corr_blank_last_error. */
 corr_status corr_blank_voltages(const int8_t *d_x, int64_t row_stride, int32_t S, int64_t n, int32_t block,
                                 float M, const float *d_table, int64_t table_len, int64_t sample0, int8_t *d_out,

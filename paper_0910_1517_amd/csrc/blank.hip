@@ -41,6 +41,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 
 #include "corr_internal.h"
@@ -452,7 +453,8 @@ corr_status corr_blank_voltages(const int8_t *d_x, int64_t row_stride, int32_t S
     if (!(M > 0.f) || !std::isfinite(M)) return blank_fail(CORR_ERR_INVALID, "threshold M must be finite and > 0");
     if (table_len < 1 || table_len > kBlankMaxTable || (table_len & (table_len - 1)))
         return blank_fail(CORR_ERR_INVALID, "table_len=%lld must be a power of two in [1, 2^31]", (long long)table_len);
-    if (sample0 < 0) return blank_fail(CORR_ERR_INVALID, "sample0 is negative");
+    if (sample0 < 0 || sample0 > INT64_MAX - n)
+        return blank_fail(CORR_ERR_INVALID, "sample0 must be >= 0 with sample0 + n <= 2^63 - 1");
     const int64_t nblk = (n + block - 1) / block;
     if (nblk > 0x7FFFFFFF) return blank_fail(CORR_ERR_INVALID, "more than 2^31 - 1 blocks per row");
     if (n == 0) return CORR_OK;

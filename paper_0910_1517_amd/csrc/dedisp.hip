@@ -410,12 +410,11 @@ __global__ __launch_bounds__(256) void dd_detect_kernel(const float2 *z, int npo
 template <int LOGR, int MODE>
 hipError_t dd_fft(const float2 *in, float2 *out, int npol, int64_t L, int64_t Bp, const DdChirp &ch, hipStream_t st) {
     using Sh = DdShape<LOGR>;
-    static bool attr = false;  // per process: raise the dynamic LDS limit once
-    if (!attr && Sh::lds_bytes > 0) {
+    if constexpr (Sh::lds_bytes > 65536) {  // above the default dynamic LDS limit (R = 8192 only)
+        // set on every call: no process-wide state, right for whichever device is current
         hipError_t e = hipFuncSetAttribute((const void *)dd_fft_kernel<LOGR, MODE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)Sh::lds_bytes);
         if (e != hipSuccess) return e;
-        attr = true;
     }
     const dim3 grid((unsigned)(L / Sh::TILE), (unsigned)npol);
     hipLaunchKernelGGL((dd_fft_kernel<LOGR, MODE>), grid, dim3(kDdThreads), Sh::lds_bytes, st, in, out, L, Bp, ch);

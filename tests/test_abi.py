@@ -217,7 +217,7 @@ def test_blanker_rejects_bad_arguments():
     assert bv(block=8) == -1 and bv(block=100) == -1 and bv(block=65552) == -1
     assert bv(M=0.0) == -1 and bv(M=-1.0) == -1 and bv(M=float("inf")) == -1 and bv(M=float("nan")) == -1
     assert bv(tl=0) == -1 and bv(tl=1000) == -1 and bv(tl=1 << 32) == -1
-    assert bv(s0=-1) == -1
+    assert bv(s0=-1) == -1 and bv(s0=(1 << 63) - 1000) == -1             # sample0 + n would overflow
     assert bv(n=1 << 40, rs=1 << 40, block=16) == -1                     # 2^36 blocks per row
     assert L.corr_blank_last_error()
     assert bv(n=0, counts=None, stats=None) == 0                         # nothing to do, nothing launched
