@@ -122,24 +122,30 @@ __device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, 
     const int i = threadIdx.x;
     const bool cp = i < S * 8;
     const int lds_dst = (i >> 3) * kRowPitch + (i & 7) * 16;
-    const uint4 *gsrc = reinterpret_cast<const uint4 *>(spec) + (int64_t)kb * S * 8 + i;
+    // threads beyond the block load its last 16 bytes and discard them, so
+    // every thread issues the same loads (the compiler can then count the
+    // loads in flight across steps and wait only for the older set)
+    const uint4 *gsrc = reinterpret_cast<const uint4 *>(spec) + (int64_t)kb * S * 8 + (cp ? i : S * 8 - 1);
     const int64_t gstride = (int64_t)C * S;  // 16-byte units between chunks g and g+1
-    uint4 p0 = make_uint4(0, 0, 0, 0), p1 = p0, p2 = p0, p3 = p0;
-#define X_GLOAD(st)                                                   \
-    if (cp) {                                                         \
+    // two register sets (a, b) alternate between the next two K-steps'
+    // chunks, so each load has two steps of MFMA work to land before its LDS
+    // store
+    uint4 pa0 = make_uint4(0, 0, 0, 0), pa1 = pa0, pa2 = pa0, pa3 = pa0, pb0 = pa0, pb1 = pa0, pb2 = pa0, pb3 = pa0;
+#define X_GLOAD(st, R)                                                \
+    {                                                                 \
         const uint4 *g_ = gsrc + 4 * ((int64_t)sp * steps + (st)) * gstride; \
-        p0 = g_[0];                                                   \
-        p1 = g_[gstride];                                             \
-        p2 = g_[2 * gstride];                                         \
-        p3 = g_[3 * gstride];                                         \
+        R##0 = g_[0];                                                 \
+        R##1 = g_[gstride];                                           \
+        R##2 = g_[2 * gstride];                                       \
+        R##3 = g_[3 * gstride];                                       \
     }
-#define X_LSTORE(buf)                                                 \
+#define X_LSTORE(buf, R)                                              \
     if (cp) {                                                         \
         uint8_t *l_ = lds + (buf) * 4 * kBlk + lds_dst;               \
-        *reinterpret_cast<uint4 *>(l_) = p0;                          \
-        *reinterpret_cast<uint4 *>(l_ + kBlk) = p1;                   \
-        *reinterpret_cast<uint4 *>(l_ + 2 * kBlk) = p2;               \
-        *reinterpret_cast<uint4 *>(l_ + 3 * kBlk) = p3;               \
+        *reinterpret_cast<uint4 *>(l_) = R##0;                        \
+        *reinterpret_cast<uint4 *>(l_ + kBlk) = R##1;                 \
+        *reinterpret_cast<uint4 *>(l_ + 2 * kBlk) = R##2;             \
+        *reinterpret_cast<uint4 *>(l_ + 3 * kBlk) = R##3;             \
     }
 
     V16 accR[ntri(NT)], accM[NT * NT];
@@ -151,13 +157,22 @@ __device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, 
 #pragma unroll
     for (int a = 0; a < NT; ++a) valid[a] = (32 * a + row) < S;
 
-    X_GLOAD(0)
-    X_LSTORE(0)
+    X_GLOAD(0, pa)
+    X_LSTORE(0, pa)
+    X_GLOAD(steps > 1 ? 1 : 0, pa)
     __syncthreads();
-    for (int st = 0; st < steps; ++st) {
+    // K-step st (B = st is odd): set a (even st) or b (odd st) holds step
+    // st + 1's chunks, stored to the other LDS buffer at the end; the other
+    // set receives step st + 2's
+    auto kstep = [&](int st, auto odd) __attribute__((always_inline)) {
+        constexpr bool B = decltype(odd)::value;
         const int buf = st & 1;
-        if (st + 1 < steps) {
-            X_GLOAD(st + 1)
+        // step st + 2's chunks (the last step's again near the end: unused)
+        const int nx = st + 2 < steps ? st + 2 : steps - 1;
+        if constexpr (B) {
+            X_GLOAD(nx, pa)
+        } else {
+            X_GLOAD(nx, pb)
         }
         v4i c0[NT], c1[NT];
 #pragma unroll
@@ -273,10 +288,20 @@ __device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, 
             }
         }
         if (st + 1 < steps) {
-            X_LSTORE(buf ^ 1)
+            if constexpr (B) {
+                X_LSTORE(buf ^ 1, pb)
+            } else {
+                X_LSTORE(buf ^ 1, pa)
+            }
         }
         __syncthreads();
+    };
+    int st = 0;
+    for (; st + 1 < steps; st += 2) {  // whole pairs, so every loop entry sees the same loads in flight
+        kstep(st, std::false_type{});
+        kstep(st + 1, std::true_type{});
     }
+    if (st < steps) kstep(st, std::false_type{});
 #undef X_GLOAD
 #undef X_LSTORE
     // the staging buffers are free now: the epilogue's M-tile exchange reuses them
