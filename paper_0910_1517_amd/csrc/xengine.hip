@@ -117,6 +117,7 @@ __device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, 
     const int G = (PREC == CORR_FP32) ? kChunk32 : kChunk8;
     const int steps = T / G / 4 / splits;
     const int64_t P = (int64_t)S * (S + 1) / 2;
+    if (steps < 1) return;  // no K-step (the plan's splits always leave one): nothing to add
 
     // staging copy: thread i moves bytes [16 i, 16 i + 16) of each block
     const int i = threadIdx.x;
