@@ -113,10 +113,9 @@ __global__ void __launch_bounds__(BK) beam_kernel(const uint4 *__restrict__ spec
     }
     const bool do_inc = inc != nullptr;
 
-    // signal s of polarisation POL: accumulate its 8 spectra
-    auto add = [&](const Chunk<PREC> &ch, int s, auto pol_tag) {
+    // signal s of polarisation POL, dequantisation scale sc: accumulate its 8 spectra
+    auto add = [&](const Chunk<PREC> &ch, float sc, int s, auto pol_tag) {
         constexpr int POL = decltype(pol_tag)::value;
-        const float sc = PREC == CORR_FP32 ? 1.f : scale[(int64_t)s * C + k];
         float re[8], im[8];
         decode<PREC>(ch, re, im);
         if (do_inc) {
@@ -137,44 +136,55 @@ __global__ void __launch_bounds__(BK) beam_kernel(const uint4 *__restrict__ spec
     };
 
     // signals in polarisation pairs (2a, 2a + 1), fetched LA pairs ahead into a
-    // ring of LA + 1 pair slots (the loads in flight keep HBM busy; FP32 chunks
-    // are 4x larger); the pair loop runs LA + 1 pairs at a time so every ring
-    // slot is a constant
+    // ring of LA + 1 pair slots with their scales (the loads in flight keep HBM
+    // busy; FP32 chunks are 4x larger); the pair loop runs LA + 1 pairs at a
+    // time so every ring slot is a constant.  Every fetch is issued (past the
+    // last pair it loads the last pair again, unused), so the compiler sees
+    // the same loads in flight at every pair and waits only for the oldest.
     constexpr int LA = PREC == CORR_FP32 ? 1 : 3, R = LA + 1;
     const std::integral_constant<int, 0> p0{};
     const std::integral_constant<int, 1> p1{};
     const int npair = S / 2;
     const uint4 *sp = spec + c0;
+    const float *scp = scale + k;
     Chunk<PREC> ring[R][2];
+    float rsc[R][2];
     auto fetch = [&](int q, auto slot_tag) {
         constexpr int SL = decltype(slot_tag)::value;
-        if (q < npair) {
-            load_chunk<PREC>(sp, 16 * (int64_t)q, cpg, ring[SL][0]);
-            load_chunk<PREC>(sp, 16 * (int64_t)q + 8, cpg, ring[SL][1]);
+        const int qc = q < npair ? q : npair - 1;
+        load_chunk<PREC>(sp, 16 * (int64_t)qc, cpg, ring[SL][0]);
+        load_chunk<PREC>(sp, 16 * (int64_t)qc + 8, cpg, ring[SL][1]);
+        if constexpr (PREC == CORR_FP32) {
+            rsc[SL][0] = rsc[SL][1] = 1.f;
+        } else {
+            rsc[SL][0] = scp[(int64_t)(2 * qc) * C];
+            rsc[SL][1] = scp[(int64_t)(2 * qc + 1) * C];
         }
     };
-    fetch(0, std::integral_constant<int, 0>{});
-    if constexpr (LA > 1) fetch(1, std::integral_constant<int, 1>{});
-    if constexpr (LA > 2) fetch(2, std::integral_constant<int, 2>{});
-    for (int pr = 0; pr < npair; pr += R) {
-        auto one = [&](auto j_tag) {
-            constexpr int J = decltype(j_tag)::value;
-            const int q = pr + J;
-            if (q < npair) {
+    if (npair > 0) {
+        fetch(0, std::integral_constant<int, 0>{});
+        if constexpr (LA > 1) fetch(1, std::integral_constant<int, 1>{});
+        if constexpr (LA > 2) fetch(2, std::integral_constant<int, 2>{});
+        for (int pr = 0; pr < npair; pr += R) {
+            auto one = [&](auto j_tag) {
+                constexpr int J = decltype(j_tag)::value;
+                const int q = pr + J;
                 fetch(q + LA, std::integral_constant<int, (J + LA) % R>{});
-                add(ring[J][0], 2 * q, p0);
-                add(ring[J][1], 2 * q + 1, p1);
-            }
-        };
-        one(std::integral_constant<int, 0>{});
-        one(std::integral_constant<int, 1>{});
-        if constexpr (R > 2) one(std::integral_constant<int, 2>{});
-        if constexpr (R > 3) one(std::integral_constant<int, 3>{});
+                if (q < npair) {
+                    add(ring[J][0], rsc[J][0], 2 * q, p0);
+                    add(ring[J][1], rsc[J][1], 2 * q + 1, p1);
+                }
+            };
+            one(std::integral_constant<int, 0>{});
+            one(std::integral_constant<int, 1>{});
+            if constexpr (R > 2) one(std::integral_constant<int, 2>{});
+            if constexpr (R > 3) one(std::integral_constant<int, 3>{});
+        }
     }
     if (S & 1) {  // last signal: polarisation 0 only
         Chunk<PREC> ch;
         load_chunk<PREC>(spec, c0 + 8 * (S - 1), cpg, ch);
-        add(ch, S - 1, p0);
+        add(ch, PREC == CORR_FP32 ? 1.f : scale[(int64_t)(S - 1) * C + k], S - 1, p0);
     }
 
     const int64_t plane = (T >> lt) * C;
