@@ -61,10 +61,10 @@ MEASURED_TRAFFIC = {
     "cnn_infer_c5": {"source": "paper_0910_1517_amd/csrc/cnn.hip",
                      "sha256": "11897de3ea8f1fed2ff75202bd8832f9f067f1821c5b36ebff85b1240076a554",
                      "read": 13.562e9, "write": 2.147e9},
-    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4201819 KiB x 2.000, WRITE_SIZE 1572864 KiB x 1.000
+    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4197483 KiB x 2.000, WRITE_SIZE 1572864 KiB x 1.000
     "beam_int8_c3": {"source": "paper_0910_1517_amd/csrc/beam.hip",
-                     "sha256": "c4b752f8785e1887ba24a549df17dcb04d350f6aef77a9cf576275e4ed864124",
-                     "read": 8.606e9, "write": 1.611e9},
+                     "sha256": "fdea2c6b6d608a65e64c732609303dc9d4f9377b18ad830e8b407f4c35843b4f",
+                     "read": 8.597e9, "write": 1.611e9},
     # profiles/blank_int8_64sig_134Msamples.md: out of place FETCH_SIZE 4211175 KiB x 2.000, WRITE_SIZE 9624595 KiB
     "blank_out_c3": {"source": "paper_0910_1517_amd/csrc/blank.hip",
                      "sha256": "932989e03f2c17f7f9787d198612f4ac306c305cc65e08067a953112c19261bd",
