@@ -366,7 +366,6 @@ fengine_kernel(FLaunch a) {
             *reinterpret_cast<uint4 *>(&lds_in[u][4 * t]) = d;
         }
         __syncthreads();
-        if (active && r < 15) fetch(m + 1);
         // 2a. first radix-8 pass straight from the staged int8 samples
         {
             const int16_t *in16 = reinterpret_cast<const int16_t *>(&lds_in[u][0]);
@@ -412,13 +411,21 @@ fengine_kernel(FLaunch a) {
         const float2 *zbz = (tt == 0) ? Z : (Z + padc(M) + nb);  // j = 0: index (M - t) mod M
         // chunk of spectrum m: 16-byte index g*C*S + ((t/8) S + s) 8 + t%8 + j L S
         const int64_t obase = (int64_t)(m / G) * M * a.S + (((tt >> 3) * a.S + s) << 3) + (tt & 7);
+        // the split twiddles are this spectrum's last table loads: fetch the
+        // next window only after them, so that waiting for a table load never
+        // waits for the window (loads complete in issue order), and the window
+        // is not held in registers through the transform
+        float2 wv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) wv[j] = wn[tt + L * j];
+        if (active && r < 15) fetch(m + 1);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const float2 za = za0[padc(L * j)];
             const float2 zb0 = (j == 0) ? zbz[0] : zb0p[padc((8 - j) * L)];
             const float2 zb = make_float2(zb0.x, -zb0.y);
             const float2 sm = cadd(za, zb), df = csub(za, zb);
-            const float2 w = wn[tt + L * j];
+            const float2 w = wv[j];
             // 2 X = (a + b) - i w (a - b)
             float2 X;
             X.x = sm.x + (w.x * df.y + w.y * df.x);
