@@ -415,9 +415,13 @@ fengine_kernel(FLaunch a) {
         // next window only after them, so that waiting for a table load never
         // waits for the window (loads complete in issue order), and the window
         // is not held in registers through the transform
-        float2 wv[8];
+        float2 wv[8], ev[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) wv[j] = wn[tt + L * j];
+        for (int j = 0; j < 8; ++j) {
+            wv[j] = wn[tt + L * j];
+            // table mode: the table entry nearest each channel's phase, a table load too
+            if constexpr (PL) ev[j] = a.lut[lut_index(c_lut, (double)(tt + L * j) * fn)];
+        }
         if (active && r < 15) fetch(m + 1);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -437,7 +441,7 @@ fengine_kernel(FLaunch a) {
                     a.power[((int64_t)s * a.T + m) * M + tt + L * j] = 0.25f * (X.x * X.x + X.y * X.y);
                 float2 Y;
                 if constexpr (PL) {  // table entry nearest the channel's phase; ramp = 1/2 (x 1/scale)
-                    const float2 e = a.lut[lut_index(c_lut, (double)(tt + L * j) * fn)];
+                    const float2 e = ev[j];
                     Y = make_float2(ramp[j].x * (X.x * e.x - X.y * e.y), ramp[j].x * (X.x * e.y + X.y * e.x));
                 } else {
                     Y = cmul(cmul(X, ramp[j]), rot);
