@@ -22,6 +22,7 @@
 //     tile runs all three layers with the activations in LDS ring buffers and
 //     writes only the flags (and optionally the logits).
 #include <algorithm>
+#include <type_traits>
 
 #include "corr_internal.h"
 
@@ -423,7 +424,9 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
     // tile bases are uniform 64-bit pointers.
     auto roff = [&](int r, int c) { return __umul24((uint32_t)r, (uint32_t)C) + (uint32_t)c; };
     int tile = blockIdx.x;
-    float csum = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f;
+    // p0, p1: input rows -1 + xh, 1 + xh of a tile; p2 .. p5: rows 3 + xh ..
+    // 9 + xh, the first four slots of the input ring
+    float csum = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f;
     if (tile < n_tiles) {
         const float *tb = power + tile_base(tile);
 #pragma unroll 8
@@ -431,6 +434,9 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
         p0 = xh ? tb[xc] : 0.f;
         p1 = tb[roff(1 + xh, xc)];
         p2 = tb[roff(3 + xh, xc)];
+        p3 = tb[roff(5 + xh, xc)];
+        p4 = tb[roff(7 + xh, xc)];
+        p5 = tb[roff(9 + xh, xc)];
     }
     for (; tile < n_tiles; tile += gridDim.x) {
         const int64_t base = tile_base(tile);
@@ -457,7 +463,9 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
         };
         x_put(-1 + xh, p0);
         x_put(1 + xh, p1);
-        float xnext = p2, cnext = 0.f;
+        // input ring: step j puts row 2j + 5 + xh from slot (j + 1) mod 4 and
+        // loads row 2j + 13 + xh, which step j + 4 puts, into the same slot
+        float xr0 = p2, xr1 = p3, xr2 = p4, xr3 = p5, cnext = 0.f;
         csum = 0.f;
         __syncthreads();
 
@@ -465,19 +473,28 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
 #pragma unroll
         for (int dv = 0; dv < 3; ++dv) Fa[dv] = Fb[dv] = zero8;
 
-        auto step = [&](const int j) {
-            // (a) input row 2j + 5 + xh; row 2j + 7 + xh is fetched for the next step, and row
-            //     2j + 2 + xh of the next tile for its column sums (added one step later)
+        auto step = [&](const int j, auto slot_tag) {
+            constexpr int SL = decltype(slot_tag)::value;  // (j + 1) mod 4
+            float &xs_slot = SL == 0 ? xr0 : SL == 1 ? xr1 : SL == 2 ? xr2 : xr3;
+            // (a) input row 2j + 5 + xh; row 2j + 13 + xh is fetched for step j + 4, and row
+            //     2j + 2 + xh of the next tile for its column sums (added one step later).
+            //     Both loads are issued at every step (rows clamped into the tile, values
+            //     past its end unused), so the loads in flight are the same on every path.
             {
                 const int r = 2 * j + 5 + xh;
-                x_put(r, xnext);
-                xnext = (r + 2 < H) ? tb[roff(r + 2, xc)] : 0.f;
+                x_put(r, xs_slot);
+                xs_slot = tb[roff(r + 8 < H ? r + 8 : H - 1, xc)];
                 if (j >= 0 && j <= H / 2 - 1) csum += cnext;
-                if (j <= H / 2 - 2) cnext = has_next ? tn[roff(2 * j + 2 + xh, xc)] : 0.f;
+                const int rc = 2 * j + 2 + xh;
+                const float cn = tn[roff(rc < H ? (rc > 0 ? rc : 0) : H - 1, xc)];
+                cnext = (j <= H / 2 - 2 && has_next) ? cn : 0.f;
                 if (j == H / 2 && has_next) {
                     p0 = xh ? tn[xc] : 0.f;
                     p1 = tn[roff(1 + xh, xc)];
                     p2 = tn[roff(3 + xh, xc)];
+                    p3 = tn[roff(5 + xh, xc)];
+                    p4 = tn[roff(7 + xh, xc)];
+                    p5 = tn[roff(9 + xh, xc)];
                 }
             }
             // (b) layer 1 for rows R, R + 1, R = 2j + 2 (input rows R - 1 .. R + 2); row 64 is zero
@@ -570,10 +587,10 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
         // steps -1 .. 34, four at a time: 2j mod 8 is fixed within each group
         for (int i = 0; i < (H / 2 + 4) / 4; ++i) {
             const int jb = 4 * i - 1;
-            step(jb);
-            step(jb + 1);
-            step(jb + 2);
-            step(jb + 3);
+            step(jb, std::integral_constant<int, 0>{});
+            step(jb + 1, std::integral_constant<int, 1>{});
+            step(jb + 2, std::integral_constant<int, 2>{});
+            step(jb + 3, std::integral_constant<int, 3>{});
         }
     }
 }
