@@ -57,10 +57,10 @@ MEASURED_TRAFFIC = {
     "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
                         "sha256": "4d2788f0d5f71d03e576e55f9fa36dbd93bff8586bf3a25b7c7e4fad20eab618",
                         "read": 9.675e9, "write": 8.590e9},
-    # profiles/cnn_flagged_64sig_8192pt_8192spec.md: FETCH_SIZE 6622274 KiB x 2.000, WRITE_SIZE 2097152 KiB x 1.000
+    # profiles/cnn_flagged_64sig_8192pt_8192spec.md: FETCH_SIZE 5484065 KiB x 2.000, WRITE_SIZE 2097152 KiB x 1.000
     "cnn_infer_c5": {"source": "paper_0910_1517_amd/csrc/cnn.hip",
-                     "sha256": "11897de3ea8f1fed2ff75202bd8832f9f067f1821c5b36ebff85b1240076a554",
-                     "read": 13.562e9, "write": 2.147e9},
+                     "sha256": "e36bc79513397116c36e380c1519ce59689c93a9a1116b5f53ee3bbe98c6f595",
+                     "read": 11.231e9, "write": 2.147e9},
     # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4197483 KiB x 2.000, WRITE_SIZE 1572864 KiB x 1.000
     "beam_int8_c3": {"source": "paper_0910_1517_amd/csrc/beam.hip",
                      "sha256": "fdea2c6b6d608a65e64c732609303dc9d4f9377b18ad830e8b407f4c35843b4f",
