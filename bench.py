@@ -53,9 +53,9 @@ FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
 # calibration copy, see profiles/), valid only for the kernel source they were
 # taken from: reported as `traffic` when the source hash still matches.
 MEASURED_TRAFFIC = {
-    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4724104 KiB x 2.000, WRITE_SIZE 8388608 KiB x 1.000
+    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4723963 KiB x 2.000, WRITE_SIZE 8388608 KiB x 1.000
     "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
-                        "sha256": "4d2788f0d5f71d03e576e55f9fa36dbd93bff8586bf3a25b7c7e4fad20eab618",
+                        "sha256": "e7729c6fe3ac3baada8ff9f2d87a99e95bb14c280e8437228f1cb132bc1f0e7a",
                         "read": 9.675e9, "write": 8.590e9},
     # profiles/cnn_flagged_64sig_8192pt_8192spec.md: FETCH_SIZE 5484065 KiB x 2.000, WRITE_SIZE 2097152 KiB x 1.000
     "cnn_infer_c5": {"source": "paper_0910_1517_amd/csrc/cnn.hip",
