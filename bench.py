@@ -37,7 +37,7 @@ FS = 66.666666e6
 CONFIGS = {
     # name: (S, N, T, description)
     "c3": (64, 4096, 32768, "precision form: 64 signals, 4096-pt FFT (2048 ch), 32768 spectra"),
-    "c2": (64, 1024, 16384, "GMRT scale: 64 signals, 1024-pt FFT (512 ch), 16384 spectra"),
+    "c2": (64, 1024, 16384, "GMRT scale: 64 signals with 8 point sources, 1024-pt FFT (512 ch), 16384 spectra, FP32"),
 }
 HBM_PEAK = 8.0e12           # B/s
 INT8_PEAK = 5.0e15          # dense int8 MFMA OP/s
@@ -48,6 +48,7 @@ CNN_FLOP_PER_CELL = 2 * (16 * 9 + 16 * 16 * 9 + 16 * 9)  # 2592 MACs of the thre
 # emits): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.  The 157.3
 # TFLOP/s datasheet figure assumes two FP32 FMAs per lane per cycle (packed).
 FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
+FP32_PUBLISHED_PEAK = 157.3e12  # the datasheet's FP32 vector figure (packed FP32)
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the
 # calibration copy, see profiles/), valid only for the kernel source they were
@@ -67,12 +68,12 @@ MEASURED_TRAFFIC = {
                      "read": 8.597e9, "write": 1.611e9},
     # profiles/blank_int8_64sig_134Msamples.md: out of place FETCH_SIZE 4211175 KiB x 2.000, WRITE_SIZE 9624595 KiB
     "blank_out_c3": {"source": "paper_0910_1517_amd/csrc/blank.hip",
-                     "sha256": "932989e03f2c17f7f9787d198612f4ac306c305cc65e08067a953112c19261bd",
+                     "sha256": "3d7db02ee39e54f695df0e2e89e58bb8292bdfc262d90a9c60d3e880341b0b8b",
                      "read": 8.624e9, "write": 9.856e9},
-    # same profile, in place: FETCH_SIZE 4211023 KiB x 2.000, WRITE_SIZE 900710 KiB.  (The record follows a
-    # host-side change to blank.hip whose device code compiles to the same instructions.)
+    # same profile, in place: FETCH_SIZE 4211023 KiB x 2.000, WRITE_SIZE 900710 KiB.  (Both blank.hip records
+    # follow host-side and comment changes whose device code compiles to the same instructions.)
     "blank_in_c3": {"source": "paper_0910_1517_amd/csrc/blank.hip",
-                    "sha256": "932989e03f2c17f7f9787d198612f4ac306c305cc65e08067a953112c19261bd",
+                    "sha256": "3d7db02ee39e54f695df0e2e89e58bb8292bdfc262d90a9c60d3e880341b0b8b",
                     "read": 8.624e9, "write": 0.922e9},
 }
 
@@ -109,13 +110,19 @@ def x_algorithmic(S, N, T, in_bytes_per_ch):
     return 8.0 * P * C * T, float(S * C * T * in_bytes_per_ch)
 
 
-def run_path(corr, torch, prec, S, N, T, x_dev, rs, g_dev, steps, warmup, scale=None):
-    """Time `steps` F+X+integrate passes one after another on one stream;
-    per-kernel times from HIP events on the launch stream."""
+def run_path(corr, torch, prec, S, N, T, x_dev, rs, g_dev, steps, warmup, scale=None, graph=True):
+    """One step = F-engine + X-engine + integrate (dump and reset) on one stream.
+
+    Per-kernel times: HIP events around each launch of `steps` eager steps
+    after `warmup` ones, median over the steps.  Step time: the same three
+    calls captured once into a HIP graph, `warmup` replays, then the median of
+    `steps` replays bracketed by events on the replay stream; the graph's dumped
+    visibilities must equal the eager run's bit for bit."""
     plan = corr.Plan(S, N, T, precision=prec, max_delay=16, scale_mode=corr.SCALE_HOLD)
     spec = plan.alloc("spectra", zero=False)
     acc, state, vis = plan.alloc("acc"), plan.alloc("state"), plan.alloc("vis")
-    st = torch.cuda.current_stream()
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
 
     def step(e=None):
@@ -135,13 +142,36 @@ def run_path(corr, torch, prec, S, N, T, x_dev, rs, g_dev, steps, warmup, scale=
         step(ev[i])
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    tf = np.mean([e[0].elapsed_time(e[1]) for e in ev]) * 1e-3
-    tx = np.mean([e[1].elapsed_time(e[2]) for e in ev]) * 1e-3
-    ti = np.mean([e[2].elapsed_time(e[3]) for e in ev]) * 1e-3
-    tstep = np.mean([e[0].elapsed_time(e[3]) for e in ev]) * 1e-3
+    med = lambda a, b: float(np.median([e[a].elapsed_time(e[b]) for e in ev])) * 1e-3
+    out = dict(t_f=med(0, 1), t_x=med(1, 2), t_int=med(2, 3), t_eager_step=med(0, 3), wall=wall,
+               splits=plan.splits)
+    out["t_step"] = out["t_eager_step"]
     plan.check_device_errors()
+    if graph:
+        eager_vis = vis.clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st):
+            step()
+        vis.zero_()
+        ge = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        with torch.cuda.stream(st):
+            for _ in range(warmup):
+                g.replay()
+            st.synchronize()
+            ok = bool(torch.equal(vis, eager_vis))  # a replay reproduces the eager step
+            for e0, e1 in ge:
+                e0.record(st)
+                g.replay()
+                e1.record(st)
+        torch.cuda.synchronize()
+        ok = ok and bool(torch.equal(vis, eager_vis))
+        if not ok:
+            raise RuntimeError("graph replay of the step differs from the eager step")
+        out["t_step"] = float(np.median([a.elapsed_time(b) for a, b in ge])) * 1e-3
+        out["graph_matches_eager"] = ok
+        del g, eager_vis
     del spec, acc, state, vis
-    return dict(t_step=tstep, t_f=tf, t_x=tx, t_int=ti, wall=wall, splits=plan.splits)
+    return out
 
 
 def run_pipelined(corr, torch, prec, S, N, T, x_dev, rs, g_dev, steps, warmup, scale=None):
@@ -197,9 +227,32 @@ def calibrate_scales(corr, torch, S, N, T, x_dev, rs, g_dev, prec=None):
     return scale
 
 
-def cpu_baseline(S, N, T_sample, chunk=256):
-    """The CPU oracle (FP64 F-engine, int8 requantisation, int64 X-engine, FP64 scaling),
-    as it stands, on T_sample spectra of the same shape; returns MHz and cores used."""
+def _omp_set_threads(n):
+    """Set the OpenMP thread count of the oracle's runtime (libgomp) for the calls
+    that follow; returns the count it reports."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
+
+
+def cpu_model():
+    import subprocess
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    for line in txt.splitlines():
+        if line.startswith("Model name:"):
+            return line.split(":", 1)[1].strip()
+    return None
+
+
+def cpu_baseline(S, N, T_sample, threads, prec="int8", chunk=128):
+    """The CPU oracle as it stands, on T_sample spectra of the workload's shape,
+    with `threads` OpenMP threads: F-engine (FP64 DFT, phase) and X-engine
+    (int8 requantisation, int64 products, FP64 scaling; or the FP64 products of
+    the FP32 path) timed apart.  Returns a dict (MHz = N T / (2 t))."""
     import oracle
     import synth
     geo = synth.make_geometry(S // 2, seed=synth.BASE_SEED + 2)
@@ -207,21 +260,51 @@ def cpu_baseline(S, N, T_sample, chunk=256):
     x = synth.voltages(S, N * T_sample + 64, geo, FS, mode="bulk", seed=synth.BASE_SEED + 2,
                        tone_bin=37, tone_N=N)
     oracle.build()
-    t0 = time.perf_counter()
-    A = None
-    scale = None
+    used = _omp_set_threads(threads)
+    tf = tx = 0.0
+    A = V = scale = None
     for m0 in range(0, T_sample, chunk):
+        n = min(chunk, T_sample - m0)
         xs = np.ascontiguousarray(x[:, m0 * N:])
-        Y = oracle.fengine(xs, N, chunk, og, FS, spectrum0=m0)
-        if scale is None:
-            scale = oracle.int8_scale(oracle.sigma(Y)).astype(np.float64)
-        q = oracle.quantize_int8(Y, scale)
-        A = oracle.xengine_int(q, A)
-    V = oracle.scale_visibilities(A, scale)
-    dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Y = oracle.fengine(xs, N, n, og, FS, spectrum0=m0)
+        t1 = time.perf_counter()
+        if prec == "int8":
+            if scale is None:
+                scale = oracle.int8_scale(oracle.sigma(Y)).astype(np.float64)
+            A = oracle.xengine_int(oracle.quantize_int8(Y, scale), A)
+        else:
+            V = oracle.xengine(Y, V)
+        tx += time.perf_counter() - t1
+        tf += t1 - t0
+    t1 = time.perf_counter()
+    if prec == "int8":
+        V = oracle.scale_visibilities(A, scale)
+    tx += time.perf_counter() - t1
     assert np.isfinite(V).all()
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return N * T_sample / (2 * dt) / 1e6, dt, cores
+    bw = lambda t: N * T_sample / (2 * t) / 1e6
+    return {"value": bw(tf + tx), "threads": used, "t_s": tf + tx, "f_engine_mhz": bw(tf), "x_engine_mhz": bw(tx),
+            "f_s": tf, "x_s": tx, "spectra": T_sample}
+
+
+def cpu_baseline_record(S, N, prec, sample_all, sample_one):
+    """cpu_baseline at every host core (the reported value) and at one thread."""
+    ncores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    allc = cpu_baseline(S, N, sample_all, ncores, prec)
+    one = cpu_baseline(S, N, sample_one, 1, prec)
+    _omp_set_threads(ncores)
+    desc = ("%s path of the oracle (FP64 F-engine: DFT and Eq. 2 phase; %s), %d signals, N = %d"
+            % (prec, "int8 requantisation + int64 X-engine + FP64 scaling" if prec == "int8" else
+               "FP64 X-engine", S, N))
+    return {"value": round(allc["value"], 4), "unit": "MHz", "cores": allc["threads"], "kind": "oracle",
+            "sample": "%d spectra (%.1f s) of the workload's shape; %s" % (allc["spectra"], allc["t_s"], desc),
+            "cpu_model": cpu_model(),
+            "f_engine_mhz": round(allc["f_engine_mhz"], 4), "x_engine_mhz": round(allc["x_engine_mhz"], 4),
+            "f_s": round(allc["f_s"], 3), "x_s": round(allc["x_s"], 3),
+            "single_thread": {"value": round(one["value"], 5), "cores": one["threads"],
+                              "sample": "%d spectra (%.1f s)" % (one["spectra"], one["t_s"]),
+                              "f_engine_mhz": round(one["f_engine_mhz"], 5),
+                              "x_engine_mhz": round(one["x_engine_mhz"], 5)}}
 
 
 BATCH_SHAPES = [  # (signals, channels, spectra) of the six uneven sub-arrays
@@ -273,7 +356,7 @@ def bench_batch(args):
         b.launch(stream)
         e1.record(stream)
     stream.synchronize()
-    t = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev])) * 1e-3
+    t = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev])) * 1e-3
     per = []
     tot_bw = tot_ops = 0.0
     for (S, C, T) in BATCH_SHAPES:
@@ -351,7 +434,7 @@ def bench_rfi(args):
         step(e)
     torch.cuda.synchronize()
     plan.check_device_errors()
-    t = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in ev])) * 1e-3 for i, n in enumerate(names)}
+    t = {n: float(np.median([e[i].elapsed_time(e[i + 1]) for e in ev])) * 1e-3 for i, n in enumerate(names)}
     # the MAD flagger on the same power (the fallback and the network's teacher), timed apart
     mad = plan.alloc("flags", zero=False)
     em = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
@@ -361,8 +444,8 @@ def bench_rfi(args):
         plan.mad_flag(power, mad, 3.0, stream=st)
         e1.record(st)
     torch.cuda.synchronize()
-    t_mad = float(np.mean([e0.elapsed_time(e1) for e0, e1 in em])) * 1e-3
-    t_step = float(np.mean([e[0].elapsed_time(e[6]) for e in ev])) * 1e-3
+    t_mad = float(np.median([e0.elapsed_time(e1) for e0, e1 in em])) * 1e-3
+    t_step = float(np.median([e[0].elapsed_time(e[6]) for e in ev])) * 1e-3
     cells = S * T * C
     cnn_flops = float(cells) * CNN_FLOP_PER_CELL
     ach = cnn_flops / t["cnn_infer"] / 1e12
@@ -454,7 +537,7 @@ def bench_blanker(corr, torch, synth, S, n, x_dev, geo, steps, warmup, block=163
     frac = counts.sum().item() / (S * n)
     del x_rfi, y, table, counts
     torch.cuda.empty_cache()
-    return {"ms_out_of_place": ms_out, "ms_in_place": float(np.mean(ms_in[1:])), "blanked_fraction": frac,
+    return {"ms_out_of_place": ms_out, "ms_in_place": float(np.median(ms_in[1:])), "blanked_fraction": frac,
             "bytes_out_of_place": 2.0 * S * n, "bytes_read": 1.0 * S * n}
 
 
@@ -482,7 +565,7 @@ def bench_gated(corr, torch, S, N, T, x_dev, rs, g_dev, scale, steps, warmup, pe
         for b in range(2):
             plan.integrate(acc[b * words:(b + 1) * words], states[b], None, scale, flags=0)
     torch.cuda.synchronize()
-    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
     del spec, acc, states, plan
     torch.cuda.empty_cache()
     return ms
@@ -584,10 +667,14 @@ def main():
     ap.add_argument("--config", default="c3", choices=sorted(CONFIGS) + ["c4", "c5"])
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="skip the legs beside the step (beams, blanker, ...)")
     ap.add_argument("--streamed", action="store_true",
                     help="also time blocks streamed (F of block i+1 beside X of block i) and report that as the value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2048, help="spectra in the CPU-oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="spectra in the all-core CPU-oracle sample (default 2048 for c3, 8192 for c2)")
+    ap.add_argument("--cpu-sample-1t", type=int, default=None,
+                    help="spectra in the one-thread CPU-oracle sample (default 128 for c3, 512 for c2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -603,56 +690,64 @@ def main():
     import synth
 
     S, N, T, desc = CONFIGS[args.config]
+    gmrt = args.config == "c2"  # FP32 form with 8 point sources; c3 is the int8 precision form
     C = N // 2
     torch.cuda.set_device(0)
     geo = synth.make_geometry(S // 2, seed=synth.BASE_SEED + 2)
     rs = (N * T + 16 + 255) // 256 * 256
     log("generating %d x %d int8 samples on the GPU" % (S, rs))
-    x_dev = synth.voltages_device(S, N * T + 16, geo, seed=synth.BASE_SEED + 2, tone_bin=37, tone_N=N,
-                                  row_stride=rs)
+    if gmrt:
+        src = synth.point_sources(S, 8, 0.3, seed=synth.BASE_SEED + 2)
+        x_dev = synth.voltages_device_physical(S, N * T + 16, geo, FS, seed=synth.BASE_SEED + 2, sources=src,
+                                               tone_bin=37, tone_N=N, row_stride=rs)
+    else:
+        x_dev = synth.voltages_device(S, N * T + 16, geo, seed=synth.BASE_SEED + 2, tone_bin=37, tone_N=N,
+                                      row_stride=rs)
     g_dev = corr.geom_to_device(corr.geom_array(geo.D, geo.f, geo.psi0, geo.rate))
     # a plain elementwise copy of known size (reads 1 GiB, writes 1 GiB; its kernel
     # is named neg_kernel), outside the timed region: the reference that scales
     # the HBM byte counters of a profiled run
-    src = x_dev.view(-1)[: 1 << 30].view(torch.int32)
-    torch.neg(src, out=torch.empty_like(src))
-    del src
+    src_c = x_dev.view(-1)[: 1 << 30].view(torch.int32)
+    torch.neg(src_c, out=torch.empty_like(src_c))
+    del src_c
     torch.cuda.synchronize()
 
     log("calibrating int8 scales")
     scale = calibrate_scales(corr, torch, S, N, T, x_dev, rs, g_dev)
-    log("timing int8 path: %d warmup + %d steps" % (args.warmup, args.steps))
+    log("timing int8 path: %d warmup + %d steps (eager, then graph replays)" % (args.warmup, args.steps))
     r8 = run_path(corr, torch, corr.INT8, S, N, T, x_dev, rs, g_dev, args.steps, args.warmup, scale)
-    log("int8: step %.3f ms (F %.3f, X %.3f, int %.3f)" % (r8["t_step"] * 1e3, r8["t_f"] * 1e3,
-                                                          r8["t_x"] * 1e3, r8["t_int"] * 1e3))
+    log("int8: step %.3f ms (F %.3f, X %.3f, int %.3f; eager step %.3f)" % (
+        r8["t_step"] * 1e3, r8["t_f"] * 1e3, r8["t_x"] * 1e3, r8["t_int"] * 1e3, r8["t_eager_step"] * 1e3))
     t8 = r8["t_step"]
     if args.streamed:
         torch.cuda.empty_cache()
         t8 = run_pipelined(corr, torch, corr.INT8, S, N, T, x_dev, rs, g_dev, args.steps, args.warmup, scale)
         log("int8 streamed (F of block i+1 beside X of block i): %.3f ms per block" % (t8 * 1e3))
-    torch.cuda.empty_cache()
-    log("timing the beamformer (one incoherent + one full-polar coherent beam)")
-    tb_ms, tb_bytes = bench_beamformer(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
-    log("beamformer: %.3f ms per call" % tb_ms)
-    torch.cuda.empty_cache()
-    log("timing the voltage blanker (blocks of 16384 samples, M = 3, impulsive bursts on a copy of the input)")
-    rb = bench_blanker(corr, torch, synth, S, N * T + 16, x_dev, geo, args.steps, args.warmup)
-    log("blanker: %.3f ms out of place, %.3f ms in place, %.4f of the samples blanked"
-        % (rb["ms_out_of_place"], rb["ms_in_place"], rb["blanked_fraction"]))
-    log("timing the gated X-engine (two pulse-phase gates)")
-    tg_ms = bench_gated(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
-    log("gated X-engine: %.3f ms per call (ungated %.3f ms)" % (tg_ms, r8["t_x"] * 1e3))
-    log("timing the int8 F-engine with the 1440-step phase table")
-    tt_ms = bench_table_phase(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
-    log("table-phase F-engine: %.3f ms (direct sincos %.3f ms)" % (tt_ms, r8["t_f"] * 1e3))
-    log("timing coherent dedispersion of one beam (DM 71 at 325 MHz)")
-    rd = bench_dedisperse(corr, torch, N, T, max(2, args.steps // 2), min(1, args.warmup))
-    log("dedispersion: %.3f ms per %.2f s block (%.0fx real time)" % (rd[0], rd[2], rd[2] / (rd[0] * 1e-3)))
-    log("timing the ADC demultiplexing and unpacking (4-bit and 8-bit card streams)")
-    ra = bench_adc(corr, torch, S, N * T + 16, args.steps, args.warmup)
-    log("adc unpack: %.3f ms (4-bit), %.3f ms (8-bit)" % (ra[4][0], ra[8][0]))
+    legs = not (args.no_legs or gmrt)
+    if legs:
+        torch.cuda.empty_cache()
+        log("timing the beamformer (one incoherent + one full-polar coherent beam)")
+        tb_ms, tb_bytes = bench_beamformer(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
+        log("beamformer: %.3f ms per call" % tb_ms)
+        torch.cuda.empty_cache()
+        log("timing the voltage blanker (blocks of 16384 samples, M = 3, impulsive bursts on a copy of the input)")
+        rb = bench_blanker(corr, torch, synth, S, N * T + 16, x_dev, geo, args.steps, args.warmup)
+        log("blanker: %.3f ms out of place, %.3f ms in place, %.4f of the samples blanked"
+            % (rb["ms_out_of_place"], rb["ms_in_place"], rb["blanked_fraction"]))
+        log("timing the gated X-engine (two pulse-phase gates)")
+        tg_ms = bench_gated(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
+        log("gated X-engine: %.3f ms per call (ungated %.3f ms)" % (tg_ms, r8["t_x"] * 1e3))
+        log("timing the int8 F-engine with the 1440-step phase table")
+        tt_ms = bench_table_phase(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
+        log("table-phase F-engine: %.3f ms (direct sincos %.3f ms)" % (tt_ms, r8["t_f"] * 1e3))
+        log("timing coherent dedispersion of one beam (DM 71 at 325 MHz)")
+        rd = bench_dedisperse(corr, torch, N, T, max(2, args.steps // 2), min(1, args.warmup))
+        log("dedispersion: %.3f ms per %.2f s block (%.0fx real time)" % (rd[0], rd[2], rd[2] / (rd[0] * 1e-3)))
+        log("timing the ADC demultiplexing and unpacking (4-bit and 8-bit card streams)")
+        ra = bench_adc(corr, torch, S, N * T + 16, args.steps, args.warmup)
+        log("adc unpack: %.3f ms (4-bit), %.3f ms (8-bit)" % (ra[4][0], ra[8][0]))
     r8f = None
-    if not args.no_fp8:
+    if not args.no_fp8 and not gmrt:
         torch.cuda.empty_cache()
         log("timing fp8 (e4m3) path")
         scale8 = calibrate_scales(corr, torch, S, N, T, x_dev, rs, g_dev, corr.FP8_E4M3)
@@ -663,11 +758,11 @@ def main():
         del scale8
     r32 = None
     t32 = None
-    if not args.no_fp32:
+    if gmrt or not args.no_fp32:
         torch.cuda.empty_cache()
+        n32 = args.steps if gmrt else max(3, args.steps // 4)
         log("timing fp32 path")
-        r32 = run_path(corr, torch, corr.FP32, S, N, T, x_dev, rs, g_dev, max(3, args.steps // 4),
-                       min(2, args.warmup))
+        r32 = run_path(corr, torch, corr.FP32, S, N, T, x_dev, rs, g_dev, n32, args.warmup)
         log("fp32: step %.3f ms (F %.3f, X %.3f, int %.3f)" % (r32["t_step"] * 1e3, r32["t_f"] * 1e3,
                                                               r32["t_x"] * 1e3, r32["t_int"] * 1e3))
         t32 = r32["t_step"]
@@ -679,99 +774,115 @@ def main():
 
     bw = lambda t: N * T / (2.0 * t) / 1e6  # correlated bandwidth, MHz
     xops8, xin8 = x_algorithmic(S, N, T, 2)
+    xops32, xin32 = x_algorithmic(S, N, T, 8)
     ff8, fb8 = f_algorithmic(S, N, T, 2)
+    ff32, fb32 = f_algorithmic(S, N, T, 8)
+    head, t_head = (r32, t32) if gmrt else (r8, t8)
     out = {
         "metric": "correlated bandwidth (MHz) & X-engine TOP/s, 64 signals: int8-MFMA vs FP32",
-        "value": round(bw(t8), 3),
+        "value": round(bw(t_head), 3),
         "unit": "MHz",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t8 * 1e3, 4),
+        "ms_per_step": round(t_head * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
-        "data": "synthetic (seeded Gaussian + common source + tone, generated on the GPU)",
+        "dtype": "f32" if gmrt else "int8",
+        "data": ("synthetic (seeded physical recipe on the GPU: fractional delays, fringe rotation, 8 point "
+                 "sources + noise + tone)" if gmrt else
+                 "synthetic (seeded Gaussian + common source + tone, generated on the GPU)"),
         "config": {"workload": desc, "signals": S, "fft_len": N, "channels": C, "spectra": T,
                    "pairs": S * (S + 1) // 2, "sample_rate_hz": FS, "parallelism": "single GPU"},
-        "step_mode": "streamed: F-engine of block i+1 beside X-engine + integrate of block i (two streams, "
-                     "two spectra buffers)" if args.streamed else "one stream: F-engine, X-engine, integrate",
-        "int8": {"x_engine_tops": round(xops8 / r8["t_x"] / 1e12, 3),
+        "step_mode": ("streamed: F-engine of block i+1 beside X-engine + integrate of block i (two streams, "
+                      "two spectra buffers)" if args.streamed else
+                      "one HIP graph replay of F-engine, X-engine, integrate (median of the timed replays; "
+                      "per-kernel times: median of eager steps)"),
+        "int8": {"correlated_bandwidth_mhz": round(bw(t8), 3),
+                 "x_engine_tops": round(xops8 / r8["t_x"] / 1e12, 3),
                  "ms": {k: round(v * 1e3, 4) for k, v in r8.items() if k.startswith("t_")},
-                 "sequential_step_ms": round(r8["t_step"] * 1e3, 4),
-                 "x_splits": r8["splits"]},
+                 "x_splits": r8["splits"], "graph_matches_eager": r8.get("graph_matches_eager")},
     }
-    # dominant kernel of the int8 step and its roofline
-    tf, tx = r8["t_f"], r8["t_x"]
-    x_part = {"kernel": "xengine_kernel<2, 1> (int8 MFMA X-engine)", "bound": "hbm",
-              "achieved_gbs": round(xin8 / tx / 1e9, 1), "hbm_frac": round(xin8 / tx / HBM_PEAK, 4),
-              "mfma_frac_algorithmic": round(xops8 / tx / INT8_PEAK, 4)}
-    f_part = {"kernel": "fengine_kernel<log2M, 1> (int8 F-engine)",
-              "alu_tflops": round(ff8 / tf / 1e12, 3), "alu_frac": round(ff8 / tf / FP32_VALU_PEAK, 4),
-              "hbm_gbs": round(fb8 / tf / 1e9, 1), "hbm_frac": round(fb8 / tf / HBM_PEAK, 4)}
-    if tf >= tx:
-        bound = "alu" if ff8 / FP32_VALU_PEAK > fb8 / HBM_PEAK else "hbm"
-        if bound == "alu":
-            ach, peak, unit = ff8 / tf / 1e12, FP32_VALU_PEAK / 1e12, "TFLOP/s"
-        else:
-            ach, peak, unit = fb8 / tf / 1e9, HBM_PEAK / 1e9, "GB/s"
-        kern, traffic = f_part["kernel"], measured_traffic("fengine_int8_%s" % args.config)
+
+    def f_roof(tf, fflops, fbytes, kernel):
+        # HBM-bound by the algorithmic bytes (N int8 in, C channels x code size out per spectrum);
+        # the FP32 vector fraction beside it against both the non-packed issue rate (this library
+        # never emits packed FP32) and the published 157.3 TF
+        return {"kernel": kernel, "bound": "hbm", "achieved": round(fbytes / tf / 1e9, 1), "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": round(fbytes / tf / HBM_PEAK, 4), "algorithmic_bytes": fbytes,
+                "valu_tflops": round(fflops / tf / 1e12, 3),
+                "valu_frac_nonpacked_78.6TF": round(fflops / tf / FP32_VALU_PEAK, 4),
+                "valu_frac_published_157.3TF": round(fflops / tf / FP32_PUBLISHED_PEAK, 4)}
+
+    if gmrt:
+        tf, tx = r32["t_f"], r32["t_x"]
+        f_part = f_roof(tf, ff32, fb32, "fengine_kernel<9, 0> (FP32 F-engine)")
+        x_part = {"kernel": "xengine_kernel<2, 0> (FP32 MFMA X-engine)", "bound": "mfma",
+                  "achieved": round(xops32 / tx / 1e12, 3), "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                  "frac": round(xops32 / tx / FP32_MFMA_PEAK, 4), "hbm_gbs": round(xin32 / tx / 1e9, 1)}
+        dom = f_part if tf >= tx else x_part
+        traffic = measured_traffic("fengine_fp32_c2") if tf >= tx else None
     else:
-        bound, ach, peak, unit = "hbm", xin8 / tx / 1e9, HBM_PEAK / 1e9, "GB/s"
-        kern, traffic = x_part["kernel"], None
-    out["roofline"] = {"kernel": kern, "bound": bound, "achieved": round(ach, 3), "peak": round(peak, 2),
-                       "unit": unit, "frac": round(ach / peak, 4), "traffic": traffic,
-                       "f_engine": f_part, "x_engine": x_part}
-    out["beamformer"] = {"kernel": "beam_kernel<int8, 1 beam> (B-engine)", "bound": "hbm",
-                         "beams": "1 incoherent (2 pol) + 1 coherent full-polar (4 products), tint 1",
-                         "ms": round(tb_ms, 4), "achieved_gbs": round(tb_bytes / tb_ms / 1e6, 1),
-                         "hbm_frac": round(tb_bytes / tb_ms / 1e6 / (HBM_PEAK / 1e9), 4),
-                         "algorithmic_bytes": tb_bytes,
-                         "traffic": measured_traffic("beam_int8_%s" % args.config)}
-    gbs = rb["bytes_out_of_place"] / rb["ms_out_of_place"] / 1e6
-    out["voltage_blanker"] = {
-        "kernel": "blank_kernel<4> (MAD blanker, blocks of 16384 samples)", "bound": "hbm",
-        "input": "the int8 input rows with impulsive bursts added to about 2.5 % of the samples",
-        "blanked_fraction": round(rb["blanked_fraction"], 5),
-        "ms_out_of_place": round(rb["ms_out_of_place"], 4), "achieved_gbs": round(gbs, 1),
-        "hbm_frac": round(gbs / (HBM_PEAK / 1e9), 4), "algorithmic_bytes": rb["bytes_out_of_place"],
-        "traffic": measured_traffic("blank_out_%s" % args.config),
-        "ms_in_place": round(rb["ms_in_place"], 4),
-        "in_place_read_gbs": round(rb["bytes_read"] / rb["ms_in_place"] / 1e6, 1),
-        "traffic_in_place": measured_traffic("blank_in_%s" % args.config),
-        "share_of_step": round(rb["ms_in_place"] / (t8 * 1e3), 4)}
-    out["gated_xengine"] = {
-        "kernel": "xengine_gated_kernel<2, int8> (two pulse-phase gates, one launch)", "bound": "hbm",
-        "ms": round(tg_ms, 4), "ungated_ms": round(r8["t_x"] * 1e3, 4),
-        "achieved_gbs": round(xin8 / (tg_ms * 1e-3) / 1e9, 1),
-        "hbm_frac": round(xin8 / (tg_ms * 1e-3) / HBM_PEAK, 4),
-        "mfma_frac_issued": round(2 * xops8 / (tg_ms * 1e-3) / INT8_PEAK, 4)}
-    out["table_phase_fengine"] = {
-        "kernel": "fengine_kernel<log2M, 5> (int8, phase from the 1440-step table)", "bound": "alu",
-        "ms": round(tt_ms, 4), "direct_sincos_ms": round(r8["t_f"] * 1e3, 4),
-        "alu_frac": round(ff8 / (tt_ms * 1e-3) / FP32_VALU_PEAK, 4)}
-    out["coherent_dedispersion"] = {
-        "kernel": "dd_fft_kernel<log2R> passes + chirp + detection (one beam, two polarisations)", "bound": "hbm",
-        "block": "%d spectra x %d channels = 2^%d complex samples per polarisation" % (T, N // 2, int(np.log2(T * N // 2))),
-        "dm": 71.0, "nu0_hz": 325e6, "ms": round(rd[0], 4), "block_seconds": round(rd[2], 4),
-        "real_time_factor": round(rd[2] / (rd[0] * 1e-3), 1), "valid_fraction": round(rd[3], 4),
-        "pass_bytes": rd[1], "achieved_gbs": round(rd[1] / rd[0] / 1e6, 1),
-        "hbm_frac": round(rd[1] / rd[0] / 1e6 / (HBM_PEAK / 1e9), 4)}
-    out["adc_unpack"] = {
-        "kernel": "adc_unpack_kernel<bits> (4-input demultiplexing, 4-bit to 8-bit)", "bound": "hbm",
-        "cards": S // 4,
-        **{"bits%d" % b: {"ms": round(ra[b][0], 4), "algorithmic_bytes": ra[b][1],
-                           "achieved_gbs": round(ra[b][1] / ra[b][0] / 1e6, 1),
-                           "hbm_frac": round(ra[b][1] / ra[b][0] / 1e6 / (HBM_PEAK / 1e9), 4)} for b in (4, 8)}}
+        tf, tx = r8["t_f"], r8["t_x"]
+        f_part = f_roof(tf, ff8, fb8, "fengine_kernel<11, 1> (int8 F-engine)")
+        x_part = {"kernel": "xengine_kernel<2, 1> (int8 MFMA X-engine)", "bound": "hbm",
+                  "achieved": round(xin8 / tx / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                  "frac": round(xin8 / tx / HBM_PEAK, 4), "mfma_frac_algorithmic": round(xops8 / tx / INT8_PEAK, 4)}
+        dom = f_part if tf >= tx else x_part
+        traffic = measured_traffic("fengine_int8_%s" % args.config) if tf >= tx else None
+    out["roofline"] = {k: dom[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}
+    out["roofline"]["traffic"] = traffic
+    out["roofline"]["f_engine"] = f_part
+    out["roofline"]["x_engine"] = x_part
+    if legs:
+        out["beamformer"] = {"kernel": "beam_kernel<int8, 1 beam> (B-engine)", "bound": "hbm",
+                             "beams": "1 incoherent (2 pol) + 1 coherent full-polar (4 products), tint 1",
+                             "ms": round(tb_ms, 4), "achieved_gbs": round(tb_bytes / tb_ms / 1e6, 1),
+                             "hbm_frac": round(tb_bytes / tb_ms / 1e6 / (HBM_PEAK / 1e9), 4),
+                             "algorithmic_bytes": tb_bytes,
+                             "traffic": measured_traffic("beam_int8_%s" % args.config)}
+        gbs = rb["bytes_out_of_place"] / rb["ms_out_of_place"] / 1e6
+        out["voltage_blanker"] = {
+            "kernel": "blank_kernel<4> (MAD blanker, blocks of 16384 samples)", "bound": "hbm",
+            "input": "the int8 input rows with impulsive bursts added to about 2.5 % of the samples",
+            "blanked_fraction": round(rb["blanked_fraction"], 5),
+            "ms_out_of_place": round(rb["ms_out_of_place"], 4), "achieved_gbs": round(gbs, 1),
+            "hbm_frac": round(gbs / (HBM_PEAK / 1e9), 4), "algorithmic_bytes": rb["bytes_out_of_place"],
+            "traffic": measured_traffic("blank_out_%s" % args.config),
+            "ms_in_place": round(rb["ms_in_place"], 4),
+            "in_place_read_gbs": round(rb["bytes_read"] / rb["ms_in_place"] / 1e6, 1),
+            "traffic_in_place": measured_traffic("blank_in_%s" % args.config),
+            "share_of_step": round(rb["ms_in_place"] / (t8 * 1e3), 4)}
+        out["gated_xengine"] = {
+            "kernel": "xengine_gated_kernel<2, int8> (two pulse-phase gates, one launch)", "bound": "hbm",
+            "ms": round(tg_ms, 4), "ungated_ms": round(r8["t_x"] * 1e3, 4),
+            "achieved_gbs": round(xin8 / (tg_ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(xin8 / (tg_ms * 1e-3) / HBM_PEAK, 4),
+            "mfma_frac_issued": round(2 * xops8 / (tg_ms * 1e-3) / INT8_PEAK, 4)}
+        out["table_phase_fengine"] = {
+            "kernel": "fengine_kernel<log2M, 5> (int8, phase from the 1440-step table)", "bound": "hbm",
+            "ms": round(tt_ms, 4), "direct_sincos_ms": round(r8["t_f"] * 1e3, 4),
+            "hbm_frac": round(fb8 / (tt_ms * 1e-3) / HBM_PEAK, 4)}
+        out["coherent_dedispersion"] = {
+            "kernel": "dd_fft_kernel<log2R> passes + chirp + detection (one beam, two polarisations)", "bound": "hbm",
+            "block": "%d spectra x %d channels = 2^%d complex samples per polarisation" % (T, N // 2, int(np.log2(T * N // 2))),
+            "dm": 71.0, "nu0_hz": 325e6, "ms": round(rd[0], 4), "block_seconds": round(rd[2], 4),
+            "real_time_factor": round(rd[2] / (rd[0] * 1e-3), 1), "valid_fraction": round(rd[3], 4),
+            "pass_bytes": rd[1], "achieved_gbs": round(rd[1] / rd[0] / 1e6, 1),
+            "hbm_frac": round(rd[1] / rd[0] / 1e6 / (HBM_PEAK / 1e9), 4)}
+        out["adc_unpack"] = {
+            "kernel": "adc_unpack_kernel<bits> (4-input demultiplexing, 4-bit to 8-bit)", "bound": "hbm",
+            "cards": S // 4,
+            **{"bits%d" % b: {"ms": round(ra[b][0], 4), "algorithmic_bytes": ra[b][1],
+                               "achieved_gbs": round(ra[b][1] / ra[b][0] / 1e6, 1),
+                               "hbm_frac": round(ra[b][1] / ra[b][0] / 1e6 / (HBM_PEAK / 1e9), 4)} for b in (4, 8)}}
     if r32:
-        xops32, xin32 = x_algorithmic(S, N, T, 8)
         out["fp32"] = {"correlated_bandwidth_mhz": round(bw(t32), 3), "ms_per_step": round(t32 * 1e3, 4),
-                       "sequential_step_ms": round(r32["t_step"] * 1e3, 4),
                        "x_engine_tops": round(xops32 / r32["t_x"] / 1e12, 3),
                        "ms": {k: round(v * 1e3, 4) for k, v in r32.items() if k.startswith("t_")},
                        "x_mfma_frac_algorithmic": round(xops32 / r32["t_x"] / FP32_MFMA_PEAK, 4),
-                       "x_splits": r32["splits"]}
+                       "x_splits": r32["splits"], "graph_matches_eager": r32.get("graph_matches_eager")}
         out["int8_vs_fp32_speedup"] = round(t32 / t8, 3)
     if r8f:
         out["fp8_e4m3"] = {"correlated_bandwidth_mhz": round(bw(r8f["t_step"]), 3),
@@ -781,11 +892,12 @@ def main():
                            "x_hbm_frac": round(xin8 / r8f["t_x"] / HBM_PEAK, 4),
                            "x_splits": r8f["splits"]}
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on %d spectra" % args.cpu_sample)
-        mhz, dt, cores = cpu_baseline(S, N, args.cpu_sample)
-        out["cpu_baseline"] = {"value": round(mhz, 4), "unit": "MHz", "cores": cores, "kind": "oracle",
-                               "sample": "%d spectra x %d signals, N=%d, int8 path (FP64 F-engine, "
-                                         "int64 X-engine), %.1f s" % (args.cpu_sample, S, N, dt)}
+        prec = "fp32" if gmrt else "int8"
+        args.cpu_sample = args.cpu_sample or (8192 if gmrt else 2048)
+        args.cpu_sample_1t = args.cpu_sample_1t or (512 if gmrt else 128)
+        log("cpu baseline: oracle (%s path) on %d spectra at all cores and %d at one thread"
+            % (prec, args.cpu_sample, args.cpu_sample_1t))
+        out["cpu_baseline"] = cpu_baseline_record(S, N, prec, args.cpu_sample, args.cpu_sample_1t)
     print(json.dumps(out), flush=True)
 
 

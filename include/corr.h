@@ -18,7 +18,7 @@
  *   RFI        the MAD statistic of section 5 (Eq. 3 and 4) on power tiles
  *              with zeroing and exact pair counts, a learned flagger, and
  *              the time-domain voltage blanker with noise replacement.
- *   B-engine   incoherent and coherent array beams (section 3).
+ *   B-engine   incoherent and coherent array beams (section 2.2).
  *
  * Conventions used everywhere below
  *   S   number of signals (antenna a, polarisation pol -> s = 2a + pol)
@@ -121,6 +121,41 @@ typedef struct {
 } corr_geom_t;
 
 typedef struct corr_plan corr_plan_t;
+
+/*
+ * Geometry of one call from an antenna-based delay model (section 2.1, Eq. 1
+ * and Eq. 2; host arithmetic in FP64, like the per-slice delay parameters of
+ * section 2.3.2).  The total delay of signal s at stream time t (seconds
+ * since sample 0 of its row) is
+ *   tau_s(t) = h_tau0[s] + h_taudot[s] (t - t0)        (seconds, s/s)
+ * and the call's geometry is
+ *   D_s + f_s = tau_s(t_delay) * sample_rate, D_s = floor(.), f_s in [0, 1):
+ *       the integer delay (read-pointer advance) and the fractional sample
+ *       time correction, held for the whole call (t_delay is normally the
+ *       call's centre);
+ *   psi0_s + rate_s t_m = nu_lo * tau_s(t_m + tau_s(t_delay)): the fringe
+ *       term (nu_RF - nu_BB) tau_tot of Eq. 2, nu_lo = nu_RF - nu_BB >= 0 the
+ *       local-oscillator frequency, at the time the samples of spectrum m
+ *       arrived -- its aligned time stamp t_m (corr_geom_t) plus the delay
+ *       the read pointer skips (rate * tau is up to 6.4e-4 cycles at 5 Hz and
+ *       128 us).  So rate_s = nu_lo * h_taudot[s] (Hz) and psi0_s =
+ *       nu_lo * (tau_s(0) + h_taudot[s] tau_s(t_delay)) reduced mod 1
+ *       (cycles).  Its sign is the plan's sideband, which the F-engine
+ *       applies.
+ * f_s is stored as float: a fraction that rounds up to 1 is carried into D_s.
+ * nu_lo * tau_s(0) is formed with error-free transforms (the rounding errors
+ * of its products and difference are kept and added after the reduction mod
+ * 1), so psi0 carries ~1e-16 cycles of error for any nu_lo tau below 2^50
+ * cycles -- 1.4 GHz x 128 us is 179200 cycles.
+ *   n_signals >= 1; h_tau0, h_taudot: double[n_signals]; h_geom: corr_geom_t
+ *   [n_signals] (host).  max_delay >= 0 bounds D_s (pass the plan's).
+ * Errors: NULL, INVALID (n_signals < 1, a non-finite input, sample_rate <= 0,
+ * nu_lo < 0, or a signal whose D_s falls outside [0, max_delay]); the message
+ * names the signal, via corr_last_error(NULL).  Nothing is written on error.
+ */
+corr_status corr_geom_from_model(int32_t n_signals, const double *h_tau0, const double *h_taudot, double t0,
+                                 double t_delay, double sample_rate, double nu_lo, int32_t max_delay,
+                                 corr_geom_t *h_geom);
 
 /* ----------------------------------------------------------------- plans */
 
@@ -234,8 +269,8 @@ corr_status corr_pulsar_gates(int64_t spectrum0, int64_t n_spectra, int32_t fft_
 /* ------------------------------------------------------------- beamformer */
 
 /*
- * Array beams from X-layout spectra: the two beamformer modes of section 3,
- * on the F-engine output as in section 4 (one incoherent and coherent beams
+ * Array beams from X-layout spectra: the two beamformer modes of section 2.2,
+ * on the F-engine output as in section 2.3.2 (one incoherent and coherent beams
  * at the raw FFT time resolution, optionally summed over a few spectra).
  * Per spectrum m, channel k and polarisation pol (signals s = 2a + pol; an
  * odd S leaves the last antenna with polarisation 0 only), with Y_s the
@@ -453,7 +488,9 @@ typedef struct {
     uint32_t flags;          /* corr_integrate flags                           */
 } corr_batch_io_t;
 
-/* Errors: NULL, INVALID (count), UNSUPPORTED (non-INT8), DEVICE, NOMEM. */
+/* Errors: NULL, INVALID (count, scale mode), UNSUPPORTED (non-INT8), OVERFLOW
+ * (an entry with more than 66572 spectra: one run sums its whole call in the
+ * int32 accumulator before integrating it), DEVICE, NOMEM. */
 corr_status corr_batch_create(const corr_desc_t *descs, int n, corr_batch_t **out);
 void corr_batch_destroy(corr_batch_t *batch);
 /* Sub-plan i (owned by the batch): query its sizes and bind its workspace. */

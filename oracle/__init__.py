@@ -120,6 +120,46 @@ class Geometry:
         self.rate = np.ascontiguousarray(rate, dtype=np.float64)
 
 
+def geom_from_model(tau0, taudot, fs: float, nu_lo: float, t0: float = 0.0, t_delay: float = 0.0) -> Geometry:
+    """Per-call geometry from an antenna-based delay model (section 2.1, Eq. 1-2).
+
+    tau_s(t) = tau0[s] + taudot[s] (t - t0) seconds at stream time t.  The
+    integer delay and the fractional sample-time correction are taken at
+    t_delay: D + f = tau_s(t_delay) fs, D = floor, f in [0, 1) (f kept as the
+    nearest float32, a fraction that rounds to 1 carried into D).  The fringe
+    term of Eq. 2, nu_lo tau_tot(t), is taken when the samples of a spectrum
+    arrived: at its aligned time stamp t_m plus the delay tau_c = tau_s(t_delay)
+    that the read pointer skips, so psi0 + rate t_m = nu_lo tau_s(t_m + tau_c):
+    rate = nu_lo taudot[s], psi0 = nu_lo (tau_s(0) + taudot[s] tau_c) mod 1
+    (the sideband sign is the F-engine's).
+
+    Evaluated in exact rational arithmetic on the binary values of the inputs
+    (fractions.Fraction), each result rounded once at the end.
+    """
+    from fractions import Fraction as Fr
+    tau0 = np.atleast_1d(np.asarray(tau0, dtype=np.float64))
+    taudot = np.atleast_1d(np.asarray(taudot, dtype=np.float64))
+    S = tau0.size
+    D = np.zeros(S, dtype=np.int32)
+    f = np.zeros(S)
+    psi0 = np.zeros(S)
+    rate = np.zeros(S)
+    for s in range(S):
+        a, b = Fr(float(tau0[s])), Fr(float(taudot[s]))
+        x = (a + b * (Fr(float(t_delay)) - Fr(float(t0)))) * Fr(float(fs))
+        d = x.numerator // x.denominator                # floor of the exact value
+        fr = float(np.float32(float(x - d)))            # the fraction, nearest float32
+        if fr >= 1.0:
+            d, fr = d + 1, 0.0
+        c = Fr(float(nu_lo)) * (a - b * Fr(float(t0)) + b * x / Fr(float(fs)))  # cycles at t_m = 0
+        c -= c.numerator // c.denominator               # mod 1, exactly
+        D[s], f[s], psi0[s] = d, fr, float(c)
+        if psi0[s] >= 1.0:
+            psi0[s] = 0.0
+        rate[s] = float(Fr(float(nu_lo)) * b)
+    return Geometry(D, f, psi0, rate)
+
+
 def fengine(x: np.ndarray, N: int, T: int, geom: Geometry, fs: float, nu_bb: float = 0.0,
             sideband: int = 1, spectrum0: int = 0, method: str = "fft") -> np.ndarray:
     """F-engine of section 2.1 / 2.3.2 with Eq. 2 phase; returns Y[S][T][C] complex128.
@@ -221,7 +261,7 @@ def xengine_int(q: np.ndarray, A: np.ndarray | None = None) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Array beams (section 3)
+# Array beams (section 2.2)
 # ---------------------------------------------------------------------------
 BEAM_INTENSITY, BEAM_FULLPOL, BEAM_VOLTAGE = 0, 1, 2
 
@@ -230,7 +270,7 @@ def beamform(Y: np.ndarray, w=None, c=None, mode: int = BEAM_FULLPOL, tint: int 
     """Incoherent beam (detected intensities of the selected signals added,
     weights w [S]) and coherent beams (voltages added with complex weights
     c [nb][S], then detected: |V_0|^2, |V_1|^2 and, full-polar, V_0 conj(V_1);
-    or the voltages), the two beamformer modes of section 3.  Y: complex
+    or the voltages), the two beamformer modes of section 2.2.  Y: complex
     [S][T][C]; signal s = 2a + pol.  Returns (inc [2][T/tint][C] or None,
     coh [nb][planes][T/tint][C] or None), sums over tint spectra."""
     Y = np.ascontiguousarray(Y, dtype=np.complex128)

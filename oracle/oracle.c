@@ -21,7 +21,7 @@
  *   requantisation       section 4.1 (fixed-point pipeline up to the MAC,
  *                        32-bit products, float long-term accumulation)
  *   MAD statistic        Eq. 3 and Eq. 4 of section 5
- *   array beams          section 3 (incoherent and coherent beamformer)
+ *   array beams          section 2.2 (incoherent and coherent beamformer)
  *   ADC unpacking        sections 2.3.2 and 3.3 (four-input demultiplexing,
  *                        4-bit samples to 8 bits)
  *   voltage blanker      section 5 (Eq. 3 and 4 on voltage blocks, outliers
@@ -534,7 +534,7 @@ void orc_pair_counts(const uint8_t *flags, int S, int64_t T, int64_t C, int64_t 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Array beams (section 3).  Signal s = 2a + pol.  Per spectrum m, channel k: */
+/* Array beams (section 2.2).  Signal s = 2a + pol.  Per spectrum m, channel k: */
 /*   incoherent  I_pol  = sum over s of pol of  w_s |Y_s|^2                  */
 /*   coherent    V_b,pol = sum over s of pol of  c_b,s Y_s                    */
 /* and the coherent products by mode: 0 |V_0|^2, |V_1|^2; 1 those and Re, Im  */

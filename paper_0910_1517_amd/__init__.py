@@ -77,6 +77,7 @@ SYMBOLS = [
     "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
     "corr_adc_unpack", "corr_adc_last_error", "corr_xengine_gated", "corr_pulsar_gates",
     "corr_dedisperse", "corr_dedisperse_workspace_bytes", "corr_dedisperse_last_error",
+    "corr_geom_from_model",
 ]
 
 
@@ -190,6 +191,9 @@ def lib():
     L.corr_adc_unpack.restype = st
     L.corr_adc_last_error.argtypes = []
     L.corr_adc_last_error.restype = ctypes.c_char_p
+    dbl = ctypes.c_double
+    L.corr_geom_from_model.argtypes = [i32, P, P, dbl, dbl, dbl, dbl, i32, P]
+    L.corr_geom_from_model.restype = st
     L.corr_status_string.argtypes = [st]
     L.corr_status_string.restype = ctypes.c_char_p
     L.corr_last_error.argtypes = [P]
@@ -772,6 +776,23 @@ def geom_array(D, frac, psi0, rate) -> np.ndarray:
     """corr_geom_t[S] as a numpy structured array (host)."""
     g = np.zeros(len(D), dtype=GEOM_DTYPE)
     g["D"], g["frac"], g["psi0"], g["rate"] = D, frac, psi0, rate
+    return g
+
+
+def geom_from_model(tau0, taudot, *, t0: float = 0.0, t_delay: float = 0.0, sample_rate: float,
+                    nu_lo: float, max_delay: int) -> np.ndarray:
+    """corr_geom_t[S] (host structured array) from the delay model
+    tau_s(t) = tau0[s] + taudot[s] (t - t0); see corr_geom_from_model (host arithmetic)."""
+    tau0 = np.ascontiguousarray(tau0, dtype=np.float64)
+    taudot = np.ascontiguousarray(taudot, dtype=np.float64)
+    if tau0.shape != taudot.shape or tau0.ndim != 1:
+        raise ValueError("tau0 and taudot must be 1-D arrays of the same length")
+    g = np.zeros(tau0.size, dtype=GEOM_DTYPE)
+    rc = lib().corr_geom_from_model(tau0.size, tau0.ctypes.data_as(ctypes.c_void_p),
+                                    taudot.ctypes.data_as(ctypes.c_void_p), t0, t_delay, sample_rate, nu_lo,
+                                    max_delay, g.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise CorrError(rc, lib().corr_last_error(None).decode())
     return g
 
 

@@ -1,7 +1,7 @@
 // B-engine: incoherent and coherent (phased) array beams from the X-layout
-// spectra, the beamformer of section 3 (two modes: detected intensities added,
+// spectra, the beamformer of section 2.2 (two modes: detected intensities added,
 // or voltages added and then detected, with the voltage cross products that
-// the Stokes parameters need) run on the F-engine output as in section 4.
+// the Stokes parameters need) run on the F-engine output as in section 2.3.2.
 //
 // Per spectrum m, channel k and polarisation pol (signals s = 2a + pol), with
 // Y_s the dequantised spectra:

@@ -13,10 +13,9 @@
 // One workgroup per (block, signal).  The block (up to 64 KiB) is loaded once
 // into registers and never re-read.  int8 has 256 values, so the median and
 // the MAD are exact order statistics of a 256-bin histogram built with LDS
-// atomics.  The counters are 16 bits wide, two bins to a word, and the words
-// have 32 copies (thread t adds to copy t mod 32, so the lanes of a half-wave
-// never share a bank); the whole histogram is 16 KiB.  After the block-wide inclusive prefix sum P of the merged
-// histogram:
+// atomics.  The counters are 32 bits wide, one bin to a word, in 16 copies
+// (thread t adds to copy t mod 16); the whole histogram is 16 KiB.  After the
+// block-wide inclusive prefix sum P of the merged histogram:
 //   k-th smallest sample           = #{u : P[u] < k} - 128,
 //   #{samples with |2x - 2x~| <= D} = P[hi(D)] - P[lo(D) - 1], a range query,
 //   k-th smallest |2x - 2x~|       = #{D : count(D) < k},

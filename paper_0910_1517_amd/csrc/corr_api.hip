@@ -361,6 +361,54 @@ corr_status corr_pulsar_gates(int64_t spectrum0, int64_t n_spectra, int32_t fft_
     return CORR_OK;
 }
 
+corr_status corr_geom_from_model(int32_t n, const double *tau0, const double *taudot, double t0, double t_delay,
+                                 double fs, double nu_lo, int32_t max_delay, corr_geom_t *out) {
+    if (!tau0 || !taudot || !out) return fail(nullptr, CORR_ERR_NULL, "h_tau0, h_taudot and h_geom are required");
+    if (n < 1) return fail(nullptr, CORR_ERR_INVALID, "n_signals %d < 1", n);
+    if (!std::isfinite(t0) || !std::isfinite(t_delay) || !std::isfinite(fs) || !(fs > 0) ||
+        !std::isfinite(nu_lo) || nu_lo < 0 || max_delay < 0)
+        return fail(nullptr, CORR_ERR_INVALID, "t0, t_delay finite, sample_rate > 0, nu_lo >= 0 and "
+                                               "max_delay >= 0 required");
+    std::vector<corr_geom_t> g(n);
+    for (int s = 0; s < n; ++s) {
+        if (!std::isfinite(tau0[s]) || !std::isfinite(taudot[s]))
+            return fail(nullptr, CORR_ERR_INVALID, "signal %d: non-finite delay model", s);
+        // integer + fractional delay at t_delay, in samples
+        const double x = (tau0[s] + taudot[s] * (t_delay - t0)) * fs;
+        double D = std::floor(x);
+        float f = (float)(x - D);  // x - D is exact in FP64 (|x| < 2^52); one rounding to float
+        if (f >= 1.0f) {           // rounded up to a whole sample: carry
+            D += 1.0;
+            f = 0.0f;
+        }
+        if (!(D >= 0.0) || D > (double)max_delay)
+            return fail(nullptr, CORR_ERR_INVALID, "signal %d: delay of %.6f samples outside [0, max_delay = %d]",
+                        s, x, max_delay);
+        // fringe phase at t = 0, nu_lo * (tau0 - taudot t0) mod 1, with error-free transforms:
+        // taudot t0 = q + eq and tau0 - q = z + ez exactly, nu_lo z = p + ep exactly; the
+        // fraction of p is exact and the small terms are added after it
+        const double q = taudot[s] * t0;
+        const double eq = std::fma(taudot[s], t0, -q);
+        const double z = tau0[s] - q;
+        const double bz = z - tau0[s];
+        const double ez = (tau0[s] - (z - bz)) + (-q - bz);
+        const double p = nu_lo * z;
+        const double ep = std::fma(nu_lo, z, -p);
+        // the F-engine time-stamps spectrum m at the aligned window centre t_m, while its samples
+        // arrived tau later (read-pointer advance), when the fringe phase was rate * tau further on
+        const double arrive = (nu_lo * taudot[s]) * (x / fs);
+        double c = (p - std::floor(p)) + (ep + nu_lo * (ez - eq) + arrive);
+        c -= std::floor(c);
+        if (c >= 1.0) c = 0.0;  // a tiny negative c rounds to 1 above
+        g[s].D = (int32_t)D;
+        g[s].frac = f;
+        g[s].psi0 = c;
+        g[s].rate = nu_lo * taudot[s];
+    }
+    std::memcpy(out, g.data(), sizeof(corr_geom_t) * n);
+    return CORR_OK;
+}
+
 corr_status corr_integrate(corr_plan_t *p, void *d_acc, const float *d_scale, double *d_state, float *d_vis_out,
                            uint32_t flags, void *stream) {
     if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
@@ -454,6 +502,10 @@ corr_status corr_batch_create(const corr_desc_t *descs, int n, corr_batch_t **ou
             return fail(nullptr, CORR_ERR_UNSUPPORTED, "batched correlation is INT8 only (entry %d)", i);
         if (descs[i].scale_mode != CORR_SCALE_HOLD)
             return fail(nullptr, CORR_ERR_INVALID, "batched correlation needs held scales (entry %d)", i);
+        // one run accumulates a whole call into the int32 accumulator before integrating it
+        if (descs[i].n_spectra > kMaxInt8Spectra)
+            return fail(nullptr, CORR_ERR_OVERFLOW, "entry %d: %lld spectra per run exceed the int32 bound (%lld)", i,
+                        (long long)descs[i].n_spectra, (long long)kMaxInt8Spectra);
     }
     corr_batch *b = new (std::nothrow) corr_batch;
     if (!b) return fail(nullptr, CORR_ERR_NOMEM, "batch allocation failed");

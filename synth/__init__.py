@@ -320,6 +320,65 @@ def voltages_device(S: int, n_samples: int, geom: Geom, *, seed: int = BASE_SEED
     return out
 
 
+def voltages_device_physical(S: int, n_samples: int, geom: Geom, fs: float, *, seed: int = BASE_SEED,
+                             rho: float = 0.3, sigma_t: float = 12.0, sideband: int = 1, n_pol: int = 2,
+                             sources: list | None = None, tone_bin: int | None = None, tone_N: int | None = None,
+                             tone_amp: float = 4.0, block: int = 1 << 20, row_stride: int | None = None,
+                             device="cuda"):
+    """The ``physical`` recipe of :func:`voltages` (fractional delays, fringe
+    rotation, point sources, tone) generated on the GPU with torch's FFT and
+    seeded generator, for full-size inputs.  Same model as the numpy version,
+    other random numbers.  Returns an int8 device tensor [S][row_stride] whose
+    first n_samples columns hold the streams (the rest is zero)."""
+    import torch
+    if sources is None:
+        sources = [{"power": rho}]
+    tot_src = float(sum(src["power"] for src in sources))
+    rs = row_stride or n_samples
+    out = torch.zeros((S, rs), dtype=torch.int8, device=device)
+    gen = torch.Generator(device=device)
+    nu = torch.fft.fftfreq(block, d=1.0 / block, device=device, dtype=torch.float64)  # cycles per block
+    nb_half = block // 2 - 1
+    amp = np.sqrt(2.0 / nb_half) / np.sqrt(2.0)
+    for b in range(-(-n_samples // block)):
+        n0 = b * block
+        nb = min(block, n_samples - n0)
+        t = (n0 + torch.arange(nb, device=device, dtype=torch.float64)) / fs
+        acc = torch.zeros((S, nb), dtype=torch.float64, device=device)
+        for si, src in enumerate(sources):
+            amp_src = float(np.sqrt(src["power"]))
+            dD = np.asarray(src.get("dD", np.zeros(S)), dtype=np.float64)
+            drate = np.asarray(src.get("drate", np.zeros(S)), dtype=np.float64)
+            for pol in range(n_pol):
+                gen.manual_seed((int(seed) * 7919 + 104729 * b + 1009 * si + 31 * pol + 3) & 0x7FFFFFFFFFFFFFFF)
+                Z = torch.zeros(block, dtype=torch.complex128, device=device)
+                Z[1:block // 2] = amp * torch.complex(
+                    torch.randn(nb_half, generator=gen, device=device, dtype=torch.float64),
+                    torch.randn(nb_half, generator=gen, device=device, dtype=torch.float64))
+                for s in range(pol, S, n_pol):
+                    tau = float(geom.D[s] + geom.f[s] + dD[s])
+                    u = torch.fft.ifft(Z * torch.exp(-2j * np.pi * nu * (tau / block))) * block
+                    ph = torch.exp(-2j * np.pi * sideband * (float(geom.psi0[s]) + (float(geom.rate[s]) + drate[s]) * t))
+                    acc[s] += amp_src * (u[:nb] * ph).real
+                    del u, ph
+                del Z
+        for s in range(S):
+            gen.manual_seed((int(seed) * 15485863 + 7 * b + 1000003 * (s + 1)) & 0x7FFFFFFFFFFFFFFF)
+            acc[s] += np.sqrt(max(0.0, 1.0 - tot_src)) * torch.randn(nb, generator=gen, device=device,
+                                                                      dtype=torch.float64)
+        acc *= sigma_t
+        if tone_bin is not None:
+            n = n0 + torch.arange(nb, device=device, dtype=torch.float64)
+            for s in range(S):
+                tau = float(geom.D[s] + geom.f[s])
+                ph = 2 * np.pi * (tone_bin / tone_N) * (n - tau) \
+                    - 2 * np.pi * sideband * (float(geom.psi0[s]) + float(geom.rate[s]) * t)
+                acc[s] += tone_amp * torch.cos(ph)
+        out[:, n0:n0 + nb] = acc.round_().clamp_(-127, 127).to(torch.int8)
+        del acc
+    return out
+
+
 def random_spectra_int8(S: int, T: int, C: int, seed: int = BASE_SEED, sigma: float = 32.0,
                         extremes: bool = True) -> np.ndarray:
     """Requantised-spectrum-like int8 [S][T][C][2] in [-127, 127] for X-engine tests.

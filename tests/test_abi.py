@@ -289,3 +289,28 @@ def test_dedisperse_rejects_bad_arguments():
     assert dd(work=f) == -1  # the input must not be the workspace
     assert L.corr_dedisperse_last_error()
     assert L.corr_dedisperse_workspace_bytes(2, 1024, 64) == 2 * 1024 * 64 * 8
+
+
+# ------------------------------------------------------ int32 accumulator bound
+def test_xengine_rejects_a_call_past_the_int32_bound():
+    # 66592 spectra (the first multiple of 32 above 66572) in one INT8 call: rejected on the
+    # host before any launch, so the placeholder pointers are never dereferenced
+    L = corr.lib()
+    rc, h = create(n_signals=8, fft_len=512, n_spectra=66592, precision=corr.INT8)
+    assert rc == 0
+    try:
+        fake = ctypes.c_void_p(1 << 20)
+        assert L.corr_xengine(h, fake, fake, None) == -6
+        assert b"int32" in L.corr_last_error(h)
+        # FP32 has no such bound: the same shape is not rejected for it (not called here)
+    finally:
+        L.corr_plan_destroy(h)
+
+
+def test_batch_rejects_an_entry_past_the_int32_bound():
+    # one batch run sums each entry's whole call in int32 before integrating it
+    descs = (corr.CorrDesc * 2)(corr.make_desc(8, 512, 1024, precision=corr.INT8),
+                                corr.make_desc(16, 1024, 66592, precision=corr.INT8))
+    h = ctypes.c_void_p()
+    assert corr.lib().corr_batch_create(descs, 2, ctypes.byref(h)) == -6 and not h.value
+    assert b"entry 1" in corr.lib().corr_last_error(None)

@@ -1,4 +1,4 @@
-"""B-engine (array beams, section 3) through the C ABI against the oracle.
+"""B-engine (array beams, section 2.2) through the C ABI against the oracle.
 
 Spectra are packed by the library's corner turn from host values the oracle
 sees too: FP32 values, INT8 codes or finite e4m3 codes with per-(signal,

@@ -62,6 +62,45 @@ def test_gmrt_scale_fp32_sampled_channels():
     assert e_max <= 1e-5
 
 
+def test_gmrt_scale_point_sources_fp32_sampled_channels():
+    """The GMRT-scale form as specified: 64 signals drawn from the physical recipe
+    (fractional delays, fringe rotation) with 8 random coherent point sources --
+    source 0 at the phase centre, the others with extra per-antenna delays and
+    fringe rates -- 1024-pt FFT, 16384 spectra, FP32 F + X + integrate: sampled
+    channels against the FP64 oracle at e_max <= 1e-5."""
+    S, N, T = 64, 1024, 16384
+    C = N // 2
+    seed = synth.BASE_SEED + 1
+    geo = synth.make_geometry(S // 2, seed=seed)
+    src = synth.point_sources(S, 8, 0.3, seed=seed)
+    rs = (N * T + 16 + 255) // 256 * 256
+    x = synth.voltages_device_physical(S, N * T + 16, geo, FS, seed=seed, sources=src, tone_bin=37, tone_N=N,
+                                       row_stride=rs)
+    g = corr.geom_to_device(corr.geom_array(geo.D, geo.f, geo.psi0, geo.rate))
+    plan = corr.Plan(S, N, T, precision=corr.FP32)
+    spec = plan.alloc("spectra", zero=False)
+    acc, state, vis = plan.alloc("acc"), plan.alloc("state"), plan.alloc("vis")
+    plan.fengine(x, g, spec, row_stride=rs)
+    plan.xengine(spec, acc)
+    plan.integrate(acc, state, vis, flags=corr.DUMP)
+    plan.check_device_errors()
+    chans = [1, 37, 260, 510]
+    V = state_channels(state, C, plan.P, chans)
+    xh = x.cpu().numpy()
+    V64 = oracle.xengine(oracle.fengine_channels(xh, N, T, ogeom(geo), FS, chans))
+    e_max, e_fro = oracle.normalized_error(V, V64, S)
+    print("c2 with 8 point sources, sampled channels: e_max %.3g e_fro %.3g" % (e_max, e_fro))
+    assert e_max <= 1e-5
+    # the sources are there: same-polarisation cross coherence well above the noise
+    # level sqrt(1/T) ~ 0.008 on average, cross-polarisation coherence at it
+    auto = lambda i: V64[:, oracle.pair_index(i, i)].real
+    coh = lambda i, j: np.abs(V64[:, oracle.pair_index(i, j)]) / np.sqrt(auto(i) * auto(j))
+    same = np.mean([coh(i, j) for i in range(0, 16, 2) for j in range(i + 2, 16, 2)])
+    cross = np.mean([coh(i, i + 1) for i in range(0, 16, 2)])
+    print("c2 mean coherence: same pol %.4f, cross pol %.4f" % (same, cross))
+    assert same > 0.03 and cross < 0.02
+
+
 def test_precision_form_int8_sampled_channels():
     """64 signals, 4096-pt, 32768 spectra, int8 with held scales (calibration
     pass first, as the benchmark does): quantiser codes and visibilities of

@@ -1,4 +1,4 @@
-"""Pins of the oracle beamformer (section 3: incoherent array mode = detected
+"""Pins of the oracle beamformer (section 2.2: incoherent array mode = detected
 intensities added; coherent mode = voltages added, then detected, with the
 voltage cross products the Stokes parameters need) against facts outside its
 own loops: the correlator's visibilities (oracle.xengine, a separate
