@@ -92,9 +92,11 @@ def test_gmrt_scale_point_sources_fp32_sampled_channels():
     print("c2 with 8 point sources, sampled channels: e_max %.3g e_fro %.3g" % (e_max, e_fro))
     assert e_max <= 1e-5
     # the sources are there: same-polarisation cross coherence well above the noise
-    # level sqrt(1/T) ~ 0.008 on average, cross-polarisation coherence at it
-    auto = lambda i: V64[:, oracle.pair_index(i, i)].real
-    coh = lambda i, j: np.abs(V64[:, oracle.pair_index(i, j)]) / np.sqrt(auto(i) * auto(j))
+    # level sqrt(1/T) ~ 0.008 on average, cross-polarisation coherence at it (channel 37,
+    # where the tone common to both polarisations dominates, left out)
+    sel = [0, 2, 3]
+    auto = lambda i: V64[sel, oracle.pair_index(i, i)].real
+    coh = lambda i, j: np.abs(V64[sel, oracle.pair_index(i, j)]) / np.sqrt(auto(i) * auto(j))
     same = np.mean([coh(i, j) for i in range(0, 16, 2) for j in range(i + 2, 16, 2)])
     cross = np.mean([coh(i, i + 1) for i in range(0, 16, 2)])
     print("c2 mean coherence: same pol %.4f, cross pol %.4f" % (same, cross))
