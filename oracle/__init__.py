@@ -53,6 +53,9 @@ def _load():
     lib.orc_fengine_channels.restype = i32
     lib.orc_xengine_f64.argtypes = [P, i32, i64, i64, P]
     lib.orc_xengine_int.argtypes = [P, i32, i64, i64, P]
+    lib.orc_xengine_i16.argtypes = [P, i32, i64, i64, P]
+    lib.orc_fix16_table.argtypes = [P]
+    lib.orc_fix16_spectra.argtypes = [P, i32, i64, i64, i64, P, P, P, dbl, dbl, i32, P, P, P]
     lib.orc_beamform.argtypes = [P, i32, i64, i64, P, P, i32, i32, i32, P, P]
     lib.orc_sigma.argtypes = [P, i32, i64, i64, P]
     lib.orc_quantize_int8.argtypes = [P, P, i32, i64, i64, P]
@@ -258,6 +261,43 @@ def xengine_int(q: np.ndarray, A: np.ndarray | None = None) -> np.ndarray:
         A = np.zeros((C, n_pairs(S), 2), dtype=np.int64)
     _load().orc_xengine_int(_p(q), S, T, C, _p(A))
     return A
+
+
+def xengine_i16(q: np.ndarray, A: np.ndarray | None = None) -> np.ndarray:
+    """A[C][P][2] += sum_m q_i conj(q_j) in int64 on 16-bit integer spectra
+    (sections 3.1 and 4.1: 16-bit data, exact 32-bit products).  q: int16 [S][T][C][2]."""
+    q = np.ascontiguousarray(q, dtype=np.int16)
+    S, T, C, two = q.shape
+    assert two == 2
+    if A is None:
+        A = np.zeros((C, n_pairs(S), 2), dtype=np.int64)
+    _load().orc_xengine_i16(_p(q), S, T, C, _p(A))
+    return A
+
+
+def fix16_table() -> np.ndarray:
+    """The 1440-step phase table as Q14 integers (cos, sin) [1440][2] (section 4.1)."""
+    w = np.zeros((1440, 2), dtype=np.int32)
+    _load().orc_fix16_table(_p(w))
+    return w
+
+
+def fix16_spectra(X: np.ndarray, geom: Geometry, fs: float, scale: np.ndarray, nu_bb: float = 0.0,
+                  sideband: int = 1, spectrum0: int = 0):
+    """The 16-bit fixed-point spectra of the real-time pipeline (sections 3.1
+    and 4.1) from the unrotated FFT output X [S][T][C] (complex): the 16-bit
+    fixed-point FFT output q = sat16(rne(X / scale)) (X and scale FP32 values,
+    the division in FP32), then the integer fringe
+    stop and FSTC y = sat16(round((q w_j) / 2^14)) with the Q14 table entry j of
+    the Eq. 2 phase.  Returns (q, y), int16 [S][T][C][2] each."""
+    X = np.ascontiguousarray(np.stack([X.real, X.imag], -1), dtype=np.float64)
+    S, T, C, _ = X.shape
+    scale = np.ascontiguousarray(scale, dtype=np.float64).reshape(S, C)
+    q = np.zeros((S, T, C, 2), dtype=np.int16)
+    y = np.zeros((S, T, C, 2), dtype=np.int16)
+    _load().orc_fix16_spectra(_p(X), S, T, C, spectrum0, _p(geom.f), _p(geom.psi0), _p(geom.rate), fs, nu_bb,
+                              sideband, _p(scale), _p(q), _p(y))
+    return q, y
 
 
 # ---------------------------------------------------------------------------

@@ -318,6 +318,97 @@ void orc_xengine_int(const int8_t *q, int S, int64_t T, int64_t C, int64_t *A)
     }
 }
 
+/* The same cross products on 16-bit integer spectra (the 16-bit fixed-point   */
+/* data of the real-time pipeline, sections 3.1 and 4.1): every product is    */
+/* exact in 32 bits and the sums are int64.                                    */
+void orc_xengine_i16(const int16_t *q, int S, int64_t T, int64_t C, int64_t *A)
+{
+    int64_t P = (int64_t)S * (S + 1) / 2;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < C; ++k) {
+        for (int j = 0; j < S; ++j) {
+            for (int i = 0; i <= j; ++i) {
+                int64_t re = 0, im = 0;
+                for (int64_t m = 0; m < T; ++m) {
+                    const int16_t *a = q + (((int64_t)i * T + m) * C + k) * 2;
+                    const int16_t *b = q + (((int64_t)j * T + m) * C + k) * 2;
+                    re += (int64_t)a[0] * b[0] + (int64_t)a[1] * b[1];
+                    im += (int64_t)a[1] * b[0] - (int64_t)a[0] * b[1];
+                }
+                int64_t p = (int64_t)j * (j + 1) / 2 + i;
+                A[(k * P + p) * 2] += re;
+                A[(k * P + p) * 2 + 1] += im;
+            }
+        }
+    }
+}
+
+/* The 1440-step table of section 2.3.2 as the integers the real-time code    */
+/* multiplies by (section 4.1: scaled so that a 16-bit spectrum times the      */
+/* table keeps its result in the low half of a 32-bit product): Q14,           */
+/* w[j] = (rint(2^14 cos(2 pi j / 1440)), rint(2^14 sin(2 pi j / 1440))).        */
+void orc_fix16_table(int32_t *w)
+{
+    for (int j = 0; j < 1440; ++j) {
+        double th = 2.0 * M_PI * (double)j / 1440.0;
+        w[2 * j] = (int32_t)rint(16384.0 * cos(th));
+        w[2 * j + 1] = (int32_t)rint(16384.0 * sin(th));
+    }
+}
+
+/* floor(v / 2^14) for any sign */
+static int64_t floor_div16384(int64_t v) { return v >= 0 ? v / 16384 : -((-v + 16383) / 16384); }
+static int64_t sat16(int64_t v) { return v > 32767 ? 32767 : (v < -32767 ? -32767 : v); }
+/* the 16-bit code of one component: x / level in FP32 (the precision of the   */
+/* spectra the code is taken from), rounded half to even, saturated            */
+static int64_t code16(double x, double level)
+{
+    double r = nearbyint((double)((float)x / (float)level));
+    return r > 32767.0 ? 32767 : (r < -32767.0 ? -32767 : (int64_t)r);
+}
+
+/* The 16-bit fixed-point spectra of the real-time pipeline (sections 3.1 and  */
+/* 4.1), from the unrotated FFT output X [S][T][C][2] (FP64):                  */
+/*   q = sat16(round-half-even(X / scale[s][k])) per component: the 16-bit      */
+/*       fixed-point FFT output, the level set per signal and channel (the       */
+/*       division in FP32, X and scale being FP32 values);                       */
+/*   j = the table entry of the Eq. 2 phase, chosen as in orc_fengine_lut;       */
+/*   y = sat16(floor((q w_j + 2^13) / 2^14)) per component, q w_j the complex    */
+/*       product in integers: the integer fringe stop and FSTC, rounded to the   */
+/*       nearest (halves up) rather than truncated.                             */
+/* Saturation at +-32767 keeps negation (and conjugation) exact.               */
+void orc_fix16_spectra(const double *X, int S, int64_t T, int64_t C, int64_t spectrum0, const double *f,
+                       const double *psi0, const double *rate, double fs, double nu_bb, int sideband,
+                       const double *scale, int16_t *q16, int16_t *y16)
+{
+    int32_t w[2 * 1440];
+    orc_fix16_table(w);
+    int64_t N = 2 * C;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int s = 0; s < S; ++s) {
+        for (int64_t m = 0; m < T; ++m) {
+            double t_spec = (double)N / fs;
+            double tm = ((double)(spectrum0 + m) + 0.5) * t_spec;
+            double c = nu_bb * f[s] / fs + (double)sideband * (psi0[s] + rate[s] * tm);
+            c -= floor(c);
+            double fn = f[s] / (double)N;
+            for (int64_t k = 0; k < C; ++k) {
+                int64_t o = (((int64_t)s * T + m) * C + k) * 2;
+                double sc = scale[(int64_t)s * C + k];
+                int64_t qr = code16(X[o], sc);
+                int64_t qi = code16(X[o + 1], sc);
+                double phi = c + (double)k * fn;
+                int64_t j = (int64_t)rint(phi * 1440.0) % 1440;
+                int64_t wr = w[2 * j], wi = w[2 * j + 1];
+                q16[o] = (int16_t)qr;
+                q16[o + 1] = (int16_t)qi;
+                y16[o] = (int16_t)sat16(floor_div16384(qr * wr - qi * wi + 8192));
+                y16[o + 1] = (int16_t)sat16(floor_div16384(qr * wi + qi * wr + 8192));
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Requantisation (section 4.1: fixed point up to the MAC with tuned levels). */
 /* sigma[s][k] = sqrt( sum_m |Y_s[m,k]|^2 / (2T) )  -- RMS of one component. */

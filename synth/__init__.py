@@ -402,6 +402,20 @@ def random_spectra_f32(S: int, T: int, C: int, seed: int = BASE_SEED, sigma: flo
     return (re + 1j * im).astype(np.complex64)
 
 
+def random_spectra_int16(S: int, T: int, C: int, seed: int = BASE_SEED, sigma: float = 8000.0,
+                         extremes: bool = True) -> np.ndarray:
+    """int16 [S][T][C][2] in [-32767, 32767] (Gaussian of the given sigma,
+    clipped) for tests of the 16-bit X-engine; with ``extremes`` a few entries
+    are forced to +-32767 so that the largest products are exercised."""
+    g = rng(seed, 8, S, T, C)
+    q = np.clip(np.rint(g.standard_normal((S, T, C, 2), dtype=np.float32) * sigma), -32767, 32767)
+    q = q.astype(np.int16)
+    if extremes and q.size:
+        idx = g.integers(0, q.size, size=max(1, q.size // 1000))
+        q.reshape(-1)[idx] = np.where(g.random(idx.size) < 0.5, -32767, 32767).astype(np.int16)
+    return q
+
+
 def point_sources(S: int, n_src: int, power: float, seed: int = BASE_SEED, n_pol: int = 2):
     """n_src sources sharing total power; source 0 at the phase centre, the others
     with per-antenna extra delay U[-2, 2] samples and rate U[-0.5, 0.5] Hz."""
