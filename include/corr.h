@@ -314,6 +314,42 @@ corr_status corr_beamform(corr_plan_t *plan, const void *d_spec, const float *d_
 corr_status corr_integrate(corr_plan_t *plan, void *d_acc, const float *d_scale,
                            double *d_state, float *d_vis_out, uint32_t flags, void *stream);
 
+/* ---------------------------------------- 16-bit fixed-point emulation */
+
+/* The 16-bit fixed-point numerics of the paper's real-time pipeline, beside
+ * the FP32, INT8 and FP8 paths for the precision comparison of section 4.1:
+ * the FFT output held as 16-bit integers (section 3.1's 16-bit fixed-point
+ * real FFT, whose butterflies run in floating point), the fringe stop and
+ * FSTC by an integer multiply with the phase table scaled so that the result
+ * keeps 16 bits (section 4.1), and exact correlation products of the 16-bit
+ * data (32-bit products, section 4.1) accumulated in integers, then floating
+ * point.
+ *
+ * corr_fix16_spectra reads the spectra an FP32 plan's corr_fengine wrote with
+ * a geometry whose frac, psi0 and rate are zero (the integer delay applied,
+ * the FFT output unrotated; nu_BB of the plan then plays no part in it), and
+ * per signal s, spectrum m, channel k and component:
+ *   q = sat16(round-half-even(X / d_scale[s][k]))   the 16-bit FFT output
+ *   j = nearest of the 1440 steps of section 2.3.2 to the Eq. 2 phase of
+ *       d_geom (formed in FP64 as in phase_lut mode, spectrum0 + m absolute)
+ *   y = sat16(floor((q w_j + 2^13) / 2^14))         (complex product; w_j =
+ *       rint(2^14 cos, 2^14 sin) of the step: rounded, not truncated)
+ * with sat16 clamping to [-32767, 32767].  d_y16 (and d_q16 if not NULL):
+ * int16 [S][T][C][2], 4-byte aligned.  d_scale: float [S][C] (the level of
+ * each signal and channel; 4 sigma / 32767 uses the 16-bit range as the int8
+ * path uses its own).  Errors: NULL, INVALID (not an FP32 plan, spectrum0),
+ * ALIGN, WORKSPACE, DEVICE. */
+corr_status corr_fix16_spectra(corr_plan_t *plan, const void *d_spec, const corr_geom_t *d_geom, int64_t spectrum0,
+                               const float *d_scale, int16_t *d_q16, int16_t *d_y16, void *stream);
+
+/* d_acc[k][p] = sum over the plan's T spectra of y_i conj(y_j) (int64, [C][P]
+ * [2]; each product exact in 32 bits, the sums exact), and, if d_vis is not
+ * NULL, d_vis[k][p] = d_acc * scale_i[k] * scale_j[k] in FP64 ([C][P][2]).
+ * d_y16 as corr_fix16_spectra writes it.  Writes (does not accumulate).
+ * Errors: NULL, ALIGN, DEVICE. */
+corr_status corr_fix16_xengine(corr_plan_t *plan, const int16_t *d_y16, const float *d_scale, int64_t *d_acc,
+                               double *d_vis, void *stream);
+
 /* --------------------------------------------------------------- flagging */
 
 /* RFI flags from the MAD statistic of section 5 (Eq. 3: MAD = median

@@ -77,7 +77,7 @@ SYMBOLS = [
     "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
     "corr_adc_unpack", "corr_adc_last_error", "corr_xengine_gated", "corr_pulsar_gates",
     "corr_dedisperse", "corr_dedisperse_workspace_bytes", "corr_dedisperse_last_error",
-    "corr_geom_from_model",
+    "corr_geom_from_model", "corr_fix16_spectra", "corr_fix16_xengine",
 ]
 
 
@@ -183,6 +183,10 @@ def lib():
     L.corr_pulsar_gates.restype = st
     L.corr_dedisperse.argtypes = [P, i32, i64, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32, P, P, P]
     L.corr_dedisperse.restype = st
+    L.corr_fix16_spectra.argtypes = [P, P, P, i64, P, P, P, P]
+    L.corr_fix16_spectra.restype = st
+    L.corr_fix16_xengine.argtypes = [P, P, P, P, P, P]
+    L.corr_fix16_xengine.restype = st
     L.corr_dedisperse_workspace_bytes.argtypes = [i32, i64, i32]
     L.corr_dedisperse_workspace_bytes.restype = ctypes.c_size_t
     L.corr_dedisperse_last_error.argtypes = []
@@ -409,6 +413,29 @@ class Plan:
             _need(coh, "coh", n_beams * per * self.C, (torch.float32, torch.complex64))
         self._check(lib().corr_beamform(self._h, _ptr(spec), _ptr(scale), _ptr(w), _ptr(inc), _ptr(c), n_beams,
                                         mode, _ptr(coh), tint, _stream(stream)))
+
+    def fix16_spectra(self, spec, geom, scale, y16, q16=None, spectrum0=0, stream=None):
+        """corr_fix16_spectra: 16-bit fixed-point spectra (int16 [S][T][C][2]) from the
+        unrotated FP32 spectra of this FP32 plan."""
+        import torch
+        n = 4 * self.S * self.T * self.C
+        _need(spec, "spec", self.spectra_bytes)
+        _need(geom, "geom", 24 * self.S)
+        _need(scale, "scale", 4 * self.S * self.C, torch.float32)
+        _need(y16, "y16", n, torch.int16)
+        _need(q16, "q16", n, torch.int16, optional=True)
+        self._check(lib().corr_fix16_spectra(self._h, _ptr(spec), _ptr(geom), spectrum0, _ptr(scale), _ptr(q16),
+                                             _ptr(y16), _stream(stream)))
+
+    def fix16_xengine(self, y16, acc, scale=None, vis=None, stream=None):
+        """corr_fix16_xengine: exact int64 sums [C][P][2] of the 16-bit spectra's
+        products, and optionally the scaled FP64 visibilities."""
+        import torch
+        _need(y16, "y16", 4 * self.S * self.T * self.C, torch.int16)
+        _need(acc, "acc", 16 * self.C * self.P, torch.int64)
+        _need(vis, "vis", 16 * self.C * self.P, torch.float64, optional=True)
+        _need(scale, "scale", 4 * self.S * self.C, torch.float32, optional=True)
+        self._check(lib().corr_fix16_xengine(self._h, _ptr(y16), _ptr(scale), _ptr(acc), _ptr(vis), _stream(stream)))
 
     def integrate(self, acc, state, vis=None, scale=None, flags=DUMP, stream=None):
         import torch

@@ -12,12 +12,18 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcorr.so")
-SOURCES = ["corr_api.hip", "fengine.hip", "xengine.hip", "integrate.hip", "flag.hip", "cnn.hip", "cnn_api.hip", "beam.hip", "blank.hip", "adc.hip", "dedisp.hip"]
+SOURCES = ["corr_api.hip", "fengine.hip", "fengine4.hip", "xengine.hip", "integrate.hip", "flag.hip", "cnn.hip", "cnn_api.hip", "beam.hip", "blank.hip", "adc.hip", "dedisp.hip", "fix16.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -packed-fp32-ops: never emit v_pk_{add,mul,fma}_f32 (plain FP32 VALU only).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable"]
+
+
+# per-source flags: the four-step F-engine keeps its matrix-core results in
+# ordinary VGPRs (no accumulation-register reads between the MFMAs and the VALU
+# work that consumes them)
+EXTRA = {"fengine4.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:
@@ -30,7 +36,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -136,6 +136,16 @@ corr_status corr_plan_create(const corr_desc_t *desc, corr_plan_t **out) {
     w.pairs = o; o = round_up(o + sizeof(uint16_t) * 2 * p->P, 256);
     w.err = o; o = round_up(o + 16, 256);
     w.lut = o; o = round_up(o + sizeof(float2) * kLutSteps, 256);
+    {
+        const int n1 = d.fft_len / 64;
+        size_t ntwb = 0;
+        fengine4_tables(p->log2m, nullptr, nullptr, nullptr, &ntwb, nullptr);
+        w.afrag = o; o = round_up(o + sizeof(uint16_t) * 2 * 64 * 64, 256);
+        w.tw4 = o; o = round_up(o + sizeof(float2) * n1 * 32, 256);
+        w.twb = o; o = round_up(o + sizeof(float2) * std::max<size_t>(ntwb, 1), 256);
+        w.wsp = o; o = round_up(o + sizeof(float2) * n1, 256);
+    }
+    w.w16 = o; o = round_up(o + sizeof(int2) * kLutSteps, 256);
     w.part = o;
     if (d.precision != CORR_FP32 && d.scale_mode == CORR_SCALE_COMPUTE)
         o = round_up(o + sizeof(float) * d.n_signals * (d.n_spectra / 16) * p->M, 256);
@@ -196,9 +206,24 @@ corr_status corr_plan_bind_workspace(corr_plan_t *p, void *d_ws, size_t bytes, v
             pairs[2 * q] = (uint16_t)i;
             pairs[2 * q + 1] = (uint16_t)j;
         }
+    // four-step F-engine tables
+    const int n1 = N / 64;
+    size_t ntwb = 0;
+    fengine4_tables(p->log2m, nullptr, nullptr, nullptr, &ntwb, nullptr);
+    std::vector<uint16_t> afrag(2 * 64 * 64);
+    std::vector<float2> tw4((size_t)n1 * 32), twb(std::max<size_t>(ntwb, 1)), wsp(n1);
+    fengine4_tables(p->log2m, afrag.data(), tw4.data(), twb.data(), &ntwb, wsp.data());
+    std::vector<int2> w16(kLutSteps);
+    fix16_table(w16.data());
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)d_ws;
-    if ((e = hipMemcpyAsync(ws + p->ws.twp, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice, st)) ||
+    if ((e = hipMemcpyAsync(ws + p->ws.w16, w16.data(), sizeof(int2) * w16.size(), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(ws + p->ws.afrag, afrag.data(), sizeof(uint16_t) * afrag.size(), hipMemcpyHostToDevice,
+                            st)) ||
+        (e = hipMemcpyAsync(ws + p->ws.tw4, tw4.data(), sizeof(float2) * tw4.size(), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(ws + p->ws.twb, twb.data(), sizeof(float2) * twb.size(), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(ws + p->ws.wsp, wsp.data(), sizeof(float2) * wsp.size(), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(ws + p->ws.twp, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice, st)) ||
         (e = hipMemcpyAsync(ws + p->ws.wn, wn.data(), sizeof(float2) * M, hipMemcpyHostToDevice, st)) ||
         (e = hipMemcpyAsync(ws + p->ws.pairs, pairs.data(), sizeof(uint16_t) * pairs.size(),
                             hipMemcpyHostToDevice, st)) ||
@@ -248,17 +273,25 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
     a.fs = p->d.sample_rate;
     a.nu_bb = p->d.nu_bb;
     a.lut = reinterpret_cast<const float2 *>(p->d_ws + p->ws.lut);
+    a.afrag = reinterpret_cast<const uint16_t *>(p->d_ws + p->ws.afrag);
+    a.tw4 = reinterpret_cast<const float2 *>(p->d_ws + p->ws.tw4);
+    a.twb = reinterpret_cast<const float2 *>(p->d_ws + p->ws.twb);
+    a.wsp = reinterpret_cast<const float2 *>(p->d_ws + p->ws.wsp);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
+    // the four-step (matrix-core) F-engine up to kF4MaxLog2M, the LDS-radix one above
+    auto launch = [&](int mode) {
+        return p->log2m <= kF4MaxLog2M ? launch_fengine4(p->log2m, mode, a, st) : launch_fengine(p->log2m, mode, a, st);
+    };
     if (q8 && p->d.scale_mode == CORR_SCALE_COMPUTE) {
         a.power = nullptr;
-        if ((e = launch_fengine(p->log2m, 3, a, st)) != hipSuccess) return hip_fail(p, e, "calibration pass");
+        if ((e = launch(3)) != hipSuccess) return hip_fail(p, e, "calibration pass");
         if ((e = launch_calib_reduce(a.part, a.S, p->M, a.T / 16, a.T, p->d.precision, d_scale, st)) != hipSuccess)
             return hip_fail(p, e, "calibration reduce");
     }
     a.power = d_power;
     const int mode = (p->d.precision == CORR_FP32 ? 0 : (p->d.precision == CORR_INT8 ? 1 : 2)) + (p->d.phase_lut ? 4 : 0);
-    if ((e = launch_fengine(p->log2m, mode, a, st)) != hipSuccess) return hip_fail(p, e, "F-engine launch");
+    if ((e = launch(mode)) != hipSuccess) return hip_fail(p, e, "F-engine launch");
     return CORR_OK;
 }
 
@@ -407,6 +440,35 @@ corr_status corr_geom_from_model(int32_t n, const double *tau0, const double *ta
     }
     std::memcpy(out, g.data(), sizeof(corr_geom_t) * n);
     return CORR_OK;
+}
+
+corr_status corr_fix16_spectra(corr_plan_t *p, const void *d_spec, const corr_geom_t *d_geom, int64_t spectrum0,
+                               const float *d_scale, int16_t *d_q16, int16_t *d_y16, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_spec || !d_geom || !d_scale || !d_y16) return fail(p, CORR_ERR_NULL, "d_spec, d_geom, d_scale and d_y16 are required");
+    if (p->d.precision != CORR_FP32)
+        return fail(p, CORR_ERR_INVALID, "the 16-bit path reads the spectra of an FP32 plan");
+    if (!p->bound) return fail(p, CORR_ERR_WORKSPACE, "no workspace bound");
+    if (!aligned(d_spec, 256) || !aligned(d_geom, 8) || !aligned(d_scale, 4) || !aligned(d_y16, 4) ||
+        (d_q16 && !aligned(d_q16, 4)))
+        return fail(p, CORR_ERR_ALIGN, "d_spec 256 B, d_geom 8 B, d_scale, d_q16 and d_y16 4 B alignment");
+    if (spectrum0 < 0) return fail(p, CORR_ERR_INVALID, "spectrum0 must be >= 0");
+    hipError_t e = launch_fix16(d_spec, d_geom, spectrum0, d_scale, reinterpret_cast<const int2 *>(p->d_ws + p->ws.w16),
+                                p->d.n_signals, (int)p->d.n_spectra, p->M, p->d.sample_rate, p->d.nu_bb, p->d.sideband,
+                                d_q16, d_y16, (hipStream_t)stream);
+    return e == hipSuccess ? CORR_OK : hip_fail(p, e, "16-bit spectra launch");
+}
+
+corr_status corr_fix16_xengine(corr_plan_t *p, const int16_t *d_y16, const float *d_scale, int64_t *d_acc,
+                               double *d_vis, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_y16 || !d_acc) return fail(p, CORR_ERR_NULL, "d_y16 and d_acc are required");
+    if (d_vis && !d_scale) return fail(p, CORR_ERR_NULL, "d_vis needs d_scale");
+    if (!aligned(d_y16, 4) || !aligned(d_acc, 8) || (d_vis && !aligned(d_vis, 8)) || (d_scale && !aligned(d_scale, 4)))
+        return fail(p, CORR_ERR_ALIGN, "d_y16 4 B, d_acc and d_vis 8 B, d_scale 4 B alignment");
+    hipError_t e = launch_xengine16(d_y16, p->d.n_signals, p->d.n_spectra, p->M, d_scale, d_acc, d_vis,
+                                    (hipStream_t)stream);
+    return e == hipSuccess ? CORR_OK : hip_fail(p, e, "16-bit X-engine launch");
 }
 
 corr_status corr_integrate(corr_plan_t *p, void *d_acc, const float *d_scale, double *d_state, float *d_vis_out,

@@ -31,6 +31,11 @@ struct WsLayout {
     size_t err;       // uint32[4]   device error words
     size_t part;      // float[S][nblk*fpar][C] calibration partial sums
     size_t lut;       // float2[kLutSteps] cos, sin of 2 pi j / kLutSteps (table mode)
+    size_t afrag;     // uint16[2][64][64] FP16 rows of the DFT-64 (four-step F-engine)
+    size_t tw4;       // float2[N1][32]    W_N^(n1 k2)
+    size_t twb;       // float2[...]       column-pass twiddles
+    size_t wsp;       // float2[N1]        W_2N1^j
+    size_t w16;       // int2[kLutSteps]   Q14 phase table of the 16-bit fixed-point path
     size_t total;
 };
 
@@ -53,7 +58,17 @@ struct FLaunch {
     double fs;
     double nu_bb;
     const float2 *lut;   // phase table (table mode only)
+    // four-step F-engine tables (fengine4_tables)
+    const uint16_t *afrag;
+    const float2 *tw4;
+    const float2 *twb;
+    const float2 *wsp;
 };
+
+// The four-step F-engine serves log2 M up to this; longer transforms use the
+// LDS-radix one (fengine.hip), which measured faster at log2 M = 12 (7.6 against
+// 10.9 ms for 64 signals of 8192-point spectra; at 13 the four-step one spills).
+constexpr int kF4MaxLog2M = 11;
 
 // Phase look-up table of section 2.3.2: 1440 steps of 0.25 degrees.
 constexpr int kLutSteps = 1440;
@@ -66,6 +81,21 @@ int fengine_spectra_per_block(int log2m);
 int fengine_fpar(int log2m);
 // per-pass twiddle table of the Stockham passes: W_{P R}^{r k} at [pass][k][r]
 void fengine_twiddle_table(int log2m, float2 *out, size_t *count);
+
+// Four-step F-engine (fengine4.hip): the first step, a real DFT-64 of the
+// int8 samples, on the FP16 matrix cores.  Tables: afrag 2 x 64 x 64 FP16,
+// tw4 N1 x 32, twb the column-pass twiddles (count in *ntwb), wsp N1 (N1 = N/64).
+void fengine4_tables(int log2m, uint16_t *afrag, float2 *tw4, float2 *twb, size_t *ntwb, float2 *wsp);
+int fengine4_spectra_per_block(int log2m);
+hipError_t launch_fengine4(int log2m, int mode, const FLaunch &a, hipStream_t st);
+
+// 16-bit fixed-point numerics (fix16.hip)
+void fix16_table(int2 *w);  // rint(2^14 cos, sin) of the kLutSteps phase steps
+hipError_t launch_fix16(const void *spec, const corr_geom_t *geom, int64_t spectrum0, const float *scale,
+                        const int2 *wtab, int S, int T, int C, double fs, double nu_bb, int sideband, int16_t *q16,
+                        int16_t *y16, hipStream_t st);
+hipError_t launch_xengine16(const int16_t *y16, int S, int64_t T, int C, const float *scale, int64_t *acc,
+                            double *vis, hipStream_t st);
 
 hipError_t launch_calib_reduce(const float *part, int S, int C, int nparts, int T, int precision,
                                float *scale, hipStream_t st);

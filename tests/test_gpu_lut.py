@@ -4,7 +4,7 @@ table index with the same FP64 operations: FP32 spectra at several lengths,
 sidebands, baseband offsets and spectrum offsets, the whole FX chain at the
 FP32 gate, and the int8 codes.  Also the precision diagnostics of section 4.1
 (mean-to-rms ratio of auto spectra, spread of visibility ratios), comparing
-the table, int8 and e4m3 paths with the FP32 path."""
+the table, 16-bit fixed-point, int8 and e4m3 paths with the FP32 path."""
 import numpy as np
 import pytest
 
@@ -82,16 +82,17 @@ def test_table_mode_int8_codes():
 
 def test_precision_diagnostics():
     """Section 4.1's two diagnostics on one synthetic observation: for each
-    path (FP32 with the table phase, int8, e4m3), the mean-to-rms ratio of
+    path (FP32 with the table phase, the 16-bit fixed-point path, int8,
+    e4m3), the mean-to-rms ratio of
     every auto spectrum over 32 sub-integrations relative to the FP32 path's,
     and the rms spread of V_path / V_fp32 - 1 over the cross visibilities.
     The paper reports 1.5% and 2% degradation for its 16-bit fixed-point
     path; the printed figures are this library's.  A phase step of 0.25
     degree moves a product by at most 2 sin(pi / 1440) = 4.4e-3, but the
     ratio of two sums is not bounded where a channel's cross visibility is
-    small, so the test holds each path to a ceiling: the table below the
-    paper's fixed-point spread (0.02), the requantised paths below a few
-    times their step."""
+    small, so the test holds each path to a ceiling: the table and 16-bit
+    paths below the paper's fixed-point spread (0.02), the requantised paths
+    below a few times their step."""
     import torch
     S, N, Tsub, nsub = 8, 1024, 256, 32
     geo = synth.make_geometry(S // 2, seed=41)
@@ -117,15 +118,38 @@ def test_precision_diagnostics():
             _, state, _ = run_x_integrate(plan, spec, scale)
             vis.append(state)
         out[name] = np.stack(vis)  # [nsub][C][P]
+    # the 16-bit fixed-point path: the FP32 F-engine without the fractional-delay and fringe
+    # terms (the bare FFT of the integer-delayed samples), 16-bit codes at a level of
+    # 8 sigma / 32767 (the int8 calibration's 4 sigma / 127, rescaled: codes of rms 4096 that
+    # never clip; at 4 sigma the clipped tails alone move the mean/rms ratio by ~0.13%), the
+    # integer rotation by the Q14 table, exact integer sums
+    plan = corr.Plan(S, N, Tsub, precision=corr.FP32)
+    cal = corr.Plan(S, N, Tsub, precision=corr.INT8, scale_mode=corr.SCALE_COMPUTE)
+    s8 = torch.zeros(S * plan.C, dtype=torch.float32, device="cuda")
+    cal.fengine(x_dev, g_dev, cal.alloc("spectra", zero=False), s8, row_stride=rs)
+    sc16 = s8 * np.float32(2 * 127.0 / 32767.0)
+    bare = corr.geom_to_device(corr.geom_array(geo.D, np.zeros(S), np.zeros(S), np.zeros(S)))
+    spec = plan.alloc("spectra", zero=False)
+    y16 = torch.empty((S, Tsub, plan.C, 2), dtype=torch.int16, device="cuda")
+    acc = torch.empty(plan.C * plan.P * 2, dtype=torch.int64, device="cuda")
+    v16 = torch.empty(plan.C * plan.P * 2, dtype=torch.float64, device="cuda")
+    vis = []
+    for i in range(nsub):
+        plan.fengine(x_dev[:, i * Tsub * N:], bare, spec, None, row_stride=rs, spectrum0=i * Tsub)
+        plan.fix16_spectra(spec, g_dev, sc16, y16, spectrum0=i * Tsub)
+        plan.fix16_xengine(y16, acc, scale=sc16, vis=v16)
+        v = v16.cpu().numpy().reshape(plan.C, plan.P, 2)
+        vis.append(v[..., 0] + 1j * v[..., 1])
+    out["fix16"] = np.stack(vis)
     auto = [oracle.pair_index(i, i) for i in range(S)]
     cross = [oracle.pair_index(i, j) for j in range(S) for i in range(j) if i // 2 != j // 2]
     mr = {k: (v[:, 1:, auto].real.mean(0) / v[:, 1:, auto].real.std(0)) for k, v in out.items()}
     total = {k: v.sum(0) for k, v in out.items()}
-    for k in ("table", "int8", "e4m3"):
+    for k in ("table", "fix16", "int8", "e4m3"):
         deg = 1.0 - np.mean(mr[k]) / np.mean(mr["fp32"])
         ratio = total[k][1:, cross] / total["fp32"][1:, cross] - 1.0
         spread = float(np.sqrt(np.mean(np.abs(ratio) ** 2)))
         print("precision diagnostics %s: mean/rms change %.3g%%, visibility ratio spread %.3g"
               % (k, 100 * deg, spread), flush=True)
-        assert abs(deg) < {"table": 1e-3, "int8": 0.01, "e4m3": 0.05}[k]
-        assert spread < {"table": 0.02, "int8": 0.1, "e4m3": 0.3}[k]
+        assert abs(deg) < {"table": 1e-3, "fix16": 1e-3, "int8": 0.01, "e4m3": 0.05}[k]
+        assert spread < {"table": 0.02, "fix16": 0.02, "int8": 0.1, "e4m3": 0.3}[k]
