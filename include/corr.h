@@ -416,6 +416,19 @@ size_t corr_plan_keep_bytes(const corr_plan_t *plan);
 corr_status corr_dedisperse(const float *d_v, int32_t npol, int64_t T, int32_t C, double sample_rate, double nu0,
                             double dm, int32_t n_int, float *d_work, float *d_out, void *stream);
 size_t corr_dedisperse_workspace_bytes(int32_t npol, int64_t T, int32_t C);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): corr_dedisperse
+ * without d_work.  Its work buffer is a file-scope device array of
+ * CORR_DEDISPERSE_NOALLOC_MAX complex samples (32 MiB) that the library holds
+ * on every GPU it runs on until the process ends; the call itself allocates
+ * nothing.  Same arguments, results and errors as corr_dedisperse, plus
+ * INVALID when npol * T * C exceeds CORR_DEDISPERSE_NOALLOC_MAX, and
+ * UNSUPPORTED on a device id of 64 or more.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race, and each call's transform overwrites the previous one's. */
+#define CORR_DEDISPERSE_NOALLOC_MAX ((int64_t)1 << 22)
+corr_status corr_dedisperse_noalloc(const float *d_v, int32_t npol, int64_t T, int32_t C, double sample_rate,
+                                    double nu0, double dm, int32_t n_int, float *d_out, void *stream);
 const char *corr_dedisperse_last_error(void);
 
 /* ------------------------------------------------------------- ADC input */

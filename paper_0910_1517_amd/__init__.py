@@ -77,7 +77,7 @@ SYMBOLS = [
     "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
     "corr_adc_unpack", "corr_adc_last_error", "corr_xengine_gated", "corr_pulsar_gates",
     "corr_dedisperse", "corr_dedisperse_workspace_bytes", "corr_dedisperse_last_error",
-    "corr_geom_from_model", "corr_fix16_spectra", "corr_fix16_xengine",
+    "corr_geom_from_model", "corr_dedisperse_noalloc", "corr_fix16_spectra", "corr_fix16_xengine",
 ]
 
 
@@ -183,6 +183,9 @@ def lib():
     L.corr_pulsar_gates.restype = st
     L.corr_dedisperse.argtypes = [P, i32, i64, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32, P, P, P]
     L.corr_dedisperse.restype = st
+    L.corr_dedisperse_noalloc.argtypes = [P, i32, i64, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
+                                          P, P]
+    L.corr_dedisperse_noalloc.restype = st
     L.corr_fix16_spectra.argtypes = [P, P, P, i64, P, P, P, P]
     L.corr_fix16_spectra.restype = st
     L.corr_fix16_xengine.argtypes = [P, P, P, P, P, P]
@@ -713,6 +716,24 @@ def dedisperse(v, *, sample_rate: float, nu0: float, dm: float, n_int: int, work
     if rc != 0:
         raise CorrError(rc, lib().corr_dedisperse_last_error().decode())
     return out, work
+
+
+DEDISPERSE_NOALLOC_MAX = 1 << 22  # complex samples (npol T C) of corr_dedisperse_noalloc
+
+
+def dedisperse_noalloc(v, out, *, sample_rate: float, nu0: float, dm: float, n_int: int, stream=None):
+    """corr_dedisperse_noalloc: the same dedispersion with the library's own
+    device scratch (no workspace argument, nothing allocated by the call);
+    npol T C at most DEDISPERSE_NOALLOC_MAX.  Writes out (float [T C / n_int])."""
+    import torch
+    npol, T, C = v.shape
+    L = T * C
+    _need(v, "v", 8 * npol * L, torch.complex64)
+    _need(out, "out", 4 * (L // max(int(n_int), 1)), torch.float32)
+    rc = lib().corr_dedisperse_noalloc(_ptr(v), npol, T, C, sample_rate, nu0, dm, n_int, _ptr(out), _stream(stream))
+    if rc != 0:
+        raise CorrError(rc, lib().corr_dedisperse_last_error().decode())
+    return out
 
 
 def _blank_check(rc):

@@ -38,6 +38,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <type_traits>
@@ -49,6 +50,10 @@ namespace {
 constexpr int kDdThreads = 256;
 constexpr double kDmConst = 4.148808e15;  // Hz^2 s / (pc cm^-3): delay = K DM / nu^2
 constexpr int kDdMaxPasses = 8;
+// corr_dedisperse_noalloc: complex samples of its device scratch array (32 MiB)
+// and the devices it keeps that array's address for
+constexpr int64_t kDdScratchSamples = (int64_t)1 << 22;
+constexpr int kDdMaxDevices = 64;
 
 struct DdPasses {
     int n;                     // number of passes of the long transform
@@ -460,19 +465,11 @@ int ilog2(int64_t v) {
 
 }  // namespace
 
-extern "C" {
-
-size_t corr_dedisperse_workspace_bytes(int32_t npol, int64_t T, int32_t C) {
-    if (npol < 1 || T < 1 || C < 1) return 0;
-    return sizeof(float) * 2 * (size_t)npol * (size_t)T * (size_t)C;
-}
-
-corr_status corr_dedisperse(const float *d_v, int32_t npol, int64_t T, int32_t C, double sample_rate, double nu0,
-                            double dm, int32_t n_int, float *d_work, float *d_out, void *stream) {
-    g_dd_err[0] = 0;
-    if (!d_v || !d_work || !d_out) return dd_fail(CORR_ERR_NULL, "d_v, d_work and d_out are required");
-    if (((uintptr_t)d_v & 7) || ((uintptr_t)d_work & 7) || ((uintptr_t)d_out & 3))
-        return dd_fail(CORR_ERR_ALIGN, "d_v and d_work 8-byte, d_out 4-byte alignment");
+// Argument checks shared by both entry points (everything but the work buffer).
+static corr_status dd_check(const float *d_v, int32_t npol, int64_t T, int32_t C, double sample_rate, double nu0,
+                            double dm, int32_t n_int, float *d_out) {
+    if (!d_v || !d_out) return dd_fail(CORR_ERR_NULL, "d_v and d_out are required");
+    if (((uintptr_t)d_v & 7) || ((uintptr_t)d_out & 3)) return dd_fail(CORR_ERR_ALIGN, "d_v 8-byte, d_out 4-byte alignment");
     if (npol < 1 || npol > 2) return dd_fail(CORR_ERR_INVALID, "npol=%d must be 1 or 2", npol);
     if (C < 16 || C > 8192 || (C & (C - 1))) return dd_fail(CORR_ERR_INVALID, "C=%d must be a power of two in [16, 8192]", C);
     if (T < 1 || (T & (T - 1))) return dd_fail(CORR_ERR_INVALID, "T=%lld must be a power of two", (long long)T);
@@ -484,10 +481,14 @@ corr_status corr_dedisperse(const float *d_v, int32_t npol, int64_t T, int32_t C
     if (!(sample_rate > 0) || !std::isfinite(sample_rate) || !(nu0 > 0) || !std::isfinite(nu0) || !(dm >= 0) ||
         !std::isfinite(dm))
         return dd_fail(CORR_ERR_INVALID, "sample_rate and nu0 must be finite and > 0, dm finite and >= 0");
-    if ((const void *)d_v == (const void *)d_work) return dd_fail(CORR_ERR_INVALID, "d_v and d_work must differ");
-    hipStream_t st = (hipStream_t)stream;
+    return CORR_OK;
+}
+
+// The transforms and the detection on a work buffer z of npol T C complex samples.
+static corr_status dd_run(const float *d_v, int32_t npol, int64_t T, int32_t C, double sample_rate, double nu0,
+                          double dm, int32_t n_int, float2 *z, float *d_out, hipStream_t st) {
+    const int64_t L = T * (int64_t)C;
     const float2 *v = reinterpret_cast<const float2 *>(d_v);
-    float2 *z = reinterpret_cast<float2 *>(d_work);
     // 1. broadband series: inverse C-point DFT of every spectrum
     const int lgL = ilog2(L);
     DdChirp ch{};
@@ -522,6 +523,63 @@ corr_status corr_dedisperse(const float *d_v, int32_t npol, int64_t T, int32_t C
         e = hipGetLastError();
     }
     return e == hipSuccess ? CORR_OK : dd_fail(CORR_ERR_DEVICE, "dedispersion launch: %s", hipGetErrorString(e));
+}
+
+// Work buffer of corr_dedisperse_noalloc: a file-scope device array, one copy on
+// every GPU the library runs on, held until the process ends.  Host code reaches
+// each device's copy only through the address hipGetSymbolAddress returns there.
+static __device__ __align__(256) float2 dd_scratch[kDdScratchSamples];
+static std::mutex g_dd_scratch_mu;
+static float2 *g_dd_scratch_at[kDdMaxDevices];
+
+// This device's address of dd_scratch (looked up once per device, with it current).
+static corr_status dd_scratch_ptr(float2 **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return dd_fail(CORR_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kDdMaxDevices) return dd_fail(CORR_ERR_UNSUPPORTED, "device %d beyond %d", dev, kDdMaxDevices);
+    std::lock_guard<std::mutex> lock(g_dd_scratch_mu);
+    if (!g_dd_scratch_at[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(dd_scratch));
+        if (e != hipSuccess || !p)
+            return dd_fail(CORR_ERR_DEVICE, "hipGetSymbolAddress(dd_scratch): %s", hipGetErrorString(e));
+        g_dd_scratch_at[dev] = static_cast<float2 *>(p);
+    }
+    *out = g_dd_scratch_at[dev];
+    return CORR_OK;
+}
+
+extern "C" {
+
+size_t corr_dedisperse_workspace_bytes(int32_t npol, int64_t T, int32_t C) {
+    if (npol < 1 || T < 1 || C < 1) return 0;
+    return sizeof(float) * 2 * (size_t)npol * (size_t)T * (size_t)C;
+}
+
+corr_status corr_dedisperse(const float *d_v, int32_t npol, int64_t T, int32_t C, double sample_rate, double nu0,
+                            double dm, int32_t n_int, float *d_work, float *d_out, void *stream) {
+    g_dd_err[0] = 0;
+    if (!d_work) return dd_fail(CORR_ERR_NULL, "d_v, d_work and d_out are required");
+    if ((uintptr_t)d_work & 7) return dd_fail(CORR_ERR_ALIGN, "d_v and d_work 8-byte, d_out 4-byte alignment");
+    corr_status cs = dd_check(d_v, npol, T, C, sample_rate, nu0, dm, n_int, d_out);
+    if (cs != CORR_OK) return cs;
+    if ((const void *)d_v == (const void *)d_work) return dd_fail(CORR_ERR_INVALID, "d_v and d_work must differ");
+    return dd_run(d_v, npol, T, C, sample_rate, nu0, dm, n_int, reinterpret_cast<float2 *>(d_work), d_out,
+                  (hipStream_t)stream);
+}
+
+corr_status corr_dedisperse_noalloc(const float *d_v, int32_t npol, int64_t T, int32_t C, double sample_rate,
+                                    double nu0, double dm, int32_t n_int, float *d_out, void *stream) {
+    g_dd_err[0] = 0;
+    corr_status cs = dd_check(d_v, npol, T, C, sample_rate, nu0, dm, n_int, d_out);
+    if (cs != CORR_OK) return cs;
+    if ((int64_t)npol * T * (int64_t)C > kDdScratchSamples)
+        return dd_fail(CORR_ERR_INVALID, "npol*T*C=%lld exceeds the no-allocation limit of %lld samples",
+                       (long long)((int64_t)npol * T * (int64_t)C), (long long)kDdScratchSamples);
+    float2 *z = nullptr;
+    if ((cs = dd_scratch_ptr(&z)) != CORR_OK) return cs;
+    return dd_run(d_v, npol, T, C, sample_rate, nu0, dm, n_int, z, d_out, (hipStream_t)stream);
 }
 
 const char *corr_dedisperse_last_error(void) { return g_dd_err; }
