@@ -144,7 +144,7 @@ def run_path(corr, torch, prec, S, N, T, x_dev, rs, g_dev, steps, warmup, scale=
     wall = (time.perf_counter() - t0) / steps
     med = lambda a, b: float(np.median([e[a].elapsed_time(e[b]) for e in ev])) * 1e-3
     out = dict(t_f=med(0, 1), t_x=med(1, 2), t_int=med(2, 3), t_eager_step=med(0, 3), wall=wall,
-               splits=plan.splits)
+               splits=plan.splits, fkernel=plan.fengine_kernel)
     out["t_step"] = out["t_eager_step"]
     plan.check_device_errors()
     if graph:
@@ -588,9 +588,10 @@ def bench_table_phase(corr, torch, S, N, T, x_dev, rs, g_dev, scale, steps, warm
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    name = plan.fengine_kernel
     del spec, plan
     torch.cuda.empty_cache()
-    return ms
+    return ms, name
 
 
 def bench_dedisperse(corr, torch, N, T, steps, warmup, dm=71.0, nu0=325e6, n_int=1024):
@@ -738,7 +739,7 @@ def main():
         tg_ms = bench_gated(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
         log("gated X-engine: %.3f ms per call (ungated %.3f ms)" % (tg_ms, r8["t_x"] * 1e3))
         log("timing the int8 F-engine with the 1440-step phase table")
-        tt_ms = bench_table_phase(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
+        tt_ms, tt_name = bench_table_phase(corr, torch, S, N, T, x_dev, rs, g_dev, scale, args.steps, args.warmup)
         log("table-phase F-engine: %.3f ms (direct sincos %.3f ms)" % (tt_ms, r8["t_f"] * 1e3))
         log("timing coherent dedispersion of one beam (DM 71 at 325 MHz)")
         rd = bench_dedisperse(corr, torch, N, T, max(2, args.steps // 2), min(1, args.warmup))
@@ -817,7 +818,7 @@ def main():
 
     if gmrt:
         tf, tx = r32["t_f"], r32["t_x"]
-        f_part = f_roof(tf, ff32, fb32, "fengine_kernel<9, 0> (FP32 F-engine)")
+        f_part = f_roof(tf, ff32, fb32, "%s (FP32 F-engine)" % r32["fkernel"])
         x_part = {"kernel": "xengine_kernel<2, 0> (FP32 MFMA X-engine)", "bound": "mfma",
                   "achieved": round(xops32 / tx / 1e12, 3), "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                   "frac": round(xops32 / tx / FP32_MFMA_PEAK, 4), "hbm_gbs": round(xin32 / tx / 1e9, 1)}
@@ -825,7 +826,7 @@ def main():
         traffic = measured_traffic("fengine_fp32_c2") if tf >= tx else None
     else:
         tf, tx = r8["t_f"], r8["t_x"]
-        f_part = f_roof(tf, ff8, fb8, "fengine_kernel<11, 1> (int8 F-engine)")
+        f_part = f_roof(tf, ff8, fb8, "%s (int8 F-engine)" % r8["fkernel"])
         x_part = {"kernel": "xengine_kernel<2, 1> (int8 MFMA X-engine)", "bound": "hbm",
                   "achieved": round(xin8 / tx / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                   "frac": round(xin8 / tx / HBM_PEAK, 4), "mfma_frac_algorithmic": round(xops8 / tx / INT8_PEAK, 4)}
@@ -861,7 +862,7 @@ def main():
             "hbm_frac": round(xin8 / (tg_ms * 1e-3) / HBM_PEAK, 4),
             "mfma_frac_issued": round(2 * xops8 / (tg_ms * 1e-3) / INT8_PEAK, 4)}
         out["table_phase_fengine"] = {
-            "kernel": "fengine_kernel<log2M, 5> (int8, phase from the 1440-step table)", "bound": "hbm",
+            "kernel": "%s (int8, phase from the 1440-step table)" % tt_name, "bound": "hbm",
             "ms": round(tt_ms, 4), "direct_sincos_ms": round(r8["t_f"] * 1e3, 4),
             "hbm_frac": round(fb8 / (tt_ms * 1e-3) / HBM_PEAK, 4)}
         out["coherent_dedispersion"] = {

@@ -177,6 +177,12 @@ size_t corr_plan_acc_bytes(const corr_plan_t *plan);
 size_t corr_plan_state_bytes(const corr_plan_t *plan);
 size_t corr_plan_vis_bytes(const corr_plan_t *plan);
 int32_t corr_plan_x_splits(const corr_plan_t *plan);
+/* Name of the F-engine kernel the plan's corr_fengine launches for its data
+ * (as a profiler lists it: "fengine4_kernel<log2 M, mode>" for the four-step
+ * one, "fengine_kernel<...>" for the LDS-radix one; mode 0 FP32, 1 int8, 2
+ * e4m3, plus 4 in table mode).  The string is valid until the calling
+ * thread's next call; "" for a NULL plan. */
+const char *corr_plan_fengine_kernel(const corr_plan_t *plan);
 
 /* Attach caller-owned device workspace (>= workspace_bytes, 256-byte
  * aligned) and upload the tables on `stream`.  The workspace must stay

@@ -77,7 +77,7 @@ SYMBOLS = [
     "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
     "corr_adc_unpack", "corr_adc_last_error", "corr_xengine_gated", "corr_pulsar_gates",
     "corr_dedisperse", "corr_dedisperse_workspace_bytes", "corr_dedisperse_last_error",
-    "corr_geom_from_model", "corr_dedisperse_noalloc", "corr_fix16_spectra", "corr_fix16_xengine",
+    "corr_geom_from_model", "corr_dedisperse_noalloc", "corr_plan_fengine_kernel", "corr_fix16_spectra", "corr_fix16_xengine",
 ]
 
 
@@ -112,6 +112,8 @@ def lib():
         f.restype = sz
     L.corr_plan_x_splits.argtypes = [P]
     L.corr_plan_x_splits.restype = ctypes.c_int32
+    L.corr_plan_fengine_kernel.argtypes = [P]
+    L.corr_plan_fengine_kernel.restype = ctypes.c_char_p
     L.corr_plan_bind_workspace.argtypes = [P, P, sz, P]
     L.corr_plan_bind_workspace.restype = st
     L.corr_fengine.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P]
@@ -323,6 +325,8 @@ class Plan:
     state_bytes = property(lambda self: self._size("state"))
     vis_bytes = property(lambda self: self._size("vis"))
     splits = property(lambda self: int(lib().corr_plan_x_splits(self._h)))
+    # the F-engine kernel corr_fengine launches for this plan (as a profiler names it)
+    fengine_kernel = property(lambda self: lib().corr_plan_fengine_kernel(self._h).decode())
 
     def _check(self, rc):
         if rc != 0:

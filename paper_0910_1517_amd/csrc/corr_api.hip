@@ -169,6 +169,16 @@ size_t corr_plan_state_bytes(const corr_plan_t *p) { return p ? (size_t)p->M * p
 size_t corr_plan_vis_bytes(const corr_plan_t *p) { return p ? (size_t)p->M * p->P * 2 * 4 : 0; }
 int32_t corr_plan_x_splits(const corr_plan_t *p) { return p ? p->splits : 0; }
 
+const char *corr_plan_fengine_kernel(const corr_plan_t *p) {
+    if (!p) return "";
+    int mode = p->d.precision == CORR_FP32 ? 0 : p->d.precision == CORR_INT8 ? 1 : 2;
+    if (p->d.phase_lut) mode += 4;
+    static thread_local char name[64];
+    snprintf(name, sizeof name, "%s<%d, %d>", use_fengine4(p->log2m) ? "fengine4_kernel" : "fengine_kernel",
+             p->log2m, mode);
+    return name;
+}
+
 corr_status corr_plan_bind_workspace(corr_plan_t *p, void *d_ws, size_t bytes, void *stream) {
     if (!p || !d_ws) return fail(p, CORR_ERR_NULL, "plan and workspace must be non-null");
     if (!aligned(d_ws, 256)) return fail(p, CORR_ERR_ALIGN, "workspace must be 256-byte aligned");
@@ -279,9 +289,8 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
     a.wsp = reinterpret_cast<const float2 *>(p->d_ws + p->ws.wsp);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
-    // the four-step (matrix-core) F-engine up to kF4MaxLog2M, the LDS-radix one above
     auto launch = [&](int mode) {
-        return p->log2m <= kF4MaxLog2M ? launch_fengine4(p->log2m, mode, a, st) : launch_fengine(p->log2m, mode, a, st);
+        return use_fengine4(p->log2m) ? launch_fengine4(p->log2m, mode, a, st) : launch_fengine(p->log2m, mode, a, st);
     };
     if (q8 && p->d.scale_mode == CORR_SCALE_COMPUTE) {
         a.power = nullptr;

@@ -65,10 +65,15 @@ struct FLaunch {
     const float2 *wsp;
 };
 
-// The four-step F-engine serves log2 M up to this; longer transforms use the
-// LDS-radix one (fengine.hip), which measured faster at log2 M = 12 (7.6 against
-// 10.9 ms for 64 signals of 8192-point spectra; at 13 the four-step one spills).
-constexpr int kF4MaxLog2M = 11;
+// Which F-engine serves a transform length: the four-step (matrix-core) one at
+// log2 M = 8, 10 and 11, the LDS-radix one (fengine.hip) at 9, 12 and 13.  The
+// choice is measured: 64 signals of 2^27 samples, int8 output, ms per call
+//   log2 M         8      9      10     11     12
+//   four-step    7.99  10.20   9.40   9.64  15.92
+//   LDS-radix    9.05   9.28  10.35  10.69  12.12
+// (FP32 output: the four-step kernel 2-15% faster at 8-11, 10% slower at 12);
+// at 13 the four-step kernel spills registers.
+constexpr bool use_fengine4(int log2m) { return log2m == 8 || log2m == 10 || log2m == 11; }
 
 // Phase look-up table of section 2.3.2: 1440 steps of 0.25 degrees.
 constexpr int kLutSteps = 1440;

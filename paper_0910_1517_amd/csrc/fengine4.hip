@@ -60,6 +60,7 @@ namespace {
 typedef _Float16 f4_half8 __attribute__((ext_vector_type(8)));
 typedef float f4_float16 __attribute__((ext_vector_type(16)));
 typedef int f4_int2 __attribute__((ext_vector_type(2)));
+typedef unsigned f4_uint4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) f4_int2 lds_int2;
 
 template <int LOGM>
@@ -468,9 +469,18 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) fengine4_kernel(FLaunch a) {
         for (int kt = 0; kt < 4; ++kt) {
             const f4_int2 raw = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
                 (lds_int2 *)(lds_xb + tr_off + 16 * N1 * kt));
-            f4_half8 bf;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) bf[e] = (_Float16)(int8_t)(raw[e >> 2] >> (8 * (e & 3)));
+            // int8 -> FP16, exactly: b ^ 0x80 is b + 128 (0..255); under the byte 0x64 it
+            // forms the FP16 number 1024 + b + 128, and one packed subtraction of 1152
+            // leaves b (all integers below 2048 are FP16 numbers).  The subtraction is
+            // written on the whole vector: written per FP16 pair, this compiler merged
+            // the four byte selections into one.
+            const uint32_t x0 = (uint32_t)raw[0] ^ 0x80808080u, x1 = (uint32_t)raw[1] ^ 0x80808080u;
+            f4_uint4 hb;
+            hb[0] = __builtin_amdgcn_perm(0x64646464u, x0, 0x04010400u);
+            hb[1] = __builtin_amdgcn_perm(0x64646464u, x0, 0x04030402u);
+            hb[2] = __builtin_amdgcn_perm(0x64646464u, x1, 0x04010400u);
+            hb[3] = __builtin_amdgcn_perm(0x64646464u, x1, 0x04030402u);
+            const f4_half8 bf = __builtin_bit_cast(f4_half8, hb) - (f4_half8)((_Float16)1152.0f);
             const f4_half8 alo = *reinterpret_cast<const f4_half8 *>(&lds_a[1][a_off + 16 * kt]);
             const f4_half8 ahi = *reinterpret_cast<const f4_half8 *>(&lds_a[0][a_off + 16 * kt]);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, bf, acc, 0, 0, 0);
