@@ -174,7 +174,7 @@ const char *corr_plan_fengine_kernel(const corr_plan_t *p) {
     int mode = p->d.precision == CORR_FP32 ? 0 : p->d.precision == CORR_INT8 ? 1 : 2;
     if (p->d.phase_lut) mode += 4;
     static thread_local char name[64];
-    snprintf(name, sizeof name, "%s<%d, %d>", use_fengine4(p->log2m) ? "fengine4_kernel" : "fengine_kernel",
+    snprintf(name, sizeof name, "%s<%d, %d>", use_fengine4(p->log2m, mode) ? "fengine4_kernel" : "fengine_kernel",
              p->log2m, mode);
     return name;
 }
@@ -290,7 +290,8 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     auto launch = [&](int mode) {
-        return use_fengine4(p->log2m) ? launch_fengine4(p->log2m, mode, a, st) : launch_fengine(p->log2m, mode, a, st);
+        return use_fengine4(p->log2m, mode) ? launch_fengine4(p->log2m, mode, a, st)
+                                             : launch_fengine(p->log2m, mode, a, st);
     };
     if (q8 && p->d.scale_mode == CORR_SCALE_COMPUTE) {
         a.power = nullptr;

@@ -65,15 +65,19 @@ struct FLaunch {
     const float2 *wsp;
 };
 
-// Which F-engine serves a transform length: the four-step (matrix-core) one at
-// log2 M = 8, 10 and 11, the LDS-radix one (fengine.hip) at 9, 12 and 13.  The
-// choice is measured: 64 signals of 2^27 samples, int8 output, ms per call
+// Which F-engine serves a launch: the four-step (matrix-core) one at log2 M =
+// 8, 10 and 11 outside table mode (launch modes 0-3), the LDS-radix one
+// (fengine.hip) otherwise.  The choice is measured: 64 signals of 2^27
+// samples, int8 output, ms per call
 //   log2 M         8      9      10     11     12
 //   four-step    7.99  10.20   9.40   9.64  15.92
 //   LDS-radix    9.05   9.28  10.35  10.69  12.12
-// (FP32 output: the four-step kernel 2-15% faster at 8-11, 10% slower at 12);
-// at 13 the four-step kernel spills registers.
-constexpr bool use_fengine4(int log2m) { return log2m == 8 || log2m == 10 || log2m == 11; }
+// (FP32 output: the four-step kernel 2-15% faster at 8-11, 10% slower at 12;
+// table mode at 11: 14.7 against 12.0 ms); at 13 the four-step kernel spills
+// registers.
+constexpr bool use_fengine4(int log2m, int mode) {
+    return mode < 4 && (log2m == 8 || log2m == 10 || log2m == 11);
+}
 
 // Phase look-up table of section 2.3.2: 1440 steps of 0.25 degrees.
 constexpr int kLutSteps = 1440;

@@ -42,9 +42,8 @@
 //  5. FSTC and fringe stop (Eq. 2): Y[k] = X[k] exp(2 pi i (k f / N + c_m)),
 //     the per-channel ramp computed once per workgroup, c_m = nu_BB f / fs +
 //     sideband (psi0 + rate t_m) reduced mod 1 in FP64 once per spectrum and
-//     workgroup.  Table mode (the 1440-step sin/cos table of section 2.3.2):
-//     the phase k f / N + c_m in FP64 per channel, rounded to the nearest of
-//     1440 steps;
+//     workgroup (table mode, the 1440-step sin/cos table of section 2.3.2,
+//     runs on the LDS-radix kernel);
 //  6. requantisation (section 4.1's fixed point ahead of the MAC) and the
 //     corner turn: a thread owns the same channels in every spectrum and
 //     gathers a whole 16-byte X-layout chunk per channel (8 spectra of int8 or
@@ -240,45 +239,26 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
     return x * q + min(x, rem) + i;
 }
 
-__device__ inline double lut_spectrum_phase(double c_bb, int sideband, double psi0, double rate, int64_t m,
-                                            double t_spec) {
-#pragma clang fp contract(off)
-    const double tm = ((double)m + 0.5) * t_spec;
-    double c = c_bb + (double)sideband * (psi0 + rate * tm);
-    return c - floor(c);
-}
-__device__ inline int lut_index(double c, double kfn) {
-#pragma clang fp contract(off)
-    const int i = (int)rint((c + kfn) * (double)kLutSteps);
-    return i % kLutSteps;
-}
-
 // One output channel of a thread: its ramp (x 1/scale), its corner-turn staging
-// and, in calibration mode, its |X|^2 sum.  INT8/FP8 stage half a chunk -- the
-// re and im bytes of 4 spectra -- and store it when complete.
+// and, in calibration mode, its |X|^2 sum.  INT8/FP8 stage a chunk -- the re and
+// im bytes of 8 spectra -- and store it when complete.
 struct Chan {
     float2 ramp;
-    uint32_t q, h;  // INT8/FP8: re and im bytes of spectra 4g..4g+3
+    uint32_t q, h;    // INT8/FP8: re and im bytes of the spectra 4j..4j+3 in progress
+    uint32_t q0, h0;  // INT8/FP8: those of the first four spectra of the chunk
     float2 f0;      // FP32: the even spectrum of the pair
     float pacc;
 };
 
 // Phase, requantisation and corner turn of channel k's value X in spectrum r of
 // the slot; chunk is the channel's 16-byte X-layout chunk of this spectrum group.
-template <int BM, bool PL>
-__device__ __forceinline__ void emit(Chan &c, int k, float2 X, float2 rot, int r, uint32_t bsel, const FLaunch &a,
-                                     bool active, double c_lut, double fn, uint4 *chunk) {
+template <int BM>
+__device__ __forceinline__ void emit(Chan &c, float2 X, float2 rot, int r, uint32_t bsel, bool active, uint4 *chunk) {
     if constexpr (BM == 3) {
         c.pacc += X.x * X.x + X.y * X.y;
         return;
     } else {
-        float2 Y;
-        if constexpr (PL) {
-            const float2 e = a.lut[lut_index(c_lut, (double)k * fn)];
-            Y = make_float2(c.ramp.x * (X.x * e.x - X.y * e.y), c.ramp.x * (X.x * e.y + X.y * e.x));
-        } else {
-            Y = cmul(cmul(X, c.ramp), rot);
-        }
+        const float2 Y = cmul(cmul(X, c.ramp), rot);
         if constexpr (BM == 0) {
             if (r & 1) {
                 if (active) *reinterpret_cast<float4 *>(chunk) = make_float4(c.f0.x, c.f0.y, Y.x, Y.y);
@@ -294,20 +274,23 @@ __device__ __forceinline__ void emit(Chan &c, int k, float2 X, float2 rot, int r
                 c.q = __builtin_amdgcn_perm(w, c.q, bsel);
                 c.h = __builtin_amdgcn_perm(w, c.h, bsel + (1u << (8 * (r & 3))));
             }
-            if ((r & 3) == 3 && active) {  // re bytes at 0-3 or 4-7, im bytes at 8-11 or 12-15
-                uint32_t *d = reinterpret_cast<uint32_t *>(chunk) + ((r >> 2) & 1);
-                d[0] = c.q;
-                d[2] = c.h;
+            // the chunk holds the re bytes of its 8 spectra, then their im bytes: it is
+            // stored whole, once, after its last spectrum (a half written four spectra
+            // before the other leaves L2 twice)
+            if ((r & 7) == 3) {
+                c.q0 = c.q;
+                c.h0 = c.h;
+            } else if ((r & 7) == 7 && active) {
+                *chunk = make_uint4(c.q0, c.q, c.h0, c.h);
             }
         }
     }
 }
 
 template <int LOGM, int MODE>
-__global__ void __launch_bounds__(F4Cfg<LOGM>::WG) fengine4_kernel(FLaunch a) {
+__global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_per_eu(3))) fengine4_kernel(FLaunch a) {
     using C = F4Cfg<LOGM>;
-    constexpr int BM = MODE & 3;          // 0 FP32, 1 INT8, 2 FP8, 3 calibration
-    constexpr bool PL = (MODE & 4) != 0;  // phase from the 1440-step table
+    constexpr int BM = MODE;  // 0 FP32, 1 INT8, 2 FP8, 3 calibration
     constexpr int M = C::M, N = C::N, N1 = C::N1, L = C::L, FPAR = C::FPAR, WG = C::WG;
     constexpr int SPS = C::SPS, SPB = SPS * FPAR;
     constexpr int G = (BM == 0) ? kChunk32 : kChunk8;
@@ -319,7 +302,6 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) fengine4_kernel(FLaunch a) {
     __shared__ __attribute__((aligned(16))) uint16_t lds_a[2][64 * C::AP];  // FP16 rows (hi, lo)
     __shared__ __attribute__((aligned(16))) float2 lds_u[FPAR * N1];  // column 0 outputs
     __shared__ float2 lds_rot[SPB];
-    __shared__ double lds_clut[PL ? SPB : 1];
 
     const int tid = threadIdx.x;
     const int nblk = (a.T + SPB - 1) / SPB;
@@ -337,14 +319,11 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) fengine4_kernel(FLaunch a) {
     }
     const double t_spec = (double)N / a.fs;
     const double c_bb = a.nu_bb * (double)g.frac / a.fs;
-    const double fn = (double)g.frac / (double)N;
 
     // per-spectrum phase of the whole workgroup, once: FP64 reduction, FP32 sincos
     if (tid < SPB) {
         const int64_t m = a.spectrum0 + mblk + tid;
-        if constexpr (PL) {
-            lds_clut[tid] = lut_spectrum_phase(c_bb, a.sideband, g.psi0, g.rate, m, t_spec);
-        } else if constexpr (BM != 3) {
+        if constexpr (BM != 3) {
             const double tm = ((double)m + 0.5) * t_spec;
             double c = c_bb + (double)a.sideband * (g.psi0 + g.rate * tm);
             c -= floor(c);
@@ -399,13 +378,13 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) fengine4_kernel(FLaunch a) {
 #pragma unroll
     for (int o = 0; o < 9; ++o) {
         Chan &c = ch[o];
-        c.q = c.h = 0u;
+        c.q = c.h = c.q0 = c.h0 = 0u;
         c.f0 = make_float2(0.f, 0.f);
         c.pacc = 0.f;
         const int k = o == 8 ? (tid < C::NSPEC ? ch_s : 0) : (cp == 0 ? 0 : chan(o));
         // column 0 unfolds 2 X, so its ramp carries the factor 1/2 (exact)
         const float hf = o == 8 ? 0.5f : 1.0f;
-        if constexpr (PL || BM == 3) {
+        if constexpr (BM == 3) {
             c.ramp = make_float2(hf, 0.f);
         } else {
             float sn, cs;
@@ -515,7 +494,6 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) fengine4_kernel(FLaunch a) {
         // 5-6. phase, requantisation and corner turn of every channel
         const int mc = m_c0 + r;
         const float2 rot_c = lds_rot[SPS * bu + r];
-        const double clut_c = PL ? lds_clut[SPS * bu + r] : 0.0;
         const uint32_t bsel = (0x03020100u & ~(0xFFu << (8 * (r & 3)))) | (0x04u << (8 * (r & 3)));
         uint4 *gbase_c = reinterpret_cast<uint4 *>(a.spec) + (int64_t)(mc / G) * M * a.S;
         if (cp != 0) {
@@ -525,7 +503,7 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) fengine4_kernel(FLaunch a) {
                 const int k = chan(o);
                 const float2 X = q < RL / 2 ? z[o] : make_float2(z[o].x, -z[o].y);
                 if (BM != 3 && a.power && c_active) a.power[((int64_t)s * a.T + mc) * M + k] = X.x * X.x + X.y * X.y;
-                emit<BM, PL>(ch[o], k, X, rot_c, r, bsel, a, c_active, clut_c, fn, gbase_c + chunk_base(k));
+                emit<BM>(ch[o], X, rot_c, r, bsel, c_active, gbase_c + chunk_base(k));
             }
         }
         // column 0's outputs are written by threads tid < J and unfolded by threads
@@ -548,12 +526,11 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) fengine4_kernel(FLaunch a) {
             X.x = fmaf(wsp.x, df.y, fmaf(wsp.y, df.x, sm.x));
             X.y = fmaf(-wsp.x, df.x, fmaf(wsp.y, df.y, sm.y));
             const float2 rot_s = lds_rot[SPS * nspec_u + r];
-            const double clut_s = PL ? lds_clut[SPS * nspec_u + r] : 0.0;
             uint4 *gbase_s = reinterpret_cast<uint4 *>(a.spec) + (int64_t)(ms / G) * M * a.S;
             // column 0 unfolds 2 X: power and the calibration sum take |X|^2 = |2 X|^2 / 4
             if constexpr (BM != 3) {
                 if (a.power && s_active) a.power[((int64_t)s * a.T + ms) * M + ch_s] = 0.25f * (X.x * X.x + X.y * X.y);
-                emit<BM, PL>(ch[8], ch_s, X, rot_s, r, bsel, a, s_active, clut_s, fn, gbase_s + chunk_base(ch_s));
+                emit<BM>(ch[8], X, rot_s, r, bsel, s_active, gbase_s + chunk_base(ch_s));
             } else {
                 ch[8].pacc += 0.25f * (X.x * X.x + X.y * X.y);
             }
@@ -590,9 +567,6 @@ hipError_t launch4_one(int mode, const FLaunch &a, hipStream_t st) {
     case 1: hipLaunchKernelGGL((fengine4_kernel<LOGM, 1>), grid, block, 0, st, a); break;
     case 2: hipLaunchKernelGGL((fengine4_kernel<LOGM, 2>), grid, block, 0, st, a); break;
     case 3: hipLaunchKernelGGL((fengine4_kernel<LOGM, 3>), grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((fengine4_kernel<LOGM, 4>), grid, block, 0, st, a); break;
-    case 5: hipLaunchKernelGGL((fengine4_kernel<LOGM, 5>), grid, block, 0, st, a); break;
-    case 6: hipLaunchKernelGGL((fengine4_kernel<LOGM, 6>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -653,11 +627,8 @@ void fengine4_tables(int log2m, uint16_t *afrag, float2 *tw4, float2 *twb, size_
 int fengine4_spectra_per_block(int log2m) {
     switch (log2m) {
     case 8: return F4Cfg<8>::SPS * F4Cfg<8>::FPAR;
-    case 9: return F4Cfg<9>::SPS * F4Cfg<9>::FPAR;
     case 10: return F4Cfg<10>::SPS * F4Cfg<10>::FPAR;
     case 11: return F4Cfg<11>::SPS * F4Cfg<11>::FPAR;
-    case 12: return F4Cfg<12>::SPS * F4Cfg<12>::FPAR;
-    case 13: return F4Cfg<13>::SPS * F4Cfg<13>::FPAR;
     default: return 0;
     }
 }
@@ -665,12 +636,9 @@ int fengine4_spectra_per_block(int log2m) {
 hipError_t launch_fengine4(int log2m, int mode, const FLaunch &a, hipStream_t st) {
     switch (log2m) {
     case 8: return launch4_one<8>(mode, a, st);
-    case 9: return launch4_one<9>(mode, a, st);
     case 10: return launch4_one<10>(mode, a, st);
     case 11: return launch4_one<11>(mode, a, st);
-    case 12: return launch4_one<12>(mode, a, st);
-    case 13: return launch4_one<13>(mode, a, st);
-    default: return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;  // the other lengths run on the LDS-radix kernel
     }
 }
 
