@@ -400,7 +400,8 @@ def bench_rfi(args):
     torch.neg(src, out=torch.empty_like(src))
     del src
     scale = calibrate_scales(corr, torch, S, N, T, x, rs, g)
-    plan = corr.Plan(S, N, T, precision=corr.INT8, scale_mode=corr.SCALE_HOLD)
+    # power cells in FP16 (|X|^2 / N^2): half the bytes of FP32 for the F-engine to write and the CNN to read
+    plan = corr.Plan(S, N, T, precision=corr.INT8, scale_mode=corr.SCALE_HOLD, power_fp16=1)
     spec = plan.alloc("spectra", zero=False)
     power = plan.alloc("power", zero=False).view(S, T, C)
     flags = plan.alloc("flags", zero=False).view(S, T, C)
@@ -458,7 +459,7 @@ def bench_rfi(args):
         "data": "synthetic (seeded Gaussian + common source + tone, generated on the GPU); "
                 "CNN weights He-normal random (the kernel's time does not depend on them)",
         "config": {"workload": "64 signals, 8192-pt FFT (4096 ch), 8192 spectra, int8 X-engine, "
-                               "learned flagger on %d power cells (%d tiles of 64 x 256)" % (cells, cells // 16384),
+                               "learned flagger on %d FP16 power cells (%d tiles of 64 x 256)" % (cells, cells // 16384),
                    "parallelism": "single GPU"},
         "ms": {n: round(v * 1e3, 4) for n, v in t.items()},
         "mad_flag_ms": round(t_mad * 1e3, 4),

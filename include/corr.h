@@ -97,7 +97,10 @@ typedef struct {
                           /* formed in FP64 per channel and spectrum, rounded   */
                           /* to the nearest 0.25 degree step, and that step's   */
                           /* FP32 cos and sin are used (error <= 0.125 deg)     */
-    int32_t reserved[6];  /* must be zero                                        */
+    int32_t power_fp16;   /* power cells of corr_fengine / corr_mad_flag: 0 FP32 */
+                          /* |X|^2; 1 FP16 |X|^2 / N^2 (half the bytes; real    */
+                          /* int8 input keeps |X| <= 127 N, so no overflow)     */
+    int32_t reserved[5];  /* must be zero                                        */
 } corr_desc_t;
 
 /*
@@ -210,14 +213,18 @@ corr_status corr_plan_bind_workspace(corr_plan_t *plan, void *d_ws, size_t bytes
  *              written (scale = 4 sigma / 127 or 4 sigma / 448, sigma the RMS
  *              of one component of Y over this call) in COMPUTE mode.
  *              Unused (may be NULL) for FP32.
- *   d_power    optional (NULL: not written) FP32 power |X|^2 of every cell,
- *              [S][T][C] -- the dynamic spectra the flaggers below read
- *              (corr_plan_power_bytes).
+ *   d_power    optional (NULL: not written) power of every cell, [S][T][C]
+ *              -- the dynamic spectra the flaggers below read
+ *              (corr_plan_power_bytes): FP32 |X|^2, or with the plan's
+ *              power_fp16 FP16 |X|^2 / N^2 (the FP32 value times the exact
+ *              power of two, rounded to nearest even); X before phase
+ *              rotation and requantisation (the rotation keeps |X|).  4-byte
+ *              (FP32) or 2-byte (FP16) aligned.
  * Errors: NULL, ALIGN, INVALID (row_stride), WORKSPACE, DEVICE.
  */
 corr_status corr_fengine(corr_plan_t *plan, const int8_t *d_x, int64_t row_stride,
                          const corr_geom_t *d_geom, int64_t spectrum0, void *d_spec,
-                         float *d_scale, float *d_power, void *stream);
+                         float *d_scale, void *d_power, void *stream);
 
 /* Corner turn of externally produced spectra into the X layout above.
  *   d_in: [S][T][C][2] elements (float for FP32, int8 for INT8, e4m3 bytes
@@ -365,11 +372,13 @@ corr_status corr_fix16_xengine(corr_plan_t *plan, const int16_t *d_y16, const fl
  * broadband bursts, the column statistic (mean power of a channel over the
  * tile's spectra) persistent tones; a cell is flagged (1) when its row or its
  * column is.  Median of an even count = mean of the two middle values.
- *   d_power  [S][T][C] float, 16-byte aligned.
+ *   d_power  [S][T][C], the plan's power type (FP32, or FP16 with
+ *            power_fp16: the statistics are taken in FP32 either way and do
+ *            not depend on the scale), 16-byte aligned.
  *   d_flags  [S][T][C] uint8 (corr_plan_flags_bytes), 16-byte aligned.
  * Needs T % 64 == 0 (C = N/2 >= 256 is always a multiple of 256).
  * Errors: NULL, ALIGN, INVALID (shape, M <= 0), DEVICE. */
-corr_status corr_mad_flag(corr_plan_t *plan, const float *d_power, float M, uint8_t *d_flags,
+corr_status corr_mad_flag(corr_plan_t *plan, const void *d_power, float M, uint8_t *d_flags,
                           void *stream);
 
 /* Zero the flagged cells of X-layout spectra in place (both components), and
@@ -653,6 +662,12 @@ corr_status corr_cnn_check_device_errors(corr_cnn_t *cnn, void *stream);
  * DEVICE; messages via corr_cnn_last_error(NULL). */
 corr_status corr_cnn_infer(const float *d_params, const float *d_power, int32_t S, int64_t T, int32_t C,
                            float threshold, uint8_t *d_flags, float *d_logits, void *stream);
+/* The same inference on FP16 power (as corr_fengine writes it with the plan's
+ * power_fp16; any scale, the input normalisation divides it out), read as
+ * FP16 and widened to FP32 before the normalisation.  2-byte aligned.
+ * Errors as corr_cnn_infer. */
+corr_status corr_cnn_infer_f16(const float *d_params, const void *d_power16, int32_t S, int64_t T, int32_t C,
+                               float threshold, uint8_t *d_flags, float *d_logits, void *stream);
 
 /* Save / load parameters and Adam state (each d_* CORR_CNN_PARAMS floats;
  * d_m and d_v may be NULL) to a little-endian binary file: magic "CORRCNN1",

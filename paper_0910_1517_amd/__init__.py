@@ -48,7 +48,8 @@ class CorrDesc(ctypes.Structure):
         ("nu_bb", ctypes.c_double),
         ("x_split", ctypes.c_int32),
         ("phase_lut", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("power_fp16", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -73,7 +74,7 @@ SYMBOLS = [
     "corr_autotune_scratch_bytes", "corr_autotune_x_split",
     "corr_cnn_create", "corr_cnn_destroy", "corr_cnn_workspace_bytes", "corr_cnn_bind_workspace",
     "corr_cnn_forward", "corr_cnn_loss_grad", "corr_cnn_adam", "corr_cnn_train_step",
-    "corr_cnn_check_device_errors", "corr_cnn_infer", "corr_cnn_save", "corr_cnn_load", "corr_cnn_last_error",
+    "corr_cnn_check_device_errors", "corr_cnn_infer", "corr_cnn_infer_f16", "corr_cnn_save", "corr_cnn_load", "corr_cnn_last_error",
     "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
     "corr_adc_unpack", "corr_adc_last_error", "corr_xengine_gated", "corr_pulsar_gates",
     "corr_dedisperse", "corr_dedisperse_workspace_bytes", "corr_dedisperse_last_error",
@@ -166,6 +167,8 @@ def lib():
     L.corr_cnn_train_step.argtypes = [P, P, P, P, i64, P, P, i32, i64, i32, P, i32, P, P]
     L.corr_cnn_check_device_errors.argtypes = [P, P]
     L.corr_cnn_infer.argtypes = [P, P, i32, i64, i32, f32, P, P, P]
+    L.corr_cnn_infer_f16.argtypes = [P, P, i32, i64, i32, f32, P, P, P]
+    L.corr_cnn_infer_f16.restype = ctypes.c_int32
     L.corr_cnn_save.argtypes = [ctypes.c_char_p, P, P, P, i64]
     L.corr_cnn_load.argtypes = [ctypes.c_char_p, P, P, P, ctypes.POINTER(i64)]
     for n in ("create", "bind_workspace", "forward", "loss_grad", "adam", "train_step", "check_device_errors",
@@ -274,11 +277,13 @@ def _stream(stream):
 
 
 def make_desc(n_signals, fft_len, n_spectra, *, max_delay=16, precision=FP32, sideband=1,
-              scale_mode=SCALE_HOLD, sample_rate=66.666666e6, nu_bb=0.0, x_split=0, phase_lut=0) -> CorrDesc:
+              scale_mode=SCALE_HOLD, sample_rate=66.666666e6, nu_bb=0.0, x_split=0, phase_lut=0,
+              power_fp16=0) -> CorrDesc:
     d = CorrDesc()
     d.n_signals, d.fft_len, d.n_spectra = n_signals, fft_len, n_spectra
     d.max_delay, d.precision, d.sideband, d.scale_mode = max_delay, precision, sideband, scale_mode
     d.sample_rate, d.nu_bb, d.x_split, d.phase_lut = sample_rate, nu_bb, x_split, phase_lut
+    d.power_fp16 = power_fp16
     return d
 
 
@@ -288,11 +293,11 @@ class Plan:
     def __init__(self, n_signals: int, fft_len: int, n_spectra: int, *, max_delay: int = 16,
                  precision: int = FP32, sideband: int = 1, scale_mode: int = SCALE_HOLD,
                  sample_rate: float = 66.666666e6, nu_bb: float = 0.0, x_split: int = 0, phase_lut: int = 0,
-                 device=None, bind: bool = True, _handle=None):
+                 power_fp16: int = 0, device=None, bind: bool = True, _handle=None):
         L = lib()
         self.desc = make_desc(n_signals, fft_len, n_spectra, max_delay=max_delay, precision=precision,
                               sideband=sideband, scale_mode=scale_mode, sample_rate=sample_rate,
-                              nu_bb=nu_bb, x_split=x_split, phase_lut=phase_lut)
+                              nu_bb=nu_bb, x_split=x_split, phase_lut=phase_lut, power_fp16=power_fp16)
         self._owned = _handle is None
         if _handle is None:
             h = ctypes.c_void_p()
@@ -306,6 +311,7 @@ class Plan:
         self.C = fft_len // 2
         self.P = n_signals * (n_signals + 1) // 2
         self.precision = precision
+        self.power_fp16 = power_fp16
         self.max_delay = max_delay
         self.workspace = None
         if bind:
@@ -345,7 +351,8 @@ class Plan:
         import torch
         n = self._size(what)
         dt = {"spectra": torch.uint8, "acc": torch.int32 if self.precision == INT8 else torch.float32,
-              "state": torch.float64, "vis": torch.float32, "power": torch.float32,
+              "state": torch.float64, "vis": torch.float32,
+              "power": torch.float16 if self.power_fp16 else torch.float32,
               "flags": torch.uint8, "keep": torch.int32}[what]
         el = torch.tensor([], dtype=dt).element_size()
         f = torch.zeros if zero else torch.empty
@@ -361,13 +368,14 @@ class Plan:
         _need(geom, "geom", 24 * self.S)
         _need(spec, "spec", self.spectra_bytes)
         _need(scale, "scale", 4 * self.S * self.C, torch.float32, optional=self.precision == FP32)
-        _need(power, "power", self._size("power"), torch.float32, optional=True)
+        _need(power, "power", self._size("power"), torch.float16 if self.power_fp16 else torch.float32,
+              optional=True)
         self._check(lib().corr_fengine(self._h, _ptr(x), rs, _ptr(geom), spectrum0, _ptr(spec),
                                        _ptr(scale), _ptr(power), _stream(stream)))
 
     def mad_flag(self, power, flags, M=3.0, stream=None):
         import torch
-        _need(power, "power", self._size("power"), torch.float32)
+        _need(power, "power", self._size("power"), torch.float16 if self.power_fp16 else torch.float32)
         _need(flags, "flags", self._size("flags"), torch.uint8)
         self._check(lib().corr_mad_flag(self._h, _ptr(power), M, _ptr(flags), _stream(stream)))
 
@@ -637,16 +645,18 @@ class CNN:
 
 
 def cnn_infer(params, power, flags, *, threshold: float = 0.5, logits=None, stream=None):
-    """Flags (and optionally logits) of every tile of power [S][T][C] from the
-    fused FP16 inference kernel."""
+    """Flags (and optionally logits) of every tile of power [S][T][C] (float32,
+    or float16 as the F-engine writes it with power_fp16) from the fused FP16
+    inference kernel."""
     import torch
     S, T, C = power.shape
+    f16 = power.dtype == torch.float16
     _need(params, "params", 4 * CNN_PARAMS, torch.float32)
-    _need(power, "power", 4 * S * T * C, torch.float32)
+    _need(power, "power", (2 if f16 else 4) * S * T * C, (torch.float16, torch.float32))
     _need(flags, "flags", S * T * C, torch.uint8)
     _need(logits, "logits", 4 * S * T * C, torch.float32, optional=True)
-    _cnn_check(lib().corr_cnn_infer(_ptr(params), _ptr(power), S, T, C, threshold, _ptr(flags), _ptr(logits),
-                                    _stream(stream)))
+    fn = lib().corr_cnn_infer_f16 if f16 else lib().corr_cnn_infer
+    _cnn_check(fn(_ptr(params), _ptr(power), S, T, C, threshold, _ptr(flags), _ptr(logits), _stream(stream)))
 
 
 def cnn_save(path: str, params, m=None, v=None, step: int = 0):

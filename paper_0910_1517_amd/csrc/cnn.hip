@@ -346,8 +346,9 @@ __device__ inline int a1_off(int pcol, int h) { return 32 * pcol + 16 * (h ^ (((
 //            directly from the layer-2 accumulator (its 8 channels per lane
 //            are exactly one lane's K slots), then z3[p] = b3 + sum of U over
 //            the 9 shifted neighbours of p.
+template <typename PT>
 __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict__ params,
-                                                        const float *__restrict__ power, int64_t T, int C,
+                                                        const PT *__restrict__ power, int64_t T, int C,
                                                         int n_tiles, float thr_logit, uint8_t *__restrict__ flags,
                                                         float *__restrict__ logits) {
     __shared__ __align__(16) _Float16 xs[XCOLS][XPITCH];  // column-major input ring (slot = (row + 1) mod 8)
@@ -428,7 +429,7 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
     // 9 + xh, the first four slots of the input ring
     float csum = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f;
     if (tile < n_tiles) {
-        const float *tb = power + tile_base(tile);
+        const PT *tb = power + tile_base(tile);
 #pragma unroll 8
         for (int q = 0; q < 32; ++q) csum += tb[roff(2 * q + xh, xc)];
         p0 = xh ? tb[xc] : 0.f;
@@ -440,9 +441,9 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
     }
     for (; tile < n_tiles; tile += gridDim.x) {
         const int64_t base = tile_base(tile);
-        const float *tb = power + base;
+        const PT *tb = power + base;
         const bool has_next = tile + (int)gridDim.x < n_tiles;
-        const float *tn = has_next ? power + tile_base(tile + gridDim.x) : tb;
+        const PT *tn = has_next ? power + tile_base(tile + gridDim.x) : tb;
         uint8_t *fb = flags + base;
         float *lb = logits ? logits + base : nullptr;
 
@@ -641,8 +642,8 @@ hipError_t launch_cnn_adam(float *params, float *m, float *v, const float *grad,
     return hipGetLastError();
 }
 
-hipError_t launch_cnn_infer(const float *params, const float *power, int S, int64_t T, int C, float thr_logit,
-                            uint8_t *flags, float *logits, hipStream_t st) {
+hipError_t launch_cnn_infer(const float *params, const void *power, bool f16, int S, int64_t T, int C,
+                            float thr_logit, uint8_t *flags, float *logits, hipStream_t st) {
     const int n_tiles = (int)((int64_t)S * (T / H) * (C / W));
     // persistent: one workgroup per compute unit (the LDS use allows one), each
     // fetching its next tile's power while it computes the current one
@@ -651,8 +652,12 @@ hipError_t launch_cnn_infer(const float *params, const float *power, int S, int6
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
     const int grid = std::max(1, std::min(n_tiles, cus));
-    hipLaunchKernelGGL(cnn_infer_kernel, dim3(grid), dim3(IWG), 0, st, params, power, T, C, n_tiles, thr_logit,
-                       flags, logits);
+    if (f16)
+        hipLaunchKernelGGL(cnn_infer_kernel<_Float16>, dim3(grid), dim3(IWG), 0, st, params,
+                           static_cast<const _Float16 *>(power), T, C, n_tiles, thr_logit, flags, logits);
+    else
+        hipLaunchKernelGGL(cnn_infer_kernel<float>, dim3(grid), dim3(IWG), 0, st, params,
+                           static_cast<const float *>(power), T, C, n_tiles, thr_logit, flags, logits);
     return hipGetLastError();
 }
 

@@ -115,7 +115,9 @@ corr_status corr_plan_create(const corr_desc_t *desc, corr_plan_t **out) {
         return fail(nullptr, CORR_ERR_INVALID, "x_split %d outside 0..4096", d.x_split);
     if (d.phase_lut != 0 && d.phase_lut != 1)
         return fail(nullptr, CORR_ERR_INVALID, "phase_lut must be 0 or 1 (got %d)", d.phase_lut);
-    for (int i = 0; i < 6; ++i)
+    if (d.power_fp16 != 0 && d.power_fp16 != 1)
+        return fail(nullptr, CORR_ERR_INVALID, "power_fp16 must be 0 or 1 (got %d)", d.power_fp16);
+    for (int i = 0; i < 5; ++i)
         if (d.reserved[i]) return fail(nullptr, CORR_ERR_INVALID, "reserved[%d] must be zero", i);
 
     corr_plan *p = new (std::nothrow) corr_plan;
@@ -247,7 +249,7 @@ corr_status corr_plan_bind_workspace(corr_plan_t *p, void *d_ws, size_t bytes, v
 }
 
 corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, const corr_geom_t *d_geom,
-                         int64_t spectrum0, void *d_spec, float *d_scale, float *d_power, void *stream) {
+                         int64_t spectrum0, void *d_spec, float *d_scale, void *d_power, void *stream) {
     if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
     if (!d_x || !d_geom || !d_spec) return fail(p, CORR_ERR_NULL, "d_x, d_geom and d_spec are required");
     const bool q8 = p->d.precision != CORR_FP32;
@@ -257,7 +259,8 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
     if (!aligned(d_geom, 8)) return fail(p, CORR_ERR_ALIGN, "d_geom must be 8-byte aligned");
     if (!aligned(d_spec, 256)) return fail(p, CORR_ERR_ALIGN, "d_spec must be 256-byte aligned");
     if (d_scale && !aligned(d_scale, 4)) return fail(p, CORR_ERR_ALIGN, "d_scale must be 4-byte aligned");
-    if (d_power && !aligned(d_power, 4)) return fail(p, CORR_ERR_ALIGN, "d_power must be 4-byte aligned");
+    if (d_power && !aligned(d_power, p->d.power_fp16 ? 2 : 4))
+        return fail(p, CORR_ERR_ALIGN, "d_power must be %d-byte aligned", p->d.power_fp16 ? 2 : 4);
     const int64_t need = (int64_t)p->d.fft_len * p->d.n_spectra + p->d.max_delay;
     if (row_stride < need)
         return fail(p, CORR_ERR_INVALID, "row_stride %lld < T*N + max_delay = %lld", (long long)row_stride,
@@ -273,6 +276,8 @@ corr_status corr_fengine(corr_plan_t *p, const int8_t *d_x, int64_t row_stride, 
     a.scale = d_scale;
     a.part = reinterpret_cast<float *>(p->d_ws + p->ws.part);
     a.power = d_power;
+    a.power_f16 = p->d.power_fp16;
+    a.power_scale = std::ldexp(1.0f, -2 * (p->log2m + 1));  // 1 / N^2
     a.twp = reinterpret_cast<const float2 *>(p->d_ws + p->ws.twp);
     a.wn = reinterpret_cast<const float2 *>(p->d_ws + p->ws.wn);
     a.err = reinterpret_cast<uint32_t *>(p->d_ws + p->ws.err);
@@ -500,7 +505,7 @@ corr_status corr_integrate(corr_plan_t *p, void *d_acc, const float *d_scale, do
     return CORR_OK;
 }
 
-corr_status corr_mad_flag(corr_plan_t *p, const float *d_power, float M, uint8_t *d_flags, void *stream) {
+corr_status corr_mad_flag(corr_plan_t *p, const void *d_power, float M, uint8_t *d_flags, void *stream) {
     if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
     if (!d_power || !d_flags) return fail(p, CORR_ERR_NULL, "d_power and d_flags are required");
     if (!aligned(d_power, 16) || !aligned(d_flags, 16))
@@ -509,8 +514,8 @@ corr_status corr_mad_flag(corr_plan_t *p, const float *d_power, float M, uint8_t
         return fail(p, CORR_ERR_INVALID, "flagging needs T %% %d == 0 and C %% %d == 0", kFlagTileSpectra,
                     kFlagTileChannels);
     if (!(M > 0) || !std::isfinite(M)) return fail(p, CORR_ERR_INVALID, "threshold M must be finite and > 0");
-    hipError_t e = launch_mad_flag(d_power, p->d.n_signals, (int)p->d.n_spectra, p->M, M, d_flags,
-                                   (hipStream_t)stream);
+    hipError_t e = launch_mad_flag(d_power, p->d.power_fp16 != 0, p->d.n_signals, (int)p->d.n_spectra, p->M, M,
+                                   d_flags, (hipStream_t)stream);
     return e == hipSuccess ? CORR_OK : hip_fail(p, e, "MAD flag launch");
 }
 
@@ -541,7 +546,7 @@ size_t corr_plan_keep_bytes(const corr_plan_t *p) {
     return p ? (size_t)p->M * p->d.n_signals * (p->d.n_spectra / 32) * 4 : 0;
 }
 size_t corr_plan_power_bytes(const corr_plan_t *p) {
-    return p ? (size_t)p->d.n_signals * p->d.n_spectra * p->M * 4 : 0;
+    return p ? (size_t)p->d.n_signals * p->d.n_spectra * p->M * (p->d.power_fp16 ? 2 : 4) : 0;
 }
 
 /* ------------------------------------------------------------------ batch */

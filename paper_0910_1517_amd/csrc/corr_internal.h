@@ -47,7 +47,9 @@ struct FLaunch {
     void *spec;
     const float *scale;  // HOLD-mode scales [S][C]
     float *part;         // calibration partials
-    float *power;        // optional |X|^2 output [S][T][C] (nullptr: none)
+    void *power;         // optional power output [S][T][C] (nullptr: none)
+    int power_f16;       // 0: FP32 |X|^2; 1: FP16 |X|^2 * power_scale
+    float power_scale;   // 1 / N^2 (exact) for FP16
     const float2 *twp;
     const float2 *wn;
     uint32_t *err;
@@ -64,6 +66,14 @@ struct FLaunch {
     const float2 *twb;
     const float2 *wsp;
 };
+
+// One power cell of the F-engine: FP32 |X|^2, or FP16 |X|^2 / N^2 (nearest even).
+__device__ __forceinline__ void put_power(const FLaunch &a, int64_t i, float p) {
+    if (a.power_f16)
+        reinterpret_cast<_Float16 *>(a.power)[i] = (_Float16)(p * a.power_scale);
+    else
+        reinterpret_cast<float *>(a.power)[i] = p;
+}
 
 // Which F-engine serves a launch: the four-step (matrix-core) one at log2 M =
 // 8, 10 and 11 outside table mode (launch modes 0-3), the LDS-radix one
@@ -132,7 +142,8 @@ hipError_t launch_xengine_batch(const XBatchArgs &a, hipStream_t st);
 hipError_t launch_xpack(int precision, const void *in, void *spec, int S, int C, int T,
                         hipStream_t st);
 
-hipError_t launch_mad_flag(const float *power, int S, int T, int C, float M, uint8_t *flags, hipStream_t st);
+hipError_t launch_mad_flag(const void *power, bool f16, int S, int T, int C, float M, uint8_t *flags,
+                           hipStream_t st);
 hipError_t launch_apply_flags(int precision, const uint8_t *flags, void *spec, uint32_t *keep, int S, int T,
                               int C, hipStream_t st);
 hipError_t launch_pair_counts(const uint32_t *keep, const uint16_t *pairs, int S, int T, int C, int32_t *counts,
@@ -228,7 +239,7 @@ hipError_t launch_cnn_backward(const float *params, int n, const CnnTrainBufs &b
 hipError_t launch_cnn_adam(float *params, float *m, float *v, const float *grad, float lr, float beta1,
                            float beta2, float eps, float c1, float c2, hipStream_t st);
 // fused FP16 MFMA inference over every tile of power [S][T][C]
-hipError_t launch_cnn_infer(const float *params, const float *power, int S, int64_t T, int C, float thr_logit,
-                            uint8_t *flags, float *logits, hipStream_t st);
+hipError_t launch_cnn_infer(const float *params, const void *power, bool f16, int S, int64_t T, int C,
+                            float thr_logit, uint8_t *flags, float *logits, hipStream_t st);
 
 }  // namespace corr

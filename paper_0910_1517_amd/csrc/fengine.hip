@@ -436,7 +436,7 @@ fengine_kernel(FLaunch a) {
                 pacc[j] += X.x * X.x + X.y * X.y;
             } else {
                 if (a.power && active)  // |X|^2 = |2X|^2 / 4 (the phase rotation keeps it)
-                    a.power[((int64_t)s * a.T + m) * M + tt + L * j] = 0.25f * (X.x * X.x + X.y * X.y);
+                    put_power(a, ((int64_t)s * a.T + m) * M + tt + L * j, 0.25f * (X.x * X.x + X.y * X.y));
                 float2 Y;
                 if constexpr (PL) {  // table entry nearest the channel's phase; ramp = 1/2 (x 1/scale)
                     const float2 e = ev[j];

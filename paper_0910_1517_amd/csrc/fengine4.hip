@@ -502,7 +502,7 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
                 const int q = o % RL;
                 const int k = chan(o);
                 const float2 X = q < RL / 2 ? z[o] : make_float2(z[o].x, -z[o].y);
-                if (BM != 3 && a.power && c_active) a.power[((int64_t)s * a.T + mc) * M + k] = X.x * X.x + X.y * X.y;
+                if (BM != 3 && a.power && c_active) put_power(a, ((int64_t)s * a.T + mc) * M + k, X.x * X.x + X.y * X.y);
                 emit<BM>(ch[o], X, rot_c, r, bsel, c_active, gbase_c + chunk_base(k));
             }
         }
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
             uint4 *gbase_s = reinterpret_cast<uint4 *>(a.spec) + (int64_t)(ms / G) * M * a.S;
             // column 0 unfolds 2 X: power and the calibration sum take |X|^2 = |2 X|^2 / 4
             if constexpr (BM != 3) {
-                if (a.power && s_active) a.power[((int64_t)s * a.T + ms) * M + ch_s] = 0.25f * (X.x * X.x + X.y * X.y);
+                if (a.power && s_active) put_power(a, ((int64_t)s * a.T + ms) * M + ch_s, 0.25f * (X.x * X.x + X.y * X.y));
                 emit<BM>(ch[8], X, rot_s, r, bsel, s_active, gbase_s + chunk_base(ch_s));
             } else {
                 ch[8].pacc += 0.25f * (X.x * X.x + X.y * X.y);

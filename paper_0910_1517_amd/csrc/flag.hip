@@ -46,7 +46,8 @@ __device__ inline float wave_median64(float x, int lane) {
 // flag[i] = |x_i - med| > M MAD / 0.6745, the median of an even count being
 // the mean of the two middle values.  One wave sorts the row statistic while
 // another sorts the column statistic.
-__global__ void __launch_bounds__(KT) mad_tile_kernel(const float *__restrict__ power, int S, int T, int C,
+template <typename PT>
+__global__ void __launch_bounds__(KT) mad_tile_kernel(const PT *__restrict__ power, int S, int T, int C,
                                                       float M, uint8_t *flags) {
     __shared__ float tile[TT][KT + 1];
     __shared__ float rowp[KT / TT][TT];
@@ -59,12 +60,20 @@ __global__ void __launch_bounds__(KT) mad_tile_kernel(const float *__restrict__ 
     const int kt = b % ntk, mt = (b / ntk) % ntm, s = b / (ntk * ntm);
     const int t = threadIdx.x;
     const int64_t tbase = ((int64_t)s * T + (int64_t)mt * TT) * C + (int64_t)kt * KT;  // tile corner
-    {  // 16-byte loads: columns 4 (t mod 64) .. + 3 of rows t / 64 + 4 i
+    {  // columns 4 (t mod 64) .. + 3 of rows t / 64 + 4 i: 16-byte (FP32) or 8-byte (FP16) loads
         const int cq = t & 63, r0 = t >> 6;
 #pragma unroll
         for (int i = 0; i < TT / 4; ++i) {
             const int r = r0 + 4 * i;
-            const float4 v = *reinterpret_cast<const float4 *>(power + tbase + (int64_t)r * C + 4 * cq);
+            const PT *src = power + tbase + (int64_t)r * C + 4 * cq;
+            float4 v;
+            if constexpr (sizeof(PT) == 4) {
+                v = *reinterpret_cast<const float4 *>(src);
+            } else {
+                typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+                const h4 w = *reinterpret_cast<const h4 *>(src);
+                v = make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
+            }
             tile[r][4 * cq + 0] = v.x;
             tile[r][4 * cq + 1] = v.y;
             tile[r][4 * cq + 2] = v.z;
@@ -219,9 +228,15 @@ __global__ void __launch_bounds__(256) pair_counts_kernel(const uint32_t *__rest
 
 }  // namespace
 
-hipError_t launch_mad_flag(const float *power, int S, int T, int C, float M, uint8_t *flags, hipStream_t st) {
+hipError_t launch_mad_flag(const void *power, bool f16, int S, int T, int C, float M, uint8_t *flags,
+                           hipStream_t st) {
     const int nb = S * (T / TT) * (C / KT);
-    hipLaunchKernelGGL(mad_tile_kernel, dim3(nb), dim3(KT), 0, st, power, S, T, C, M, flags);
+    if (f16)
+        hipLaunchKernelGGL(mad_tile_kernel<_Float16>, dim3(nb), dim3(KT), 0, st,
+                           static_cast<const _Float16 *>(power), S, T, C, M, flags);
+    else
+        hipLaunchKernelGGL(mad_tile_kernel<float>, dim3(nb), dim3(KT), 0, st, static_cast<const float *>(power), S,
+                           T, C, M, flags);
     return hipGetLastError();
 }
 

@@ -51,6 +51,7 @@ def create(**kw):
     (dict(n_spectra=0), -1), (dict(max_delay=-1), -1), (dict(precision=7), -1),
     (dict(sideband=0), -1), (dict(scale_mode=3), -1), (dict(sample_rate=0.0), -1),
     (dict(sample_rate=float("nan")), -1), (dict(x_split=-2), -1), (dict(phase_lut=2), -1),
+    (dict(power_fp16=2), -1), (dict(power_fp16=-1), -1),
 ])
 def test_plan_create_rejects_bad_descriptions(kw, code):
     rc, h = create(**kw)
@@ -87,6 +88,19 @@ def test_plan_sizes_and_calls_without_workspace():
         assert L.corr_fengine(h, None, 0, fake, 0, fake, fake, None, None) == -2
     finally:
         L.corr_plan_destroy(h)
+
+
+def test_power_cells_are_half_the_bytes_in_fp16():
+    L = corr.lib()
+    rc1, h1 = create(n_signals=8, fft_len=1024, n_spectra=64)
+    rc2, h2 = create(n_signals=8, fft_len=1024, n_spectra=64, power_fp16=1)
+    assert rc1 == 0 and rc2 == 0
+    try:
+        assert L.corr_plan_power_bytes(h1) == 4 * 8 * 64 * 512
+        assert L.corr_plan_power_bytes(h2) == 2 * 8 * 64 * 512
+    finally:
+        L.corr_plan_destroy(h1)
+        L.corr_plan_destroy(h2)
 
 
 def test_workspace_grows_with_compute_scale_mode():

@@ -135,6 +135,20 @@ def test_infer_matches_oracle_over_several_tiles():
     _check_infer(he_params(4), power)
 
 
+def test_infer_fp16_power_matches_oracle():
+    # FP16 power cells (the F-engine's power_fp16 output: |X|^2 / N^2, here synthetic cells
+    # rounded on the host, some in the FP16 subnormal range): the oracle on the same values,
+    # and the FP32-input kernel on the same values gives bit-identical logits and flags
+    power = synth.power_spectra(2, 128, 512, seed=16) * np.float32(2.0 ** -20)
+    power[1, :, 256:512] *= np.float32(2.0 ** -12)  # cells of ~2^-22: subnormal in FP16
+    p16 = power.astype(np.float16)
+    params = he_params(8)
+    f16, z16 = _infer(params, p16)
+    _check_infer(params, p16)
+    f32, z32 = _infer(params, p16.astype(np.float32))
+    assert np.array_equal(z16, z32) and np.array_equal(f16, f32)
+
+
 def test_infer_many_tiles_per_workgroup():
     """1280 tiles, several per workgroup (one workgroup per compute unit, each
     walking its tiles as one stream): sampled tiles against the oracle, and

@@ -41,6 +41,49 @@ def test_power_output_matches_oracle(prec):
     assert np.max(np.abs(pg - P64) / ref) < 1e-5
 
 
+@pytest.mark.parametrize("N", [1024, 2048, 8192])
+def test_power_fp16_output_matches_oracle(N):
+    # FP16 power cells |X|^2 / N^2 from both F-engine kernels (1024 and 8192 points on the
+    # LDS-radix one, 2048 on the four-step one): within the FP16 rounding (half a unit in the
+    # last place, 2^-11 relative; 2^-25 absolute in the subnormal range) plus the FP32 FFT error
+    # of the FP32 power test, against the FP64 oracle's |X|^2 scaled by the same power of two
+    import torch
+    S, T = 4, 64
+    geo, x = rfi_case(S, N, T, seed=12)
+    plan = corr.Plan(S, N, T, precision=corr.INT8, power_fp16=1)
+    assert plan.alloc("power").dtype == torch.float16 and plan.alloc("power").numel() == S * T * plan.C
+    x_dev, rs = upload_streams(x, N, T, 16)
+    pw = plan.alloc("power", zero=False)
+    spec = plan.alloc("spectra", zero=False)
+    scale = torch.full((S * plan.C,), 1000.0, device="cuda")
+    plan.fengine(x_dev, geom_dev(geo), spec, scale, power=pw, row_stride=rs)
+    torch.cuda.synchronize()
+    P64 = oracle.power(oracle.fengine(x, N, T, ogeom(geo), FS)) / float(N) ** 2
+    pg = pw.cpu().numpy().astype(np.float64).reshape(S, T, plan.C)
+    ref = np.maximum(P64, P64.mean(axis=-1, keepdims=True))
+    bound = np.maximum(2.0 ** -11 * P64, 2.0 ** -25) + 1e-5 * ref
+    print("FP16 power, N %d: max error / bound %.3g, %s" % (N, np.max(np.abs(pg - P64) / bound), plan.fengine_kernel))
+    assert np.all(np.abs(pg - P64) <= bound)
+
+
+def test_mad_flags_fp16_power_match_oracle():
+    # the MAD flagger reading FP16 power (synthetic cells rounded to FP16 on the host, at the
+    # scale |X|^2 / N^2 puts them): the same flags as the FP64 oracle on the same FP16 values,
+    # except where a statistic lies at the threshold
+    import torch
+    S, T, C = 4, 256, 512
+    p16 = (synth.power_spectra(S, T, C, seed=23) * np.float32(2.0 ** -20)).astype(np.float16)
+    plan = corr.Plan(S, 2 * C, T, precision=corr.FP32, power_fp16=1)
+    flags = plan.alloc("flags", zero=False)
+    plan.mad_flag(torch.from_numpy(p16).cuda(), flags, 3.0)
+    torch.cuda.synchronize()
+    P64 = p16.astype(np.float64)
+    fo = oracle.mad_tile_flags(P64, 3.0)
+    fg = flags.cpu().numpy().reshape(S, T, C)
+    assert not np.any((fg != fo) & ~near_threshold_cells(P64))
+    assert fo.mean() > 0.01
+
+
 def test_mad_flags_match_oracle():
     import torch
     S, N, T = 4, 1024, 256
