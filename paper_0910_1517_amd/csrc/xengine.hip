@@ -341,10 +341,11 @@ xengine_gated_kernel(const uint8_t *__restrict__ spec, const uint8_t *__restrict
 // One launch over the tasks of a batch of correlations of different shapes
 // (one per sub-array).  The batch table travels by value as the kernel
 // argument, so every field is a uniform scalar; workgroup b runs task b: the
-// correlation whose task range holds b, then its (channel block, split).  All
-// tasks use the two-tile body (signals beyond S are zero rows): a one-tile
-// variant in the same kernel would double its registers, and the sub-arrays
-// with S <= 32 are small and HBM-bound.
+// correlation whose task range holds b, then its (channel block, split).  Each
+// task runs the body of its sub-array's size, as corr_xengine would: two
+// 32-signal tiles above 32 signals, one tile otherwise (the two-tile body on
+// a small sub-array issues 7 matrix products per step where 3 suffice).  The
+// branch is uniform per workgroup.
 __global__ void __launch_bounds__(64 * kXWaves) xengine_batch_kernel(XBatchArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[x_lds_bytes<2>()];
     const int b = blockIdx.x;
@@ -353,8 +354,12 @@ __global__ void __launch_bounds__(64 * kXWaves) xengine_batch_kernel(XBatchArgs 
     const XBatchEntry &e = a.cor[i];
     const int local = b - a.first[i];
     const int nkb = e.C / kXWaves;
-    xengine_block<2, CORR_INT8, int32_t>((const uint8_t *)e.spec, (int32_t *)e.acc, e.S, e.C, e.T, e.splits,
-                                         local % nkb, local / nkb, lds);
+    if (e.S > 32)
+        xengine_block<2, CORR_INT8, int32_t>((const uint8_t *)e.spec, (int32_t *)e.acc, e.S, e.C, e.T, e.splits,
+                                             local % nkb, local / nkb, lds);
+    else
+        xengine_block<1, CORR_INT8, int32_t>((const uint8_t *)e.spec, (int32_t *)e.acc, e.S, e.C, e.T, e.splits,
+                                             local % nkb, local / nkb, lds);
 }
 
 // --------------------------------------------------------------- xpack ----
