@@ -183,8 +183,9 @@ int32_t corr_plan_x_splits(const corr_plan_t *plan);
 /* Name of the F-engine kernel the plan's corr_fengine launches for its data
  * (as a profiler lists it: "fengine4_kernel<log2 M, mode>" for the four-step
  * one, "fengine_kernel<...>" for the LDS-radix one; mode 0 FP32, 1 int8, 2
- * e4m3, plus 4 in table mode).  The string is valid until the calling
- * thread's next call; "" for a NULL plan. */
+ * e4m3, plus 4 in table mode), for a call without power cells (with them the
+ * four-step kernel's mode adds 4 for FP32 and 8 for FP16 cells).  The string
+ * is valid until the calling thread's next call; "" for a NULL plan. */
 const char *corr_plan_fengine_kernel(const corr_plan_t *plan);
 
 /* Attach caller-owned device workspace (>= workspace_bytes, 256-byte
@@ -572,9 +573,12 @@ const char *corr_batch_last_error(const corr_batch_t *batch);
 
 /* --------------------------------------------------------------- autotune */
 
-/* Time the X-engine of desc for every K-split 1, 2, 4, ..., 64 that divides
- * T/32 and return the fastest in *best_split (its time in *best_ms when non-
- * NULL); the split goes into corr_desc_t.x_split.  Uses caller scratch of
+/* Time the X-engine of desc for every K-split in 1..64 that divides T/32
+ * (each the median of 5 launches after one warm-up launch) and return the
+ * fastest in *best_split (its median time in *best_ms when non-NULL); the
+ * split goes into corr_desc_t.x_split.  The tile body is fixed by S (one
+ * 32-signal tile up to 32 signals, two above: the two-tile body on fewer
+ * signals does more matrix work on the same bytes).  Uses caller scratch of
  * corr_autotune_scratch_bytes(desc) (256-byte aligned; contents ignored) and
  * synchronises `stream`.  Errors: NULL, ALIGN, WORKSPACE, INVALID, DEVICE. */
 size_t corr_autotune_scratch_bytes(const corr_desc_t *desc);

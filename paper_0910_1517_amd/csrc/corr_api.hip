@@ -731,7 +731,7 @@ corr_status corr_autotune_x_split(const corr_desc_t *desc, void *d_scratch, size
     float best = 1e30f;
     int bsplit = 1;
     corr_status result = CORR_OK;
-    for (int cand = 1; cand <= 64 && cand <= steps; cand *= 2) {
+    for (int cand = 1; cand <= 64 && cand <= steps; ++cand) {
         if (steps % cand) continue;
         corr_desc_t d = *desc;
         d.x_split = cand;
@@ -739,17 +739,17 @@ corr_status corr_autotune_x_split(const corr_desc_t *desc, void *d_scratch, size
         if ((result = corr_plan_create(&d, &p)) != CORR_OK) break;
         char *spec = (char *)d_scratch;
         char *acc = spec + round_up(corr_plan_spectra_bytes(p), 256);
-        float ms = 0.f;
+        float ts[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         hipError_t e = hipSuccess;
-        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // first run warms up
+        for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {  // the first launch warms up
             e = hipEventRecord(e0, st);
             if (e == hipSuccess) e = launch_xengine(d.precision, spec, acc, d.n_signals, p->M, (int)d.n_spectra, p->splits, st);
             if (e == hipSuccess) e = hipEventRecord(e1, st);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float t = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-            if (rep > 0) ms += t / 2;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ts[rep], e0, e1);
         }
+        std::sort(ts + 1, ts + 6);
+        const float ms = ts[3];  // median of the 5 timed launches
         corr_plan_destroy(p);
         if (e != hipSuccess) { result = fail(nullptr, CORR_ERR_DEVICE, "autotune run: %s", hipGetErrorString(e)); break; }
         if (ms < best) { best = ms; bsplit = cand; }

@@ -290,7 +290,14 @@ __device__ __forceinline__ void emit(Chan &c, float2 X, float2 rot, int r, uint3
 template <int LOGM, int MODE>
 __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_per_eu(3))) fengine4_kernel(FLaunch a) {
     using C = F4Cfg<LOGM>;
-    constexpr int BM = MODE;  // 0 FP32, 1 INT8, 2 FP8, 3 calibration
+    constexpr int BM = MODE & 3;  // 0 FP32, 1 INT8, 2 FP8, 3 calibration
+    // power cells: 0 none, 1 FP32 |X|^2, 2 FP16 |X|^2 / N^2 -- a template choice, so that a
+    // launch without power output carries none of its registers
+    constexpr int PW = MODE >> 2;
+    auto store_power = [&](int64_t i, float p) {
+        if constexpr (PW == 1) reinterpret_cast<float *>(a.power)[i] = p;
+        if constexpr (PW == 2) reinterpret_cast<_Float16 *>(a.power)[i] = (_Float16)(p * a.power_scale);
+    };
     constexpr int M = C::M, N = C::N, N1 = C::N1, L = C::L, FPAR = C::FPAR, WG = C::WG;
     constexpr int SPS = C::SPS, SPB = SPS * FPAR;
     constexpr int G = (BM == 0) ? kChunk32 : kChunk8;
@@ -502,7 +509,7 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
                 const int q = o % RL;
                 const int k = chan(o);
                 const float2 X = q < RL / 2 ? z[o] : make_float2(z[o].x, -z[o].y);
-                if (BM != 3 && a.power && c_active) put_power(a, ((int64_t)s * a.T + mc) * M + k, X.x * X.x + X.y * X.y);
+                if (PW && c_active) store_power(((int64_t)s * a.T + mc) * M + k, X.x * X.x + X.y * X.y);
                 emit<BM>(ch[o], X, rot_c, r, bsel, c_active, gbase_c + chunk_base(k));
             }
         }
@@ -529,7 +536,7 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
             uint4 *gbase_s = reinterpret_cast<uint4 *>(a.spec) + (int64_t)(ms / G) * M * a.S;
             // column 0 unfolds 2 X: power and the calibration sum take |X|^2 = |2 X|^2 / 4
             if constexpr (BM != 3) {
-                if (a.power && s_active) put_power(a, ((int64_t)s * a.T + ms) * M + ch_s, 0.25f * (X.x * X.x + X.y * X.y));
+                if (PW && s_active) store_power(((int64_t)s * a.T + ms) * M + ch_s, 0.25f * (X.x * X.x + X.y * X.y));
                 emit<BM>(ch[8], X, rot_s, r, bsel, s_active, gbase_s + chunk_base(ch_s));
             } else {
                 ch[8].pacc += 0.25f * (X.x * X.x + X.y * X.y);
@@ -562,11 +569,14 @@ hipError_t launch4_one(int mode, const FLaunch &a, hipStream_t st) {
     const int spb = C::SPS * C::FPAR;
     const int nblk = (a.T + spb - 1) / spb;
     const dim3 grid(a.S * nblk), block(C::WG);
-    switch (mode) {
-    case 0: hipLaunchKernelGGL((fengine4_kernel<LOGM, 0>), grid, block, 0, st, a); break;
-    case 1: hipLaunchKernelGGL((fengine4_kernel<LOGM, 1>), grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((fengine4_kernel<LOGM, 2>), grid, block, 0, st, a); break;
-    case 3: hipLaunchKernelGGL((fengine4_kernel<LOGM, 3>), grid, block, 0, st, a); break;
+    const int pw = (mode == 3 || !a.power) ? 0 : (a.power_f16 ? 2 : 1);
+    switch (mode | (pw << 2)) {
+#define F4_CASE(m) \
+    case m: hipLaunchKernelGGL((fengine4_kernel<LOGM, m>), grid, block, 0, st, a); break;
+    F4_CASE(0) F4_CASE(1) F4_CASE(2) F4_CASE(3)     // no power cells
+    F4_CASE(4) F4_CASE(5) F4_CASE(6)                // FP32 power
+    F4_CASE(8) F4_CASE(9) F4_CASE(10)               // FP16 power
+#undef F4_CASE
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
