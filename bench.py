@@ -54,14 +54,18 @@ FP32_PUBLISHED_PEAK = 157.3e12  # the datasheet's FP32 vector figure (packed FP3
 # calibration copy, see profiles/), valid only for the kernel source they were
 # taken from: reported as `traffic` when the source hash still matches.
 MEASURED_TRAFFIC = {
-    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4723963 KiB x 2.000, WRITE_SIZE 8388608 KiB x 1.000
-    "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
-                        "sha256": "e7729c6fe3ac3baada8ff9f2d87a99e95bb14c280e8437228f1cb132bc1f0e7a",
-                        "read": 9.675e9, "write": 8.590e9},
-    # profiles/cnn_flagged_64sig_8192pt_8192spec.md: FETCH_SIZE 5484065 KiB x 2.000, WRITE_SIZE 2097152 KiB x 1.000
+    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4472219 KiB x 2.000, WRITE_SIZE 8389032 KiB x 1.000
+    "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine4.hip",
+                        "sha256": "1508e85835372139b6615e80dc73bf38658fc2bb65e532f8202998cc06006356",
+                        "read": 9.159e9, "write": 8.590e9},
+    # profiles/fx_fp32_64sig_1024pt_16384spec_pointsources.md: FETCH_SIZE 537852 KiB x 2.000, WRITE_SIZE 4194304 KiB
+    "fengine_fp32_c2": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
+                        "sha256": "f9485e8243748b8007245bbf925f3ad490fc7afe7a664cd5d9e323cb1bc1d01c",
+                        "read": 1.102e9, "write": 4.295e9},
+    # profiles/cnn_flagged_64sig_8192pt_8192spec.md (FP16 power): FETCH_SIZE 2097367 KiB x 2.000, WRITE_SIZE 2097152 KiB
     "cnn_infer_c5": {"source": "paper_0910_1517_amd/csrc/cnn.hip",
-                     "sha256": "e36bc79513397116c36e380c1519ce59689c93a9a1116b5f53ee3bbe98c6f595",
-                     "read": 11.231e9, "write": 2.147e9},
+                     "sha256": "38ac56aa3d90aeee8cdd5e27df21828eb2f4e63d138bc7be6d595580dfee3e39",
+                     "read": 4.295e9, "write": 2.147e9},
     # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4197483 KiB x 2.000, WRITE_SIZE 1572864 KiB x 1.000
     "beam_int8_c3": {"source": "paper_0910_1517_amd/csrc/beam.hip",
                      "sha256": "fdea2c6b6d608a65e64c732609303dc9d4f9377b18ad830e8b407f4c35843b4f",
