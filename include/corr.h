@@ -232,6 +232,16 @@ corr_status corr_fengine(corr_plan_t *plan, const int8_t *d_x, int64_t row_strid
  *   for FP8), 16-byte aligned.  Errors: NULL, ALIGN, DEVICE. */
 corr_status corr_xpack(corr_plan_t *plan, const void *d_in, void *d_spec, void *stream);
 
+/* Requantisation of externally produced FP32 spectra with the F-engine's own
+ * encoders (section 4.1: a fixed-point format with a per-channel level ahead
+ * of the MAC): per component q = enc(v * (1 / d_scale[s][k])), enc the INT8
+ * plan's clamp(rne(.), +-127) or the FP8 plan's OCP e4m3 (nearest even,
+ * saturating at +-448, +0 for values that round to zero; NaN gives -127 or
+ * -448).  d_in: float [S][T][C][2], 8-byte aligned; d_scale: float [S][C];
+ * d_out: codes [S][T][C][2] (int8 or e4m3 bytes), 2-byte aligned, ready for
+ * corr_xpack.  Errors: NULL, ALIGN, UNSUPPORTED (an FP32 plan), DEVICE. */
+corr_status corr_requantize(corr_plan_t *plan, const float *d_in, const float *d_scale, void *d_out, void *stream);
+
 /* --------------------------------------------------------------- X-engine */
 
 /*

@@ -78,7 +78,7 @@ SYMBOLS = [
     "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
     "corr_adc_unpack", "corr_adc_last_error", "corr_xengine_gated", "corr_pulsar_gates",
     "corr_dedisperse", "corr_dedisperse_workspace_bytes", "corr_dedisperse_last_error",
-    "corr_geom_from_model", "corr_dedisperse_noalloc", "corr_plan_fengine_kernel", "corr_fix16_spectra", "corr_fix16_xengine",
+    "corr_geom_from_model", "corr_dedisperse_noalloc", "corr_plan_fengine_kernel", "corr_requantize", "corr_fix16_spectra", "corr_fix16_xengine",
 ]
 
 
@@ -115,6 +115,8 @@ def lib():
     L.corr_plan_x_splits.restype = ctypes.c_int32
     L.corr_plan_fengine_kernel.argtypes = [P]
     L.corr_plan_fengine_kernel.restype = ctypes.c_char_p
+    L.corr_requantize.argtypes = [P, P, P, P, P]
+    L.corr_requantize.restype = st
     L.corr_plan_bind_workspace.argtypes = [P, P, sz, P]
     L.corr_plan_bind_workspace.restype = st
     L.corr_fengine.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P]
@@ -395,6 +397,16 @@ class Plan:
         _need(inp, "inp", self.S * self.T * self.C * 2 * (4 if self.precision == FP32 else 1))
         _need(spec, "spec", self.spectra_bytes)
         self._check(lib().corr_xpack(self._h, _ptr(inp), _ptr(spec), _stream(stream)))
+
+    def requantize(self, inp, scale, out, stream=None):
+        """corr_requantize: FP32 spectra [S][T][C][2] -> this plan's codes [S][T][C][2]
+        (int8, or e4m3 bytes as uint8) with the F-engine's encoders."""
+        import torch
+        n = self.S * self.T * self.C * 2
+        _need(inp, "inp", 4 * n, torch.float32)
+        _need(scale, "scale", 4 * self.S * self.C, torch.float32)
+        _need(out, "out", n, (torch.int8, torch.uint8))
+        self._check(lib().corr_requantize(self._h, _ptr(inp), _ptr(scale), _ptr(out), _stream(stream)))
 
     def xengine(self, spec, acc, stream=None):
         _need(spec, "spec", self.spectra_bytes)

@@ -319,6 +319,17 @@ corr_status corr_xpack(corr_plan_t *p, const void *d_in, void *d_spec, void *str
     return e == hipSuccess ? CORR_OK : hip_fail(p, e, "xpack launch");
 }
 
+corr_status corr_requantize(corr_plan_t *p, const float *d_in, const float *d_scale, void *d_out, void *stream) {
+    if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
+    if (!d_in || !d_scale || !d_out) return fail(p, CORR_ERR_NULL, "d_in, d_scale and d_out are required");
+    if (p->d.precision == CORR_FP32) return fail(p, CORR_ERR_UNSUPPORTED, "an FP32 plan has no codes");
+    if (!aligned(d_in, 8) || !aligned(d_scale, 4) || !aligned(d_out, 2))
+        return fail(p, CORR_ERR_ALIGN, "d_in 8 B, d_scale 4 B, d_out 2 B alignment");
+    hipError_t e = launch_requantize(p->d.precision, d_in, d_scale, p->d.n_signals, p->d.n_spectra, p->M,
+                                     static_cast<uint8_t *>(d_out), (hipStream_t)stream);
+    return e == hipSuccess ? CORR_OK : hip_fail(p, e, "requantize launch");
+}
+
 corr_status corr_beamform(corr_plan_t *p, const void *d_spec, const float *d_scale, const float *d_w, float *d_inc,
                           const float *d_c, int32_t n_beams, int32_t mode, float *d_coh, int32_t tint,
                           void *stream) {

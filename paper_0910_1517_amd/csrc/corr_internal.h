@@ -67,6 +67,32 @@ struct FLaunch {
     const float2 *wsp;
 };
 
+// The requantisation encoders shared by both F-engines and corr_requantize
+// (section 4.1's fixed point ahead of the MAC, at 8 bits).
+//
+// OCP e4m3 codes (bias 7, max 448) of two already-scaled values, in bytes 0
+// and 1: nearest-even, saturating to +-448, a value that rounds to zero
+// encoded as +0 whatever its sign.  The hardware conversion rounds to nearest
+// even; the clamp makes it saturate, and flushing |v| <= 2^-10 (half the
+// smallest subnormal, a tie that rounds to 0) to +0 keeps it from writing -0.
+// NaN leaves the clamp as -448 (code 0xFE); +-inf saturate to +-448.
+__device__ __forceinline__ uint32_t e4m3_pair(float a, float b) {
+    float ca = fminf(fmaxf(a, -448.f), 448.f), cb = fminf(fmaxf(b, -448.f), 448.f);
+    ca = fabsf(ca) <= 0x1p-10f ? 0.f : ca;
+    cb = fabsf(cb) <= 0x1p-10f ? 0.f : cb;
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(ca, cb, 0, false);
+}
+
+// int8 code of an already-scaled value in the low byte: clamp to [-127, 127]
+// (integers, so the clamp commutes with rounding), then add 1.5 * 2^23 -- the
+// FP32 add rounds to the nearest integer, ties to even, and leaves it in the
+// low mantissa bits, whose low byte is the two's-complement code.  NaN leaves
+// the clamp as -127.
+__device__ __forceinline__ uint32_t quant_i8(float v) {
+    const float c = fminf(fmaxf(v, -127.0f), 127.0f);
+    return __float_as_uint(c + 12582912.0f);  // only the low byte is used
+}
+
 // One power cell of the F-engine: FP32 |X|^2, or FP16 |X|^2 / N^2 (nearest even).
 __device__ __forceinline__ void put_power(const FLaunch &a, int64_t i, float p) {
     if (a.power_f16)
@@ -141,6 +167,8 @@ struct XBatchArgs {
 hipError_t launch_xengine_batch(const XBatchArgs &a, hipStream_t st);
 hipError_t launch_xpack(int precision, const void *in, void *spec, int S, int C, int T,
                         hipStream_t st);
+hipError_t launch_requantize(int precision, const float *in, const float *scale, int S, int64_t T, int C,
+                             uint8_t *out, hipStream_t st);
 
 hipError_t launch_mad_flag(const void *power, bool f16, int S, int T, int C, float M, uint8_t *flags,
                            hipStream_t st);

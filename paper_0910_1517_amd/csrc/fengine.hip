@@ -204,29 +204,6 @@ __device__ __forceinline__ float2 *result_buffer(float2 *b0, float2 *b1) {
     else return ((FCfg<LOGM>::NPASS - 1) & 1) ? b1 : b0;
 }
 
-// OCP e4m3 codes (bias 7, max 448) of two already-scaled values, in bytes 0
-// and 1: nearest-even, saturating to +-448, a value that rounds to zero
-// encoded as +0 whatever its sign.  The hardware conversion rounds to nearest
-// even; the clamp makes it saturate, and flushing |v| <= 2^-10 (half the
-// smallest subnormal, a tie that rounds to 0) to +0 keeps it from writing -0.
-// Checked against a software RNE/satfinite encoder on every code boundary and
-// tie and on 2 million random values: identical codes.
-__device__ __forceinline__ uint32_t e4m3_pair(float a, float b) {
-    float ca = fminf(fmaxf(a, -448.f), 448.f), cb = fminf(fmaxf(b, -448.f), 448.f);
-    ca = fabsf(ca) <= 0x1p-10f ? 0.f : ca;
-    cb = fabsf(cb) <= 0x1p-10f ? 0.f : cb;
-    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(ca, cb, 0, false);
-}
-
-// int8 code of an already-scaled value: clamp to [-127, 127] (integers, so the
-// clamp commutes with rounding), then add 1.5 * 2^23 -- the FP32 add rounds to
-// the nearest integer, ties to even, and leaves it in the low mantissa bits,
-// whose low byte is the two's-complement code.
-__device__ __forceinline__ uint32_t quant_i8(float v) {
-    const float c = fminf(fmaxf(v, -127.0f), 127.0f);
-    return __float_as_uint(c + 12582912.0f);  // only the low byte is used
-}
-
 // Logical workgroup id with consecutive ids on the same XCD (hardware hands
 // workgroups to the 8 XCDs round-robin), so that the chunks of neighbouring
 // signals, which are adjacent in the X layout, meet in one L2.

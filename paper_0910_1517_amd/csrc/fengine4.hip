@@ -213,24 +213,6 @@ __device__ __forceinline__ void col_passes(float2 *b0, float2 *b1, const float2 
     }
 }
 
-// OCP e4m3 codes of two scaled values in bytes 0 and 1 (nearest even,
-// saturating at +-448; a value that rounds to zero is +0): the hardware
-// conversion after a clamp and a flush of |v| <= 2^-10.
-__device__ __forceinline__ uint32_t e4m3_pair(float a, float b) {
-    float ca = fminf(fmaxf(a, -448.f), 448.f), cb = fminf(fmaxf(b, -448.f), 448.f);
-    ca = fabsf(ca) <= 0x1p-10f ? 0.f : ca;
-    cb = fabsf(cb) <= 0x1p-10f ? 0.f : cb;
-    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(ca, cb, 0, false);
-}
-
-// int8 code of a scaled value in the low byte: clamp to +-127, then the FP32
-// add of 1.5 * 2^23 rounds to the nearest integer (ties to even) into the
-// low mantissa bits.
-__device__ __forceinline__ uint32_t quant_i8(float v) {
-    const float c = fminf(fmaxf(v, -127.0f), 127.0f);
-    return __float_as_uint(c + 12582912.0f);
-}
-
 // Consecutive logical ids on one XCD (workgroups are dealt to the 8 XCDs in
 // turn), so that neighbouring signals' chunks meet in one L2.
 __device__ __forceinline__ int xcd_remap(int bid, int nb) {

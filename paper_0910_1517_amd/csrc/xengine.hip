@@ -389,7 +389,40 @@ __global__ void xpack_kernel(const E *__restrict__ in, E *out, int S, int C, int
     }
 }
 
+// Requantisation of FP32 spectra [S][T][C][2] to codes [S][T][C][2] with
+// the F-engines' encoders: q = enc(v * (1 / scale[s][k])) per component.  One
+// thread per complex value.
+template <int PREC>
+__global__ void requantize_kernel(const float2 *__restrict__ in, const float *__restrict__ scale, int S, int64_t T,
+                                  int C, uint16_t *out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)S * T * C) return;
+    const int k = (int)(idx % C);
+    const int s = (int)(idx / ((int64_t)T * C));
+    const float inv = 1.0f / scale[(int64_t)s * C + k];
+    const float2 v = in[idx];
+    if constexpr (PREC == CORR_INT8)
+        out[idx] = (uint16_t)((quant_i8(v.x * inv) & 0xFFu) | ((quant_i8(v.y * inv) & 0xFFu) << 8));
+    else
+        out[idx] = (uint16_t)(e4m3_pair(v.x * inv, v.y * inv) & 0xFFFFu);
+}
+
 }  // namespace
+
+hipError_t launch_requantize(int precision, const float *in, const float *scale, int S, int64_t T, int C,
+                             uint8_t *out, hipStream_t st) {
+    const int64_t n = (int64_t)S * T * C;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (precision == CORR_INT8)
+        hipLaunchKernelGGL(requantize_kernel<CORR_INT8>, grid, block, 0, st, reinterpret_cast<const float2 *>(in),
+                           scale, S, T, C, reinterpret_cast<uint16_t *>(out));
+    else if (precision == CORR_FP8_E4M3)
+        hipLaunchKernelGGL(requantize_kernel<CORR_FP8_E4M3>, grid, block, 0, st,
+                           reinterpret_cast<const float2 *>(in), scale, S, T, C, reinterpret_cast<uint16_t *>(out));
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int C, int T, int splits,
                           hipStream_t st) {
