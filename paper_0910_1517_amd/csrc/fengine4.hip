@@ -146,10 +146,20 @@ __device__ __forceinline__ void dftR(float2 *v) {
 }
 
 constexpr int pass_radix(int logn, int ps) { return ps < logn / 3 ? 8 : (1 << (logn % 3)); }
-constexpr int twiddle_offset(int logn, int ps) {
+// LDS pitch (float2) of a butterfly's twiddle row [k][0..R): a radix-8 row is
+// read as 4 float4 by lanes whose k differ, and at 64 bytes per row the lanes
+// of k and k + 4 met in one bank; 80 bytes spreads the 8 rows over all banks
+constexpr int tw_pitch(int r) { return r == 8 ? 10 : r; }
+constexpr int twiddle_offset(int logn, int ps) {  // in the LDS copy
     int o = 0;
-    for (int q = 1; q < ps; ++q) o += (1 << (3 * q)) * pass_radix(logn, q);
+    for (int q = 1; q < ps; ++q) o += (1 << (3 * q)) * tw_pitch(pass_radix(logn, q));
     return o;
+}
+constexpr int twl_count(int logn) {
+    int n = 0;
+    const int np8 = logn / 3, rl = 1 << (logn % 3), np = np8 + (rl > 1 ? 1 : 0);
+    for (int ps = 1; ps < np; ++ps) n += (1 << (3 * ps)) * tw_pitch(ps < np8 ? 8 : rl);
+    return n;
 }
 
 // One radix-R Stockham pass PS over a column of N1 points: butterfly i reads
@@ -175,7 +185,7 @@ __device__ __forceinline__ void col_pass(const float2 *src, float2 *dst, const f
     for (int u = 0; u < NB; ++u) {
         if constexpr (PS > 0) {
             const int k = (b + BPC * u) & (P - 1);
-            const float4 *tw4 = reinterpret_cast<const float4 *>(twp + twiddle_offset(C::LOGN1, PS) + k * R);
+            const float4 *tw4 = reinterpret_cast<const float4 *>(twp + twiddle_offset(C::LOGN1, PS) + k * tw_pitch(R));
             float2 w[8];
 #pragma unroll
             for (int hh = 0; hh < R / 2; ++hh) {
@@ -286,7 +296,7 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
     constexpr int RL = C::RLAST == 1 ? 8 : C::RLAST;  // radix of the last column pass
     constexpr int NBL = 8 / RL;                       // its butterflies per thread
     __shared__ __attribute__((aligned(16))) uint32_t lds_x[2][FPAR][N / 4];  // window bytes, double-buffered
-    __shared__ __attribute__((aligned(16))) float2 lds_tw[twb_count(C::LOGN1) > 0 ? twb_count(C::LOGN1) : 1];
+    __shared__ __attribute__((aligned(16))) float2 lds_tw[twl_count(C::LOGN1) > 0 ? twl_count(C::LOGN1) : 1];
     __shared__ __attribute__((aligned(16))) float2 lds_b[C::NBUF][FPAR * 32 * C::CS];
     __shared__ __attribute__((aligned(16))) uint16_t lds_a[2][64 * C::AP];  // FP16 rows (hi, lo)
     __shared__ __attribute__((aligned(16))) float2 lds_u[FPAR * N1];  // column 0 outputs
@@ -334,7 +344,17 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
             reinterpret_cast<const uint4 *>(a.afrag)[(hl * 64 * 64 + row * 64) / 8 + c8];
     }
     const int a_off = (32 * mt + (ln & 31)) * C::AP + 8 * hh;  // this lane's A fragment, K-tile 0
-    for (int i = tid; i < twb_count(C::LOGN1); i += WG) lds_tw[i] = a.twb[i];
+    for (int i = tid; i < twb_count(C::LOGN1); i += WG) {  // table entry i -> its padded LDS place
+        int q = 1, off = 0;
+        for (;;) {
+            const int n = (1 << (3 * q)) * pass_radix(C::LOGN1, q);
+            if (i < off + n) break;
+            off += n;
+            ++q;
+        }
+        const int R = pass_radix(C::LOGN1, q), l = i - off;
+        lds_tw[twiddle_offset(C::LOGN1, q) + (l / R) * tw_pitch(R) + l % R] = a.twb[i];
+    }
     // transposing-read address of this lane: its 16-lane group holds 8 rows (n2)
     // of 16 consecutive columns, each row given as two 8-byte halves
     const int tr_i = ln & 15, tr_g = ln >> 4;
