@@ -71,6 +71,8 @@ def _load():
     lib.orc_mad_flags.restype = i64
     lib.orc_mad_tile_flags.argtypes = [P, i32, i64, i64, i32, i32, dbl, P]
     lib.orc_mad_tile_flags.restype = i32
+    lib.orc_mad_tile_flags_which.argtypes = [P, i32, i64, i64, i32, i32, dbl, i32, P]
+    lib.orc_mad_tile_flags_which.restype = i32
     lib.orc_pair_counts.argtypes = [P, i32, i64, i64, P]
     lib.orc_adc_unpack.argtypes = [P, i64, i32, i64, i32, P, i64]
     lib.orc_philox4x32_10.argtypes = [P, P, P]
@@ -575,12 +577,15 @@ def power(Y: np.ndarray) -> np.ndarray:
     return np.abs(np.asarray(Y)) ** 2
 
 
-def mad_tile_flags(pw: np.ndarray, M: float = 3.0, TT: int = 64, KT: int = 256) -> np.ndarray:
-    """Eq. 3 / Eq. 4 on TT x KT power tiles (row and column statistics); flags [S][T][C] uint8."""
+def mad_tile_flags(pw: np.ndarray, M: float = 3.0, TT: int = 64, KT: int = 256, stats: str = "both") -> np.ndarray:
+    """Eq. 3 / Eq. 4 on TT x KT power tiles; flags [S][T][C] uint8.  stats:
+    "both" (a cell is flagged when its row or its column is), "rows" or
+    "columns" (one statistic only)."""
     pw = np.ascontiguousarray(pw, dtype=np.float64)
     S, T, C = pw.shape
     fl = np.empty((S, T, C), dtype=np.uint8)
-    if _load().orc_mad_tile_flags(_p(pw), S, T, C, TT, KT, M, _p(fl)) != 0:
+    which = {"rows": 1, "columns": 2, "both": 3}[stats]
+    if _load().orc_mad_tile_flags_which(_p(pw), S, T, C, TT, KT, M, which, _p(fl)) != 0:
         raise ValueError("T must be a multiple of %d and C of %d" % (TT, KT))
     return fl
 
@@ -725,6 +730,19 @@ def cnn_tile_logits(params, power, TT: int = 64, KT: int = 256):
                 out[s, mt * TT:(mt + 1) * TT, kt * KT:(kt + 1) * KT] = z[i, 0]
                 i += 1
     return out
+
+
+def cnn_guarded_flags(params, power, threshold: float = 0.5, guard_m: float = 3.0, TT: int = 64, KT: int = 256):
+    """Flags of the learned flagger with the column guard: a cell is flagged
+    when sigmoid(its logit) > threshold, or when its tile column is an outlier
+    of the MAD column statistic (Eq. 3 and Eq. 4 with M = guard_m on the
+    tile's channel means over its spectra).  guard_m <= 0: the network alone.
+    Returns (flags uint8, logits), both [S][T][C]."""
+    z = cnn_tile_logits(params, power, TT, KT)
+    f = (z > np.log(threshold / (1.0 - threshold))).astype(np.uint8)
+    if guard_m > 0:
+        f |= mad_tile_flags(power, guard_m, TT, KT, stats="columns")
+    return f, z
 
 
 # ---------------------------------------------------------------------------

@@ -572,8 +572,17 @@ int64_t orc_mad_flags(const double *x, int64_t n, double M, uint8_t *flags,
 /* or its column is.  power layout [S][T][C]; flags layout [S][T][C] (0/1).   */
 /* T must be a multiple of TT and C of KT.                                    */
 /* ------------------------------------------------------------------------ */
+/* which: 1 the row statistic only, 2 the column statistic only, 3 both.    */
+int orc_mad_tile_flags_which(const double *power, int S, int64_t T, int64_t C, int TT,
+                             int KT, double M, int which, uint8_t *flags);
 int orc_mad_tile_flags(const double *power, int S, int64_t T, int64_t C, int TT,
                        int KT, double M, uint8_t *flags)
+{
+    return orc_mad_tile_flags_which(power, S, T, C, TT, KT, M, 3, flags);
+}
+
+int orc_mad_tile_flags_which(const double *power, int S, int64_t T, int64_t C, int TT,
+                             int KT, double M, int which, uint8_t *flags)
 {
     if (T % TT || C % KT) return -1;
     double *row = (double *)malloc(sizeof(double) * (size_t)TT);
@@ -599,7 +608,8 @@ int orc_mad_tile_flags(const double *power, int S, int64_t T, int64_t C, int TT,
                 orc_mad_flags(col, KT, M, cf, NULL, NULL);
                 for (int r = 0; r < TT; ++r)
                     for (int k = 0; k < KT; ++k)
-                        flags[((int64_t)s * T + m0 + r) * C + k0 + k] = rf[r] | cf[k];
+                        flags[((int64_t)s * T + m0 + r) * C + k0 + k] =
+                            (uint8_t)(((which & 1) ? rf[r] : 0) | ((which & 2) ? cf[k] : 0));
             }
     free(row);
     free(col);

@@ -411,6 +411,41 @@ def test_mad_tile_flags_outliers_in_noise_and_tiling():
     assert not fl[0, 64:, 300].all()      # the tone only lives in the first tile
 
 
+def test_mad_tile_statistics_apart():
+    # the worked example with one statistic at a time: the loud spectrum alone, the loud
+    # channel alone, and a cell of a noisy tile flagged by both is the union of the two
+    pw = np.ones((1, 64, 256))
+    pw[0, 5, :] *= 10
+    pw[0, :, 17] *= 10
+    rows = oracle.mad_tile_flags(pw, stats="rows")[0]
+    cols = oracle.mad_tile_flags(pw, stats="columns")[0]
+    assert rows[5].all() and rows.sum() == 256
+    assert cols[:, 17].all() and cols.sum() == 64
+    g = np.random.default_rng(6)
+    pw = g.exponential(1.0, size=(2, 128, 512))
+    pw[0, 10:12, :] += 30.0
+    pw[1, :, 40] += 25.0
+    both = oracle.mad_tile_flags(pw)
+    r, c = oracle.mad_tile_flags(pw, stats="rows"), oracle.mad_tile_flags(pw, stats="columns")
+    assert np.array_equal(both, r | c)
+    assert r[0, 10:12].all() and not c[0, 10:12].all()
+    assert c[1, :, 40].all() and not r[1, :, 40].all()
+
+
+def test_guarded_flags_are_the_network_or_the_column_statistic():
+    # the guard adds the tile columns that the column statistic flags and nothing else;
+    # guard_m = 0 is the network alone
+    g = np.random.default_rng(7)
+    pw = g.exponential(1.0, size=(1, 64, 256))
+    pw[0, :, 99] += 6.0  # a weak tone: a column outlier the network's 7 x 7 view may not see
+    params = g.normal(0, 0.1, oracle.cnn_param_count())
+    f0, z = oracle.cnn_guarded_flags(params, pw, 0.5, 0.0)
+    f3, z3 = oracle.cnn_guarded_flags(params, pw, 0.5, 3.0)
+    assert np.array_equal(z, z3) and np.array_equal(f0, (z > 0).astype(np.uint8))
+    cols = oracle.mad_tile_flags(pw, 3.0, stats="columns")
+    assert np.array_equal(f3, f0 | cols) and f3[0, :, 99].all()
+
+
 def test_mad_tile_false_flag_rate_on_clean_power():
     # Clean per-cell power is exponential; a row statistic averages 256 cells and a column
     # statistic 64, both close to Gaussian, so each is flagged with probability close to
