@@ -422,7 +422,7 @@ def bench_rfi(args):
         if e: e[0].record(st)
         plan.fengine(x, g, spec, scale, power=power, row_stride=rs, stream=st)
         if e: e[1].record(st)
-        corr.cnn_infer(params, power, flags, threshold=0.5, stream=st)
+        corr.cnn_infer(params, power, flags, threshold=0.5, guard=3.0, stream=st)
         if e: e[2].record(st)
         plan.apply_flags(flags, spec, keep, stream=st)
         if e: e[3].record(st)
@@ -465,12 +465,13 @@ def bench_rfi(args):
         "data": "synthetic (seeded Gaussian + common source + tone, generated on the GPU); "
                 "CNN weights He-normal random (the kernel's time does not depend on them)",
         "config": {"workload": "64 signals, 8192-pt FFT (4096 ch), 8192 spectra, int8 X-engine, "
-                               "learned flagger on %d FP16 power cells (%d tiles of 64 x 256)" % (cells, cells // 16384),
+                               "learned flagger with the MAD column guard on %d FP16 power cells (%d tiles of 64 x 256)"
+                               % (cells, cells // 16384),
                    "parallelism": "single GPU"},
         "ms": {n: round(v * 1e3, 4) for n, v in t.items()},
         "mad_flag_ms": round(t_mad * 1e3, 4),
         "x_engine_tops": round(xops / t["xengine"] / 1e12, 3),
-        "roofline": {"kernel": "cnn_infer_kernel (fused 3-layer conv, FP16 MFMA)", "bound": "mfma",
+        "roofline": {"kernel": "cnn_infer_kernel<_Float16> (fused 3-layer conv, FP16 MFMA, column guard)", "bound": "mfma",
                      "achieved": round(ach, 3), "peak": FP16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": round(ach * 1e12 / FP16_MFMA_PEAK, 4), "traffic": measured_traffic("cnn_infer_c5"),
                      "algorithmic_flop_per_cell": CNN_FLOP_PER_CELL},

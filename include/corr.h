@@ -682,6 +682,17 @@ corr_status corr_cnn_infer(const float *d_params, const float *d_power, int32_t 
  * Errors as corr_cnn_infer. */
 corr_status corr_cnn_infer_f16(const float *d_params, const void *d_power16, int32_t S, int64_t T, int32_t C,
                                float threshold, uint8_t *d_flags, float *d_logits, void *stream);
+/* Inference with the column guard: a cell is also flagged when its tile
+ * column is an outlier of the MAD column statistic (section 5, Eq. 3 and
+ * Eq. 4 with M = guard_m on the tile's 256 channel means over its 64 spectra,
+ * the means the network's input normalisation already forms).  The guard
+ * catches weak persistent tones that the network's 7 x 7 view misses; it
+ * leaves the logits unchanged.  guard_m = 0: no guard (corr_cnn_infer /
+ * corr_cnn_infer_f16).  power_fp16 selects FP32 or FP16 cells.  Errors as
+ * corr_cnn_infer, and INVALID for guard_m < 0 or not finite. */
+corr_status corr_cnn_infer_guarded(const float *d_params, const void *d_power, int32_t power_fp16, int32_t S,
+                                   int64_t T, int32_t C, float threshold, float guard_m, uint8_t *d_flags,
+                                   float *d_logits, void *stream);
 
 /* Save / load parameters and Adam state (each d_* CORR_CNN_PARAMS floats;
  * d_m and d_v may be NULL) to a little-endian binary file: magic "CORRCNN1",

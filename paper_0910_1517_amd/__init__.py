@@ -74,7 +74,7 @@ SYMBOLS = [
     "corr_autotune_scratch_bytes", "corr_autotune_x_split",
     "corr_cnn_create", "corr_cnn_destroy", "corr_cnn_workspace_bytes", "corr_cnn_bind_workspace",
     "corr_cnn_forward", "corr_cnn_loss_grad", "corr_cnn_adam", "corr_cnn_train_step",
-    "corr_cnn_check_device_errors", "corr_cnn_infer", "corr_cnn_infer_f16", "corr_cnn_save", "corr_cnn_load", "corr_cnn_last_error",
+    "corr_cnn_check_device_errors", "corr_cnn_infer", "corr_cnn_infer_f16", "corr_cnn_infer_guarded", "corr_cnn_save", "corr_cnn_load", "corr_cnn_last_error",
     "corr_blank_voltages", "corr_blank_noise_table", "corr_blank_last_error",
     "corr_adc_unpack", "corr_adc_last_error", "corr_xengine_gated", "corr_pulsar_gates",
     "corr_dedisperse", "corr_dedisperse_workspace_bytes", "corr_dedisperse_last_error",
@@ -171,6 +171,8 @@ def lib():
     L.corr_cnn_infer.argtypes = [P, P, i32, i64, i32, f32, P, P, P]
     L.corr_cnn_infer_f16.argtypes = [P, P, i32, i64, i32, f32, P, P, P]
     L.corr_cnn_infer_f16.restype = ctypes.c_int32
+    L.corr_cnn_infer_guarded.argtypes = [P, P, i32, i32, i64, i32, f32, f32, P, P, P]
+    L.corr_cnn_infer_guarded.restype = ctypes.c_int32
     L.corr_cnn_save.argtypes = [ctypes.c_char_p, P, P, P, i64]
     L.corr_cnn_load.argtypes = [ctypes.c_char_p, P, P, P, ctypes.POINTER(i64)]
     for n in ("create", "bind_workspace", "forward", "loss_grad", "adam", "train_step", "check_device_errors",
@@ -656,10 +658,11 @@ class CNN:
             pass
 
 
-def cnn_infer(params, power, flags, *, threshold: float = 0.5, logits=None, stream=None):
+def cnn_infer(params, power, flags, *, threshold: float = 0.5, logits=None, guard: float = 0.0, stream=None):
     """Flags (and optionally logits) of every tile of power [S][T][C] (float32,
     or float16 as the F-engine writes it with power_fp16) from the fused FP16
-    inference kernel."""
+    inference kernel.  guard > 0: also flag the tile columns that the MAD
+    column statistic flags at M = guard (corr_cnn_infer_guarded)."""
     import torch
     S, T, C = power.shape
     f16 = power.dtype == torch.float16
@@ -667,6 +670,10 @@ def cnn_infer(params, power, flags, *, threshold: float = 0.5, logits=None, stre
     _need(power, "power", (2 if f16 else 4) * S * T * C, (torch.float16, torch.float32))
     _need(flags, "flags", S * T * C, torch.uint8)
     _need(logits, "logits", 4 * S * T * C, torch.float32, optional=True)
+    if guard:
+        _cnn_check(lib().corr_cnn_infer_guarded(_ptr(params), _ptr(power), int(f16), S, T, C, threshold, guard,
+                                                _ptr(flags), _ptr(logits), _stream(stream)))
+        return
     fn = lib().corr_cnn_infer_f16 if f16 else lib().corr_cnn_infer
     _cnn_check(fn(_ptr(params), _ptr(power), S, T, C, threshold, _ptr(flags), _ptr(logits), _stream(stream)))
 

@@ -349,7 +349,8 @@ __device__ inline int a1_off(int pcol, int h) { return 32 * pcol + 16 * (h ^ (((
 template <typename PT>
 __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict__ params,
                                                         const PT *__restrict__ power, int64_t T, int C,
-                                                        int n_tiles, float thr_logit, uint8_t *__restrict__ flags,
+                                                        int n_tiles, float thr_logit, float guard_m,
+                                                        uint8_t *__restrict__ flags,
                                                         float *__restrict__ logits) {
     __shared__ __align__(16) _Float16 xs[XCOLS][XPITCH];  // column-major input ring (slot = (row + 1) mod 8)
     __shared__ __align__(16) _Float16 a1s[RX][PC][16];   // layer-1 ring (slot = row mod 8)
@@ -452,11 +453,27 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
         for (int e = t; e < PC * 2; e += IWG)  // layer-1 row -1 (slot 7): zero
             reinterpret_cast<uint4 *>(a1base + (RX - 1) * AROW)[e] = make_uint4(0u, 0u, 0u, 0u);
         __syncthreads();
-        float cv[4];
+        float cv[4], cm[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cv[q] = (colv[0][4 * lane + q] + colv[1][4 * lane + q]) * (1.0f / H);
-        const float med = wave_median256(cv, lane);
+        for (int q = 0; q < 4; ++q) cm[q] = cv[q] = (colv[0][4 * lane + q] + colv[1][4 * lane + q]) * (1.0f / H);
+        const float med = wave_median256(cv, lane);  // sorts cv
         const float inv = 1.0f / (med > 0.f ? med : 1.f);
+        // column guard: the channel means are the MAD column statistic (section 5, Eq. 3
+        // and 4); a column whose mean is an outlier is flagged whole.  gcol is the guard
+        // bit of this lane's output column c0 + col (lane (c0 + col) / 4 holds its mean).
+        uint32_t gcol = 0u;
+        if (guard_m > 0.f) {
+            float d[4], dd[4];
+            uint32_t bits = 0u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dd[q] = d[q] = fabsf(cm[q] - med);
+            const float mad = wave_median256(dd, lane);
+            const float thr = guard_m * mad / 0.6745f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bits |= (d[q] > thr ? 1u : 0u) << q;
+            const int oc = c0 + col;
+            gcol = ((uint32_t)__shfl((int)bits, oc >> 2) >> (oc & 3)) & 1u;
+        }
         // x of tile row r -> input ring slot (r + 1) mod 8, zero outside the tile
         auto x_put = [&](int r, float pv) {
             const float v = (r >= 0 && r < H) ? __logf(1.0f + pv * inv) : 0.f;
@@ -580,7 +597,7 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
                     z += (rr >= 0 && rr < H) ? zu : 0.f;
                 }
                 const uint32_t gp = roff(r, c0 + col);
-                fb[gp] = z > thr_logit ? 1 : 0;
+                fb[gp] = (uint8_t)((z > thr_logit ? 1u : 0u) | gcol);
                 if (lb) lb[gp] = z;
             }
             __syncthreads();
@@ -643,7 +660,7 @@ hipError_t launch_cnn_adam(float *params, float *m, float *v, const float *grad,
 }
 
 hipError_t launch_cnn_infer(const float *params, const void *power, bool f16, int S, int64_t T, int C,
-                            float thr_logit, uint8_t *flags, float *logits, hipStream_t st) {
+                            float thr_logit, float guard_m, uint8_t *flags, float *logits, hipStream_t st) {
     const int n_tiles = (int)((int64_t)S * (T / H) * (C / W));
     // persistent: one workgroup per compute unit (the LDS use allows one), each
     // fetching its next tile's power while it computes the current one
@@ -654,10 +671,10 @@ hipError_t launch_cnn_infer(const float *params, const void *power, bool f16, in
     const int grid = std::max(1, std::min(n_tiles, cus));
     if (f16)
         hipLaunchKernelGGL(cnn_infer_kernel<_Float16>, dim3(grid), dim3(IWG), 0, st, params,
-                           static_cast<const _Float16 *>(power), T, C, n_tiles, thr_logit, flags, logits);
+                           static_cast<const _Float16 *>(power), T, C, n_tiles, thr_logit, guard_m, flags, logits);
     else
         hipLaunchKernelGGL(cnn_infer_kernel<float>, dim3(grid), dim3(IWG), 0, st, params,
-                           static_cast<const float *>(power), T, C, n_tiles, thr_logit, flags, logits);
+                           static_cast<const float *>(power), T, C, n_tiles, thr_logit, guard_m, flags, logits);
     return hipGetLastError();
 }
 

@@ -226,12 +226,15 @@ corr_status corr_cnn_check_device_errors(corr_cnn_t *c, void *stream) {
 }
 
 static corr_status cnn_infer_any(const float *d_params, const void *d_power, bool f16, int32_t S, int64_t T,
-                                 int32_t C, float threshold, uint8_t *d_flags, float *d_logits, void *stream) {
+                                 int32_t C, float threshold, float guard_m, uint8_t *d_flags, float *d_logits,
+                                 void *stream) {
     if (!d_params || !d_power || !d_flags) return fail(nullptr, CORR_ERR_NULL, "d_params, d_power and d_flags are required");
     if (!aligned(d_params, 4) || !aligned(d_power, f16 ? 2 : 4) || (d_logits && !aligned(d_logits, 4)))
         return fail(nullptr, CORR_ERR_ALIGN, "d_params and d_logits must be 4-byte aligned, d_power %d-byte",
                     f16 ? 2 : 4);
     if (!(threshold > 0.f && threshold < 1.f)) return fail(nullptr, CORR_ERR_INVALID, "threshold must lie in (0, 1)");
+    if (!(guard_m >= 0.f) || !std::isfinite(guard_m))
+        return fail(nullptr, CORR_ERR_INVALID, "guard_m must be finite and >= 0");
     corr_status r = check_shape(nullptr, S, T, C);
     if (r != CORR_OK) return r;
     if (C > kCnnMaxInferChannels)
@@ -239,18 +242,26 @@ static corr_status cnn_infer_any(const float *d_params, const void *d_power, boo
     // sigmoid(z) > thr  <=>  z > log(thr / (1 - thr))
     const float thr_logit = (float)std::log((double)threshold / (1.0 - (double)threshold));
     hipError_t e =
-        launch_cnn_infer(d_params, d_power, f16, S, T, C, thr_logit, d_flags, d_logits, (hipStream_t)stream);
+        launch_cnn_infer(d_params, d_power, f16, S, T, C, thr_logit, guard_m, d_flags, d_logits, (hipStream_t)stream);
     return e == hipSuccess ? CORR_OK : hip_fail(nullptr, e, "CNN inference launch");
 }
 
 corr_status corr_cnn_infer(const float *d_params, const float *d_power, int32_t S, int64_t T, int32_t C,
                            float threshold, uint8_t *d_flags, float *d_logits, void *stream) {
-    return cnn_infer_any(d_params, d_power, false, S, T, C, threshold, d_flags, d_logits, stream);
+    return cnn_infer_any(d_params, d_power, false, S, T, C, threshold, 0.f, d_flags, d_logits, stream);
 }
 
 corr_status corr_cnn_infer_f16(const float *d_params, const void *d_power16, int32_t S, int64_t T, int32_t C,
                                float threshold, uint8_t *d_flags, float *d_logits, void *stream) {
-    return cnn_infer_any(d_params, d_power16, true, S, T, C, threshold, d_flags, d_logits, stream);
+    return cnn_infer_any(d_params, d_power16, true, S, T, C, threshold, 0.f, d_flags, d_logits, stream);
+}
+
+corr_status corr_cnn_infer_guarded(const float *d_params, const void *d_power, int32_t power_fp16, int32_t S,
+                                   int64_t T, int32_t C, float threshold, float guard_m, uint8_t *d_flags,
+                                   float *d_logits, void *stream) {
+    if (power_fp16 != 0 && power_fp16 != 1) return fail(nullptr, CORR_ERR_INVALID, "power_fp16 must be 0 or 1");
+    return cnn_infer_any(d_params, d_power, power_fp16 != 0, S, T, C, threshold, guard_m, d_flags, d_logits,
+                         stream);
 }
 
 corr_status corr_cnn_save(const char *path, const float *d_params, const float *d_m, const float *d_v, int64_t step) {

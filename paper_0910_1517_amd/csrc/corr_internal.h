@@ -268,6 +268,6 @@ hipError_t launch_cnn_adam(float *params, float *m, float *v, const float *grad,
                            float beta2, float eps, float c1, float c2, hipStream_t st);
 // fused FP16 MFMA inference over every tile of power [S][T][C]
 hipError_t launch_cnn_infer(const float *params, const void *power, bool f16, int S, int64_t T, int C,
-                            float thr_logit, uint8_t *flags, float *logits, hipStream_t st);
+                            float thr_logit, float guard_m, uint8_t *flags, float *logits, hipStream_t st);
 
 }  // namespace corr

@@ -58,5 +58,6 @@ class Flagger:
         self.cnn.check_device_errors()
         return losses.cpu().numpy()
 
-    def infer(self, power, flags, *, threshold: float = 0.5, logits=None):
-        cnn_infer(self.params, power, flags, threshold=threshold, logits=logits)
+    def infer(self, power, flags, *, threshold: float = 0.5, logits=None, guard: float = 0.0):
+        """Flags of power [S][T][C]; guard > 0 adds the MAD column guard at M = guard."""
+        cnn_infer(self.params, power, flags, threshold=threshold, logits=logits, guard=guard)

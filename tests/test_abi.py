@@ -171,7 +171,19 @@ def test_cnn_infer_rejects_bad_arguments(shape, thr, code):
     fake = ctypes.c_void_p(1 << 20)
     assert L.corr_cnn_infer(fake, fake, *shape, thr, fake, None, None) == code
     assert L.corr_cnn_infer(None, fake, 1, 64, 256, 0.5, fake, None, None) == -2
+    assert L.corr_cnn_infer_f16(fake, fake, *shape, thr, fake, None, None) == code
+    for f16 in (0, 1):
+        assert L.corr_cnn_infer_guarded(fake, fake, f16, *shape, thr, 3.0, fake, None, None) == code
     assert L.corr_cnn_last_error(None)
+
+
+def test_cnn_infer_guarded_rejects_bad_guard_and_cell_type():
+    L = corr.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.corr_cnn_infer_guarded(fake, fake, 0, 1, 64, 256, 0.5, -1.0, fake, None, None) == -1
+    assert L.corr_cnn_infer_guarded(fake, fake, 0, 1, 64, 256, 0.5, float("nan"), fake, None, None) == -1
+    assert L.corr_cnn_infer_guarded(fake, fake, 2, 1, 64, 256, 0.5, 3.0, fake, None, None) == -1
+    assert L.corr_cnn_infer_guarded(None, fake, 0, 1, 64, 256, 0.5, 3.0, fake, None, None) == -2
 
 
 def test_cnn_load_rejects_missing_and_foreign_files(tmp_path):

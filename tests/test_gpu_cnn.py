@@ -149,6 +149,42 @@ def test_infer_fp16_power_matches_oracle():
     assert np.array_equal(z16, z32) and np.array_equal(f16, f32)
 
 
+@pytest.mark.parametrize("f16", [False, True])
+def test_guarded_inference_matches_the_oracle(f16):
+    # the network's flags OR the MAD column statistic's (M = 3): weak tone columns that the
+    # network's 7 x 7 view misses are flagged whole; the logits are those of the plain kernel
+    import torch
+    from gpu_util import near_threshold_cells
+    power = synth.power_spectra(2, 128, 768, seed=17, tone_k=(0.3, 2.0))  # weak persistent tones
+    if f16:
+        power = (power * np.float32(2.0 ** -20)).astype(np.float16)
+    params = he_params(9)
+    S, T, C = power.shape
+    flags = torch.empty((S, T, C), dtype=torch.uint8, device="cuda")
+    logits = torch.empty((S, T, C), device="cuda")
+    corr.cnn_infer(dev(params), dev(power), flags, logits=logits, guard=3.0)
+    torch.cuda.synchronize()
+    f0, z0 = _infer(params, power)
+    z = logits.cpu().numpy().astype(np.float64)
+    assert np.array_equal(z, z0)  # the guard does not touch the logits
+    P = power.astype(np.float64)
+    fo, z64 = oracle.cnn_guarded_flags(params.astype(np.float64), P, 0.5, 3.0)
+    scale = 1.0 + np.abs(z64).max()
+    clear = (np.abs(z64) > INFER_TOL * scale) & ~near_threshold_cells(P)
+    fg = flags.cpu().numpy()
+    cols = oracle.mad_tile_flags(P, 3.0, stats="columns")
+    print("guarded inference: %d guard columns, %d cells added by the guard, %d not clear"
+          % (cols[:, 0, :].sum(), int(((fg != 0) & (f0 == 0)).sum()), int((~clear).sum())))
+    assert cols.any() and ((fg != 0) & (f0 == 0)).any()
+    assert np.array_equal(fg[clear], fo[clear])
+    assert np.all(fg >= f0)  # the guard only adds flags
+    # guard = 0 is the plain kernel
+    g0 = torch.empty_like(flags)
+    corr.cnn_infer(dev(params), dev(power), g0, guard=0.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(g0.cpu().numpy(), f0)
+
+
 def test_infer_many_tiles_per_workgroup():
     """1280 tiles, several per workgroup (one workgroup per compute unit, each
     walking its tiles as one stream): sampled tiles against the oracle, and

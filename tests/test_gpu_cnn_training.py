@@ -18,11 +18,14 @@ neighbourhood and learns the local look of interference.
 
 The flagged data then go through the int8 path (zeroing, X-engine, exact pair
 counts) and the count-normalised visibilities are compared with those of the
-same data without interference.  Both flaggers must remove most of the damage;
-the numbers of each are printed.  The network's per-cell gain does not carry
-over to the visibilities' worst pairs: a 7 x 7 view misses a small fraction of
-the moderately strong tone cells (10-25 times the noise power) that a whole
-tile column of MAD statistics catches, mostly on tile-edge rows.
+same data without interference.  The network alone does not carry its
+per-cell gain over to the visibilities' worst pairs: a 7 x 7 view misses a
+small fraction of the moderately strong tone cells (10-25 times the noise
+power) that a whole tile column of MAD statistics catches, mostly on
+tile-edge rows.  With the column guard (the MAD column statistic of the same
+tile, OR'd into the network's flags inside the inference kernel) the learned
+flagger has fewer per-cell errors, fewer false flags and a visibility error
+tail no worse than MAD's, at N = 1024 and at the flagged form's N = 8192.
 """
 import numpy as np
 import pytest
@@ -38,7 +41,7 @@ N, SIGMA_T = 1024, 12.0
 MIXED = dict(bl_frac=0.5, nb_p=0.01)  # band-limited bursts, intermittent lines
 
 
-def dataset(S, T, seed, mixed):
+def dataset(S, T, seed, mixed, N=N):
     """Device power [S][T][C] and MAD labels of RFI-injected voltages, and the
     host truth mask."""
     import torch
@@ -61,7 +64,7 @@ def dataset(S, T, seed, mixed):
     return power, mad, truth
 
 
-def visibilities(S, T, x, geo, flags):
+def visibilities(S, T, x, geo, flags, N=N):
     """int8 path with held scales from a calibration pass: zero the flagged cells,
     correlate, count unflagged products; returns V / count [C][P] and the kept
     fraction.  flags None: no flagging, FP32 path (the clean reference)."""
@@ -111,37 +114,61 @@ def errors(flags, truth):
     return fp, fn, fp / max(1, (~truth).sum()), fn / max(1, truth.sum())
 
 
-def test_learned_flagger_beats_its_mad_teacher_on_held_out_data():
+def _train_and_evaluate(n, t_train, t_eval):
+    """Train at FFT length n on t_train spectra of mixed RFI, evaluate on two
+    held-out seeds of t_eval spectra: per-cell errors against the truth and
+    count-normalised visibilities against the same data without interference,
+    for MAD, the network, and the network with the MAD column guard."""
     import torch
-    train = dataset(8, 2048, 1000, mixed=True)
+    train = dataset(8, t_train, 1000, mixed=True, N=n)
     fl = Flagger(seed=1, batch=16, lr=2e-3)
     losses = fl.train(train[0], train[1], 1000)
     first, last = losses[:10].mean(), losses[-50:].mean()
-    print("loss %.4f -> %.4f" % (first, last))
+    print("N %d: loss %.4f -> %.4f" % (n, first, last))
     assert np.isfinite(losses).all() and last < 0.3 * first
+    out = {}
     for seed, mixed in [(2100, True), (3100, False)]:
-        power, mad, truth = dataset(8, 1024, seed, mixed)
-        cnn = torch.empty_like(mad)
+        power, mad, truth = dataset(8, t_eval, seed, mixed, N=n)
+        cnn, grd = torch.empty_like(mad), torch.empty_like(mad)
         fl.infer(power, cnn, threshold=0.5)
+        fl.infer(power, grd, threshold=0.5, guard=3.0)
         torch.cuda.synchronize()
-        m = errors(mad.cpu().numpy(), truth)
-        c = errors(cnn.cpu().numpy(), truth)
-        print("seed %d (%s RFI): MAD false %.4f miss %.4f errors %d | CNN false %.4f miss %.4f errors %d"
-              % (seed, "mixed" if mixed else "tones+bursts", m[2], m[3], m[0] + m[1], c[2], c[3], c[0] + c[1]))
-        assert c[0] + c[1] < m[0] + m[1]   # fewer per-cell errors than the teacher
-        assert c[2] < m[2]                 # and less clean data thrown away
-        assert c[3] < 0.35                 # while still catching most of the interference
-        # end to end: count-normalised visibilities against the same data without interference
         geo = synth.make_geometry(4, seed=seed)
-        rfi = synth.RFI(N, seed=seed + 1, **(MIXED if mixed else {}))
-        x = synth.voltages(8, N * 1024 + 16, geo, FS, seed=seed, sigma_t=SIGMA_T, rfi=rfi)
-        x0 = synth.voltages(8, N * 1024 + 16, geo, FS, seed=seed, sigma_t=SIGMA_T)
-        R, _ = visibilities(8, 1024, x0, geo, None)
-        e = {}
-        for name, f in [("none", torch.zeros_like(mad)), ("MAD", mad), ("CNN", cnn)]:
-            V, kept = visibilities(8, 1024, x, geo, f)
-            e[name] = (vis_error_p99(V, R, 8), kept)
-        print("  visibilities, p99 |dV|/sqrt(V_ii V_jj) (data kept): none %.3g (%.3f), MAD %.3g (%.3f), CNN %.3g (%.3f)"
-              % (*e["none"], *e["MAD"], *e["CNN"]))
-        assert e["MAD"][0] < 0.1 * e["none"][0] and e["CNN"][0] < 0.1 * e["none"][0]
-        assert e["CNN"][1] >= e["MAD"][1] - 1e-3
+        rfi = synth.RFI(n, seed=seed + 1, **(MIXED if mixed else {}))
+        x = synth.voltages(8, n * t_eval + 16, geo, FS, seed=seed, sigma_t=SIGMA_T, rfi=rfi)
+        x0 = synth.voltages(8, n * t_eval + 16, geo, FS, seed=seed, sigma_t=SIGMA_T)
+        R, _ = visibilities(8, t_eval, x0, geo, None, N=n)
+        res = {}
+        for name, f in [("none", torch.zeros_like(mad)), ("MAD", mad), ("CNN", cnn), ("CNN+guard", grd)]:
+            V, kept = visibilities(8, t_eval, x, geo, f, N=n)
+            fp, fn, ffl, fmi = errors(f.cpu().numpy(), truth)
+            res[name] = dict(errors=fp + fn, false=ffl, miss=fmi, p99=vis_error_p99(V, R, 8), kept=kept)
+        for name, r in res.items():
+            print("  N %d seed %d (%s) %-9s false %.4f miss %.4f errors %7d | p99 |dV|/sqrt(V_ii V_jj) %.3g kept %.3f"
+                  % (n, seed, "mixed" if mixed else "tones+bursts", name, r["false"], r["miss"], r["errors"],
+                     r["p99"], r["kept"]))
+        out[seed] = res
+    return out
+
+
+def test_learned_flagger_beats_its_mad_teacher_on_held_out_data():
+    # at N = 1024: the network alone makes fewer per-cell errors than MAD and throws away
+    # less clean data; with the column guard it also has the lower visibility error tail
+    res = _train_and_evaluate(N, 2048, 1024)
+    for seed, r in res.items():
+        m, c, g = r["MAD"], r["CNN"], r["CNN+guard"]
+        assert c["errors"] < m["errors"] and c["false"] < m["false"] and c["miss"] < 0.35
+        assert m["p99"] < 0.1 * r["none"]["p99"] and c["p99"] < 0.1 * r["none"]["p99"]
+        assert c["kept"] >= m["kept"] - 1e-3
+        assert g["errors"] < m["errors"] and g["false"] < m["false"] and g["p99"] <= m["p99"], seed
+
+
+def test_learned_flagger_with_column_guard_at_the_flagged_form():
+    # at the flagged form's channelisation (8192-point FFT, 4096 channels): trained there, the
+    # guarded network makes fewer per-cell errors than MAD, flags less clean data, keeps as
+    # much, and has the lower visibility error tail on both held-out sets
+    res = _train_and_evaluate(8192, 512, 256)
+    for seed, r in res.items():
+        m, g = r["MAD"], r["CNN+guard"]
+        assert g["errors"] < m["errors"] and g["false"] < m["false"] and g["p99"] <= m["p99"], seed
+        assert g["kept"] >= m["kept"] - 2e-3, seed
