@@ -356,6 +356,7 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
     __shared__ __align__(16) _Float16 a1s[RX][PC][16];   // layer-1 ring (slot = row mod 8)
     __shared__ float us[RX][PC][9];                      // tap-sum ring (slot = row mod 8)
     __shared__ float colv[2][W];                         // column sums of even / odd rows
+    __shared__ float srt[IWG / 64][W];                   // each wave's sorted channel means (guard)
 
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int half = lane >> 5, col = lane & 31;
@@ -463,11 +464,11 @@ __global__ void __launch_bounds__(IWG) cnn_infer_kernel(const float *__restrict_
         // bit of this lane's output column c0 + col (lane (c0 + col) / 4 holds its mean).
         uint32_t gcol = 0u;
         if (guard_m > 0.f) {
-            float d[4], dd[4];
+            float d[4];
             uint32_t bits = 0u;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dd[q] = d[q] = fabsf(cm[q] - med);
-            const float mad = wave_median256(dd, lane);
+            for (int q = 0; q < 4; ++q) d[q] = fabsf(cm[q] - med);
+            const float mad = wave_mad256_sorted(cv, med, lane, srt[wv]);
             const float thr = guard_m * mad / 0.6745f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) bits |= (d[q] > thr ? 1u : 0u) << q;

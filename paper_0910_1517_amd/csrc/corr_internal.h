@@ -236,6 +236,32 @@ __device__ inline float wave_median256(float (&v)[4], int lane) {
     return 0.5f * (__shfl(v[3], 31) + __shfl(v[0], 32));  // sorted elements 127 and 128
 }
 
+// Median of |s_i - med| over the 256 values s that wave_median256 sorted into v
+// (s[4 lane + q] in v[q]), med their median, without a second sort.  Below the
+// median the deviations A[i] = med - s[127 - i] ascend with i, above it
+// B[j] = s[128 + j] - med ascend with j (both exactly the FP32 |s - med|), so
+// the 128 smallest deviations are A[0 .. p - 1] and B[0 .. 127 - p] for the
+// split p = #{i < 128 : B[127 - i] > A[i]} (the comparison holds on a prefix
+// of i), and the two middle ones are max(A[p - 1], B[127 - p]) and
+// min(A[p], B[128 - p]).  buf: 256 floats of LDS used by this wave alone.
+__device__ inline float wave_mad256_sorted(const float (&v)[4], float med, int lane, float *buf) {
+    *reinterpret_cast<float4 *>(buf + 4 * lane) = make_float4(v[0], v[1], v[2], v[3]);
+    int p = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        p += __popcll(__ballot(buf[255 - i] - med > med - buf[127 - i]));
+    }
+    const float inf = __builtin_inff();
+    const float a_lo = med - buf[p > 0 ? 128 - p : 0];     // A[p - 1]
+    const float b_lo = buf[p < 128 ? 255 - p : 128] - med;  // B[127 - p]
+    const float a_hi = med - buf[p < 128 ? 127 - p : 0];   // A[p]
+    const float b_hi = buf[p > 0 ? 256 - p : 128] - med;    // B[128 - p]
+    const float lo = fmaxf(p > 0 ? a_lo : -inf, p < 128 ? b_lo : -inf);
+    const float hi = fminf(p < 128 ? a_hi : inf, p > 0 ? b_hi : inf);
+    return 0.5f * (lo + hi);
+}
+
 hipError_t launch_beamform(int precision, const void *spec, const float *scale, const float *w, const float *cb,
                            int n_beams, int S, int C, int64_t T, int tint, int mode, float *inc, float *coh,
                            hipStream_t st);

@@ -35,17 +35,37 @@ __device__ inline float wave_sort64(float x, int lane) {
 }
 
 
-// Median of 64 floats, one per lane.
-__device__ inline float wave_median64(float x, int lane) {
-    const float y = wave_sort64(x, lane);
+// Median of 64 floats, one per lane; y receives them sorted (element lane).
+__device__ inline float wave_median64(float x, int lane, float &y) {
+    y = wave_sort64(x, lane);
     return 0.5f * (__shfl(y, 31) + __shfl(y, 32));
+}
+
+// Median of |s_i - med| over 64 sorted values (s[lane] in y, med their median)
+// without a second sort, as wave_mad256_sorted does for 256: the deviations
+// A[i] = med - s[31 - i] and B[j] = s[32 + j] - med ascend, and the 32 smallest
+// are A[0 .. p - 1] and B[0 .. 31 - p] for p = #{i < 32 : B[31 - i] > A[i]}.
+// buf: 64 floats of LDS used by this wave alone.
+__device__ inline float wave_mad64_sorted(float y, float med, int lane, float *buf) {
+    buf[lane] = y;
+    const int i = lane & 31;
+    const bool gt = buf[63 - i] - med > med - buf[31 - i];
+    const int p = __popcll(__ballot(lane < 32 && gt));
+    const float inf = __builtin_inff();
+    const float a_lo = med - buf[p > 0 ? 32 - p : 0];    // A[p - 1]
+    const float b_lo = buf[p < 32 ? 63 - p : 32] - med;  // B[31 - p]
+    const float a_hi = med - buf[p < 32 ? 31 - p : 0];   // A[p]
+    const float b_hi = buf[p > 0 ? 64 - p : 32] - med;   // B[32 - p]
+    const float lo = fmaxf(p > 0 ? a_lo : -inf, p < 32 ? b_lo : -inf);
+    const float hi = fminf(p < 32 ? a_hi : inf, p > 0 ? b_hi : inf);
+    return 0.5f * (lo + hi);
 }
 
 // One tile (signal s, spectra m0..m0+63, channels k0..k0+255) per workgroup.
 // Eq. 3 / Eq. 4 on the 64 row means and the 256 column means:
 // flag[i] = |x_i - med| > M MAD / 0.6745, the median of an even count being
 // the mean of the two middle values.  One wave sorts the row statistic while
-// another sorts the column statistic.
+// another sorts the column statistic; the MADs come from the sorted values.
 template <typename PT>
 __global__ void __launch_bounds__(KT) mad_tile_kernel(const PT *__restrict__ power, int S, int T, int C,
                                                       float M, uint8_t *flags) {
@@ -53,6 +73,7 @@ __global__ void __launch_bounds__(KT) mad_tile_kernel(const PT *__restrict__ pow
     __shared__ float rowp[KT / TT][TT];
     __shared__ float rowv[TT], colv[KT], rdev[TT], cdev[KT];
     __shared__ float sel[2];  // MAD of the rows, MAD of the columns
+    __shared__ __align__(16) float srt[TT + KT];  // sorted row / column statistics
     __shared__ uint8_t rowf[TT];
     __shared__ __align__(16) uint8_t colf[KT];
     const int ntk = C / KT, ntm = T / TT;
@@ -100,21 +121,20 @@ __global__ void __launch_bounds__(KT) mad_tile_kernel(const PT *__restrict__ pow
     const int lane = t & 63, wv = t >> 6;
     if (wv == 0) {
         const float x = rowv[lane];
-        const float med = wave_median64(x, lane);
+        float y;
+        const float med = wave_median64(x, lane, y);
         const float d = fabsf(x - med);
-        const float mad = wave_median64(d, lane);
+        const float mad = wave_mad64_sorted(y, med, lane, srt);
         rdev[lane] = d;
         if (lane == 0) sel[0] = mad;
     } else if (wv == 1) {
-        float v[4], w[4];
+        float v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = colv[4 * lane + q];
         const float med = wave_median256(v, lane);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            cdev[4 * lane + q] = w[q] = fabsf(colv[4 * lane + q] - med);
-        }
-        const float mad = wave_median256(w, lane);
+        for (int q = 0; q < 4; ++q) cdev[4 * lane + q] = fabsf(colv[4 * lane + q] - med);
+        const float mad = wave_mad256_sorted(v, med, lane, srt + TT);
         if (lane == 0) sel[1] = mad;
     }
     __syncthreads();

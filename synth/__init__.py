@@ -173,11 +173,18 @@ class RFI:
         out = np.zeros((S, n_samples))
         n = np.arange(n_samples)
         ch, freq, k = self.tones()
-        for s in range(S):
-            ph = rng(self.seed, 11, s).uniform(0, 2 * np.pi, ch.size)
-            amp = 2.0 * sigma_t * np.sqrt(k / N)  # (A N / 2)^2 = k N sigma_t^2
+        amp = 2.0 * sigma_t * np.sqrt(k / N)  # (A N / 2)^2 = k N sigma_t^2
+        phs = [rng(self.seed, 11, s).uniform(0, 2 * np.pi, ch.size) for s in range(S)]
+
+        def tone_job(job):  # every sample's tones are summed in the same order in any job
+            s, lo, hi = job
             for c in range(ch.size):
-                out[s] += amp[c] * np.cos(2 * np.pi * freq[c] * n + ph[c])
+                out[s, lo:hi] += amp[c] * np.cos(2 * np.pi * freq[c] * n[lo:hi] + phs[s][c])
+
+        span = 1 << 20
+        jobs = [(s, lo, min(n_samples, lo + span)) for s in range(S) for lo in range(0, n_samples, span)]
+        with _cf.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(tone_job, jobs))
         for a, bl in enumerate(self.bursts(S // n_pol, n_samples // N)):
             for (m0, ln, kk, band) in bl:
                 lo, hi = m0 * N, min(n_samples, (m0 + ln) * N)
@@ -222,7 +229,9 @@ def voltages(S: int, n_samples: int, geom: Geom, fs: float, *, seed: int = BASE_
     out = np.empty((S, n_samples), dtype=np.int8)
     n_blocks = -(-n_samples // block)
     nu = np.fft.fftfreq(block) * block  # integer frequencies (cycles per block)
-    for b in range(n_blocks):
+    rfi_sig = rfi.signal(S, n_samples, sigma_t, n_pol) if rfi is not None else None
+
+    def work(b):  # blocks are independent (their random streams are keyed by b)
         n0 = b * block
         nb = min(block, n_samples - n0)
         t = (n0 + np.arange(nb)) / fs
@@ -249,11 +258,17 @@ def voltages(S: int, n_samples: int, geom: Geom, fs: float, *, seed: int = BASE_
                 ph = 2 * np.pi * (tone_bin / tone_N) * (n - tau) \
                     - 2 * np.pi * sideband * (geom.psi0[s] + geom.rate[s] * t)
                 acc[s] += tone_amp * np.cos(ph)
-        if rfi is not None:
-            if b == 0:
-                rfi_sig = rfi.signal(S, n_samples, sigma_t, n_pol)
+        if rfi_sig is not None:
             acc += rfi_sig[:, n0:n0 + nb]
         out[:, n0:n0 + nb] = np.clip(np.rint(acc), -127, 127).astype(np.int8)
+
+    threads = threads or min(16, os.cpu_count() or 1)
+    if n_blocks == 1 or threads == 1:
+        for b in range(n_blocks):
+            work(b)
+    else:
+        with _cf.ThreadPoolExecutor(min(threads, n_blocks)) as ex:
+            list(ex.map(work, range(n_blocks)))
     return out
 
 

@@ -27,6 +27,8 @@ tile, OR'd into the network's flags inside the inference kernel) the learned
 flagger has fewer per-cell errors, fewer false flags and a visibility error
 tail no worse than MAD's, at N = 1024 and at the flagged form's N = 8192.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -120,11 +122,13 @@ def _train_and_evaluate(n, t_train, t_eval):
     count-normalised visibilities against the same data without interference,
     for MAD, the network, and the network with the MAD column guard."""
     import torch
+    t0 = time.time()
     train = dataset(8, t_train, 1000, mixed=True, N=n)
+    print("N %d: training set %.1f s" % (n, time.time() - t0), flush=True)
     fl = Flagger(seed=1, batch=16, lr=2e-3)
     losses = fl.train(train[0], train[1], 1000)
     first, last = losses[:10].mean(), losses[-50:].mean()
-    print("N %d: loss %.4f -> %.4f" % (n, first, last))
+    print("N %d: loss %.4f -> %.4f (%.1f s)" % (n, first, last, time.time() - t0), flush=True)
     assert np.isfinite(losses).all() and last < 0.3 * first
     out = {}
     for seed, mixed in [(2100, True), (3100, False)]:
@@ -147,6 +151,7 @@ def _train_and_evaluate(n, t_train, t_eval):
             print("  N %d seed %d (%s) %-9s false %.4f miss %.4f errors %7d | p99 |dV|/sqrt(V_ii V_jj) %.3g kept %.3f"
                   % (n, seed, "mixed" if mixed else "tones+bursts", name, r["false"], r["miss"], r["errors"],
                      r["p99"], r["kept"]))
+        print("  (%.1f s)" % (time.time() - t0), flush=True)
         out[seed] = res
     return out
 
