@@ -387,8 +387,9 @@ def bench_batch(args):
 
 def bench_rfi(args):
     """Flagged int8 path with the learned flagger: F-engine (held scales, power
-    output) -> CNN inference (fused FP16 MFMA kernel) -> zero flagged cells and
-    keep bits -> X-engine -> exact per-pair unflagged counts -> integrate.
+    output) -> CNN inference (fused FP16 MFMA kernel) -> keep bits from the
+    flags -> X-engine with the keep bits applied as it stages the spectra, and
+    the exact per-pair unflagged counts, in one corr_xengine call -> integrate.
     Prints one JSON line."""
     import torch
     import paper_0910_1517_amd as corr
@@ -417,7 +418,7 @@ def bench_rfi(args):
     counts = torch.zeros(C * plan.P, dtype=torch.int32, device="cuda")
     params = torch.from_numpy(init_params(1)).cuda()
     st = torch.cuda.current_stream()
-    names = ["fengine", "cnn_infer", "apply_flags", "xengine", "pair_counts", "integrate"]
+    names = ["fengine", "cnn_infer", "keep_bits", "xengine_masked_with_counts", "integrate"]
 
     def step(e=None):
         if e: e[0].record(st)
@@ -425,19 +426,17 @@ def bench_rfi(args):
         if e: e[1].record(st)
         corr.cnn_infer(params, power, flags, threshold=0.5, guard=3.0, stream=st)
         if e: e[2].record(st)
-        plan.apply_flags(flags, spec, keep, stream=st)
+        plan.apply_flags(flags, None, keep, stream=st)  # keep words only: the X-engine applies them
         if e: e[3].record(st)
-        plan.xengine(spec, acc, stream=st)
+        plan.xengine(spec, acc, keep=keep, counts=counts, stream=st)
         if e: e[4].record(st)
-        plan.pair_counts(keep, counts, stream=st)
-        if e: e[5].record(st)
         plan.integrate(acc, state, vis, scale, flags=corr.DUMP | corr.RESET, stream=st)
-        if e: e[6].record(st)
+        if e: e[5].record(st)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
     for e in ev:
         step(e)
     torch.cuda.synchronize()
@@ -453,7 +452,7 @@ def bench_rfi(args):
         e1.record(st)
     torch.cuda.synchronize()
     t_mad = float(np.median([e0.elapsed_time(e1) for e0, e1 in em])) * 1e-3
-    t_step = float(np.median([e[0].elapsed_time(e[6]) for e in ev])) * 1e-3
+    t_step = float(np.median([e[0].elapsed_time(e[5]) for e in ev])) * 1e-3
     cells = S * T * C
     cnn_flops = float(cells) * CNN_FLOP_PER_CELL
     ach = cnn_flops / t["cnn_infer"] / 1e12
@@ -471,7 +470,7 @@ def bench_rfi(args):
                    "parallelism": "single GPU"},
         "ms": {n: round(v * 1e3, 4) for n, v in t.items()},
         "mad_flag_ms": round(t_mad * 1e3, 4),
-        "x_engine_tops": round(xops / t["xengine"] / 1e12, 3),
+        "x_engine_tops_with_counts": round(xops / t["xengine_masked_with_counts"] / 1e12, 3),
         "roofline": {"kernel": "cnn_infer_kernel<_Float16> (fused 3-layer conv, FP16 MFMA, column guard)", "bound": "mfma",
                      "achieved": round(ach, 3), "peak": FP16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": round(ach * 1e12 / FP16_MFMA_PEAK, 4), "traffic": measured_traffic("cnn_infer_c5"),

@@ -246,15 +246,32 @@ corr_status corr_requantize(corr_plan_t *plan, const float *d_in, const float *d
 
 /*
  * d_acc[split][k][p] += sum over this split's spectra of Y_i conj(Y_j), for
- * every channel k and pair p (int32 exact for INT8; float for FP32/FP8).
- * d_acc holds corr_plan_acc_bytes, 256-byte aligned, and must be zeroed once
- * before the first call (corr_integrate zeroes it afterwards).  INT8: rejects
- * with OVERFLOW a call that would take the spectra accumulated since the
- * last corr_integrate above 66572 (2 * 127^2 * T < 2^31).  COMPUTE scale mode:
- * rejects with STATE a second call before corr_integrate, since the scales
- * change per call.  Errors: NULL, ALIGN, OVERFLOW, STATE, DEVICE.
+ * every channel k and pair p (section 2.1's cross-multiplication of every
+ * pair, integrated over time; int32 exact for INT8; float for FP32/FP8).
+ *   d_spec   the X layout above, 256-byte aligned; not modified.
+ *   d_keep   optional flag mask (section 5: flagged data take no part in the
+ *            products) as the bit-packed keep words of corr_apply_flags,
+ *            [C/8][T/32][S][8] uint32 (channel k's word w of signal s at
+ *            ((k/8 * T/32 + w) S + s) 8 + k mod 8), bit i of word w =
+ *            spectrum 32 w + i kept;
+ *            a cleared bit zeroes that cell of Y inside the X-engine, so the
+ *            result equals corr_apply_flags' zeroing followed by this call
+ *            without d_keep (bit-exact), without writing the spectra.  NULL:
+ *            every cell.  4-byte aligned.
+ *   d_acc    corr_plan_acc_bytes, 256-byte aligned, zeroed once before the
+ *            first call (corr_integrate zeroes it afterwards).
+ *   d_counts optional (needs d_keep and the bound workspace): += the exact
+ *            per-pair unflagged counts, as corr_pair_counts (int32 [C][P]),
+ *            4-byte aligned.
+ * INT8: rejects with OVERFLOW a call that would take the spectra accumulated
+ * since the last corr_integrate above 66572 (2 * 127^2 * T < 2^31).  COMPUTE
+ * scale mode: rejects with STATE a second call before corr_integrate, since
+ * the scales change per call.  Errors: NULL (also d_counts without d_keep),
+ * ALIGN, WORKSPACE (d_counts without a bound workspace), OVERFLOW, STATE,
+ * DEVICE.
  */
-corr_status corr_xengine(corr_plan_t *plan, const void *d_spec, void *d_acc, void *stream);
+corr_status corr_xengine(corr_plan_t *plan, const void *d_spec, const uint32_t *d_keep, void *d_acc,
+                         int32_t *d_counts, void *stream);
 
 /* ------------------------------------------------------- gated correlator */
 
@@ -392,11 +409,15 @@ corr_status corr_fix16_xengine(corr_plan_t *plan, const int16_t *d_y16, const fl
 corr_status corr_mad_flag(corr_plan_t *plan, const void *d_power, float M, uint8_t *d_flags,
                           void *stream);
 
-/* Zero the flagged cells of X-layout spectra in place (both components), and
- * optionally (d_keep != NULL) write bit-packed keep masks [C][S][T/32] uint32
- * (bit i of word w = spectrum 32 w + i not flagged; corr_plan_keep_bytes).
- * d_flags may come from corr_mad_flag or from any other flagger.
- * Errors: NULL, ALIGN, DEVICE. */
+/* Zero the flagged cells of X-layout spectra in place (both components;
+ * d_spec NULL: leave the spectra alone), and optionally (d_keep != NULL) write
+ * bit-packed keep masks [C/8][T/32][S][8] uint32 (channel k's word w of
+ * signal s at ((k/8 * T/32 + w) S + s) 8 + k mod 8: the order in which the
+ * X-engine reads them; bit i of word w = spectrum
+ * 32 w + i not flagged; corr_plan_keep_bytes), which corr_xengine can apply
+ * itself instead of the zeroing.  d_flags may come from corr_mad_flag or from
+ * any other flagger.  Errors: NULL (also d_spec and d_keep both NULL), ALIGN,
+ * DEVICE. */
 corr_status corr_apply_flags(corr_plan_t *plan, const uint8_t *d_flags, void *d_spec,
                              uint32_t *d_keep, void *stream);
 

@@ -129,7 +129,7 @@ def lib():
     L.corr_fengine.restype = st
     L.corr_xpack.argtypes = [P, P, P, P]
     L.corr_xpack.restype = st
-    L.corr_xengine.argtypes = [P, P, P, P]
+    L.corr_xengine.argtypes = [P, P, P, P, P, P]
     L.corr_xengine.restype = st
     L.corr_beamform.argtypes = [P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P]
     L.corr_beamform.restype = st
@@ -384,8 +384,10 @@ class Plan:
         self._check(lib().corr_mad_flag(self._h, _ptr(power), M, _ptr(flags), _stream(stream)))
 
     def apply_flags(self, flags, spec, keep=None, stream=None):
+        """corr_apply_flags; spec None: write the keep words only (for
+        xengine(..., keep=...))."""
         _need(flags, "flags", self._size("flags"))
-        _need(spec, "spec", self.spectra_bytes)
+        _need(spec, "spec", self.spectra_bytes, optional=keep is not None)
         _need(keep, "keep", self._size("keep"), optional=True)
         self._check(lib().corr_apply_flags(self._h, _ptr(flags), _ptr(spec), _ptr(keep), _stream(stream)))
 
@@ -410,10 +412,16 @@ class Plan:
         _need(out, "out", n, (torch.int8, torch.uint8))
         self._check(lib().corr_requantize(self._h, _ptr(inp), _ptr(scale), _ptr(out), _stream(stream)))
 
-    def xengine(self, spec, acc, stream=None):
+    def xengine(self, spec, acc, keep=None, counts=None, stream=None):
+        """corr_xengine; keep: keep words [C/8][T/32][S][8] (uint32 or int32) whose
+        cleared bits are zeroed inside the X-engine, counts: int32 [C][P]
+        += the per-pair unflagged counts (needs keep)."""
+        import torch
         _need(spec, "spec", self.spectra_bytes)
         _need(acc, "acc", self.acc_bytes)
-        self._check(lib().corr_xengine(self._h, _ptr(spec), _ptr(acc), _stream(stream)))
+        _need(keep, "keep", self._size("keep"), optional=True)
+        _need(counts, "counts", 4 * self.C * self.P, torch.int32, optional=True)
+        self._check(lib().corr_xengine(self._h, _ptr(spec), _ptr(keep), _ptr(acc), _ptr(counts), _stream(stream)))
 
     def xengine_gated(self, spec, gate, n_bins, acc, stream=None):
         """Gated X-engine: acc holds n_bins accumulators of acc_bytes each;

@@ -357,18 +357,27 @@ corr_status corr_beamform(corr_plan_t *p, const void *d_spec, const float *d_sca
     return e == hipSuccess ? CORR_OK : hip_fail(p, e, "beamformer launch");
 }
 
-corr_status corr_xengine(corr_plan_t *p, const void *d_spec, void *d_acc, void *stream) {
+corr_status corr_xengine(corr_plan_t *p, const void *d_spec, const uint32_t *d_keep, void *d_acc, int32_t *d_counts,
+                         void *stream) {
     if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
     if (!d_spec || !d_acc) return fail(p, CORR_ERR_NULL, "d_spec and d_acc are required");
+    if (d_counts && !d_keep) return fail(p, CORR_ERR_NULL, "d_counts needs d_keep");
     if (!aligned(d_spec, 256) || !aligned(d_acc, 256)) return fail(p, CORR_ERR_ALIGN, "d_spec/d_acc must be 256-byte aligned");
+    if (!aligned(d_keep, 4) || !aligned(d_counts, 4)) return fail(p, CORR_ERR_ALIGN, "d_keep/d_counts must be 4-byte aligned");
+    if (d_counts && !p->bound) return fail(p, CORR_ERR_WORKSPACE, "pair counts need the bound workspace");
     if (p->d.precision == CORR_INT8 && p->acc_spectra + p->d.n_spectra > kMaxInt8Spectra)
         return fail(p, CORR_ERR_OVERFLOW, "%lld spectra since the last integrate would exceed the int32 bound (%lld)",
                     (long long)(p->acc_spectra + p->d.n_spectra), (long long)kMaxInt8Spectra);
     if (p->d.precision != CORR_FP32 && p->d.scale_mode == CORR_SCALE_COMPUTE && p->x_calls > 0)
         return fail(p, CORR_ERR_STATE, "COMPUTE scales change per call: integrate before the next X-engine call");
-    hipError_t e = launch_xengine(p->d.precision, d_spec, d_acc, p->d.n_signals, p->M, (int)p->d.n_spectra,
+    hipError_t e = launch_xengine(p->d.precision, d_spec, d_keep, d_acc, p->d.n_signals, p->M, (int)p->d.n_spectra,
                                   p->splits, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(p, e, "X-engine launch");
+    if (d_counts) {
+        e = launch_pair_counts(d_keep, reinterpret_cast<const uint16_t *>(p->d_ws + p->ws.pairs), p->d.n_signals,
+                               (int)p->d.n_spectra, p->M, d_counts, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(p, e, "pair-count launch");
+    }
     p->acc_spectra += p->d.n_spectra;
     p->x_calls += 1;
     return CORR_OK;
@@ -532,7 +541,7 @@ corr_status corr_mad_flag(corr_plan_t *p, const void *d_power, float M, uint8_t 
 
 corr_status corr_apply_flags(corr_plan_t *p, const uint8_t *d_flags, void *d_spec, uint32_t *d_keep, void *stream) {
     if (!p) return fail(nullptr, CORR_ERR_NULL, "plan is null");
-    if (!d_flags || !d_spec) return fail(p, CORR_ERR_NULL, "d_flags and d_spec are required");
+    if (!d_flags || (!d_spec && !d_keep)) return fail(p, CORR_ERR_NULL, "d_flags and one of d_spec, d_keep are required");
     if (!aligned(d_spec, 256) || (d_keep && !aligned(d_keep, 4)))
         return fail(p, CORR_ERR_ALIGN, "d_spec 256 B / d_keep 4 B alignment");
     hipError_t e = launch_apply_flags(p->d.precision, d_flags, d_spec, d_keep, p->d.n_signals,
@@ -754,7 +763,7 @@ corr_status corr_autotune_x_split(const corr_desc_t *desc, void *d_scratch, size
         hipError_t e = hipSuccess;
         for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {  // the first launch warms up
             e = hipEventRecord(e0, st);
-            if (e == hipSuccess) e = launch_xengine(d.precision, spec, acc, d.n_signals, p->M, (int)d.n_spectra, p->splits, st);
+            if (e == hipSuccess) e = launch_xengine(d.precision, spec, nullptr, acc, d.n_signals, p->M, (int)d.n_spectra, p->splits, st);
             if (e == hipSuccess) e = hipEventRecord(e1, st);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             if (e == hipSuccess) e = hipEventElapsedTime(&ts[rep], e0, e1);

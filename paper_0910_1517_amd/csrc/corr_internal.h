@@ -145,7 +145,9 @@ hipError_t launch_xengine16(const int16_t *y16, int S, int64_t T, int C, const f
 hipError_t launch_calib_reduce(const float *part, int S, int C, int nparts, int T, int precision,
                                float *scale, hipStream_t st);
 
-hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int C, int T,
+// keep: bit-packed keep words [C/8][T/32][S][8] whose clear bits are zeroed as the
+// spectra are staged (NULL: every cell)
+hipError_t launch_xengine(int precision, const void *spec, const uint32_t *keep, void *acc, int S, int C, int T,
                           int splits, hipStream_t st);
 // Gated X-engine: accumulator set b (acc_elems elements apart) sums the
 // spectra m with gate[m] == b, for b < n_bins.

@@ -160,7 +160,11 @@ __global__ void __launch_bounds__(KT) mad_tile_kernel(const PT *__restrict__ pow
 // word) x 256 channels of one signal.  Thread t builds the keep word of
 // channel k0 + t from the 32 flag bytes of that channel (the loads of the
 // workgroup's threads are consecutive bytes of a row), writes it to
-// keep[k][s][w] when keep is given; then the workgroup zeroes the flagged cells of its X-layout chunks (index
+// keep when keep is given (word (((k / 8) W + w) S + s) 8 + k mod 8: the words of
+// 8 consecutive channels of every signal for one span of 32 spectra are
+// contiguous, the order in which the X-engine stages its channel blocks); then,
+// when spec is given, the workgroup
+// zeroes the flagged cells of its X-layout chunks (index
 // g C S + (k/8) S 8 + s 8 + k mod 8 in 16-byte units), reading and writing a
 // chunk only when one of its cells is flagged.
 __device__ inline uint32_t expand4(uint32_t b) {  // 4 bits -> 4 bytes of 0x00 / 0xFF
@@ -180,7 +184,8 @@ __global__ void __launch_bounds__(256) apply_keep_kernel(const uint8_t *__restri
     uint32_t bits = 0;
 #pragma unroll
     for (int i = 0; i < 32; ++i) bits |= (f[(int64_t)i * C] ? 0u : 1u) << i;
-    if (keep) keep[((int64_t)k * S + s) * W + w] = bits;
+    if (keep) keep[(((int64_t)(k >> 3) * W + w) * S + s) * 8 + (k & 7)] = bits;
+    if (!spec) return;  // keep words only (the X-engine applies them)
     if (__syncthreads_and(bits == 0xFFFFFFFFu)) return;  // nothing flagged in this block
     uint4 *chunks = reinterpret_cast<uint4 *>(spec);
     constexpr int NG = 32 / G;  // chunks per channel in the block
@@ -224,8 +229,8 @@ __global__ void __launch_bounds__(256) pair_counts_kernel(const uint32_t *__rest
         const int nw = min(256, W - w0);
         __syncthreads();
         for (int i = t; i < S * nw; i += 256) {
-            const int s = i / nw, w = i % nw;
-            kw[s][w] = keep[((int64_t)k * S + s) * W + w0 + w];
+            const int s = i % S, w = i / S;
+            kw[s][w] = keep[(((int64_t)(k >> 3) * W + w0 + w) * S + s) * 8 + (k & 7)];
         }
         __syncthreads();
 #pragma unroll

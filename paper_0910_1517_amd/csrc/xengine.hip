@@ -103,14 +103,39 @@ __device__ inline uint32_t eq_bytes(uint32_t w, uint32_t b4) {
     return (z << 1) - (z >> 7);                                                   // 0x80 -> 0xFF
 }
 
+// 4 bits -> 4 bytes of 0x00 / 0xFF
+__device__ inline uint32_t keep_bytes(uint32_t b) { return ((b * 0x00204081u) & 0x01010101u) * 0xFFu; }
+
+// Zero the flagged cells of a staged 16-byte chunk: kb8 holds the chunk's keep
+// bits (bit i = spectrum i of the chunk kept; 8 spectra for INT8 / FP8, whose
+// chunk is 8 real bytes then 8 imaginary bytes, 2 for FP32's two complex64).
+template <int PREC>
+__device__ __forceinline__ uint4 keep_chunk(uint4 v, uint32_t kb8) {
+    if constexpr (PREC == CORR_FP32) {
+        if (!(kb8 & 1u)) v.x = v.y = 0u;
+        if (!(kb8 & 2u)) v.z = v.w = 0u;
+    } else {
+        const uint32_t lo = keep_bytes(kb8 & 15u), hi = keep_bytes((kb8 >> 4) & 15u);
+        v.x &= lo;
+        v.y &= hi;
+        v.z &= lo;
+        v.w &= hi;
+    }
+    return v;
+}
+
 // One (channel block kb, split sp) of one correlation: PREC is CORR_FP32,
 // CORR_INT8 or CORR_FP8_E4M3; ACC float or int32_t; lds holds at least
 // x_lds_bytes<NT>() bytes.  GATED: only the spectra m with gate[m] == bin
 // are summed (the B operand of every product is masked per spectrum).
-template <int NT, int PREC, typename ACC, bool GATED = false>
+// MASKED: the flagged cells (keep bits clear; keep words [C/8][T/32][S][8],
+// bit i of word w = spectrum 32 w + i) are zeroed as the chunks are staged,
+// which is the product of zeroed spectra without writing them.
+template <int NT, int PREC, typename ACC, bool GATED = false, bool MASKED = false>
 __device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, ACC *acc, int S, int C, int T,
                                               int splits, int kb, int sp, uint8_t *lds,
-                                              const uint8_t *__restrict__ gate = nullptr, int bin = 0) {
+                                              const uint8_t *__restrict__ gate = nullptr, int bin = 0,
+                                              const uint32_t *__restrict__ keep = nullptr) {
     using V16 = typename std::conditional<PREC == CORR_INT8, v16i, v16f>::type;
     const int wv = threadIdx.x >> 6, c = kXWaves * kb + wv;
     const int lane = threadIdx.x & 63, row = lane & 31, lg = lane >> 5;
@@ -128,21 +153,43 @@ __device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, 
     // loads in flight across steps and wait only for the older set)
     const uint4 *gsrc = reinterpret_cast<const uint4 *>(spec) + (int64_t)kb * S * 8 + (cp ? i : S * 8 - 1);
     const int64_t gstride = (int64_t)C * S;  // 16-byte units between chunks g and g+1
+    // keep words of this thread's (channel, signal): a K-step's 4 chunks are 32
+    // spectra (one word) for INT8 / FP8 and 8 spectra (one byte) for FP32; the
+    // words of the block's S x 8 chunks for one span of 32 spectra are
+    // contiguous, in the staging threads' order
+    const uint32_t *kw0 = nullptr;
+    const int64_t kwstride = (int64_t)S * 8;
+    if constexpr (MASKED) kw0 = keep + (int64_t)kb * (T / 32) * kwstride + (cp ? i : S * 8 - 1);
     // two register sets (a, b) alternate between the next two K-steps'
     // chunks, so each load has two steps of MFMA work to land before its LDS
     // store
     uint4 pa0 = make_uint4(0, 0, 0, 0), pa1 = pa0, pa2 = pa0, pa3 = pa0, pb0 = pa0, pb1 = pa0, pb2 = pa0, pb3 = pa0;
+    uint32_t pak = 0xFFFFFFFFu, pbk = 0xFFFFFFFFu;  // keep bits of the step each set holds (MASKED)
 #define X_GLOAD(st, R)                                                \
     {                                                                 \
-        const uint4 *g_ = gsrc + 4 * ((int64_t)sp * steps + (st)) * gstride; \
+        const int64_t s_ = (int64_t)sp * steps + (st);                \
+        const uint4 *g_ = gsrc + 4 * s_ * gstride;                    \
         R##0 = g_[0];                                                 \
         R##1 = g_[gstride];                                           \
         R##2 = g_[2 * gstride];                                       \
         R##3 = g_[3 * gstride];                                       \
+        if constexpr (MASKED) {                                       \
+            if constexpr (PREC == CORR_FP32)                          \
+                R##k = kw0[(s_ >> 2) * kwstride] >> (8 * (s_ & 3));   \
+            else                                                      \
+                R##k = kw0[s_ * kwstride];                            \
+        }                                                             \
     }
 #define X_LSTORE(buf, R)                                              \
     if (cp) {                                                         \
         uint8_t *l_ = lds + (buf) * 4 * kBlk + lds_dst;               \
+        constexpr int SH_ = PREC == CORR_FP32 ? 2 : 8;                \
+        if constexpr (MASKED) {                                       \
+            R##0 = keep_chunk<PREC>(R##0, R##k);                      \
+            R##1 = keep_chunk<PREC>(R##1, R##k >> SH_);               \
+            R##2 = keep_chunk<PREC>(R##2, R##k >> (2 * SH_));         \
+            R##3 = keep_chunk<PREC>(R##3, R##k >> (3 * SH_));         \
+        }                                                             \
         *reinterpret_cast<uint4 *>(l_) = R##0;                        \
         *reinterpret_cast<uint4 *>(l_ + kBlk) = R##1;                 \
         *reinterpret_cast<uint4 *>(l_ + 2 * kBlk) = R##2;             \
@@ -311,11 +358,13 @@ __device__ __forceinline__ void xengine_block(const uint8_t *__restrict__ spec, 
     __syncthreads();  // the LDS may be reused by the next block of a persistent loop
 }
 
-template <int NT, int PREC, typename ACC>
+template <int NT, int PREC, typename ACC, bool MASKED>
 __global__ void __launch_bounds__(64 * kXWaves)
-xengine_kernel(const uint8_t *__restrict__ spec, ACC *acc, int S, int C, int T, int splits) {
+xengine_kernel(const uint8_t *__restrict__ spec, const uint32_t *__restrict__ keep, ACC *acc, int S, int C, int T,
+               int splits) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[x_lds_bytes<NT>()];
-    xengine_block<NT, PREC, ACC>(spec, acc, S, C, T, splits, blockIdx.x, blockIdx.y, lds);
+    xengine_block<NT, PREC, ACC, false, MASKED>(spec, acc, S, C, T, splits, blockIdx.x, blockIdx.y, lds, nullptr, 0,
+                                               keep);
 }
 
 // Gated correlation: one workgroup per (task, bin), task = (channel block kb,
@@ -424,23 +473,26 @@ hipError_t launch_requantize(int precision, const float *in, const float *scale,
     return hipGetLastError();
 }
 
-hipError_t launch_xengine(int precision, const void *spec, void *acc, int S, int C, int T, int splits,
-                          hipStream_t st) {
+hipError_t launch_xengine(int precision, const void *spec, const uint32_t *keep, void *acc, int S, int C, int T,
+                          int splits, hipStream_t st) {
     const dim3 grid(C / kXWaves, splits), block(64 * kXWaves);
     const uint8_t *sp8 = (const uint8_t *)spec;
-    const bool two = S > 32;
+    auto go = [&](auto kernel, auto *a) { hipLaunchKernelGGL(kernel, grid, block, 0, st, sp8, keep, a, S, C, T, splits); };
+    const bool two = S > 32, m = keep != nullptr;
+    int32_t *ai = (int32_t *)acc;
+    float *af = (float *)acc;
     switch (precision) {
     case CORR_INT8:
-        if (two) hipLaunchKernelGGL((xengine_kernel<2, CORR_INT8, int32_t>), grid, block, 0, st, sp8, (int32_t *)acc, S, C, T, splits);
-        else hipLaunchKernelGGL((xengine_kernel<1, CORR_INT8, int32_t>), grid, block, 0, st, sp8, (int32_t *)acc, S, C, T, splits);
+        if (two) m ? go(xengine_kernel<2, CORR_INT8, int32_t, true>, ai) : go(xengine_kernel<2, CORR_INT8, int32_t, false>, ai);
+        else m ? go(xengine_kernel<1, CORR_INT8, int32_t, true>, ai) : go(xengine_kernel<1, CORR_INT8, int32_t, false>, ai);
         break;
     case CORR_FP8_E4M3:
-        if (two) hipLaunchKernelGGL((xengine_kernel<2, CORR_FP8_E4M3, float>), grid, block, 0, st, sp8, (float *)acc, S, C, T, splits);
-        else hipLaunchKernelGGL((xengine_kernel<1, CORR_FP8_E4M3, float>), grid, block, 0, st, sp8, (float *)acc, S, C, T, splits);
+        if (two) m ? go(xengine_kernel<2, CORR_FP8_E4M3, float, true>, af) : go(xengine_kernel<2, CORR_FP8_E4M3, float, false>, af);
+        else m ? go(xengine_kernel<1, CORR_FP8_E4M3, float, true>, af) : go(xengine_kernel<1, CORR_FP8_E4M3, float, false>, af);
         break;
     case CORR_FP32:
-        if (two) hipLaunchKernelGGL((xengine_kernel<2, CORR_FP32, float>), grid, block, 0, st, sp8, (float *)acc, S, C, T, splits);
-        else hipLaunchKernelGGL((xengine_kernel<1, CORR_FP32, float>), grid, block, 0, st, sp8, (float *)acc, S, C, T, splits);
+        if (two) m ? go(xengine_kernel<2, CORR_FP32, float, true>, af) : go(xengine_kernel<2, CORR_FP32, float, false>, af);
+        else m ? go(xengine_kernel<1, CORR_FP32, float, true>, af) : go(xengine_kernel<1, CORR_FP32, float, false>, af);
         break;
     default:
         return hipErrorInvalidValue;

@@ -326,7 +326,7 @@ def test_xengine_rejects_a_call_past_the_int32_bound():
     assert rc == 0
     try:
         fake = ctypes.c_void_p(1 << 20)
-        assert L.corr_xengine(h, fake, fake, None) == -6
+        assert L.corr_xengine(h, fake, None, fake, None, None) == -6
         assert b"int32" in L.corr_last_error(h)
         # FP32 has no such bound: the same shape is not rejected for it (not called here)
     finally:
@@ -340,3 +340,21 @@ def test_batch_rejects_an_entry_past_the_int32_bound():
     h = ctypes.c_void_p()
     assert corr.lib().corr_batch_create(descs, 2, ctypes.byref(h)) == -6 and not h.value
     assert b"entry 1" in corr.lib().corr_last_error(None)
+
+
+# --------------------------------------------------- X-engine keep masks and counts
+def test_xengine_mask_and_count_arguments_are_checked_on_the_host():
+    # rejected before any launch: the placeholder pointers are never dereferenced
+    L = corr.lib()
+    rc, h = create(n_signals=8, fft_len=512, n_spectra=64, precision=corr.INT8)
+    assert rc == 0
+    try:
+        fake = ctypes.c_void_p(1 << 20)
+        assert L.corr_xengine(h, fake, None, fake, fake, None) == -2       # counts without keep
+        assert L.corr_xengine(h, fake, ctypes.c_void_p((1 << 20) + 2), fake, None, None) == -3  # keep misaligned
+        assert L.corr_xengine(h, fake, fake, fake, ctypes.c_void_p((1 << 20) + 1), None) == -3  # counts misaligned
+        assert L.corr_xengine(h, fake, fake, fake, fake, None) == -5       # counts need the workspace
+        assert b"workspace" in L.corr_last_error(h)
+        assert L.corr_apply_flags(h, fake, None, None, None) == -2         # neither spectra nor keep
+    finally:
+        L.corr_plan_destroy(h)

@@ -136,7 +136,8 @@ def test_apply_flags_and_pair_counts_bit_exact(prec):
         assert np.array_equal(back[..., 1], ref.imag.astype(np.float32))
     assert np.array_equal(counts.cpu().numpy().reshape(plan.C, plan.P), oracle.pair_counts(fl))
     # keep masks: bit i of word w = spectrum 32 w + i kept
-    kb = keep.cpu().numpy().view(np.uint32).reshape(plan.C, S, T // 32)
+    # layout [C/8][T/32][S][8]
+    kb = keep.cpu().numpy().view(np.uint32).reshape(plan.C // 8, T // 32, S, 8).transpose(0, 3, 2, 1).reshape(plan.C, S, T // 32)
     bits = ((kb[..., None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(plan.C, S, T)
     assert np.array_equal(bits.transpose(1, 2, 0), (fl == 0).astype(np.uint32))
 
@@ -155,6 +156,49 @@ def test_flagged_int8_visibilities_bit_exact():
     torch.cuda.synchronize()
     A = oracle.xengine_int(np.where(fl[..., None] != 0, 0, q).astype(np.int8))
     assert np.array_equal(acc_sum(acc.cpu().numpy(), plan), A)
+
+
+@pytest.mark.parametrize("prec,S,T,split", [(corr.INT8, 8, 1024, 2), (corr.INT8, 48, 512, 1),
+                                             (corr.FP8_E4M3, 40, 512, 2), (corr.FP32, 8, 256, 4),
+                                             (corr.FP32, 64, 128, 1)])
+def test_masked_xengine_equals_zeroing_then_xengine(prec, S, T, split):
+    """corr_xengine with keep words (the flag mask applied as the spectra are
+    staged) against corr_apply_flags' zeroing followed by the unmasked
+    X-engine: the same accumulators bit for bit, the spectra untouched, and
+    the counts of the same call equal to the oracle's pair counts."""
+    import torch
+    print("masked X", prec, S, T, split, flush=True)
+    plan = corr.Plan(S, 512, T, precision=prec, x_split=split)
+    g = synth.rng(51, prec, S)
+    fl = (g.random((S, T, plan.C)) < 0.07).astype(np.uint8)
+    fl[S // 2, :, 5] = 1            # a flagged channel
+    fl[1, T // 3: T // 3 + 9] = 1   # a flagged burst
+    if prec == corr.INT8:
+        arr = synth.random_spectra_int8(S, T, plan.C, seed=52)
+    elif prec == corr.FP8_E4M3:
+        y = g.standard_normal((S, T, plan.C)) * 112 + 1j * g.standard_normal((S, T, plan.C)) * 112
+        arr = oracle.quantize_fp8(y, np.ones((S, plan.C)))
+    else:
+        y = synth.random_spectra_f32(S, T, plan.C, seed=52)
+        arr = np.stack([y.real, y.imag], -1).astype(np.float32)
+    spec = pack_input(plan, arr)
+    zeroed = spec.clone()
+    flags = torch.from_numpy(fl).cuda()
+    keep = plan.alloc("keep")
+    plan.apply_flags(flags, None, keep)            # keep words only
+    plan.apply_flags(flags, zeroed)                # zeroing only
+    acc_m, acc_z = plan.alloc("acc"), plan.alloc("acc")
+    counts = torch.zeros(plan.C * plan.P, dtype=torch.int32, device="cuda")
+    before = spec.clone()
+    plan.xengine(spec, acc_m, keep=keep, counts=counts)
+    plan.xengine(zeroed, acc_z)
+    torch.cuda.synchronize()
+    assert torch.equal(spec, before)
+    assert torch.equal(acc_m.view(torch.int32), acc_z.view(torch.int32))
+    assert np.array_equal(counts.cpu().numpy().reshape(plan.C, plan.P), oracle.pair_counts(fl))
+    if prec == corr.INT8:  # and against the oracle's integer X-engine on zeroed codes
+        A = oracle.xengine_int(np.where(fl[..., None] != 0, 0, arr).astype(np.int8))
+        assert np.array_equal(acc_sum(acc_m.cpu().numpy(), plan), A)
 
 
 def test_mad_flag_rejects_ragged_time():
