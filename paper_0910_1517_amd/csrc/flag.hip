@@ -212,13 +212,70 @@ __global__ void __launch_bounds__(256) apply_keep_kernel(const uint8_t *__restri
     }
 }
 
+// Keep words alone, when no spectra are to be zeroed.  Thread t of a
+// workgroup takes 8 consecutive channels of one signal and one span of 32
+// spectra: one 8-byte load per spectrum row, whose 8 flag bytes are reduced to
+// their top bits (set when the byte is nonzero) and gathered, 8 rows at a time,
+// as bit i of every byte; the 4 gathered words per 4 channels are then
+// transposed bytewise into the channels' 32-bit words.  The 8 words are
+// contiguous in the keep layout and leave as two 16-byte stores.  The 4 lanes
+// t = 4 c + s' (s' < 4) take signals 4 (block) + s' of the same channels, so
+// the 4 x 32 bytes they store fill one 128-byte line: keep words leave L2 as
+// whole lines.  A workgroup covers 4 signals x 512 channels x 32 spectra.
+// Needs flags 8-byte and keep 16-byte aligned (the caller checks).
+__device__ inline uint32_t flagged_bytes(uint32_t v) {  // top bit of each byte: byte != 0
+    return (((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u;
+}
+
+__device__ inline uint32_t byte_of(uint32_t a, int j) { return (a >> (8 * j)) & 0xFFu; }
+
+__global__ void __launch_bounds__(256) keep_words_kernel(const uint8_t *__restrict__ flags,
+                                                         uint32_t *__restrict__ keep, int S, int T, int C) {
+    const int nkb = (C + 511) / 512, W = T / 32;
+    const int kblk = blockIdx.x % nkb;
+    const int w = (blockIdx.x / nkb) % W;
+    const int s = 4 * (int)(blockIdx.x / (nkb * W)) + (int)(threadIdx.x & 3);
+    const int k = (kblk * 64 + (int)(threadIdx.x >> 2)) * 8;
+    if (k >= C || s >= S) return;
+    const uint8_t *f = flags + ((int64_t)s * T + (int64_t)w * 32) * C + k;
+    uint32_t a[2][4];  // a[h][g]: byte j = flag bits of spectra 8 g ... 8 g + 7 of channel k + 4 h + j
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        a[0][g] = a[1][g] = 0u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(f + (int64_t)(8 * g + i) * C);
+            a[0][g] |= flagged_bytes(v.x) >> (7 - i);
+            a[1][g] |= flagged_bytes(v.y) >> (7 - i);
+        }
+    }
+    uint32_t o[8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            o[4 * h + j] = ~(byte_of(a[h][0], j) | byte_of(a[h][1], j) << 8 | byte_of(a[h][2], j) << 16 |
+                             byte_of(a[h][3], j) << 24);
+    uint4 *dst = reinterpret_cast<uint4 *>(keep + (((int64_t)(k >> 3) * W + w) * S + s) * 8);
+    dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
+    dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
+}
+
 // counts[k][p] += popcount over time of keep_i & keep_j; one channel per
 // workgroup, the keep words of all signals staged in LDS 256 words at a time.
+// The 8 channels of a block share every 32-byte piece of the keep words, so
+// they are given to 8 workgroups that run side by side on one XCD (workgroups
+// are dealt to the 8 XCDs in turn) and share its L2: workgroup b takes channel
+// block 8 (b / 64) + b mod 8 and channel (b / 8) mod 8 in it when C is a
+// multiple of 64, else channel b.
 __global__ void __launch_bounds__(256) pair_counts_kernel(const uint32_t *__restrict__ keep,
                                                           const uint16_t *__restrict__ pairs, int S, int T,
                                                           int32_t *counts) {
-    __shared__ uint32_t kw[kMaxSignals][256 + 1];
-    const int k = blockIdx.x;
+    // rows of 256 + 4 words: 16-byte reads of four words, and lanes whose
+    // signals differ by less than 16 fall on distinct banks
+    __shared__ __align__(16) uint32_t kw[kMaxSignals][256 + 4];
+    const int b = blockIdx.x;
+    const int k = (gridDim.x & 63) ? b : 8 * (8 * (b >> 6) + (b & 7)) + ((b >> 3) & 7);
     const int t = threadIdx.x;
     const int W = T / 32;
     const int P = S * (S + 1) / 2;
@@ -227,10 +284,11 @@ __global__ void __launch_bounds__(256) pair_counts_kernel(const uint32_t *__rest
     for (int q = 0; q < 9; ++q) cnt[q] = 0;
     for (int w0 = 0; w0 < W; w0 += 256) {
         const int nw = min(256, W - w0);
+        const int nw4 = (nw + 3) & ~3;  // words past nw are staged as zero
         __syncthreads();
-        for (int i = t; i < S * nw; i += 256) {
+        for (int i = t; i < S * nw4; i += 256) {
             const int s = i % S, w = i / S;
-            kw[s][w] = keep[(((int64_t)(k >> 3) * W + w0 + w) * S + s) * 8 + (k & 7)];
+            kw[s][w] = w < nw ? keep[(((int64_t)(k >> 3) * W + w0 + w) * S + s) * 8 + (k & 7)] : 0u;
         }
         __syncthreads();
 #pragma unroll
@@ -238,9 +296,14 @@ __global__ void __launch_bounds__(256) pair_counts_kernel(const uint32_t *__rest
             const int p = t + 256 * q;
             if (p < P) {
                 const int i = pairs[2 * p], j = pairs[2 * p + 1];
-                int32_t c = 0;
-                for (int w = 0; w < nw; ++w) c += __popc(kw[i][w] & kw[j][w]);
-                cnt[q] += c;
+                const uint4 *a = reinterpret_cast<const uint4 *>(kw[i]);
+                const uint4 *c = reinterpret_cast<const uint4 *>(kw[j]);
+                int32_t n = 0;
+                for (int w = 0; w < nw4 / 4; ++w) {
+                    const uint4 x = a[w], y = c[w];
+                    n += __popc(x.x & y.x) + __popc(x.y & y.y) + __popc(x.z & y.z) + __popc(x.w & y.w);
+                }
+                cnt[q] += n;
             }
         }
     }
@@ -267,6 +330,11 @@ hipError_t launch_mad_flag(const void *power, bool f16, int S, int T, int C, flo
 
 hipError_t launch_apply_flags(int precision, const uint8_t *flags, void *spec, uint32_t *keep, int S, int T,
                               int C, hipStream_t st) {
+    if (!spec && !(reinterpret_cast<uintptr_t>(flags) & 7) && !(reinterpret_cast<uintptr_t>(keep) & 15)) {
+        const dim3 grid((unsigned)((int64_t)((S + 3) / 4) * (T / 32) * ((C + 511) / 512)));
+        hipLaunchKernelGGL(keep_words_kernel, grid, dim3(256), 0, st, flags, keep, S, T, C);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((int64_t)S * (T / 32) * (C / 256))), block(256);
     if (precision == CORR_FP32)
         hipLaunchKernelGGL((apply_keep_kernel<kChunk32>), grid, block, 0, st, flags, (uint8_t *)spec, keep, S, T, C);

@@ -106,14 +106,15 @@ def test_mad_flags_match_oracle():
     assert fo.mean() > 0.01  # the injected RFI is found
 
 
-@pytest.mark.parametrize("prec", [corr.INT8, corr.FP32])
-def test_apply_flags_and_pair_counts_bit_exact(prec):
+@pytest.mark.parametrize("prec,S", [(corr.INT8, 16), (corr.FP32, 16), (corr.INT8, 30)])
+def test_apply_flags_and_pair_counts_bit_exact(prec, S):
     import torch
-    S, T = 16, 256
+    T = 256
     plan = corr.Plan(S, 512, T, precision=prec)
     g = synth.rng(31, prec)
     fl = (g.random((S, T, plan.C)) < 0.1).astype(np.uint8)
     fl[3] = 1  # one signal fully flagged
+    fl[5] *= g.integers(1, 256, fl[5].shape, dtype=np.uint8)  # any nonzero byte flags
     flags = torch.from_numpy(fl).cuda()
     if prec == corr.INT8:
         q = synth.random_spectra_int8(S, T, plan.C, seed=32)
@@ -121,11 +122,13 @@ def test_apply_flags_and_pair_counts_bit_exact(prec):
     else:
         y = synth.random_spectra_f32(S, T, plan.C, seed=32)
         spec = pack_input(plan, np.stack([y.real, y.imag], -1).astype(np.float32))
-    keep = plan.alloc("keep")
+    keep, keep_only = plan.alloc("keep"), plan.alloc("keep")
     plan.apply_flags(flags, spec, keep)
+    plan.apply_flags(flags, None, keep_only)  # the keep-words-only kernel
     counts = torch.zeros(plan.C * plan.P, dtype=torch.int32, device="cuda")
     plan.pair_counts(keep, counts)
     torch.cuda.synchronize()
+    assert torch.equal(keep_only, keep)
     # zeroed spectra, read back through the layout
     back = corr.unpack_spectra(spec, prec, S, plan.C, T)
     if prec == corr.INT8:
