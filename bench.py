@@ -54,16 +54,16 @@ FP32_PUBLISHED_PEAK = 157.3e12  # the datasheet's FP32 vector figure (packed FP3
 # calibration copy, see profiles/), valid only for the kernel source they were
 # taken from: reported as `traffic` when the source hash still matches.
 MEASURED_TRAFFIC = {
-    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4470696 KiB x 2.000, WRITE_SIZE 8389231 KiB x 1.000
+    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4474463 KiB x 2.000, WRITE_SIZE 8389569 KiB x 1.000
+    # (medians of 7 dispatches)
     "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine4.hip",
-                        "sha256": "503d519bf6656a689d37ecf37c37d08024ac00545e9d7ddc7a7c42ca3eb8dc42",
-                        "read": 9.156e9, "write": 8.591e9},
-    # profiles/fx_fp32_64sig_1024pt_16384spec_pointsources.md: FETCH_SIZE 537852 KiB x 2.000, WRITE_SIZE 4194304 KiB
-    # (Both F-engine records follow the move of the shared encoders into corr_internal.h, after which both
-    # sources compile to the same instructions as when the counters were taken.)
+                        "sha256": "42d1df88e47d1ba553e913101860aea36b968315ce32ada7429fbf5e0d5b8645",
+                        "read": 9.163e9, "write": 8.591e9},
+    # profiles/fx_fp32_64sig_1024pt_16384spec_pointsources.md: FETCH_SIZE 537826 KiB x 2.000, WRITE_SIZE 4194304 KiB
+    # (medians of 6 dispatches)
     "fengine_fp32_c2": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
-                        "sha256": "10d730aec4af09ca4fed7dfe854a83c59be400633828d1830ac04f346ab3aa80",
-                        "read": 1.102e9, "write": 4.295e9},
+                        "sha256": "b6d39bb895f23bd84c3355b5a0b9ceaa9b644c91a7262f4f377014737ec3f44c",
+                        "read": 1.101e9, "write": 4.295e9},
     # profiles/cnn_flagged_64sig_8192pt_8192spec.md (FP16 power, column guard): FETCH_SIZE 2097377 KiB x 2.000,
     # WRITE_SIZE 2097152 KiB
     "cnn_infer_c5": {"source": "paper_0910_1517_amd/csrc/cnn.hip",

@@ -209,8 +209,11 @@ corr_status corr_plan_bind_workspace(corr_plan_t *plan, void *d_ws, size_t bytes
  *                      two complex64
  *                INT8 / FP8: chunk g = bytes 0..7 the real parts of spectra
  *                      8g..8g+7, bytes 8..15 their imaginary parts
- *   d_scale    [S][C] float; INT8: q = clamp(rne(Y / scale), -127, 127),
- *              FP8: q = e4m3_rne_satfinite(Y / scale).  Read in HOLD mode,
+ *   d_scale    [S][C] float; INT8: q = clamp(rne(Y / scale), -127, 127)
+ *              (Y / scale + 128 is formed in FP32 before the rounding, so a
+ *              code may differ from that of the exact quotient only within
+ *              2^-16 of a .5 boundary), FP8: q = e4m3_rne_satfinite(Y /
+ *              scale).  Read in HOLD mode,
  *              written (scale = 4 sigma / 127 or 4 sigma / 448, sigma the RMS
  *              of one component of Y over this call) in COMPUTE mode.
  *              Unused (may be NULL) for FP32.
@@ -233,8 +236,8 @@ corr_status corr_fengine(corr_plan_t *plan, const int8_t *d_x, int64_t row_strid
 corr_status corr_xpack(corr_plan_t *plan, const void *d_in, void *d_spec, void *stream);
 
 /* Requantisation of externally produced FP32 spectra with the F-engine's own
- * encoders (section 4.1: a fixed-point format with a per-channel level ahead
- * of the MAC): per component q = enc(v * (1 / d_scale[s][k])), enc the INT8
+ * encoders' definitions (section 4.1: a fixed-point format with a per-channel
+ * level ahead of the MAC): per component q = enc(v * (1 / d_scale[s][k])), enc the INT8
  * plan's clamp(rne(.), +-127) or the FP8 plan's OCP e4m3 (nearest even,
  * saturating at +-448, +0 for values that round to zero; NaN gives -127 or
  * -448).  d_in: float [S][T][C][2], 8-byte aligned; d_scale: float [S][C];

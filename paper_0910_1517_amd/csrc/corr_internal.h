@@ -93,6 +93,16 @@ __device__ __forceinline__ uint32_t quant_i8(float v) {
     return __float_as_uint(c + 12582912.0f);  // only the low byte is used
 }
 
+// The F-engines' int8 code, biased: vb is the scaled value plus 128 (formed
+// inside the value's last products).  Clamped below at 1 (code -127; NaN too),
+// converted with rounding to nearest even and saturation at 255 (code +127)
+// into byte sel of w.  The word's bytes are the codes xor 0x80.  Adding 128
+// before the rounding moves a result only within 2^-16 of a .5 boundary.
+__device__ __forceinline__ uint32_t put_i8_biased(float vb, int sel, uint32_t w) {
+    return __builtin_amdgcn_cvt_pk_u8_f32(fmaxf(vb, 1.0f), sel, w);
+}
+constexpr uint32_t kI8Bias = 0x80808080u;
+
 // One power cell of the F-engine: FP32 |X|^2, or FP16 |X|^2 / N^2 (nearest even).
 __device__ __forceinline__ void put_power(const FLaunch &a, int64_t i, float p) {
     if (a.power_f16)

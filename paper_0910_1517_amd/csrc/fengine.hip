@@ -414,10 +414,19 @@ fengine_kernel(FLaunch a) {
             } else {
                 if (a.power && active)  // |X|^2 = |2X|^2 / 4 (the phase rotation keeps it)
                     put_power(a, ((int64_t)s * a.T + m) * M + tt + L * j, 0.25f * (X.x * X.x + X.y * X.y));
+                // the value; for int8 the value plus 128, formed inside its last products
                 float2 Y;
                 if constexpr (PL) {  // table entry nearest the channel's phase; ramp = 1/2 (x 1/scale)
                     const float2 e = ev[j];
-                    Y = make_float2(ramp[j].x * (X.x * e.x - X.y * e.y), ramp[j].x * (X.x * e.y + X.y * e.x));
+                    const float2 u = make_float2(X.x * e.x - X.y * e.y, X.x * e.y + X.y * e.x);
+                    if constexpr (BM == 1)
+                        Y = make_float2(fmaf(ramp[j].x, u.x, 128.0f), fmaf(ramp[j].x, u.y, 128.0f));
+                    else
+                        Y = make_float2(ramp[j].x * u.x, ramp[j].x * u.y);
+                } else if constexpr (BM == 1) {
+                    const float2 t = cmul(X, ramp[j]);
+                    Y = make_float2(fmaf(t.x, rot.x, fmaf(-t.y, rot.y, 128.0f)),
+                                    fmaf(t.x, rot.y, fmaf(t.y, rot.x, 128.0f)));
                 } else {
                     Y = cmul(cmul(X, ramp[j]), rot);
                 }
@@ -434,8 +443,8 @@ fengine_kernel(FLaunch a) {
                     // insert the byte of spectrum r into the current dword (the other
                     // bytes are overwritten by the next spectra before they are used)
                     if constexpr (BM == 1) {
-                        q1[j] = __builtin_amdgcn_perm(quant_i8(Y.x), q1[j], bsel);
-                        h1[j] = __builtin_amdgcn_perm(quant_i8(Y.y), h1[j], bsel);
+                        q1[j] = put_i8_biased(Y.x, r & 3, q1[j]);
+                        h1[j] = put_i8_biased(Y.y, r & 3, h1[j]);
                     } else {  // one conversion: real code in byte 0, imaginary in byte 1
                         const uint32_t w = e4m3_pair(Y.x, Y.y);
                         q1[j] = __builtin_amdgcn_perm(w, q1[j], bsel);
@@ -446,7 +455,8 @@ fengine_kernel(FLaunch a) {
                         h0[j] = h1[j];
                     } else if ((r & 7) == 7 && active) {
                         uint4 *dst = reinterpret_cast<uint4 *>(a.spec) + obase + (int64_t)j * L * a.S;
-                        *dst = make_uint4(q0[j], q1[j], h0[j], h1[j]);
+                        constexpr uint32_t B = BM == 1 ? kI8Bias : 0u;  // int8 bytes carry the bias
+                        *dst = make_uint4(q0[j] ^ B, q1[j] ^ B, h0[j] ^ B, h1[j] ^ B);
                     }
                 }
             }

@@ -250,6 +250,20 @@ __device__ __forceinline__ void emit(Chan &c, float2 X, float2 rot, int r, uint3
         c.pacc += X.x * X.x + X.y * X.y;
         return;
     } else {
+        if constexpr (BM == 1) {
+            // int8: the codes plus 128 (formed inside the last products) go into byte
+            // r mod 4 of the words in progress; the chunk's store takes the 128 off
+            const float2 t = cmul(X, c.ramp);
+            c.q = put_i8_biased(fmaf(t.x, rot.x, fmaf(-t.y, rot.y, 128.0f)), r & 3, c.q);
+            c.h = put_i8_biased(fmaf(t.x, rot.y, fmaf(t.y, rot.x, 128.0f)), r & 3, c.h);
+            if ((r & 7) == 3) {
+                c.q0 = c.q;
+                c.h0 = c.h;
+            } else if ((r & 7) == 7 && active) {
+                *chunk = make_uint4(c.q0 ^ kI8Bias, c.q ^ kI8Bias, c.h0 ^ kI8Bias, c.h ^ kI8Bias);
+            }
+            return;
+        }
         const float2 Y = cmul(cmul(X, c.ramp), rot);
         if constexpr (BM == 0) {
             if (r & 1) {
@@ -258,10 +272,7 @@ __device__ __forceinline__ void emit(Chan &c, float2 X, float2 rot, int r, uint3
                 c.f0 = Y;
             }
         } else {
-            if constexpr (BM == 1) {
-                c.q = __builtin_amdgcn_perm(quant_i8(Y.x), c.q, bsel);
-                c.h = __builtin_amdgcn_perm(quant_i8(Y.y), c.h, bsel);
-            } else {
+            {  // e4m3
                 const uint32_t w = e4m3_pair(Y.x, Y.y);
                 c.q = __builtin_amdgcn_perm(w, c.q, bsel);
                 c.h = __builtin_amdgcn_perm(w, c.h, bsel + (1u << (8 * (r & 3))));
