@@ -127,8 +127,14 @@ def test_apply_flags_and_pair_counts_bit_exact(prec, S):
     plan.apply_flags(flags, None, keep_only)  # the keep-words-only kernel
     counts = torch.zeros(plan.C * plan.P, dtype=torch.int32, device="cuda")
     plan.pair_counts(keep, counts)
+    # flags not 8-byte aligned: the keep-only call falls back to the zeroing kernel's keep mode
+    fbuf = torch.zeros(flags.numel() + 1, dtype=torch.uint8, device="cuda")
+    fbuf[1:] = flags.reshape(-1)
+    keep_odd = plan.alloc("keep")
+    plan.apply_flags(fbuf[1:], None, keep_odd)
     torch.cuda.synchronize()
     assert torch.equal(keep_only, keep)
+    assert torch.equal(keep_odd, keep)
     # zeroed spectra, read back through the layout
     back = corr.unpack_spectra(spec, prec, S, plan.C, T)
     if prec == corr.INT8:
