@@ -374,8 +374,7 @@ corr_status corr_xengine(corr_plan_t *p, const void *d_spec, const uint32_t *d_k
                                   p->splits, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(p, e, "X-engine launch");
     if (d_counts) {
-        e = launch_pair_counts(d_keep, reinterpret_cast<const uint16_t *>(p->d_ws + p->ws.pairs), p->d.n_signals,
-                               (int)p->d.n_spectra, p->M, d_counts, (hipStream_t)stream);
+        e = launch_pair_counts(d_keep, p->d.n_signals, (int)p->d.n_spectra, p->M, d_counts, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(p, e, "pair-count launch");
     }
     p->acc_spectra += p->d.n_spectra;
@@ -554,8 +553,8 @@ corr_status corr_pair_counts(corr_plan_t *p, const uint32_t *d_keep, int32_t *d_
     if (!d_keep || !d_counts) return fail(p, CORR_ERR_NULL, "d_keep and d_counts are required");
     if (!p->bound) return fail(p, CORR_ERR_WORKSPACE, "no workspace bound");
     if (!aligned(d_keep, 4) || !aligned(d_counts, 4)) return fail(p, CORR_ERR_ALIGN, "4-byte alignment");
-    hipError_t e = launch_pair_counts(d_keep, reinterpret_cast<const uint16_t *>(p->d_ws + p->ws.pairs),
-                                      p->d.n_signals, (int)p->d.n_spectra, p->M, d_counts, (hipStream_t)stream);
+    hipError_t e = launch_pair_counts(d_keep, p->d.n_signals, (int)p->d.n_spectra, p->M, d_counts,
+                                      (hipStream_t)stream);
     return e == hipSuccess ? CORR_OK : hip_fail(p, e, "pair-count launch");
 }
 

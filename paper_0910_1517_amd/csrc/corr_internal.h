@@ -186,8 +186,7 @@ hipError_t launch_mad_flag(const void *power, bool f16, int S, int T, int C, flo
                            hipStream_t st);
 hipError_t launch_apply_flags(int precision, const uint8_t *flags, void *spec, uint32_t *keep, int S, int T,
                               int C, hipStream_t st);
-hipError_t launch_pair_counts(const uint32_t *keep, const uint16_t *pairs, int S, int T, int C, int32_t *counts,
-                              hipStream_t st);
+hipError_t launch_pair_counts(const uint32_t *keep, int S, int T, int C, int32_t *counts, hipStream_t st);
 
 // Ascending bitonic sort of n (power of two, <= blockDim.x) floats in LDS;
 // every thread of the block must call it.

@@ -261,56 +261,110 @@ __global__ void __launch_bounds__(256) keep_words_kernel(const uint8_t *__restri
     dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
 }
 
-// counts[k][p] += popcount over time of keep_i & keep_j; one channel per
-// workgroup, the keep words of all signals staged in LDS 256 words at a time.
-// The 8 channels of a block share every 32-byte piece of the keep words, so
-// they are given to 8 workgroups that run side by side on one XCD (workgroups
-// are dealt to the 8 XCDs in turn) and share its L2: workgroup b takes channel
-// block 8 (b / 64) + b mod 8 and channel (b / 8) mod 8 in it when C is a
-// multiple of 64, else channel b.
-__global__ void __launch_bounds__(256) pair_counts_kernel(const uint32_t *__restrict__ keep,
-                                                          const uint16_t *__restrict__ pairs, int S, int T,
+// counts[k][p] += number of spectra where neither signal of pair p = (i, j)
+// is flagged: the Gram matrix of the keep bits, G = B B^T with B[s][m] the
+// keep bit of signal s in spectrum m (0 or 1), taken on the int8 matrix cores
+// (v_mfma_i32_32x32x32_i8: exact int32 sums).  One wave per channel, the 8
+// waves of a workgroup on the 8 channels of a channel block, which share every
+// 32-byte piece of the keep words.  Lane l holds signals 32 a + (l mod 32)
+// (a = 0, 1) and the spectra 16 (l / 32) ... + 15 of each 32-spectrum keep
+// word, spread into 16 bytes of 0 / 1; the A and B operands are the same
+// registers, so each product pairs the same spectrum of both signals whatever
+// order the hardware gives K inside a lane.  Signals at or past S read as
+// flagged everywhere.
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v16i_t __attribute__((ext_vector_type(16)));
+
+__device__ inline v4i_t spread16(uint32_t x) {  // bit i of x -> byte i (0 or 1)
+    v4i_t r;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) r[d] = (int)((((x >> (4 * d)) & 15u) * 0x00204081u) & 0x01010101u);
+    return r;
+}
+
+// The keep words of a channel block are contiguous: spans of 32 spectra, each
+// S x 8 words.  The workgroup stages them PKB spans at a time in LDS (16-byte
+// loads over all its threads, the next batch in flight during the products)
+// at a padded place [span][signal][12] (8 words and a pad of 4).
+constexpr int PKB = 8;
+
+__global__ void __launch_bounds__(512) pair_counts_kernel(const uint32_t *__restrict__ keep, int S, int T,
                                                           int32_t *counts) {
-    // rows of 256 + 4 words: 16-byte reads of four words, and lanes whose
-    // signals differ by less than 16 fall on distinct banks
-    __shared__ __align__(16) uint32_t kw[kMaxSignals][256 + 4];
-    const int b = blockIdx.x;
-    const int k = (gridDim.x & 63) ? b : 8 * (8 * (b >> 6) + (b & 7)) + ((b >> 3) & 7);
-    const int t = threadIdx.x;
+    __shared__ __align__(16) uint32_t lk[2][PKB * kMaxSignals * 12];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, col = lane & 31, hf = lane >> 5;
+    const int kb = blockIdx.x, k = 8 * kb + wv;
     const int W = T / 32;
-    const int P = S * (S + 1) / 2;
-    int32_t cnt[9];  // pairs t, t + 256, ... (P <= 2080 < 9 * 256)
+    if (W <= 0) return;
+    const int64_t P = (int64_t)S * (S + 1) / 2;
+    const uint4 *src = reinterpret_cast<const uint4 *>(keep + (int64_t)kb * W * S * 8);
+    const int nb = (W + PKB - 1) / PKB, nu = PKB * S * 2;  // batches; 16-byte units per batch (<= 1024)
+    uint4 stg[2];
+    auto fetch = [&](int b) {  // units past the last span read as zero
+        const int nv = min(PKB, W - PKB * b) * S * 2;
+        const uint4 *bs = src + (int64_t)b * nu;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) cnt[q] = 0;
-    for (int w0 = 0; w0 < W; w0 += 256) {
-        const int nw = min(256, W - w0);
-        const int nw4 = (nw + 3) & ~3;  // words past nw are staged as zero
-        __syncthreads();
-        for (int i = t; i < S * nw4; i += 256) {
-            const int s = i % S, w = i / S;
-            kw[s][w] = w < nw ? keep[(((int64_t)(k >> 3) * W + w0 + w) * S + s) * 8 + (k & 7)] : 0u;
+        for (int e = 0; e < 2; ++e) {
+            const int u = tid + 512 * e;
+            stg[e] = u < nv ? bs[u] : make_uint4(0u, 0u, 0u, 0u);
         }
-        __syncthreads();
+    };
+    auto put = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const int p = t + 256 * q;
-            if (p < P) {
-                const int i = pairs[2 * p], j = pairs[2 * p + 1];
-                const uint4 *a = reinterpret_cast<const uint4 *>(kw[i]);
-                const uint4 *c = reinterpret_cast<const uint4 *>(kw[j]);
-                int32_t n = 0;
-                for (int w = 0; w < nw4 / 4; ++w) {
-                    const uint4 x = a[w], y = c[w];
-                    n += __popc(x.x & y.x) + __popc(x.y & y.y) + __popc(x.z & y.z) + __popc(x.w & y.w);
-                }
-                cnt[q] += n;
+        for (int e = 0; e < 2; ++e) {
+            const int u = tid + 512 * e;
+            if (u < nu) {
+                const int q = u / (2 * S), r = u - q * 2 * S;
+                *reinterpret_cast<uint4 *>(&lk[buf][(q * kMaxSignals + (r >> 1)) * 12 + 4 * (r & 1)]) = stg[e];
             }
+        }
+    };
+    // lanes past S read signal 0's place and mask the word off
+    const uint32_t m0 = col < S ? ~0u : 0u, m1 = 32 + col < S ? ~0u : 0u;
+    const int o0 = (col < S ? col : 0) * 12 + wv, o1 = (32 + col < S ? 32 + col : 0) * 12 + wv;
+    v16i_t g00 = {}, g01 = {}, g11 = {};
+    fetch(0);
+    put(0);
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+        if (b + 1 < nb) fetch(b + 1);
+        const uint32_t *L = lk[b & 1];
+#pragma unroll
+        for (int q = 0; q < PKB; ++q) {
+            const uint32_t x0 = L[q * kMaxSignals * 12 + o0] & m0, x1 = L[q * kMaxSignals * 12 + o1] & m1;
+            const v4i_t b0 = spread16(x0 >> (16 * hf)), b1 = spread16(x1 >> (16 * hf));
+            g00 = __builtin_amdgcn_mfma_i32_32x32x32_i8(b0, b0, g00, 0, 0, 0);
+            g01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(b0, b1, g01, 0, 0, 0);
+            g11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(b1, b1, g11, 0, 0, 0);
+        }
+        // the other buffer was last read in batch b - 1, before the barrier that ended it
+        if (b + 1 < nb) put((b + 1) & 1);
+        __syncthreads();
+    }
+    // accumulator r of lane l: row 8 (r / 4) + 4 (l / 32) + r mod 4 (signal i of
+    // the A tile), column l mod 32 (signal j of the B tile); pair j (j + 1) / 2 + i
+    // All 48 of a lane's counts are read before any is written back (distinct
+    // pairs: a read-add-write chain per count would wait out the memory latency
+    // 48 times); a lane's slots outside the triangle or past S are left alone.
+    int32_t *out = counts + (int64_t)k * P;
+    const v16i_t *g[3] = {&g00, &g01, &g11};
+    int32_t old[3][16];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int ta = t == 2, j = 32 * (t > 0) + col;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 32 * ta + 8 * (r >> 2) + 4 * hf + (r & 3);
+            old[t][r] = (i <= j && j < S) ? out[j * (j + 1) / 2 + i] : 0;
         }
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const int p = t + 256 * q;
-        if (p < P) counts[(int64_t)k * P + p] += cnt[q];
+    for (int t = 0; t < 3; ++t) {
+        const int ta = t == 2, j = 32 * (t > 0) + col;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 32 * ta + 8 * (r >> 2) + 4 * hf + (r & 3);
+            if (i <= j && j < S) out[j * (j + 1) / 2 + i] = old[t][r] + (*g[t])[r];
+        }
     }
 }
 
@@ -343,9 +397,8 @@ hipError_t launch_apply_flags(int precision, const uint8_t *flags, void *spec, u
     return hipGetLastError();
 }
 
-hipError_t launch_pair_counts(const uint32_t *keep, const uint16_t *pairs, int S, int T, int C, int32_t *counts,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(pair_counts_kernel, dim3(C), dim3(256), 0, st, keep, pairs, S, T, counts);
+hipError_t launch_pair_counts(const uint32_t *keep, int S, int T, int C, int32_t *counts, hipStream_t st) {
+    hipLaunchKernelGGL(pair_counts_kernel, dim3(C / 8), dim3(512), 0, st, keep, S, T, counts);
     return hipGetLastError();
 }
 
