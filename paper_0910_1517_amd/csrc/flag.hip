@@ -212,17 +212,16 @@ __global__ void __launch_bounds__(256) apply_keep_kernel(const uint8_t *__restri
     }
 }
 
-// Keep words alone, when no spectra are to be zeroed.  Thread t of a
-// workgroup takes 8 consecutive channels of one signal and one span of 32
-// spectra: one 8-byte load per spectrum row, whose 8 flag bytes are reduced to
-// their top bits (set when the byte is nonzero) and gathered, 8 rows at a time,
-// as bit i of every byte; the 4 gathered words per 4 channels are then
-// transposed bytewise into the channels' 32-bit words.  The 8 words are
-// contiguous in the keep layout and leave as two 16-byte stores.  The 4 lanes
-// t = 4 c + s' (s' < 4) take signals 4 (block) + s' of the same channels, so
-// the 4 x 32 bytes they store fill one 128-byte line: keep words leave L2 as
-// whole lines.  A workgroup covers 4 signals x 512 channels x 32 spectra.
-// Needs flags 8-byte and keep 16-byte aligned (the caller checks).
+// Keep words alone, when no spectra are to be zeroed.  Wave w of a workgroup
+// takes signal 4 (block) + w, lane l the 16 channels 16 l ... + 15 of a
+// 1024-channel chunk, and one span of 32 spectra: one 16-byte load per
+// spectrum row (a wave reads 1 KB of the row), whose flag bytes are reduced to
+// their top bits (set when the byte is nonzero) and gathered, 8 rows at a
+// time, as bit i of every byte; the 4 gathered words per 4 channels are then
+// transposed bytewise into the channels' 32-bit words.  A lane's 16 words are
+// two runs of 8 contiguous words in the keep layout (16-byte stores), and the
+// 4 waves' runs for the same channels fill whole 128-byte lines.  Needs flags
+// 16-byte and keep 16-byte aligned (the caller checks).
 __device__ inline uint32_t flagged_bytes(uint32_t v) {  // top bit of each byte: byte != 0
     return (((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u;
 }
@@ -231,34 +230,40 @@ __device__ inline uint32_t byte_of(uint32_t a, int j) { return (a >> (8 * j)) & 
 
 __global__ void __launch_bounds__(256) keep_words_kernel(const uint8_t *__restrict__ flags,
                                                          uint32_t *__restrict__ keep, int S, int T, int C) {
-    const int nkb = (C + 511) / 512, W = T / 32;
+    const int nkb = (C + 1023) / 1024, W = T / 32;
     const int kblk = blockIdx.x % nkb;
     const int w = (blockIdx.x / nkb) % W;
-    const int s = 4 * (int)(blockIdx.x / (nkb * W)) + (int)(threadIdx.x & 3);
-    const int k = (kblk * 64 + (int)(threadIdx.x >> 2)) * 8;
+    const int s = 4 * (int)(blockIdx.x / (nkb * W)) + (int)(threadIdx.x >> 6);
+    const int k = kblk * 1024 + 16 * (int)(threadIdx.x & 63);
     if (k >= C || s >= S) return;
     const uint8_t *f = flags + ((int64_t)s * T + (int64_t)w * 32) * C + k;
-    uint32_t a[2][4];  // a[h][g]: byte j = flag bits of spectra 8 g ... 8 g + 7 of channel k + 4 h + j
+    uint32_t a[4][4];  // a[h][g]: byte j = flag bits of spectra 8 g ... 8 g + 7 of channel k + 4 h + j
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        a[0][g] = a[1][g] = 0u;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) a[h][g] = 0u;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const uint2 v = *reinterpret_cast<const uint2 *>(f + (int64_t)(8 * g + i) * C);
+            const uint4 v = *reinterpret_cast<const uint4 *>(f + (int64_t)(8 * g + i) * C);
             a[0][g] |= flagged_bytes(v.x) >> (7 - i);
             a[1][g] |= flagged_bytes(v.y) >> (7 - i);
+            a[2][g] |= flagged_bytes(v.z) >> (7 - i);
+            a[3][g] |= flagged_bytes(v.w) >> (7 - i);
         }
     }
-    uint32_t o[8];
+    uint32_t o[16];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < 4; ++h)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             o[4 * h + j] = ~(byte_of(a[h][0], j) | byte_of(a[h][1], j) << 8 | byte_of(a[h][2], j) << 16 |
                              byte_of(a[h][3], j) << 24);
-    uint4 *dst = reinterpret_cast<uint4 *>(keep + (((int64_t)(k >> 3) * W + w) * S + s) * 8);
-    dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
-    dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {  // channels k + 8 e ... + 7
+        uint4 *dst = reinterpret_cast<uint4 *>(keep + ((((int64_t)(k >> 3) + e) * W + w) * S + s) * 8);
+        dst[0] = make_uint4(o[8 * e], o[8 * e + 1], o[8 * e + 2], o[8 * e + 3]);
+        dst[1] = make_uint4(o[8 * e + 4], o[8 * e + 5], o[8 * e + 6], o[8 * e + 7]);
+    }
 }
 
 // counts[k][p] += number of spectra where neither signal of pair p = (i, j)
@@ -384,8 +389,8 @@ hipError_t launch_mad_flag(const void *power, bool f16, int S, int T, int C, flo
 
 hipError_t launch_apply_flags(int precision, const uint8_t *flags, void *spec, uint32_t *keep, int S, int T,
                               int C, hipStream_t st) {
-    if (!spec && !(reinterpret_cast<uintptr_t>(flags) & 7) && !(reinterpret_cast<uintptr_t>(keep) & 15)) {
-        const dim3 grid((unsigned)((int64_t)((S + 3) / 4) * (T / 32) * ((C + 511) / 512)));
+    if (!spec && !(reinterpret_cast<uintptr_t>(flags) & 15) && !(reinterpret_cast<uintptr_t>(keep) & 15)) {
+        const dim3 grid((unsigned)((int64_t)((S + 3) / 4) * (T / 32) * ((C + 1023) / 1024)));
         hipLaunchKernelGGL(keep_words_kernel, grid, dim3(256), 0, st, flags, keep, S, T, C);
         return hipGetLastError();
     }

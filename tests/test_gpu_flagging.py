@@ -151,6 +151,24 @@ def test_apply_flags_and_pair_counts_bit_exact(prec, S):
     assert np.array_equal(bits.transpose(1, 2, 0), (fl == 0).astype(np.uint32))
 
 
+@pytest.mark.parametrize("S,T", [(1, 96), (33, 96), (64, 32), (40, 288)])
+def test_pair_counts_edge_shapes(S, T):
+    """Pair counts (the keep bits' Gram matrix on the matrix cores) at one
+    signal, one past a 32-signal tile, a single span of 32 spectra, and span
+    counts that leave a partial staging batch; counts accumulate (+=)."""
+    import torch
+    print("pair counts", S, T, flush=True)
+    plan = corr.Plan(S, 512, T, precision=corr.INT8)
+    g = synth.rng(61, S, T)
+    fl = (g.random((S, T, plan.C)) < 0.2).astype(np.uint8)
+    keep = plan.alloc("keep")
+    plan.apply_flags(torch.from_numpy(fl).cuda(), None, keep)
+    counts = torch.full((plan.C * plan.P,), 7, dtype=torch.int32, device="cuda")
+    plan.pair_counts(keep, counts)
+    torch.cuda.synchronize()
+    assert np.array_equal(counts.cpu().numpy().reshape(plan.C, plan.P), oracle.pair_counts(fl) + 7)
+
+
 def test_flagged_int8_visibilities_bit_exact():
     import torch
     S, T = 8, 512
