@@ -64,13 +64,15 @@ __device__ inline float wave_mad64_sorted(float y, float med, int lane, float *b
 // One tile (signal s, spectra m0..m0+63, channels k0..k0+255) per workgroup.
 // Eq. 3 / Eq. 4 on the 64 row means and the 256 column means:
 // flag[i] = |x_i - med| > M MAD / 0.6745, the median of an even count being
-// the mean of the two middle values.  One wave sorts the row statistic while
-// another sorts the column statistic; the MADs come from the sorted values.
+// the mean of the two middle values.  The tile is summed as it is loaded
+// (nothing of it is staged): wave w holds rows w + 4 i (i < 16), lane l
+// columns 4 l ... 4 l + 3; column sums go through LDS, row sums are reduced
+// across the wave.  One wave sorts the row statistic while another sorts the
+// column statistic; the MADs come from the sorted values.
 template <typename PT>
 __global__ void __launch_bounds__(KT) mad_tile_kernel(const PT *__restrict__ power, int S, int T, int C,
                                                       float M, uint8_t *flags) {
-    __shared__ float tile[TT][KT + 1];
-    __shared__ float rowp[KT / TT][TT];
+    __shared__ float colp[KT / 64][KT];  // column partial sums of each wave's 16 rows
     __shared__ float rowv[TT], colv[KT], rdev[TT], cdev[KT];
     __shared__ float sel[2];  // MAD of the rows, MAD of the columns
     __shared__ __align__(16) float srt[TT + KT];  // sorted row / column statistics
@@ -81,41 +83,53 @@ __global__ void __launch_bounds__(KT) mad_tile_kernel(const PT *__restrict__ pow
     const int kt = b % ntk, mt = (b / ntk) % ntm, s = b / (ntk * ntm);
     const int t = threadIdx.x;
     const int64_t tbase = ((int64_t)s * T + (int64_t)mt * TT) * C + (int64_t)kt * KT;  // tile corner
-    {  // columns 4 (t mod 64) .. + 3 of rows t / 64 + 4 i: 16-byte (FP32) or 8-byte (FP16) loads
+    {
         const int cq = t & 63, r0 = t >> 6;
+        float4 v[TT / 4];  // rows r0 + 4 i: 16-byte (FP32) or 8-byte (FP16) loads, all issued first
 #pragma unroll
         for (int i = 0; i < TT / 4; ++i) {
-            const int r = r0 + 4 * i;
-            const PT *src = power + tbase + (int64_t)r * C + 4 * cq;
-            float4 v;
+            const PT *src = power + tbase + (int64_t)(r0 + 4 * i) * C + 4 * cq;
             if constexpr (sizeof(PT) == 4) {
-                v = *reinterpret_cast<const float4 *>(src);
+                v[i] = *reinterpret_cast<const float4 *>(src);
             } else {
                 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
                 const h4 w = *reinterpret_cast<const h4 *>(src);
-                v = make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
+                v[i] = make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
             }
-            tile[r][4 * cq + 0] = v.x;
-            tile[r][4 * cq + 1] = v.y;
-            tile[r][4 * cq + 2] = v.z;
-            tile[r][4 * cq + 3] = v.w;
+        }
+        float4 cs = make_float4(0.f, 0.f, 0.f, 0.f);
+        float rp[TT / 4];
+#pragma unroll
+        for (int i = 0; i < TT / 4; ++i) {
+            cs.x += v[i].x;
+            cs.y += v[i].y;
+            cs.z += v[i].z;
+            cs.w += v[i].w;
+            rp[i] = (v[i].x + v[i].y) + (v[i].z + v[i].w);
+        }
+        *reinterpret_cast<float4 *>(&colp[r0][4 * cq]) = cs;
+        // row sums: halve the set of rows at each exchange (lane bit 5 keeps rows
+        // 8 .. 15 of 16, bit 4 the upper half of the rest, ...), then sum the last
+        // one over lane bits 1 and 0; lane l ends with row i = 8 b5 + 4 b4 + 2 b3 + b2
+        const int lane = t & 63;
+#pragma unroll
+        for (int h = 8, bit = 32; h >= 1; h >>= 1, bit >>= 1) {
+            const bool up = (lane & bit) != 0;
+#pragma unroll
+            for (int i = 0; i < h; ++i) {
+                const float send = up ? rp[i] : rp[i + h], keep = up ? rp[i + h] : rp[i];
+                rp[i] = keep + __shfl_xor(send, bit);
+            }
+        }
+        rp[0] += __shfl_xor(rp[0], 2);
+        rp[0] += __shfl_xor(rp[0], 1);
+        if ((lane & 3) == 0) {
+            const int i = 8 * ((lane >> 5) & 1) + 4 * ((lane >> 4) & 1) + 2 * ((lane >> 3) & 1) + ((lane >> 2) & 1);
+            rowv[r0 + 4 * i] = rp[0] / (float)KT;
         }
     }
     __syncthreads();
-    {
-        float cs = 0.f;
-        for (int r = 0; r < TT; ++r) cs += tile[r][t];
-        colv[t] = cs / (float)TT;
-    }
-    __syncthreads();
-    {  // partial row sums: row t mod 64 over a quarter of the columns
-        const int r = t % TT, q = t / TT;
-        float rs = 0.f;
-        for (int k = 0; k < TT; ++k) rs += tile[r][q * TT + k];
-        rowp[q][r] = rs;
-    }
-    __syncthreads();
-    if (t < TT) rowv[t] = (rowp[0][t] + rowp[1][t] + rowp[2][t] + rowp[3][t]) / (float)KT;
+    colv[t] = (colp[0][t] + colp[1][t] + colp[2][t] + colp[3][t]) / (float)TT;
     __syncthreads();
     // Eq. 3 on the rows (wave 0) and on the columns (wave 1), side by side
     const int lane = t & 63, wv = t >> 6;
