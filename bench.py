@@ -65,10 +65,11 @@ MEASURED_TRAFFIC = {
     "fengine_fp32_c2": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
                         "sha256": "b6d39bb895f23bd84c3355b5a0b9ceaa9b644c91a7262f4f377014737ec3f44c",
                         "read": 1.101e9, "write": 4.295e9},
-    # profiles/cnn_flagged_64sig_8192pt_8192spec.md (FP16 power, column guard): FETCH_SIZE 2097377 KiB x 2.000,
-    # WRITE_SIZE 2097152 KiB
+    # profiles/cnn_flagged_64sig_8192pt_8192spec.md (FP16 power, column guard, max-ilp schedule): FETCH_SIZE
+    # 2097368 KiB x 2.000, WRITE_SIZE 2097152 KiB
     "cnn_infer_c5": {"source": "paper_0910_1517_amd/csrc/cnn.hip",
                      "sha256": "262fd32417682dd772bc249c879504260bc82e884cae8115691124ba211a5e03",
+                     "flags": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
                      "read": 4.295e9, "write": 2.147e9},
     # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4197483 KiB x 2.000, WRITE_SIZE 1572864 KiB x 1.000
     "beam_int8_c3": {"source": "paper_0910_1517_amd/csrc/beam.hip",

@@ -22,10 +22,13 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 # per-source flags: the four-step F-engine keeps its matrix-core results in
 # ordinary VGPRs (no accumulation-register reads between the MFMAs and the VALU
-# work that consumes them), and is scheduled for instruction-level parallelism
-# (measured 1-3% faster than the default occupancy-first schedule, with every
-# launched instantiation still at 3 waves per SIMD and free of spills)
-EXTRA = {"fengine4.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form", "-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+# work that consumes them); it and the CNN inference kernel are scheduled for
+# instruction-level parallelism (measured 1-3% faster than the default
+# occupancy-first schedule, with the same occupancy and no spills; the
+# LDS-radix F-engine measured 1.7% slower with it and the X-engine no
+# different, so they keep the default)
+ILP = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
+EXTRA = {"fengine4.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form", *ILP], "cnn.hip": list(ILP)}
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:
