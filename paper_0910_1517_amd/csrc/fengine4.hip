@@ -50,6 +50,7 @@
 //     e4m3 re + im, or 2 complex64) before storing it.
 // Calibration mode (scale COMPUTE) sums |X|^2 per channel instead of steps 5-6.
 #include <cmath>
+#include <type_traits>
 
 #include "corr_internal.h"
 
@@ -117,19 +118,25 @@ __device__ __forceinline__ void dft4(float2 &u0, float2 &u1, float2 &u2, float2 
     u3 = csub(d0, d1);
 }
 
-// 8-point DFT (forward sign), natural output order
+// 8-point DFT (forward sign), natural output order.  The odd half takes
+// b1 W8, b2 W8^2 = -i b2 and b3 W8^3 (W8 = (1 - i) / sqrt 2); the 1 / sqrt 2
+// of b1 and b3 is applied once, to their sum and difference, inside the last
+// additions (fused multiply-adds).
 __device__ __forceinline__ void dft8(float2 *v) {
     float2 a0 = cadd(v[0], v[4]), b0 = csub(v[0], v[4]);
     float2 a1 = cadd(v[1], v[5]), b1 = csub(v[1], v[5]);
     float2 a2 = cadd(v[2], v[6]), b2 = csub(v[2], v[6]);
     float2 a3 = cadd(v[3], v[7]), b3 = csub(v[3], v[7]);
-    b1 = make_float2((b1.x + b1.y) * kRsqrt2, (b1.y - b1.x) * kRsqrt2);
-    b2 = mul_mi(b2);
-    b3 = make_float2((b3.y - b3.x) * kRsqrt2, -(b3.x + b3.y) * kRsqrt2);
     dft4(a0, a1, a2, a3);
-    dft4(b0, b1, b2, b3);
-    v[0] = a0; v[1] = b0; v[2] = a1; v[3] = b1;
-    v[4] = a2; v[5] = b2; v[6] = a3; v[7] = b3;
+    const float2 B1 = make_float2(b1.x + b1.y, b1.y - b1.x);     // b1 (1 - i)
+    const float2 B3 = make_float2(b3.y - b3.x, -(b3.x + b3.y));  // b3 (-1 - i)
+    const float2 s0 = cadd(b0, mul_mi(b2)), d0 = csub(b0, mul_mi(b2));
+    const float2 S = cadd(B1, B3), D = mul_mi(csub(B1, B3));
+    v[0] = a0; v[2] = a1; v[4] = a2; v[6] = a3;
+    v[1] = make_float2(fmaf(kRsqrt2, S.x, s0.x), fmaf(kRsqrt2, S.y, s0.y));
+    v[5] = make_float2(fmaf(-kRsqrt2, S.x, s0.x), fmaf(-kRsqrt2, S.y, s0.y));
+    v[3] = make_float2(fmaf(kRsqrt2, D.x, d0.x), fmaf(kRsqrt2, D.y, d0.y));
+    v[7] = make_float2(fmaf(-kRsqrt2, D.x, d0.x), fmaf(-kRsqrt2, D.y, d0.y));
 }
 
 template <int R>
@@ -244,47 +251,46 @@ struct Chan {
 
 // Phase, requantisation and corner turn of channel k's value X in spectrum r of
 // the slot; chunk is the channel's 16-byte X-layout chunk of this spectrum group.
-template <int BM>
+// INT8 / FP8: the codes go into byte r mod 4 of a pair of words.  H = 0 or 1
+// (the caller knows which half of the chunk spectrum r is in): the first
+// (spectra 0..3 of the chunk) or second (4..7) pair, the chunk stored whole by
+// the caller after its eighth spectrum.  H = -1: the pair in progress, copied
+// aside after the fourth spectrum and the chunk stored here after the eighth.
+template <int BM, int H>
 __device__ __forceinline__ void emit(Chan &c, float2 X, float2 rot, int r, uint32_t bsel, bool active, uint4 *chunk) {
     if constexpr (BM == 3) {
         c.pacc += X.x * X.x + X.y * X.y;
         return;
-    } else {
-        if constexpr (BM == 1) {
-            // int8: the codes plus 128 (formed inside the last products) go into byte
-            // r mod 4 of the words in progress; the chunk's store takes the 128 off
-            const float2 t = cmul(X, c.ramp);
-            c.q = put_i8_biased(fmaf(t.x, rot.x, fmaf(-t.y, rot.y, 128.0f)), r & 3, c.q);
-            c.h = put_i8_biased(fmaf(t.x, rot.y, fmaf(t.y, rot.x, 128.0f)), r & 3, c.h);
-            if ((r & 7) == 3) {
-                c.q0 = c.q;
-                c.h0 = c.h;
-            } else if ((r & 7) == 7 && active) {
-                *chunk = make_uint4(c.q0 ^ kI8Bias, c.q ^ kI8Bias, c.h0 ^ kI8Bias, c.h ^ kI8Bias);
-            }
-            return;
-        }
+    } else if constexpr (BM == 0) {
         const float2 Y = cmul(cmul(X, c.ramp), rot);
-        if constexpr (BM == 0) {
-            if (r & 1) {
-                if (active) *reinterpret_cast<float4 *>(chunk) = make_float4(c.f0.x, c.f0.y, Y.x, Y.y);
-            } else {
-                c.f0 = Y;
-            }
+        if (r & 1) {
+            if (active) *reinterpret_cast<float4 *>(chunk) = make_float4(c.f0.x, c.f0.y, Y.x, Y.y);
         } else {
-            {  // e4m3
-                const uint32_t w = e4m3_pair(Y.x, Y.y);
-                c.q = __builtin_amdgcn_perm(w, c.q, bsel);
-                c.h = __builtin_amdgcn_perm(w, c.h, bsel + (1u << (8 * (r & 3))));
-            }
-            // the chunk holds the re bytes of its 8 spectra, then their im bytes: it is
-            // stored whole, once, after its last spectrum (a half written four spectra
+            c.f0 = Y;
+        }
+    } else {
+        uint32_t &q = H == 0 ? c.q0 : c.q, &h = H == 0 ? c.h0 : c.h;
+        if constexpr (BM == 1) {
+            // int8: the codes plus 128 (formed inside the last products); the chunk's
+            // store takes the 128 off
+            const float2 t = cmul(X, c.ramp);
+            q = put_i8_biased(fmaf(t.x, rot.x, fmaf(-t.y, rot.y, 128.0f)), r & 3, q);
+            h = put_i8_biased(fmaf(t.x, rot.y, fmaf(t.y, rot.x, 128.0f)), r & 3, h);
+        } else {  // e4m3
+            const float2 Y = cmul(cmul(X, c.ramp), rot);
+            const uint32_t w = e4m3_pair(Y.x, Y.y);
+            q = __builtin_amdgcn_perm(w, q, bsel);
+            h = __builtin_amdgcn_perm(w, h, bsel + (1u << (8 * (r & 3))));
+        }
+        if constexpr (H < 0) {
+            // a chunk's two halves are stored together (a half written four spectra
             // before the other leaves L2 twice)
             if ((r & 7) == 3) {
                 c.q0 = c.q;
                 c.h0 = c.h;
             } else if ((r & 7) == 7 && active) {
-                *chunk = make_uint4(c.q0, c.q, c.h0, c.h);
+                constexpr uint32_t B = BM == 1 ? kI8Bias : 0u;
+                *chunk = make_uint4(c.q0 ^ B, c.q ^ B, c.h0 ^ B, c.h ^ B);
             }
         }
     }
@@ -446,8 +452,9 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
         return (uint32_t)((((k >> 3) * a.S + s) << 3) + (k & 7));
     };
 
-#pragma unroll 1
-    for (int r = 0; r < SPS; ++r) {
+    // one spectrum r of the slot; H: the half of the INT8 / FP8 chunk it fills
+    auto spectrum = [&](const int r, auto hsel) __attribute__((always_inline)) {
+        constexpr int H = decltype(hsel)::value;
         // 1. stage the window bytes (buffer r mod 2: its last reader, stage A two
         //    spectra back, is behind the barriers of the previous spectrum), then
         //    fetch the next window
@@ -523,7 +530,7 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
                 const int k = chan(o);
                 const float2 X = q < RL / 2 ? z[o] : make_float2(z[o].x, -z[o].y);
                 if (PW && c_active) store_power(((int64_t)s * a.T + mc) * M + k, X.x * X.x + X.y * X.y);
-                emit<BM>(ch[o], X, rot_c, r, bsel, c_active, gbase_c + chunk_base(k));
+                emit<BM, H>(ch[o], X, rot_c, r, bsel, c_active, gbase_c + chunk_base(k));
             }
         }
         // column 0's outputs are written by threads tid < J and unfolded by threads
@@ -550,11 +557,38 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
             // column 0 unfolds 2 X: power and the calibration sum take |X|^2 = |2 X|^2 / 4
             if constexpr (BM != 3) {
                 if (PW && s_active) store_power(((int64_t)s * a.T + ms) * M + ch_s, 0.25f * (X.x * X.x + X.y * X.y));
-                emit<BM>(ch[8], X, rot_s, r, bsel, s_active, gbase_s + chunk_base(ch_s));
+                emit<BM, H>(ch[8], X, rot_s, r, bsel, s_active, gbase_s + chunk_base(ch_s));
             } else {
                 ch[8].pacc += 0.25f * (X.x * X.x + X.y * X.y);
             }
         }
+    };
+    if constexpr ((BM == 1 || BM == 2) && PW == 0) {
+        // spectra in chunks of 8: the first 4 fill one pair of words, the next 4
+        // the other (which pair is a constant of each loop), then every chunk is
+        // stored whole.  (With power cells the copy of the loop body for each
+        // half does not fit the registers; those launches keep one loop.)
+        constexpr uint32_t B = BM == 1 ? kI8Bias : 0u;
+#pragma unroll 1
+        for (int r8 = 0; r8 < SPS; r8 += 8) {
+#pragma unroll 1
+            for (int r = r8; r < r8 + 4; ++r) spectrum(r, std::integral_constant<int, 0>{});
+#pragma unroll 1
+            for (int r = r8 + 4; r < r8 + 8; ++r) spectrum(r, std::integral_constant<int, 1>{});
+            if (cp != 0 && c_active) {
+                uint4 *gb = reinterpret_cast<uint4 *>(a.spec) + (int64_t)((m_c0 + r8) / G) * M * a.S;
+#pragma unroll
+                for (int o = 0; o < 8; ++o)
+                    gb[chunk_base(chan(o))] = make_uint4(ch[o].q0 ^ B, ch[o].q ^ B, ch[o].h0 ^ B, ch[o].h ^ B);
+            }
+            if (tid < C::NSPEC && s_active) {
+                uint4 *gb = reinterpret_cast<uint4 *>(a.spec) + (int64_t)((m_s0 + r8) / G) * M * a.S;
+                gb[chunk_base(ch_s)] = make_uint4(ch[8].q0 ^ B, ch[8].q ^ B, ch[8].h0 ^ B, ch[8].h ^ B);
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int r = 0; r < SPS; ++r) spectrum(r, std::integral_constant<int, -1>{});
     }
 
     if constexpr (BM == 3) {
