@@ -385,15 +385,23 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
         tws[v >> 1] = a.tw4[p * N1 + an1];
     }
 
-    // ---- column-transform thread mapping: column p, butterfly b of window slot bu
-    const int cp = tid / C::J;
-    const int cj = tid % C::J;
+    // ---- column-transform thread mapping: column p, butterfly b of window slot bu.
+    // The wave that holds column 0 (its outputs, their unfolding and the channels
+    // they give) issues more per spectrum than the other three, and wave w of a
+    // workgroup runs on one SIMD: that wave is wave wz, varied across workgroups
+    // so that the extra share falls on every SIMD alike.  ctid numbers the
+    // threads from wave wz on.
+    static_assert(WG == 256, "four waves per workgroup");
+    const int wz = (int)(((uint32_t)blockIdx.x * 0x9E3779B1u) >> 30);
+    const int ctid = (tid - 64 * wz) & (WG - 1);
+    const int cp = ctid / C::J;
+    const int cj = ctid % C::J;
     const int bu = cj / C::BPC, bb = cj % C::BPC;
     const int colo = (bu * 32 + cp) * C::CS;
-    const int nspec_u = tid / N1, nspec_j = tid % N1;  // column-0 channel 32 j (tid < NSPEC)
+    const int nspec_u = ctid / N1, nspec_j = ctid % N1;  // column-0 channel 32 j (ctid < NSPEC)
 
     // ---- output channels of this thread: 8 from column cp (none for cp = 0),
-    // plus channel 32 j of column 0 for tid < NSPEC
+    // plus channel 32 j of column 0 for ctid < NSPEC
     auto chan = [&](int o) -> int {
         const int u = o / RL, q = o % RL;
         const int k1 = bb + C::BPC * u + q * (N1 / RL);
@@ -407,7 +415,7 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
         c.q = c.h = c.q0 = c.h0 = 0u;
         c.f0 = make_float2(0.f, 0.f);
         c.pacc = 0.f;
-        const int k = o == 8 ? (tid < C::NSPEC ? ch_s : 0) : (cp == 0 ? 0 : chan(o));
+        const int k = o == 8 ? (ctid < C::NSPEC ? ch_s : 0) : (cp == 0 ? 0 : chan(o));
         // column 0 unfolds 2 X, so its ramp carries the factor 1/2 (exact)
         const float hf = o == 8 ? 0.5f : 1.0f;
         if constexpr (BM == 3) {
@@ -533,17 +541,12 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
                 emit<BM, H>(ch[o], X, rot_c, r, bsel, c_active, gbase_c + chunk_base(k));
             }
         }
-        // column 0's outputs are written by threads tid < J and unfolded by threads
-        // tid < NSPEC: both in wave 0 when the workgroup has 256 threads, where the
-        // wave's own LDS order suffices; otherwise across waves
-        if constexpr (WG == 256) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        } else {
-            __syncthreads();
-        }
-        if (tid < C::NSPEC) {
+        // column 0's outputs are written by threads ctid < J and unfolded by threads
+        // ctid < NSPEC, both in wave wz, where the wave's own LDS order suffices
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (ctid < C::NSPEC) {
             const int ms = m_s0 + r;
             const float2 U = lds_u[nspec_u * N1 + nspec_j];
             const float2 V = lds_u[nspec_u * N1 + ((N1 - nspec_j) & (N1 - 1))];
@@ -581,7 +584,7 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
                 for (int o = 0; o < 8; ++o)
                     gb[chunk_base(chan(o))] = make_uint4(ch[o].q0 ^ B, ch[o].q ^ B, ch[o].h0 ^ B, ch[o].h ^ B);
             }
-            if (tid < C::NSPEC && s_active) {
+            if (ctid < C::NSPEC && s_active) {
                 uint4 *gb = reinterpret_cast<uint4 *>(a.spec) + (int64_t)((m_s0 + r8) / G) * M * a.S;
                 gb[chunk_base(ch_s)] = make_uint4(ch[8].q0 ^ B, ch[8].q ^ B, ch[8].h0 ^ B, ch[8].h ^ B);
             }
@@ -602,7 +605,7 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
                 dst[M + chan(o)] = 0.f;
             }
         }
-        if (tid < C::NSPEC && s_active) {
+        if (ctid < C::NSPEC && s_active) {
             float *dst = a.part + ((int64_t)s * (a.T / 16) + (m_s0 >> 4)) * M;
             dst[ch_s] = ch[8].pacc;
             dst[M + ch_s] = 0.f;
