@@ -324,8 +324,20 @@ fengine_kernel(FLaunch a) {
         pacc[j] = 0.f;
     }
 
+    // The 16 spectra in two chunks of 8.  INT8 / FP8 up to 4096 channels: each
+    // chunk as two loops of 4, the copy of the loop body for half hh (a constant
+    // after unrolling) putting the codes into the chunk's first (hh = 0, spectra
+    // 0..3) or second (hh = 1) pair of words; at 8192 channels and more, where
+    // the two copies measured slower, one loop of 8 that copies the first pair
+    // aside after its fourth spectrum.  Either way the chunk is stored after its
+    // eighth spectrum, outside the loop.
+    constexpr int NH = ((BM == 1 || BM == 2) && LOGM <= 11) ? 2 : 1;
 #pragma unroll 1
-    for (int r = 0; r < 16; ++r) {
+    for (int r8 = 0; r8 < 16; r8 += 8) {
+#pragma unroll
+    for (int hh = 0; hh < NH; ++hh) {
+#pragma unroll 1
+    for (int r = r8 + (8 / NH) * hh; r < r8 + (8 / NH) * (hh + 1); ++r) {
         const int m = m0 + r;
         // all in-loop addressing derives from this opaque copy of t, so that it
         // is recomputed per spectrum instead of being hoisted and held live
@@ -440,27 +452,39 @@ fengine_kernel(FLaunch a) {
                         f0[j] = Y;
                     }
                 } else {
-                    // insert the byte of spectrum r into the current dword (the other
-                    // bytes are overwritten by the next spectra before they are used)
+                    // insert the byte of spectrum r into byte r mod 4 of the chunk's
+                    // pair of words for this half (one loop: the second pair, the
+                    // first copied aside after spectrum 3 of the chunk)
+                    uint32_t &q = (NH == 2 && hh == 0) ? q0[j] : q1[j];
+                    uint32_t &h = (NH == 2 && hh == 0) ? h0[j] : h1[j];
                     if constexpr (BM == 1) {
-                        q1[j] = put_i8_biased(Y.x, r & 3, q1[j]);
-                        h1[j] = put_i8_biased(Y.y, r & 3, h1[j]);
+                        q = put_i8_biased(Y.x, r & 3, q);
+                        h = put_i8_biased(Y.y, r & 3, h);
                     } else {  // one conversion: real code in byte 0, imaginary in byte 1
                         const uint32_t w = e4m3_pair(Y.x, Y.y);
-                        q1[j] = __builtin_amdgcn_perm(w, q1[j], bsel);
-                        h1[j] = __builtin_amdgcn_perm(w, h1[j], bsel + (1u << (8 * (r & 3))));
+                        q = __builtin_amdgcn_perm(w, q, bsel);
+                        h = __builtin_amdgcn_perm(w, h, bsel + (1u << (8 * (r & 3))));
                     }
-                    if ((r & 7) == 3) {  // spectra 0..3 of the chunk complete
+                    if (NH == 1 && (r & 7) == 3) {
                         q0[j] = q1[j];
                         h0[j] = h1[j];
-                    } else if ((r & 7) == 7 && active) {
-                        uint4 *dst = reinterpret_cast<uint4 *>(a.spec) + obase + (int64_t)j * L * a.S;
-                        constexpr uint32_t B = BM == 1 ? kI8Bias : 0u;  // int8 bytes carry the bias
-                        *dst = make_uint4(q0[j] ^ B, q1[j] ^ B, h0[j] ^ B, h1[j] ^ B);
                     }
                 }
             }
         }
+    }
+    }
+    if constexpr (BM == 1 || BM == 2) {  // the chunk of spectra r8 .. r8 + 7, whole
+        if (active) {
+            constexpr uint32_t B = BM == 1 ? kI8Bias : 0u;  // int8 bytes carry the bias
+            const int64_t ob = (int64_t)((m0 + r8) / G) * M * a.S + (((t >> 3) * a.S + s) << 3) + (t & 7);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                uint4 *dst = reinterpret_cast<uint4 *>(a.spec) + ob + (int64_t)j * L * a.S;
+                *dst = make_uint4(q0[j] ^ B, q1[j] ^ B, h0[j] ^ B, h1[j] ^ B);
+            }
+        }
+    }
     }
 
     if constexpr (BM == 3) {
