@@ -60,10 +60,11 @@ MEASURED_TRAFFIC = {
                         "sha256": "0575a7337cb0cacaccfe75035e16730f28ab822ddaf3867113aecd5f888fc064",
                         "flags": ["-mllvm", "-amdgpu-mfma-vgpr-form", "-mllvm", "-amdgpu-sched-strategy=max-ilp"],
                         "read": 9.165e9, "write": 8.590e9},
-    # profiles/fx_fp32_64sig_1024pt_16384spec_pointsources.md: FETCH_SIZE 537826 KiB x 2.000, WRITE_SIZE 4194304 KiB
+    # profiles/fx_fp32_64sig_1024pt_16384spec_pointsources.md: FETCH_SIZE 537802 KiB x 2.000, WRITE_SIZE 4194304 KiB
     # (medians of 6 dispatches)
     "fengine_fp32_c2": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
-                        "sha256": "b6d39bb895f23bd84c3355b5a0b9ceaa9b644c91a7262f4f377014737ec3f44c",
+                        "sha256": "752cc90ed275dea5e3ee47a0f95cb1472859c15dff0c235504cf6068a8a8039a",
+                        "flags": [],
                         "read": 1.101e9, "write": 4.295e9},
     # profiles/cnn_flagged_64sig_8192pt_8192spec.md (FP16 power, column guard, max-ilp schedule): FETCH_SIZE
     # 2097368 KiB x 2.000, WRITE_SIZE 2097152 KiB
