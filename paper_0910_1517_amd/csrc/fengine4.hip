@@ -62,6 +62,9 @@ typedef float f4_float16 __attribute__((ext_vector_type(16)));
 typedef int f4_int2 __attribute__((ext_vector_type(2)));
 typedef unsigned f4_uint4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) f4_int2 lds_int2;
+typedef short f4_short4 __attribute__((ext_vector_type(4)));
+typedef short f4_short8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) f4_short4 lds_short4;
 
 template <int LOGM>
 struct F4Cfg {
@@ -312,7 +315,16 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
     constexpr int G = (BM == 0) ? kChunk32 : kChunk8;
     constexpr int RL = C::RLAST == 1 ? 8 : C::RLAST;  // radix of the last column pass
     constexpr int NBL = 8 / RL;                       // its butterflies per thread
-    __shared__ __attribute__((aligned(16))) uint32_t lds_x[2][FPAR][N / 4];  // window bytes, double-buffered
+    // The window: at 2048 channels converted to FP16 once, as it is staged (rows of
+    // N1 samples at a pitch of N1 + 32 halves, so that the 8 rows a 16-bit
+    // transposing read pass touches fall on distinct banks), single-buffered (its
+    // last reader, stage A of the previous spectrum, is behind that spectrum's
+    // barriers); otherwise as bytes, double-buffered, converted after the
+    // transposing byte reads.
+    constexpr bool H16 = LOGM == 11;
+    constexpr int XP = N1 + 32;
+    __shared__ __attribute__((aligned(16))) uint32_t lds_x[H16 ? 1 : 2][FPAR][H16 ? 4 : N / 4];
+    __shared__ __attribute__((aligned(16))) _Float16 lds_xh[H16 ? FPAR : 1][H16 ? (N / N1) * XP : 8];
     __shared__ __attribute__((aligned(16))) float2 lds_tw[twl_count(C::LOGN1) > 0 ? twl_count(C::LOGN1) : 1];
     __shared__ __attribute__((aligned(16))) float2 lds_b[C::NBUF][FPAR * 32 * C::CS];
     __shared__ __attribute__((aligned(16))) uint16_t lds_a[2][64 * C::AP];  // FP16 rows (hi, lo)
@@ -377,6 +389,11 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
     const int tr_i = ln & 15, tr_g = ln >> 4;
     const int tr_c0 = 32 * nt + 16 * (tr_g & 1) + 8 * (tr_i & 1);
     const int tr_off = (tr_c0 / N1) * N + (tr_c0 % N1) + N1 * (8 * (tr_g >> 1) + (tr_i >> 1));
+    // 16-bit transposing read (FP16 window): in each 16-lane group, lane 4 q + c gives
+    // the address of row (K) q, columns 4 c .. 4 c + 3 of the group's 16, and lane i
+    // receives column i of the 4 rows; group g takes columns 16 (g mod 2) + 32 nt
+    // and rows 8 (g / 2) (the lane's K half)
+    const int t16_off = (8 * (tr_g >> 1) + (tr_i >> 2)) * (N1 + 32) + 32 * nt + 16 * (tr_g & 1) + 4 * (tr_i & 3);
     // four-step twiddles W_N^(n1 p) of this lane's column and its 8 rows p
     float2 tws[8];
 #pragma unroll
@@ -466,35 +483,54 @@ __global__ void __launch_bounds__(F4Cfg<LOGM>::WG) __attribute__((amdgpu_waves_p
         // 1. stage the window bytes (buffer r mod 2: its last reader, stage A two
         //    spectra back, is behind the barriers of the previous spectrum), then
         //    fetch the next window
+        // int8 -> FP16, exactly: b ^ 0x80 is b + 128 (0..255); under the byte 0x64 it
+        // forms the FP16 number 1024 + b + 128, and one packed subtraction of 1152
+        // leaves b (all integers below 2048 are FP16 numbers).  The subtraction is
+        // written on the whole vector: written per FP16 pair, this compiler merged
+        // the four byte selections into one.
+        auto to_half8 = [](uint32_t w0, uint32_t w1) -> f4_half8 {
+            const uint32_t x0 = w0 ^ 0x80808080u, x1 = w1 ^ 0x80808080u;
+            f4_uint4 hb;
+            hb[0] = __builtin_amdgcn_perm(0x64646464u, x0, 0x04010400u);
+            hb[1] = __builtin_amdgcn_perm(0x64646464u, x0, 0x04030402u);
+            hb[2] = __builtin_amdgcn_perm(0x64646464u, x1, 0x04010400u);
+            hb[3] = __builtin_amdgcn_perm(0x64646464u, x1, 0x04030402u);
+            return __builtin_bit_cast(f4_half8, hb) - (f4_half8)((_Float16)1152.0f);
+        };
         if (f_active) {
             uint4 d;
             d.x = __builtin_amdgcn_alignbyte(pw[1], pw[0], sh);
             d.y = __builtin_amdgcn_alignbyte(pw[2], pw[1], sh);
             d.z = __builtin_amdgcn_alignbyte(pw[3], pw[2], sh);
             d.w = __builtin_amdgcn_alignbyte(pw[4], pw[3], sh);
-            *reinterpret_cast<uint4 *>(&lds_x[r & 1][fu][4 * ft]) = d;
+            if constexpr (H16) {  // samples 16 ft .. 16 ft + 15: one row, 16 columns
+                const int n = 16 * ft;
+                _Float16 *dst = &lds_xh[fu][(n / N1) * XP + n % N1];
+                *reinterpret_cast<f4_half8 *>(dst) = to_half8(d.x, d.y);
+                *reinterpret_cast<f4_half8 *>(dst + 8) = to_half8(d.z, d.w);
+            } else {
+                *reinterpret_cast<uint4 *>(&lds_x[r & 1][fu][4 * ft]) = d;
+            }
         }
         if (f_active && r + 1 < SPS) fetch(m_f0 + r + 1);
         __syncthreads();
-        const int8_t *lds_xb = reinterpret_cast<const int8_t *>(&lds_x[r & 1][0][0]);
         // 2. (*) on the matrix cores: hi and lo twiddle halves into one FP32 sum
         f4_float16 acc = {};
 #pragma unroll
         for (int kt = 0; kt < 4; ++kt) {
-            const f4_int2 raw = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
-                (lds_int2 *)(lds_xb + tr_off + 16 * N1 * kt));
-            // int8 -> FP16, exactly: b ^ 0x80 is b + 128 (0..255); under the byte 0x64 it
-            // forms the FP16 number 1024 + b + 128, and one packed subtraction of 1152
-            // leaves b (all integers below 2048 are FP16 numbers).  The subtraction is
-            // written on the whole vector: written per FP16 pair, this compiler merged
-            // the four byte selections into one.
-            const uint32_t x0 = (uint32_t)raw[0] ^ 0x80808080u, x1 = (uint32_t)raw[1] ^ 0x80808080u;
-            f4_uint4 hb;
-            hb[0] = __builtin_amdgcn_perm(0x64646464u, x0, 0x04010400u);
-            hb[1] = __builtin_amdgcn_perm(0x64646464u, x0, 0x04030402u);
-            hb[2] = __builtin_amdgcn_perm(0x64646464u, x1, 0x04010400u);
-            hb[3] = __builtin_amdgcn_perm(0x64646464u, x1, 0x04030402u);
-            const f4_half8 bf = __builtin_bit_cast(f4_half8, hb) - (f4_half8)((_Float16)1152.0f);
+            f4_half8 bf;
+            if constexpr (H16) {
+                // two 16-bit transposing reads: rows (K) 0..3 and 4..7 of the lane's column
+                const _Float16 *xb = &lds_xh[0][0] + t16_off + 16 * XP * kt;
+                const f4_short4 k0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_short4 *)xb);
+                const f4_short4 k1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_short4 *)(xb + 4 * XP));
+                bf = __builtin_bit_cast(f4_half8, __builtin_shufflevector(k0, k1, 0, 1, 2, 3, 4, 5, 6, 7));
+            } else {
+                const int8_t *lds_xb = reinterpret_cast<const int8_t *>(&lds_x[r & 1][0][0]);
+                const f4_int2 raw = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+                    (lds_int2 *)(lds_xb + tr_off + 16 * N1 * kt));
+                bf = to_half8((uint32_t)raw[0], (uint32_t)raw[1]);
+            }
             const f4_half8 alo = *reinterpret_cast<const f4_half8 *>(&lds_a[1][a_off + 16 * kt]);
             const f4_half8 ahi = *reinterpret_cast<const f4_half8 *>(&lds_a[0][a_off + 16 * kt]);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, bf, acc, 0, 0, 0);
