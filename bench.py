@@ -54,12 +54,12 @@ FP32_PUBLISHED_PEAK = 157.3e12  # the datasheet's FP32 vector figure (packed FP3
 # calibration copy, see profiles/), valid only for the kernel source they were
 # taken from: reported as `traffic` when the source hash still matches.
 MEASURED_TRAFFIC = {
-    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4475461 KiB x 2.000, WRITE_SIZE 8388684 KiB x 1.000
+    # profiles/fx_int8_64sig_4096pt_32768spec.md: FETCH_SIZE 4468485 KiB x 2.000, WRITE_SIZE 8388932 KiB x 1.000
     # (medians of 7 dispatches, with the source's instruction-level-parallelism schedule)
     "fengine_int8_c3": {"source": "paper_0910_1517_amd/csrc/fengine4.hip",
-                        "sha256": "0575a7337cb0cacaccfe75035e16730f28ab822ddaf3867113aecd5f888fc064",
+                        "sha256": "59ba376590687bfeb9bf11ebeabfc7cccdfdcc610893e4b27ca29d0f09025fda",
                         "flags": ["-mllvm", "-amdgpu-mfma-vgpr-form", "-mllvm", "-amdgpu-sched-strategy=max-ilp"],
-                        "read": 9.165e9, "write": 8.590e9},
+                        "read": 9.151e9, "write": 8.590e9},
     # profiles/fx_fp32_64sig_1024pt_16384spec_pointsources.md: FETCH_SIZE 537802 KiB x 2.000, WRITE_SIZE 4194304 KiB
     # (medians of 6 dispatches)
     "fengine_fp32_c2": {"source": "paper_0910_1517_amd/csrc/fengine.hip",
