@@ -9,9 +9,10 @@
 //   column statistic mean power of one channel over the tile's 64 spectra
 //                    (persistent narrowband tones show up here)
 // A cell is flagged when its row or its column exceeds Eq. 4.  Flagged cells
-// are zeroed in the X-engine input, and the number of unflagged products of
-// every pair, n_ij[k] = sum_m (1 - F_i)(1 - F_j), is counted exactly from
-// bit-packed keep masks with popcounts.
+// are zeroed in the X-engine input (or masked as it stages them), and the
+// number of unflagged products of every pair, n_ij[k] = sum_m (1 - F_i)(1 - F_j),
+// is counted exactly from bit-packed keep masks, as the Gram matrix of the
+// keep bits on the int8 matrix cores.
 #include "corr_internal.h"
 
 namespace corr {
